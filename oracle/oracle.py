@@ -1,0 +1,193 @@
+"""Python front end of the FP64 CPU reference renderer (gs_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the package smoke check and the
+benchmark's CPU-baseline leg use it; the GPU library never does, and this
+module imports nothing from the GPU package.
+
+The arithmetic lives in gs_oracle.c (double precision).  This module builds
+that file with gcc, marshals numpy arrays, and derives the per-tile sets of
+Gaussians whose tile membership lies within the footprint-edge or near-plane
+guard bands (the compositing step flags pixels those could change).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gs_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+TILE = 16
+GUARD_PX = 1e-3
+GUARD_Z = 1e-6
+VISIBLE = 1
+AMB_ZNEAR = 2
+AMB_EDGES = 4 | 8 | 16 | 32
+PIX_ALPHA, PIX_T, PIX_TIE, PIX_MEMBER = 1, 2, 4, 8
+
+_dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_fp = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = False) -> str:
+    """Compile gs_oracle.c into liboracle.so (plain C, -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-shared", "-fPIC",
+                               "-o", tmp, _SRC, "-lm", "-lpthread"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            L = C.CDLL(_LIB)
+            L.oracle_sh_basis.argtypes = [C.c_int, _dp, _dp]
+            L.oracle_sh_basis.restype = None
+            L.oracle_preprocess.argtypes = [C.c_int64, C.c_int, _fp, _fp, _fp, _fp, _fp, C.c_int,
+                                            C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _i32p, _u8p]
+            L.oracle_preprocess.restype = None
+            L.oracle_lists.argtypes = [C.c_int64, _i32p, _dp, _u8p, C.c_int, C.c_int, C.c_int,
+                                       C.c_void_p, C.c_void_p, C.c_void_p]
+            L.oracle_lists.restype = C.c_int64
+            L.oracle_composite.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _i64p, _i64p,
+                                           _i64p, _i64p, _dp, C.c_int, C.c_void_p, C.c_int64,
+                                           _dp, _dp, _dp, _i64p, _u8p]
+            L.oracle_composite.restype = None
+            _lib = L
+    return _lib
+
+
+def sh_basis(deg: int, direction) -> np.ndarray:
+    d = np.ascontiguousarray(direction, np.float64)
+    out = np.zeros(16, np.float64)
+    lib().oracle_sh_basis(deg, d, out)
+    return out[: (deg + 1) ** 2]
+
+
+def _c32(a):
+    return np.ascontiguousarray(a, np.float32)
+
+
+def preprocess(scene, cam) -> dict:
+    """Per-Gaussian records: xy (n,2), depth, cov2d (n,3: xx,xy,yy), conic (n,3: a,b,c), rgb (n,3),
+    radius, rect (n,4: x0,y0,x1,y1 half-open tile ranges), flags."""
+    n = scene.n
+    out = dict(xy=np.zeros((n, 2)), depth=np.zeros(n), cov2d=np.zeros((n, 3)), conic=np.zeros((n, 3)),
+               rgb=np.zeros((n, 3)), radius=np.zeros(n), rect=np.zeros((n, 4), np.int32),
+               flags=np.zeros(n, np.uint8))
+    lib().oracle_preprocess(n, scene.sh_degree, _c32(scene.mean), _c32(scene.log_scale), _c32(scene.quat),
+                            _c32(scene.sh), cam.packed(), cam.width, cam.height, out["xy"], out["depth"],
+                            out["cov2d"], out["conic"], out["rgb"], out["radius"], out["rect"],
+                            out["flags"])
+    out["opacity"] = scene.opacity.astype(np.float64)
+    out["visible"] = (out["flags"] & VISIBLE) != 0
+    return out
+
+
+def grid(cam, group: int = 1):
+    tx = (cam.width + TILE - 1) // TILE
+    ty = (cam.height + TILE - 1) // TILE
+    return tx, ty, (tx + group - 1) // group, (ty + group - 1) // group
+
+
+def lists(rec: dict, cam, group: int = 1):
+    """CSR lists per bin (tile for group 1, GxG group otherwise): start (nbins+1), ids, masks.
+    Each bin's entries are ordered by (depth, index)."""
+    n = rec["depth"].shape[0]
+    _, _, gx, gy = grid(cam, group)
+    L = lib()
+    total = L.oracle_lists(n, rec["rect"], rec["depth"], rec["flags"], cam.width, cam.height, group,
+                           None, None, None)
+    start = np.zeros(gx * gy + 1, np.int64)
+    ids = np.zeros(max(total, 1), np.int64)
+    masks = np.zeros(max(total, 1), np.uint32)
+    L.oracle_lists(n, rec["rect"], rec["depth"], rec["flags"], cam.width, cam.height, group,
+                   start.ctypes.data, ids.ctypes.data, masks.ctypes.data)
+    return start, ids[:total], masks[:total]
+
+
+def ambiguous_membership(rec: dict, cam):
+    """Per tile, the Gaussians whose membership flips inside the footprint-edge (1e-3 px) or
+    near-plane (1e-6) guard band.  Returns CSR (start, ids)."""
+    tx, ty, _, _ = grid(cam, 1)
+    fl = rec["flags"]
+    cand = np.nonzero((fl & (AMB_ZNEAR | AMB_EDGES)) != 0)[0]
+    eps = GUARD_PX / TILE
+    per_tile = [[] for _ in range(tx * ty)]
+    for g in cand:
+        mx, my = rec["xy"][g]
+        r = rec["radius"][g]
+        lo = np.array([(mx - r) / TILE, (my - r) / TILE])
+        hi = np.array([(mx + r) / TILE, (my + r) / TILE])
+        may0 = np.floor(lo - eps).astype(int)
+        may1 = np.floor(hi + eps).astype(int)
+        sure0 = np.floor(lo + eps).astype(int)
+        sure1 = np.floor(hi - eps).astype(int)
+        lim = np.array([tx - 1, ty - 1])
+        may0 = np.maximum(may0, 0)
+        may1 = np.minimum(may1, lim)
+        zamb = bool(fl[g] & AMB_ZNEAR)
+        for yy in range(may0[1], may1[1] + 1):
+            for xx in range(may0[0], may1[0] + 1):
+                sure = (sure0[0] <= xx <= sure1[0]) and (sure0[1] <= yy <= sure1[1])
+                if zamb or not sure:
+                    per_tile[yy * tx + xx].append(int(g))
+    start = np.zeros(tx * ty + 1, np.int64)
+    start[1:] = np.cumsum([len(p) for p in per_tile])
+    ids = np.array([g for p in per_tile for g in p] or [0], np.int64)
+    return start, ids
+
+
+def composite(rec: dict, cam, start, ids, bg=(0.0, 0.0, 0.0), nthreads: int = 1, tiles=None,
+              amb=None) -> dict:
+    W, H = cam.width, cam.height
+    if amb is None:
+        amb = ambiguous_membership(rec, cam)
+    astart, aids = amb
+    image = np.zeros((3, H, W))
+    tfinal = np.zeros((H, W))
+    wsum = np.zeros((H, W))
+    neval = np.zeros((H, W), np.int64)
+    ambig = np.zeros((H, W), np.uint8)
+    sel = None if tiles is None else np.ascontiguousarray(tiles, np.int64)
+    lib().oracle_composite(W, H, np.ascontiguousarray(rec["xy"]), rec["depth"],
+                           np.ascontiguousarray(rec["conic"]), np.ascontiguousarray(rec["rgb"]),
+                           rec["opacity"], start, np.ascontiguousarray(ids if ids.size else np.zeros(1, np.int64)),
+                           astart, aids, np.ascontiguousarray(bg, np.float64), int(nthreads),
+                           None if sel is None else sel.ctypes.data, 0 if sel is None else sel.size,
+                           image, tfinal, wsum, neval, ambig)
+    return dict(image=image, tfinal=tfinal, wsum=wsum, neval=neval, ambiguous=ambig)
+
+
+def render(scene, cam, bg=(0.0, 0.0, 0.0), nthreads: int = 1) -> dict:
+    """Full FP64 render: records, tile lists, image (3,H,W), T_final, W = sum(alpha T), evaluation
+    counts, ambiguity flags, and the Gaussian-pixel evaluation total E_pix."""
+    rec = preprocess(scene, cam)
+    start, ids, _ = lists(rec, cam, 1)
+    out = composite(rec, cam, start, ids, bg, nthreads)
+    out.update(records=rec, start=start, ids=ids, e_pix=int(out["neval"].sum()))
+    return out
+
+
+def load_reduction(rec: dict, cam, group: int) -> tuple:
+    """(N_total, N_group, 1 - N_group/N_total) for GxG groups (Cross-tile grouping observation)."""
+    s1, _, _ = lists(rec, cam, 1)
+    sg, _, _ = lists(rec, cam, group)
+    n_total = int(s1[-1])
+    n_group = int(sg[-1])
+    return n_total, n_group, (1.0 - n_group / n_total) if n_total else 0.0
