@@ -1,0 +1,320 @@
+// C ABI: argument validation (host only, before any HIP call), workspace layout and the
+// order of the stages of one frame (Algorithm 1).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "gs_internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+gs_status fail(gs_status s, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+gs_status hip_fail(hipError_t e, const char *where) {
+  return fail(GS_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define GS_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+gs_status check_camera(const gs_camera *c) {
+  if (!c) return fail(GS_ERR_INVALID_ARG, "camera is NULL");
+  if (c->width <= 0 || c->height <= 0) return fail(GS_ERR_INVALID_ARG, "image size %dx%d", c->width, c->height);
+  if (c->width > 16384 || c->height > 16384)
+    return fail(GS_ERR_UNSUPPORTED, "image size %dx%d above 16384", c->width, c->height);
+  if (!(c->fx > 0.0f) || !(c->fy > 0.0f) || !std::isfinite(c->fx) || !std::isfinite(c->fy))
+    return fail(GS_ERR_INVALID_ARG, "focal lengths must be positive and finite");
+  if (!(c->znear > 0.0f) || !std::isfinite(c->znear)) return fail(GS_ERR_INVALID_ARG, "znear must be positive");
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(c->R[i])) return fail(GS_ERR_INVALID_ARG, "R has a non-finite entry");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(c->t[i])) return fail(GS_ERR_INVALID_ARG, "t has a non-finite entry");
+  if (!std::isfinite(c->cx) || !std::isfinite(c->cy)) return fail(GS_ERR_INVALID_ARG, "principal point non-finite");
+  return GS_OK;
+}
+
+gs_status check_options(const gs_options *o) {
+  if (!o) return fail(GS_ERR_INVALID_ARG, "options is NULL");
+  if (o->group < 1) return fail(GS_ERR_INVALID_ARG, "group %d", o->group);
+  if (o->group != 1 && o->group != 2 && o->group != 4) return fail(GS_ERR_UNSUPPORTED, "group %d not in {1,2,4}", o->group);
+  if (o->precision < GS_PREC_FP32 || o->precision > GS_PREC_BF16_MFMA)
+    return fail(GS_ERR_INVALID_ARG, "precision %d", o->precision);
+  if (o->precision != GS_PREC_FP32) {
+    if (o->splits < 1 || o->splits > 3) return fail(GS_ERR_INVALID_ARG, "splits %d not in 1..3", o->splits);
+    if (o->precision == GS_PREC_FP16_MFMA && o->splits == 3)
+      return fail(GS_ERR_UNSUPPORTED, "FP16 supports splits 1..2 (a third FP16 piece would be subnormal)");
+  }
+  if (o->aux_flags & ~(uint32_t)(GS_AUX_TFINAL | GS_AUX_WSUM | GS_AUX_NEVAL))
+    return fail(GS_ERR_INVALID_ARG, "aux_flags 0x%x", o->aux_flags);
+  if (o->reserved != 0) return fail(GS_ERR_INVALID_ARG, "reserved must be 0");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(o->bg[i])) return fail(GS_ERR_INVALID_ARG, "background non-finite");
+  return GS_OK;
+}
+
+gs_status check_scene(const gs_scene *s) {
+  if (!s) return fail(GS_ERR_INVALID_ARG, "scene is NULL");
+  if (s->n < 0) return fail(GS_ERR_INVALID_ARG, "n = %lld", (long long)s->n);
+  if (s->n >= (1ll << 31)) return fail(GS_ERR_UNSUPPORTED, "n = %lld >= 2^31", (long long)s->n);
+  if (s->sh_degree < 0) return fail(GS_ERR_INVALID_ARG, "sh_degree %d", s->sh_degree);
+  if (s->sh_degree > 3) return fail(GS_ERR_UNSUPPORTED, "sh_degree %d > 3", s->sh_degree);
+  if (s->n > 0 && (!s->mean || !s->log_scale || !s->quat || !s->opacity || !s->sh))
+    return fail(GS_ERR_INVALID_ARG, "scene array is NULL");
+  return GS_OK;
+}
+
+gs_status check_projected(const gs_projected *p, int64_t n, bool need_records) {
+  if (!p) return fail(GS_ERR_INVALID_ARG, "projected is NULL");
+  if (!p->offset) return fail(GS_ERR_INVALID_ARG, "projected.offset is NULL");
+  if (n > 0 && (!p->count || !p->rect || (need_records && (!p->xy || !p->conic || !p->rgb))))
+    return fail(GS_ERR_INVALID_ARG, "projected array is NULL");
+  return GS_OK;
+}
+
+gs_status check_bins(const gs_bins *b, int group, bool need_keys) {
+  if (!b) return fail(GS_ERR_INVALID_ARG, "bins is NULL");
+  if (!b->ranges || !b->vals || (need_keys && !b->keys))
+    return fail(GS_ERR_INVALID_ARG, "bins array is NULL");
+  if (group > 1 && !b->masks) return fail(GS_ERR_INVALID_ARG, "bins.masks is NULL with group %d", group);
+  return GS_OK;
+}
+
+struct Workspace {
+  void *scan;
+  uint64_t *keys_alt;
+  uint32_t *vals_alt;
+  void *sort;
+  size_t total;
+};
+
+Workspace carve(void *ws, int64_t n, uint64_t capacity) {
+  Workspace w;
+  char *p = static_cast<char *>(ws);
+  size_t off = 0;
+  w.scan = p ? p + off : nullptr;
+  off += align_up(gsi::scan_tmp_bytes(n));
+  w.keys_alt = p ? reinterpret_cast<uint64_t *>(p + off) : nullptr;
+  off += align_up((size_t)capacity * sizeof(uint64_t));
+  w.vals_alt = p ? reinterpret_cast<uint32_t *>(p + off) : nullptr;
+  off += align_up((size_t)capacity * sizeof(uint32_t));
+  w.sort = p ? p + off : nullptr;
+  off += align_up(gsi::sort_tmp_bytes(capacity));
+  w.total = off;
+  return w;
+}
+
+gsi::RasterJob make_job(const gs_projected &p, const gs_bins &b, const gsi::Grid &g, float *image, float *aux) {
+  gsi::RasterJob j;
+  j.xy = reinterpret_cast<const double2 *>(p.xy);
+  j.conic = reinterpret_cast<const float4 *>(p.conic);
+  j.rgb = reinterpret_cast<const float4 *>(p.rgb);
+  j.vals = b.vals;
+  j.masks = b.masks;
+  j.ranges = b.ranges;
+  j.image = image;
+  j.aux = aux;
+  j.W = g.W; j.H = g.H; j.TX = g.TX; j.TY = g.TY; j.GX = g.GX; j.GY = g.GY;
+  j.nbins = (int)g.nbins;
+  j.bin0 = 0;
+  return j;
+}
+
+gsi::RasterParams make_params(const gs_options &o) {
+  gsi::RasterParams p;
+  p.G = o.group;
+  p.prec = o.precision;
+  p.splits = o.splits;
+  for (int i = 0; i < 3; ++i) p.bg[i] = o.bg[i];
+  p.aux_flags = o.aux_flags;
+  return p;
+}
+
+gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam, const gs_options *opt,
+                      const gs_bins *bins, uint64_t *n_keys, void *ws, size_t ws_bytes, hipStream_t st) {
+  const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
+  const Workspace w = carve(ws, n, bins->capacity);
+  uint64_t K = 0;
+  GS_HIP(hipMemcpyAsync(&K, proj->offset + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  GS_HIP(hipStreamSynchronize(st));
+  *n_keys = K;
+  if (K > bins->capacity)
+    return fail(GS_ERR_CAPACITY, "%llu entries exceed capacity %llu", (unsigned long long)K,
+                (unsigned long long)bins->capacity);
+  if (K >= (1ull << 32)) return fail(GS_ERR_UNSUPPORTED, "%llu entries >= 2^32", (unsigned long long)K);
+  const int hi = 32 + gsi::bits_for((uint64_t)g.nbins);
+  const int passes = gsi::radix_passes(0, hi);
+  // binning writes where an odd number of passes ends in the caller's buffers
+  const bool first_alt = (passes & 1) && K > 1;
+  uint64_t *k0 = first_alt ? w.keys_alt : bins->keys;
+  uint32_t *v0 = first_alt ? w.vals_alt : bins->vals;
+  uint64_t *k1 = first_alt ? bins->keys : w.keys_alt;
+  uint32_t *v1 = first_alt ? bins->vals : w.vals_alt;
+  GS_HIP(gsi::launch_binning(*proj, n, g, bins->capacity, k0, v0, st));
+  bool in_alt = false;
+  GS_HIP(gsi::radix_sort(k0, v0, k1, v1, K, 0, hi, w.sort, st, &in_alt));
+  const bool in_caller = first_alt ? in_alt : !in_alt;
+  if (!in_caller && K > 0) {
+    GS_HIP(hipMemcpyAsync(bins->keys, in_alt ? k1 : k0, K * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    GS_HIP(hipMemcpyAsync(bins->vals, in_alt ? v1 : v0, K * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  }
+  GS_HIP(gsi::launch_ranges(bins->keys, bins->vals, K, proj->rect, g, bins->ranges,
+                            opt->group > 1 ? bins->masks : nullptr, st));
+  (void)ws_bytes;
+  return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gs_status_string(gs_status s) {
+  switch (s) {
+    case GS_OK: return "ok";
+    case GS_ERR_INVALID_ARG: return "invalid argument";
+    case GS_ERR_UNSUPPORTED: return "unsupported";
+    case GS_ERR_CAPACITY: return "capacity exceeded";
+    case GS_ERR_HIP: return "HIP error";
+  }
+  return "unknown status";
+}
+
+const char *gs_last_error(void) { return g_err; }
+
+int64_t gs_num_bins(const gs_camera *cam, int32_t group) {
+  if (!cam || cam->width <= 0 || cam->height <= 0 || group < 1) return 0;
+  return gsi::make_grid(cam->width, cam->height, group).nbins;
+}
+
+size_t gs_workspace_bytes(int64_t n, uint64_t capacity, const gs_camera *cam, const gs_options *opt) {
+  (void)cam;
+  (void)opt;
+  if (n < 0) return 0;
+  return carve(nullptr, n, capacity).total;
+}
+
+gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_options *opt, const gs_projected *out,
+                        void *ws, size_t ws_bytes, void *stream) {
+  gs_status s;
+  if ((s = check_scene(scene)) || (s = check_camera(cam)) || (s = check_options(opt)) ||
+      (s = check_projected(out, scene->n, true)))
+    return s;
+  const size_t need = align_up(gsi::scan_tmp_bytes(scene->n));
+  if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID_ARG, "workspace %zu bytes, need %zu", ws_bytes, need);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
+  GS_HIP(gsi::launch_preprocess(*scene, *cam, g, *out, st));
+  GS_HIP(gsi::launch_scan(out->count, out->offset, scene->n, ws, st));
+  return GS_OK;
+}
+
+gs_status gs_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam, const gs_options *opt,
+                      const gs_bins *bins, uint64_t *n_keys, void *ws, size_t ws_bytes, void *stream) {
+  gs_status s;
+  if (n < 0) return fail(GS_ERR_INVALID_ARG, "n = %lld", (long long)n);
+  if (n >= (1ll << 31)) return fail(GS_ERR_UNSUPPORTED, "n = %lld >= 2^31", (long long)n);
+  if ((s = check_camera(cam)) || (s = check_options(opt)) || (s = check_projected(proj, n, true)) ||
+      (s = check_bins(bins, opt->group, true)))
+    return s;
+  if (!n_keys) return fail(GS_ERR_INVALID_ARG, "n_keys is NULL");
+  const size_t need = carve(nullptr, n, bins->capacity).total;
+  if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID_ARG, "workspace %zu bytes, need %zu", ws_bytes, need);
+  return do_bin_sort(proj, n, cam, opt, bins, n_keys, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_rasterize(const gs_projected *proj, const gs_bins *bins, const gs_camera *cam, const gs_options *opt,
+                       float *image, float *aux, void *stream) {
+  gs_status s;
+  if ((s = check_camera(cam)) || (s = check_options(opt)) || (s = check_bins(bins, opt->group, false))) return s;
+  if (!proj || !proj->xy || !proj->conic || !proj->rgb) return fail(GS_ERR_INVALID_ARG, "projected record is NULL");
+  if (!image) return fail(GS_ERR_INVALID_ARG, "image is NULL");
+  if (opt->aux_flags && !aux) return fail(GS_ERR_INVALID_ARG, "aux is NULL with aux_flags set");
+  const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
+  const gsi::RasterJob j = make_job(*proj, *bins, g, image, aux);
+  const gsi::RasterParams p = make_params(*opt);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (opt->precision == GS_PREC_FP32)
+    GS_HIP(gsi::launch_raster_fp32(j, p, st));
+  else
+    GS_HIP(gsi::launch_raster_mfma(j, p, st));
+  return GS_OK;
+}
+
+gs_status gs_render(const gs_scene *scene, const gs_camera *cam, const gs_options *opt, const gs_projected *proj,
+                    const gs_bins *bins, float *image, float *aux, uint64_t *n_keys, void *ws, size_t ws_bytes,
+                    void *stream) {
+  gs_status s;
+  if ((s = check_scene(scene)) || (s = check_camera(cam)) || (s = check_options(opt)) ||
+      (s = check_projected(proj, scene->n, true)) || (s = check_bins(bins, opt->group, true)))
+    return s;
+  if (!image) return fail(GS_ERR_INVALID_ARG, "image is NULL");
+  if (opt->aux_flags && !aux) return fail(GS_ERR_INVALID_ARG, "aux is NULL with aux_flags set");
+  if (!n_keys) return fail(GS_ERR_INVALID_ARG, "n_keys is NULL");
+  const size_t need = carve(nullptr, scene->n, bins->capacity).total;
+  if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID_ARG, "workspace %zu bytes, need %zu", ws_bytes, need);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
+  GS_HIP(gsi::launch_preprocess(*scene, *cam, g, *proj, st));
+  GS_HIP(gsi::launch_scan(proj->count, proj->offset, scene->n, ws, st));
+  if ((s = do_bin_sort(proj, scene->n, cam, opt, bins, n_keys, ws, ws_bytes, st))) return s;
+  const gsi::RasterJob j = make_job(*proj, *bins, g, image, aux);
+  const gsi::RasterParams p = make_params(*opt);
+  if (opt->precision == GS_PREC_FP32)
+    GS_HIP(gsi::launch_raster_fp32(j, p, st));
+  else
+    GS_HIP(gsi::launch_raster_mfma(j, p, st));
+  return GS_OK;
+}
+
+size_t gs_sort_workspace_bytes(uint64_t n) {
+  return align_up((size_t)n * sizeof(uint64_t)) + align_up((size_t)n * sizeof(uint32_t)) +
+         align_up(gsi::sort_tmp_bytes(n));
+}
+
+gs_status gs_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t n, int32_t lo_bit, int32_t hi_bit, void *ws,
+                            size_t ws_bytes, void *stream) {
+  if (n > 0 && (!keys || !vals)) return fail(GS_ERR_INVALID_ARG, "keys or vals is NULL");
+  if (lo_bit < 0 || hi_bit > 64 || lo_bit > hi_bit) return fail(GS_ERR_INVALID_ARG, "bit range [%d, %d)", lo_bit, hi_bit);
+  if (n >= (1ull << 32)) return fail(GS_ERR_UNSUPPORTED, "n >= 2^32");
+  const size_t need = gs_sort_workspace_bytes(n);
+  if (n > 1 && (!ws || ws_bytes < need)) return fail(GS_ERR_INVALID_ARG, "workspace %zu bytes, need %zu", ws_bytes, need);
+  if (n <= 1) return GS_OK;
+  char *p = static_cast<char *>(ws);
+  uint64_t *ka = reinterpret_cast<uint64_t *>(p);
+  uint32_t *va = reinterpret_cast<uint32_t *>(p + align_up((size_t)n * sizeof(uint64_t)));
+  void *tmp = p + align_up((size_t)n * sizeof(uint64_t)) + align_up((size_t)n * sizeof(uint32_t));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  bool in_alt = false;
+  GS_HIP(gsi::radix_sort(keys, vals, ka, va, n, lo_bit, hi_bit, tmp, st, &in_alt));
+  if (in_alt) {
+    GS_HIP(hipMemcpyAsync(keys, ka, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    GS_HIP(hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  }
+  return GS_OK;
+}
+
+size_t gs_batch_table_bytes(int32_t n_jobs) {
+  return n_jobs > 0 ? (size_t)n_jobs * sizeof(gsi::RasterJob) : 0;
+}
+
+gs_status gs_rasterize_batch(const gs_job *jobs, int32_t n_jobs, const gs_options *opt, void *job_table,
+                             uint32_t *work_counter, void *stream) {
+  (void)jobs; (void)n_jobs; (void)opt; (void)job_table; (void)work_counter; (void)stream;
+  return fail(GS_ERR_UNSUPPORTED, "batched rasterization is not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,289 @@
+// Frustum culling and feature computation (one lane per Gaussian, SoA loads), and the
+// exclusive scan of per-Gaussian bin counts.
+//
+// Per Gaussian (paper, Background: "frustum culling", "feature computation"):
+//   camera-space centre t = R mu + t_cam (FP64), cull t_z <= znear;
+//   covariance Sigma = M diag(s)^2 M^T from the normalised quaternion M and s = exp(log_scale);
+//   first-order projection Sigma' = J R Sigma R^T J^T + 0.3 I with the Jacobian J of the
+//   pinhole map taken at the centre, its lateral coordinate clamped to 1.3x the half
+//   field of view (FP32), conic = Sigma'^-1 (FP32);
+//   projected centre mu' = (fx t_x/t_z + cx, fy t_y/t_z + cy) in FP64 (the centre feeds
+//   d = x - mu' of eq. power_d at absolute pixel coordinates, where FP32 would leave
+//   ~1e-4 px of rounding at 1080p);
+//   footprint half-width r = 3 sqrt(lambda_max(Sigma')), tile rectangle of the square
+//   [mu' - r, mu' + r], culled when it misses the grid;
+//   colour = real SH (degree <= 3) at the unit direction from the camera centre, + 0.5,
+//   clamped below at 0; depth = t_z.
+#include "gs_internal.hpp"
+
+namespace gsi {
+namespace {
+
+struct PreArgs {
+  int64_t n;
+  int deg;
+  const float *mean, *log_scale, *quat, *opacity, *sh;
+  double R[9], t[3];
+  float Rf[9];
+  double fx, fy, cx, cy, znear;
+  float fxf, fyf, limx, limy;
+  float campos[3];
+  int TX, TY, G;
+  double2 *xy;
+  float4 *conic;
+  float4 *rgb;
+  ushort4 *rect;
+  uint32_t *count;
+};
+
+// Real orthonormal spherical harmonics with the Condon-Shortley phase, index l*l + l + m,
+// for a unit direction (x, y, z).  Constants are sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!)
+// times sqrt(2) for m != 0, folded with the polynomial factors of P_l^|m|:
+//   l=0: 1/(2 sqrt(pi))
+//   l=1: sqrt(3/(4 pi))
+//   l=2: sqrt(15/(4 pi)), sqrt(5/(16 pi)), sqrt(15/(16 pi))
+//   l=3: sqrt(35/(32 pi)), sqrt(105/(4 pi)), sqrt(21/(32 pi)), sqrt(7/(16 pi)), sqrt(105/(16 pi))
+__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float *b) {
+  b[0] = 0.28209479177387814f;
+  if (deg < 1) return;
+  const float c1 = 0.4886025119029199f;
+  b[1] = -c1 * y;
+  b[2] = c1 * z;
+  b[3] = -c1 * x;
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  const float xy = x * y, yz = y * z, xz = x * z;
+  b[4] = 1.0925484305920792f * xy;
+  b[5] = -1.0925484305920792f * yz;
+  b[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);
+  b[7] = -1.0925484305920792f * xz;
+  b[8] = 0.5462742152960396f * (xx - yy);
+  if (deg < 3) return;
+  b[9] = -0.5900435899266435f * y * (3.0f * xx - yy);
+  b[10] = 2.890611442640554f * xy * z;
+  b[11] = -0.4570457994644658f * y * (5.0f * zz - 1.0f);
+  b[12] = 0.3731763325901154f * z * (5.0f * zz - 3.0f);
+  b[13] = -0.4570457994644658f * x * (5.0f * zz - 1.0f);
+  b[14] = 1.445305721320277f * z * (xx - yy);
+  b[15] = -0.5900435899266435f * x * (xx - 3.0f * yy);
+}
+
+__global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= a.n) return;
+  const int64_t n = a.n;
+  uint32_t cnt = 0;
+  ushort4 rc = make_ushort4(0, 0, 0, 0);
+
+  const double px = a.mean[g], py = a.mean[n + g], pz = a.mean[2 * n + g];
+  const double tx = fma(a.R[0], px, fma(a.R[1], py, fma(a.R[2], pz, a.t[0])));
+  const double ty = fma(a.R[3], px, fma(a.R[4], py, fma(a.R[5], pz, a.t[1])));
+  const double tz = fma(a.R[6], px, fma(a.R[7], py, fma(a.R[8], pz, a.t[2])));
+
+  if (tz > a.znear) {
+    // scales and rotation
+    const float s0 = expf(a.log_scale[g]), s1 = expf(a.log_scale[n + g]), s2 = expf(a.log_scale[2 * n + g]);
+    float qw = a.quat[g], qx = a.quat[n + g], qy = a.quat[2 * n + g], qz = a.quat[3 * n + g];
+    const float qi = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw *= qi; qx *= qi; qy *= qi; qz *= qi;
+    const float M[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
+                        2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
+                        2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
+    // Jacobian rows at the clamped lateral position
+    const float tzf = (float)tz;
+    const float ux = fminf(fmaxf((float)(tx / tz), -a.limx), a.limx);
+    const float uy = fminf(fmaxf((float)(ty / tz), -a.limy), a.limy);
+    const float izf = 1.0f / tzf;
+    const float j00 = a.fxf * izf, j02 = -a.fxf * ux * izf;
+    const float j11 = a.fyf * izf, j12 = -a.fyf * uy * izf;
+    // T = J R (2x3), P = T M diag(s), Sigma' = P P^T + 0.3 I
+    float T0[3], T1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      T0[k] = j00 * a.Rf[k] + j02 * a.Rf[6 + k];
+      T1[k] = j11 * a.Rf[3 + k] + j12 * a.Rf[6 + k];
+    }
+    const float sc[3] = {s0, s1, s2};
+    float P0[3], P1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      P0[k] = (T0[0] * M[k] + T0[1] * M[3 + k] + T0[2] * M[6 + k]) * sc[k];
+      P1[k] = (T1[0] * M[k] + T1[1] * M[3 + k] + T1[2] * M[6 + k]) * sc[k];
+    }
+    // Sigma' = P P^T + 0.3 I.  det(P P^T) = |P0 x P1|^2 (Cauchy-Binet), so every term of
+    // det(Sigma') is non-negative and FP32 keeps full relative precision for thin splats.
+    const float pxx = P0[0] * P0[0] + P0[1] * P0[1] + P0[2] * P0[2];
+    const float pyy = P1[0] * P1[0] + P1[1] * P1[1] + P1[2] * P1[2];
+    const float sxy = P0[0] * P1[0] + P0[1] * P1[1] + P0[2] * P1[2];
+    const float cr0 = P0[1] * P1[2] - P0[2] * P1[1];
+    const float cr1 = P0[2] * P1[0] - P0[0] * P1[2];
+    const float cr2 = P0[0] * P1[1] - P0[1] * P1[0];
+    const float sxx = pxx + 0.3f, syy = pyy + 0.3f;
+    const float det = (cr0 * cr0 + cr1 * cr1 + cr2 * cr2) + 0.3f * (pxx + pyy) + 0.09f;
+    if (det > 0.0f) {
+      const float idet = 1.0f / det;
+      const float ca = syy * idet, cb = -sxy * idet, cc = sxx * idet;
+      const double mx = a.fx * tx / tz + a.cx;
+      const double my = a.fy * ty / tz + a.cy;
+      const float mid = 0.5f * (sxx + syy), hd = 0.5f * (sxx - syy);
+      const float lmax = mid + sqrtf(hd * hd + sxy * sxy);
+      const double r = 3.0 * (double)sqrtf(lmax);
+      const double fx0 = floor((mx - r) * (1.0 / kTile)), fx1 = floor((mx + r) * (1.0 / kTile));
+      const double fy0 = floor((my - r) * (1.0 / kTile)), fy1 = floor((my + r) * (1.0 / kTile));
+      const int x0 = (int)fmax(fx0, 0.0), x1 = (int)fmin(fx1, (double)(a.TX - 1));
+      const int y0 = (int)fmax(fy0, 0.0), y1 = (int)fmin(fy1, (double)(a.TY - 1));
+      if (x0 <= x1 && y0 <= y1) {
+        const int G = a.G;
+        cnt = (uint32_t)((x1 / G - x0 / G + 1) * (y1 / G - y0 / G + 1));
+        rc = make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)(x1 + 1),
+                          (unsigned short)(y1 + 1));
+        // colour
+        float dx = (float)px - a.campos[0], dy = (float)py - a.campos[1], dz = (float)pz - a.campos[2];
+        const float di = rsqrtf(dx * dx + dy * dy + dz * dz);
+        dx *= di; dy *= di; dz *= di;
+        float b[16];
+        sh_basis(a.deg, dx, dy, dz, b);
+        const int nb = (a.deg + 1) * (a.deg + 1);
+        float col[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          float acc = 0.0f;
+          for (int k = 0; k < nb; ++k) acc = fmaf(a.sh[((int64_t)k * 3 + ch) * n + g], b[k], acc);
+          col[ch] = fmaxf(acc + 0.5f, 0.0f);
+        }
+        a.xy[g] = make_double2(mx, my);
+        a.conic[g] = make_float4(ca, cb, cc, a.opacity[g]);
+        a.rgb[g] = make_float4(col[0], col[1], col[2], tzf);
+      }
+    }
+  }
+  a.count[g] = cnt;
+  a.rect[g] = rc;
+}
+
+// ---- exclusive scan: u32 counts -> u64 offsets (n + 1 entries) ------------------
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t *sh, uint64_t *total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    uint64_t add = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  uint64_t incl = sh[t];
+  *total = sh[kBlock - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *in, int64_t n, uint64_t *bsum) {
+  __shared__ uint64_t sh[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  uint64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    int64_t idx = base + (int64_t)i * kBlock + threadIdx.x;
+    if (idx < n) s += in[idx];
+  }
+  uint64_t total;
+  block_exclusive_scan(s, sh, &total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// single workgroup: exclusive scan of the block sums in place, grand total to *total_out
+__global__ __launch_bounds__(kBlock) void k_scan_top(uint64_t *bsum, int64_t nb, uint64_t *total_out) {
+  __shared__ uint64_t sh[kBlock];
+  uint64_t carry = 0;
+  for (int64_t base = 0; base < nb; base += kBlock) {
+    int64_t idx = base + threadIdx.x;
+    uint64_t v = idx < nb ? bsum[idx] : 0;
+    uint64_t tot;
+    uint64_t ex = block_exclusive_scan(v, sh, &tot);
+    if (idx < nb) bsum[idx] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, int64_t n, const uint64_t *bsum,
+                                                      uint64_t *out) {
+  __shared__ uint64_t sh[kBlock];
+  // thread t owns the consecutive items [base + t*kScanItems, base + (t+1)*kScanItems)
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0u;
+    s += v[i];
+  }
+  uint64_t tot;
+  uint64_t run = bsum[blockIdx.x] + block_exclusive_scan(s, sh, &tot);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_preprocess(const gs_scene &s, const gs_camera &c, const Grid &g, const gs_projected &o,
+                             hipStream_t st) {
+  if (s.n == 0) return hipSuccess;
+  PreArgs a;
+  a.n = s.n;
+  a.deg = s.sh_degree;
+  a.mean = s.mean;
+  a.log_scale = s.log_scale;
+  a.quat = s.quat;
+  a.opacity = s.opacity;
+  a.sh = s.sh;
+  for (int i = 0; i < 9; ++i) {
+    a.R[i] = c.R[i];
+    a.Rf[i] = c.R[i];
+  }
+  for (int i = 0; i < 3; ++i) a.t[i] = c.t[i];
+  a.fx = c.fx; a.fy = c.fy; a.cx = c.cx; a.cy = c.cy; a.znear = c.znear;
+  a.fxf = c.fx; a.fyf = c.fy;
+  a.limx = (float)(1.3 * (0.5 * c.width) / (double)c.fx);
+  a.limy = (float)(1.3 * (0.5 * c.height) / (double)c.fy);
+  // camera centre -R^T t
+  for (int i = 0; i < 3; ++i)
+    a.campos[i] = (float)(-((double)c.R[i] * c.t[0] + (double)c.R[3 + i] * c.t[1] + (double)c.R[6 + i] * c.t[2]));
+  a.TX = g.TX; a.TY = g.TY; a.G = g.G;
+  a.xy = reinterpret_cast<double2 *>(o.xy);
+  a.conic = reinterpret_cast<float4 *>(o.conic);
+  a.rgb = reinterpret_cast<float4 *>(o.rgb);
+  a.rect = reinterpret_cast<ushort4 *>(o.rect);
+  a.count = o.count;
+  const unsigned blocks = (unsigned)((s.n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+size_t scan_tmp_bytes(int64_t n) {
+  int64_t nb = (n + kScanTile - 1) / kScanTile;
+  return (size_t)(nb + 1) * sizeof(uint64_t);
+}
+
+hipError_t launch_scan(const uint32_t *in, uint64_t *out, int64_t n, void *tmp, hipStream_t st) {
+  int64_t nb = (n + kScanTile - 1) / kScanTile;
+  uint64_t *bsum = static_cast<uint64_t *>(tmp);
+  if (nb == 0) {
+    // n == 0: offset[0] = 0
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, st, bsum, (int64_t)0, out);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, bsum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, st, bsum, nb, out + n);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, bsum, out);
+  return hipGetLastError();
+}
+
+}  // namespace gsi

@@ -1,0 +1,142 @@
+// Plain FP32 rasterizer (paper, Background: tile-based rasterization, eq. power_d, eq. power).
+//
+// One 256-lane workgroup per bin (a tile, or a GxG tile group); each lane owns one pixel
+// position and, for a group, that position in every member tile.  The bin's depth-sorted
+// list is streamed through LDS in chunks of 256 entries.  Per (entry, pixel):
+//   d = x - mu'                       (eq. power_d)
+//   log2(alpha_raw) = log2(o) + log2(e) * (-1/2 d^T conic d)   (eq. power)
+//   skip when alpha_raw < 1/255, alpha = min(0.99, alpha_raw)
+//   T' = T (1 - alpha); stop (without blending) when T' < 1e-4; else C += alpha T c, T = T'.
+// The pixel's offset to the centre is formed from a group-relative FP32 copy of the FP64
+// centre, so |d| stays small and exact.  Lanes map to 8x8 quadrants per wave so that a
+// splat that misses a quadrant is skipped by the whole wave.
+#include "gs_internal.hpp"
+
+namespace gsi {
+namespace {
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  // workgroups are dispatched round-robin over the 8 XCDs: give each XCD a contiguous
+  // range of bins so that neighbouring bins share that XCD's L2
+  const int x = b & 7, idx = b >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  return x * per + (x < rem ? x : rem) + idx;
+}
+
+template <int G, bool AUX>
+__global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParams P) {
+  constexpr int NT = G * G;
+  __shared__ float4 s_a[kBlock];  // (u, v, -a/2 log2e, -b log2e)
+  __shared__ float4 s_b[kBlock];  // (-c/2 log2e, log2 o, r, g)
+  __shared__ float4 s_c[kBlock];  // (b, mask bits, -, -)
+
+  const int bin = xcd_remap(blockIdx.x, J.nbins);
+  const int gx = bin % J.GX, gy = bin / J.GX;
+  const int ox = gx * G * kTile, oy = gy * G * kTile;
+  const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int px = (w & 1) * 8 + (lane & 7), py = (w >> 1) * 8 + (lane >> 3);
+
+  float T[NT], C0[NT], C1[NT], C2[NT], Ws[NT], cut[NT];
+  uint32_t nstop[NT], nseen[NT];
+  float X[NT], Y[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const int lx = (k % G) * kTile + px, ly = (k / G) * kTile + py;
+    X[k] = lx + 0.5f;
+    Y[k] = ly + 0.5f;
+    const bool inside = (ox + lx < J.W) && (oy + ly < J.H);
+    T[k] = 1.0f; C0[k] = C1[k] = C2[k] = 0.0f; Ws[k] = 0.0f;
+    cut[k] = inside ? kCutLog2 : INFINITY;
+    nstop[k] = 0; nseen[k] = 0;
+  }
+
+  for (uint32_t cs = start; cs < end; cs += kBlock) {
+    const int cnt = (int)min((uint32_t)kBlock, end - cs);
+    __syncthreads();
+    if (t < cnt) {
+      const uint32_t e = cs + t;
+      const uint32_t g = J.vals[e];
+      const double2 m = J.xy[g];
+      const float4 co = J.conic[g];
+      const float4 cl = J.rgb[g];
+      const uint32_t mk = (G > 1) ? (uint32_t)J.masks[e] : 1u;
+      s_a[t] = make_float4((float)(m.x - ox), (float)(m.y - oy), -0.5f * kLog2e * co.x, -kLog2e * co.y);
+      s_b[t] = make_float4(-0.5f * kLog2e * co.z, __log2f(co.w), cl.x, cl.y);
+      s_c[t] = make_float4(cl.z, __uint_as_float(mk), 0.0f, 0.0f);
+    }
+    bool alive = false;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) alive |= cut[k] != INFINITY;
+    if (!__syncthreads_or(alive)) break;
+    for (int j = 0; j < cnt; ++j) {
+      const float4 A = s_a[j];
+      const float4 B = s_b[j];
+      const float4 Cc = s_c[j];
+      const uint32_t mk = __float_as_uint(Cc.y);
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        if (G > 1 && !((mk >> k) & 1u)) continue;
+        if (AUX) nseen[k]++;
+        const float dx = X[k] - A.x, dy = Y[k] - A.y;
+        const float D = fmaf(dx, fmaf(A.z, dx, A.w * dy), fmaf(B.x * dy, dy, B.y));
+        if (D >= cut[k]) {
+          const float al = fminf(kAlphaMax, __builtin_amdgcn_exp2f(D));
+          const float Tn = T[k] * (1.0f - al);
+          if (Tn < kTMin) {
+            cut[k] = INFINITY;
+            if (AUX) nstop[k] = nseen[k];
+          } else {
+            const float wgt = al * T[k];
+            C0[k] = fmaf(wgt, B.z, C0[k]);
+            C1[k] = fmaf(wgt, B.w, C1[k]);
+            C2[k] = fmaf(wgt, Cc.x, C2[k]);
+            if (AUX) Ws[k] += wgt;
+            T[k] = Tn;
+          }
+        }
+      }
+    }
+  }
+
+  const int64_t HW = (int64_t)J.W * J.H;
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const int xx = ox + (k % G) * kTile + px, yy = oy + (k / G) * kTile + py;
+    if (xx >= J.W || yy >= J.H) continue;
+    const int64_t pix = (int64_t)yy * J.W + xx;
+    J.image[pix] = C0[k] + T[k] * P.bg[0];
+    J.image[HW + pix] = C1[k] + T[k] * P.bg[1];
+    J.image[2 * HW + pix] = C2[k] + T[k] * P.bg[2];
+    if (AUX) {
+      int plane = 0;
+      if (P.aux_flags & GS_AUX_TFINAL) J.aux[(plane++) * HW + pix] = T[k];
+      if (P.aux_flags & GS_AUX_WSUM) J.aux[(plane++) * HW + pix] = Ws[k];
+      if (P.aux_flags & GS_AUX_NEVAL) {
+        const bool stopped = (cut[k] == INFINITY);
+        J.aux[(plane++) * HW + pix] = (float)(stopped ? nstop[k] : nseen[k]);
+      }
+    }
+  }
+}
+
+template <int G, bool AUX>
+hipError_t launch_g(const RasterJob &j, const RasterParams &p, hipStream_t st) {
+  hipLaunchKernelGGL((k_raster_fp32<G, AUX>), dim3((unsigned)j.nbins), dim3(kBlock), 0, st, j, p);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_raster_fp32(const RasterJob &j, const RasterParams &p, hipStream_t st) {
+  if (j.nbins == 0) return hipSuccess;
+  const bool aux = p.aux_flags != 0;
+  switch (p.G) {
+    case 1: return aux ? launch_g<1, true>(j, p, st) : launch_g<1, false>(j, p, st);
+    case 2: return aux ? launch_g<2, true>(j, p, st) : launch_g<2, false>(j, p, st);
+    case 4: return aux ? launch_g<4, true>(j, p, st) : launch_g<4, false>(j, p, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace gsi

@@ -1,0 +1,412 @@
+// Tensorized rasterizer: the Gaussian-pixel power as a dense MFMA contraction
+// (paper: "Tensorizing the Power Computation", "Padding the Inner Dimension",
+// "Warp-Level WMMA Mapping"; cross-tile grouping: "Grouped Rasterization with Shared
+// Gaussian", Algorithm 1), re-designed for gfx950 wave64 and v_mfma_f32_32x32x16_{f16,bf16}.
+//
+// Power as a product.  In a tile-local frame with origin at the tile centre (pixel centre
+// minus tile origin minus 8.5, so x, y are integers in [-8, 7]), for a Gaussian with centre
+// (u, v) in that frame, conic [[a,b],[b,c]] and opacity o:
+//   log2(o exp(power)) = k . phi,  phi = [x^2, xy, y^2, x, y, 1]
+//   k = log2(e) [-a/2, -b, -c/2, a u + b v, b u + c v, ln o - (a u^2 + 2 b u v + c v^2)/2]
+// which is exact in real arithmetic.  The paper's printed pixel-side basis holds
+// Gaussian-dependent offsets; this separable form keeps the pixel side (B) constant for
+// every tile and every Gaussian, so it lives in registers for the whole kernel.  phi entries
+// are small integers, exact in FP16 and BF16.  The Gaussian side (A) is split into
+// `splits` FP16/BF16 pieces hi + lo 2^-s (+ lo2 2^-2s) that occupy spare K slots of the
+// 16-wide inner dimension against scaled copies of phi, so the precision lost to the 16-bit
+// operands is won back at no extra MFMA (zero-padding of unused slots is exact).
+//
+// Mapping.  One 256-lane workgroup per bin; wave w owns the 8x8 quadrant (w&1, w>>1) of each
+// member tile, as two 8x4 panels of 32 pixels.  For a block of 32 Gaussians (rows), one
+// MFMA per panel gives D[32 Gaussians][32 pixels] = log2(alpha_raw).  Lane l holds
+// D[8(j/4) + 4(l/32) + j%4][l%32] in register j; one v_permlane32_swap per register pair
+// (panel-0 value, panel-1 value) leaves lane l < 32 with all 32 rows of panel-0 pixel l and
+// lane l >= 32 with all 32 rows of panel-1 pixel l-32.  Each lane then runs the exact
+// sequential front-to-back recurrence over those rows in depth order (VALU: exp2, 1/255
+// cut as a compare on D, clamp, FP32 transmittance product, stop test, colour FMA).
+//
+// Grouping.  For G > 1 a chunk of the group's list is staged in LDS once; for every member
+// tile the entries whose mask bit is set are compacted in order (ballot + mbcnt) and their
+// A rows are built in that tile's frame.  Per-tile blending state lives in registers.  Each
+// tile sees the same Gaussians in the same order with the same arithmetic as with G = 1, so
+// grouped and ungrouped images are bit-identical.
+#include "gs_internal.hpp"
+
+namespace gsi {
+namespace {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short short8 __attribute__((ext_vector_type(8)));
+typedef float float16v __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int x = b & 7, idx = b >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  return x * per + (x < rem ? x : rem) + idx;
+}
+
+template <int PREC>
+struct Narrow;
+
+template <>
+struct Narrow<GS_PREC_FP16_MFMA> {
+  static constexpr float kScale = 2048.0f;            // 2^11
+  __device__ static __forceinline__ uint16_t enc(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+  __device__ static __forceinline__ float dec(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
+  __device__ static __forceinline__ float16v mma(short8 a, short8 b, float16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a), __builtin_bit_cast(half8, b), c, 0,
+                                                  0, 0);
+  }
+};
+
+template <>
+struct Narrow<GS_PREC_BF16_MFMA> {
+  static constexpr float kScale = 256.0f;             // 2^8
+  __device__ static __forceinline__ uint16_t enc(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+  __device__ static __forceinline__ float dec(uint16_t h) { return (float)__builtin_bit_cast(__bf16, h); }
+  __device__ static __forceinline__ float16v mma(short8 a, short8 b, float16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+  }
+};
+
+// LDS row of one Gaussian: RS 16-bit slots.  Slot (h, i) of MFMA 0 is row[8h + i]; MFMA 1
+// (splits == 3) uses row[16 + 8h + i].
+//   splits 1: [k0..k5, 0, 0 | 0 x 8]
+//   splits 2: [k0..k5, l0, l1 | l2..l5, 0 x 4]
+//   splits 3: the splits-2 row, then [m0..m5, 0, 0 | 0 x 8]
+template <int PREC, int S>
+__device__ __forceinline__ void build_row(uint16_t *row, float u, float v, float a, float b, float c, float lno) {
+  using N = Narrow<PREC>;
+  const float p3 = fmaf(a, u, b * v), p4 = fmaf(b, u, c * v);
+  const float q = fmaf(u, p3, v * p4);
+  float k[6] = {-0.5f * kLog2e * a, -kLog2e * b, -0.5f * kLog2e * c, kLog2e * p3, kLog2e * p4,
+                kLog2e * fmaf(-0.5f, q, lno)};
+  uint16_t hi[6], lo[6], lo2[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    hi[i] = N::enc(k[i]);
+    float r = (k[i] - N::dec(hi[i])) * N::kScale;
+    lo[i] = N::enc(r);
+    r = (r - N::dec(lo[i])) * N::kScale;
+    lo2[i] = N::enc(r);
+  }
+  short8 v0, v1;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) v0[i] = (short)hi[i];
+  v0[6] = S >= 2 ? (short)lo[0] : 0;
+  v0[7] = S >= 2 ? (short)lo[1] : 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v1[i] = S >= 2 ? (short)lo[2 + i] : 0;
+#pragma unroll
+  for (int i = 4; i < 8; ++i) v1[i] = 0;
+  *reinterpret_cast<short8 *>(row) = v0;
+  *reinterpret_cast<short8 *>(row + 8) = v1;
+  if (S == 3) {
+    short8 v2, v3;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v2[i] = (short)lo2[i];
+    v2[6] = v2[7] = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v3[i] = 0;
+    *reinterpret_cast<short8 *>(row + 16) = v2;
+    *reinterpret_cast<short8 *>(row + 24) = v3;
+  }
+}
+
+// A row whose D is -1000 at every pixel (never passes the 1/255 cut): pads the last block.
+template <int PREC, int S>
+__device__ __forceinline__ void pad_row(uint16_t *row) {
+  using N = Narrow<PREC>;
+  short8 v0, z;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) { v0[i] = 0; z[i] = 0; }
+  v0[5] = (short)N::enc(-1000.0f);
+  *reinterpret_cast<short8 *>(row) = v0;
+  *reinterpret_cast<short8 *>(row + 8) = z;
+  if (S == 3) {
+    *reinterpret_cast<short8 *>(row + 16) = z;
+    *reinterpret_cast<short8 *>(row + 24) = z;
+  }
+}
+
+struct TileState {
+  float T, C0, C1, C2, W, cut;
+  uint32_t nstop;
+};
+
+// Runs the rows [0, nrows) of buffer A/col for one member tile.
+template <int PREC, int S, bool AUX>
+__device__ __forceinline__ void process_rows(const uint16_t *sA, const float4 *scol, int nrows, short8 B0, short8 B1,
+                                             short8 B20, short8 B21, TileState &st, uint32_t row_base) {
+  using N = Narrow<PREC>;
+  constexpr int RS = (S == 3) ? 32 : 16;
+  const int lane = threadIdx.x & 63;
+  const int nblk = (nrows + 31) >> 5;
+  for (int blk = 0; blk < nblk; ++blk) {
+    const uint16_t *rp = sA + (size_t)(32 * blk + (lane & 31)) * RS + 8 * (lane >> 5);
+    const short8 a = *reinterpret_cast<const short8 *>(rp);
+    float16v z = {};
+    float16v d0 = N::mma(a, B0, z);
+    float16v d1 = N::mma(a, B1, z);
+    if (S == 3) {
+      const short8 a2 = *reinterpret_cast<const short8 *>(rp + 16);
+      d0 = N::mma(a2, B20, d0);
+      d1 = N::mma(a2, B21, d1);
+    }
+    float D[32];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      auto pr = __builtin_amdgcn_permlane32_swap(__float_as_uint(d0[j]), __float_as_uint(d1[j]), false, false);
+      D[8 * (j >> 2) + (j & 3)] = __uint_as_float(pr[0]);
+      D[8 * (j >> 2) + 4 + (j & 3)] = __uint_as_float(pr[1]);
+    }
+#pragma unroll
+    for (int m = 0; m < 32; ++m) {
+      if (D[m] >= st.cut) {
+        const float4 cl = scol[32 * blk + m];
+        const float al = fminf(kAlphaMax, __builtin_amdgcn_exp2f(D[m]));
+        const float Tn = st.T * (1.0f - al);
+        if (Tn < kTMin) {
+          st.cut = INFINITY;
+          if (AUX) st.nstop = row_base + 32 * blk + m + 1;
+        } else {
+          const float wgt = al * st.T;
+          st.C0 = fmaf(wgt, cl.x, st.C0);
+          st.C1 = fmaf(wgt, cl.y, st.C1);
+          st.C2 = fmaf(wgt, cl.z, st.C2);
+          if (AUX) st.W += wgt;
+          st.T = Tn;
+        }
+      }
+    }
+  }
+}
+
+template <int G, int PREC, int S, bool AUX>
+__global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParams P) {
+  constexpr int NT = G * G;
+  constexpr int RS = (S == 3) ? 32 : 16;
+  __shared__ __align__(16) uint16_t s_A[2][kBlock * RS];
+  __shared__ float4 s_col[2][kBlock];
+  __shared__ double2 s_r0[G > 1 ? kBlock : 1];  // FP64 centre; every tile rounds its own offset
+  __shared__ float4 s_r1[G > 1 ? kBlock : 1];   // (a, b, c, ln o)
+  __shared__ float4 s_r2[G > 1 ? kBlock : 1];   // (r, g, b, -)
+  __shared__ uint32_t s_wcnt[2][NT][4];          // by chunk parity: a wave may stage chunk c+1 while
+                                                 // another still reads chunk c's counts
+  __shared__ uint32_t s_alive[2][4];
+
+  const int bin = xcd_remap(blockIdx.x, J.nbins);
+  const int gx = bin % J.GX, gy = bin / J.GX;
+  const int ox = gx * G * kTile, oy = gy * G * kTile;
+  const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int qx0 = (w & 1) * 8, qy0 = (w >> 1) * 8;
+  const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
+
+  // pixel-side operand: phi of this lane's panel pixel (n = lane % 32) in both panels
+  short8 B0, B1, B20, B21;
+  {
+    using N = Narrow<PREC>;
+    const int n = lane & 31, h = lane >> 5;
+    const float inv = 1.0f / N::kScale, inv2 = inv * inv;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const float x = (float)(qx0 + (n & 7) - 8), y = (float)(qy0 + (n >> 3) + 4 * p - 8);
+      const float phi[6] = {x * x, x * y, y * y, x, y, 1.0f};
+      short8 b, b2;
+      if (h == 0) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) b[i] = (short)N::enc(phi[i]);
+        b[6] = (short)N::enc(phi[0] * inv);
+        b[7] = (short)N::enc(phi[1] * inv);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) b2[i] = (short)N::enc(phi[i] * inv2);
+        b2[6] = b2[7] = 0;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b[i] = (short)N::enc(phi[2 + i] * inv);
+#pragma unroll
+        for (int i = 4; i < 8; ++i) b[i] = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) b2[i] = 0;
+      }
+      if (p == 0) { B0 = b; B20 = b2; } else { B1 = b; B21 = b2; }
+    }
+  }
+
+  TileState st[NT];
+  uint32_t alive_mask = 0;       // uniform: member tiles with pixels still blending
+  uint32_t rows_done[NT];        // uniform: entries of each tile consumed so far
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const int tx0 = ox + (k % G) * kTile, ty0 = oy + (k / G) * kTile;
+    const bool inside = (tx0 + px < J.W) && (ty0 + py < J.H);
+    st[k].T = 1.0f; st[k].C0 = st[k].C1 = st[k].C2 = 0.0f; st[k].W = 0.0f;
+    st[k].cut = inside ? kCutLog2 : INFINITY;
+    st[k].nstop = 0;
+    rows_done[k] = 0;
+    if (tx0 < J.W && ty0 < J.H) alive_mask |= 1u << k;
+  }
+
+  int it = 0;          // processing steps so far (LDS double-buffer parity)
+  int cp = 0;          // chunk parity
+  int last_k = -1;     // tile processed in the previous step, if its alive bits are pending
+  for (uint32_t cs = start; cs < end && alive_mask; cs += kBlock) {
+    const int cnt = (int)min((uint32_t)kBlock, end - cs);
+    if (G == 1) {
+      const int buf = it & 1;
+      if (t < cnt) {
+        const uint32_t e = cs + t;
+        const uint32_t g = J.vals[e];
+        const double2 m = J.xy[g];
+        const float4 co = J.conic[g];
+        const float4 cl = J.rgb[g];
+        build_row<PREC, S>(&s_A[buf][t * RS], (float)(m.x - ((double)ox + 8.5)), (float)(m.y - ((double)oy + 8.5)),
+                           co.x, co.y, co.z, __logf(co.w));
+        s_col[buf][t] = cl;
+      } else if (t < ((cnt + 31) & ~31)) {
+        pad_row<PREC, S>(&s_A[buf][t * RS]);
+      }
+      __syncthreads();
+      if (last_k >= 0) {
+        const uint32_t any = s_alive[(it - 1) & 1][0] | s_alive[(it - 1) & 1][1] | s_alive[(it - 1) & 1][2] |
+                             s_alive[(it - 1) & 1][3];
+        if (!any) alive_mask = 0;
+        last_k = -1;
+        if (!alive_mask) break;
+      }
+      process_rows<PREC, S, AUX>(s_A[buf], s_col[buf], cnt, B0, B1, B20, B21, st[0], rows_done[0]);
+      rows_done[0] += cnt;
+      const uint64_t bal = __ballot(st[0].cut != INFINITY);
+      if (lane == 0) s_alive[it & 1][w] = bal != 0;
+      last_k = 0;
+      ++it;
+    } else {
+      // stage the chunk once for every member tile (Algorithm 1: load the chunk into shared memory)
+      uint32_t mk = 0;
+      if (t < cnt) {
+        const uint32_t e = cs + t;
+        const uint32_t g = J.vals[e];
+        const double2 m = J.xy[g];
+        const float4 co = J.conic[g];
+        const float4 cl = J.rgb[g];
+        mk = J.masks[e];
+        s_r0[t] = m;
+        s_r1[t] = make_float4(co.x, co.y, co.z, __logf(co.w));
+        s_r2[t] = cl;
+      }
+      uint64_t bal[NT];
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        bal[k] = __ballot((mk >> k) & 1u);
+        if (lane == 0) s_wcnt[cp][k][w] = (uint32_t)__popcll(bal[k]);
+      }
+      __syncthreads();
+      if (last_k >= 0) {
+        const uint32_t any = s_alive[(it - 1) & 1][0] | s_alive[(it - 1) & 1][1] | s_alive[(it - 1) & 1][2] |
+                             s_alive[(it - 1) & 1][3];
+        if (!any) alive_mask &= ~(1u << last_k);
+        last_k = -1;
+      }
+      uint32_t nk[NT], woff[NT];
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        const uint32_t c0 = s_wcnt[cp][k][0], c1 = s_wcnt[cp][k][1], c2 = s_wcnt[cp][k][2], c3 = s_wcnt[cp][k][3];
+        nk[k] = c0 + c1 + c2 + c3;
+        woff[k] = (w > 0 ? c0 : 0) + (w > 1 ? c1 : 0) + (w > 2 ? c2 : 0);
+      }
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        if (!((alive_mask >> k) & 1u) || nk[k] == 0) continue;
+        const int buf = it & 1;
+        // tile-frame origin in absolute pixels, exactly as the G = 1 path forms it
+        const double fx0 = (double)(ox + (k % G) * kTile) + 8.5, fy0 = (double)(oy + (k / G) * kTile) + 8.5;
+        if ((mk >> k) & 1u) {
+          const uint32_t pos =
+              woff[k] + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[k] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal[k], 0u));
+          const double2 r0 = s_r0[t];
+          const float4 r1 = s_r1[t];
+          build_row<PREC, S>(&s_A[buf][pos * RS], (float)(r0.x - fx0), (float)(r0.y - fy0), r1.x, r1.y, r1.z, r1.w);
+          s_col[buf][pos] = s_r2[t];
+        }
+        const uint32_t padn = ((nk[k] + 31) & ~31u) - nk[k];
+        if ((uint32_t)t < padn) pad_row<PREC, S>(&s_A[buf][(nk[k] + t) * RS]);
+        __syncthreads();
+        if (last_k >= 0) {
+          const uint32_t any = s_alive[(it - 1) & 1][0] | s_alive[(it - 1) & 1][1] | s_alive[(it - 1) & 1][2] |
+                               s_alive[(it - 1) & 1][3];
+          if (!any) alive_mask &= ~(1u << last_k);
+        }
+        process_rows<PREC, S, AUX>(s_A[buf], s_col[buf], (int)nk[k], B0, B1, B20, B21, st[k], rows_done[k]);
+        rows_done[k] += nk[k];
+        const uint64_t ab = __ballot(st[k].cut != INFINITY);
+        if (lane == 0) s_alive[it & 1][w] = ab != 0;
+        last_k = k;
+        ++it;
+      }
+      cp ^= 1;
+    }
+  }
+
+  const int64_t HW = (int64_t)J.W * J.H;
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const int xx = ox + (k % G) * kTile + px, yy = oy + (k / G) * kTile + py;
+    if (xx >= J.W || yy >= J.H) continue;
+    const int64_t pix = (int64_t)yy * J.W + xx;
+    J.image[pix] = st[k].C0 + st[k].T * P.bg[0];
+    J.image[HW + pix] = st[k].C1 + st[k].T * P.bg[1];
+    J.image[2 * HW + pix] = st[k].C2 + st[k].T * P.bg[2];
+    if (AUX) {
+      int plane = 0;
+      if (P.aux_flags & GS_AUX_TFINAL) J.aux[(plane++) * HW + pix] = st[k].T;
+      if (P.aux_flags & GS_AUX_WSUM) J.aux[(plane++) * HW + pix] = st[k].W;
+      if (P.aux_flags & GS_AUX_NEVAL) {
+        const bool stopped = st[k].cut == INFINITY;
+        J.aux[(plane++) * HW + pix] = (float)(stopped ? st[k].nstop : rows_done[k]);
+      }
+    }
+  }
+}
+
+template <int G, int PREC, int S, bool AUX>
+hipError_t launch_t(const RasterJob &j, const RasterParams &p, hipStream_t st) {
+  hipLaunchKernelGGL((k_raster_mfma<G, PREC, S, AUX>), dim3((unsigned)j.nbins), dim3(kBlock), 0, st, j, p);
+  return hipGetLastError();
+}
+
+template <int G, int PREC>
+hipError_t launch_s(const RasterJob &j, const RasterParams &p, hipStream_t st) {
+  const bool aux = p.aux_flags != 0;
+  switch (p.splits) {
+    case 1: return aux ? launch_t<G, PREC, 1, true>(j, p, st) : launch_t<G, PREC, 1, false>(j, p, st);
+    case 2: return aux ? launch_t<G, PREC, 2, true>(j, p, st) : launch_t<G, PREC, 2, false>(j, p, st);
+    case 3:
+      if (PREC == GS_PREC_FP16_MFMA) return hipErrorInvalidValue;
+      return aux ? launch_t<G, PREC, 3, true>(j, p, st) : launch_t<G, PREC, 3, false>(j, p, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int PREC>
+hipError_t launch_p(const RasterJob &j, const RasterParams &p, hipStream_t st) {
+  switch (p.G) {
+    case 1: return launch_s<1, PREC>(j, p, st);
+    case 2: return launch_s<2, PREC>(j, p, st);
+    case 4: return launch_s<4, PREC>(j, p, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_raster_mfma(const RasterJob &j, const RasterParams &p, hipStream_t st) {
+  if (j.nbins == 0) return hipSuccess;
+  if (p.prec == GS_PREC_FP16_MFMA) return launch_p<GS_PREC_FP16_MFMA>(j, p, st);
+  if (p.prec == GS_PREC_BF16_MFMA) return launch_p<GS_PREC_BF16_MFMA>(j, p, st);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gsi

@@ -1,0 +1,156 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared symbol, and
+rejects invalid calls on the host before any HIP call."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2605_17855_amd import gs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "gs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = gs.lib()
+    names = declared_functions()
+    assert "gs_render" in names and "gs_rasterize" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(gs.EXPORTS)
+
+
+def test_status_strings():
+    L = gs.lib()
+    assert L.gs_status_string(gs.GS_OK) == b"ok"
+    assert L.gs_status_string(gs.GS_ERR_CAPACITY) == b"capacity exceeded"
+
+
+def _cam(w=64, h=48):
+    return gs.camera_stub(w, h)
+
+
+def test_num_bins():
+    L = gs.lib()
+    c = _cam(1920, 1080)
+    assert L.gs_num_bins(C.byref(c), 1) == 120 * 68
+    assert L.gs_num_bins(C.byref(c), 2) == 60 * 34
+    assert L.gs_num_bins(C.byref(c), 4) == 30 * 17
+    assert L.gs_num_bins(None, 1) == 0
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("group", 0, gs.GS_ERR_INVALID_ARG),
+    ("group", 3, gs.GS_ERR_UNSUPPORTED),
+    ("group", 8, gs.GS_ERR_UNSUPPORTED),
+    ("precision", 7, gs.GS_ERR_INVALID_ARG),
+    ("splits", 0, gs.GS_ERR_INVALID_ARG),
+    ("aux_flags", 16, gs.GS_ERR_INVALID_ARG),
+    ("reserved", 1, gs.GS_ERR_INVALID_ARG),
+])
+def test_rasterize_rejects_bad_options(field, value, status):
+    L = gs.lib()
+    o = gs.options(precision="fp16")
+    setattr(o, field, value)
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1)
+    b = gs.gs_bins(1, 1, 1, 16, 1)
+    img = C.c_void_p(1)
+    assert L.gs_rasterize(C.byref(p), C.byref(b), C.byref(_cam()), C.byref(o), img, None, None) == status
+    assert L.gs_last_error()
+
+
+def test_fp16_three_splits_unsupported():
+    L = gs.lib()
+    o = gs.options(precision="fp16", splits=3)
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1)
+    b = gs.gs_bins(1, 1, 1, 16, 1)
+    assert L.gs_rasterize(C.byref(p), C.byref(b), C.byref(_cam()), C.byref(o), C.c_void_p(1), None,
+                          None) == gs.GS_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("w,h,status", [(0, 10, gs.GS_ERR_INVALID_ARG), (10, -1, gs.GS_ERR_INVALID_ARG),
+                                        (16385, 10, gs.GS_ERR_UNSUPPORTED)])
+def test_rasterize_rejects_bad_camera(w, h, status):
+    L = gs.lib()
+    c = _cam()
+    c.width, c.height = w, h
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1)
+    b = gs.gs_bins(1, 1, 1, 16, 1)
+    assert L.gs_rasterize(C.byref(p), C.byref(b), C.byref(c), C.byref(gs.options()), C.c_void_p(1), None,
+                          None) == status
+
+
+def test_camera_value_checks():
+    L = gs.lib()
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1)
+    b = gs.gs_bins(1, 1, 1, 16, 1)
+    for field, value in (("fx", 0.0), ("fy", -1.0), ("znear", 0.0), ("fx", float("nan"))):
+        c = _cam()
+        setattr(c, field, value)
+        assert L.gs_rasterize(C.byref(p), C.byref(b), C.byref(c), C.byref(gs.options()), C.c_void_p(1), None,
+                              None) == gs.GS_ERR_INVALID_ARG, field
+
+
+def test_null_arguments():
+    L = gs.lib()
+    o = gs.options()
+    c = _cam()
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1)
+    b = gs.gs_bins(1, 1, 1, 16, 1)
+    assert L.gs_rasterize(None, C.byref(b), C.byref(c), C.byref(o), C.c_void_p(1), None, None) == gs.GS_ERR_INVALID_ARG
+    assert L.gs_rasterize(C.byref(p), None, C.byref(c), C.byref(o), C.c_void_p(1), None, None) == gs.GS_ERR_INVALID_ARG
+    assert L.gs_rasterize(C.byref(p), C.byref(b), None, C.byref(o), C.c_void_p(1), None, None) == gs.GS_ERR_INVALID_ARG
+    assert L.gs_rasterize(C.byref(p), C.byref(b), C.byref(c), None, C.c_void_p(1), None, None) == gs.GS_ERR_INVALID_ARG
+    assert L.gs_rasterize(C.byref(p), C.byref(b), C.byref(c), C.byref(o), None, None, None) == gs.GS_ERR_INVALID_ARG
+    o2 = gs.options(aux_flags=gs.GS_AUX_TFINAL)
+    assert L.gs_rasterize(C.byref(p), C.byref(b), C.byref(c), C.byref(o2), C.c_void_p(1), None,
+                          None) == gs.GS_ERR_INVALID_ARG
+    # grouped rasterization needs the mask array
+    b2 = gs.gs_bins(1, 1, None, 16, 1)
+    assert L.gs_rasterize(C.byref(p), C.byref(b2), C.byref(c), C.byref(gs.options(group=2)), C.c_void_p(1), None,
+                          None) == gs.GS_ERR_INVALID_ARG
+
+
+def test_scene_checks():
+    L = gs.lib()
+    o = gs.options()
+    c = _cam()
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1)
+    ws = C.c_void_p(1)
+    for n, deg, status in ((-1, 0, gs.GS_ERR_INVALID_ARG), (1 << 31, 0, gs.GS_ERR_UNSUPPORTED),
+                           (10, 4, gs.GS_ERR_UNSUPPORTED), (10, -1, gs.GS_ERR_INVALID_ARG)):
+        s = gs.gs_scene(n, deg, 0, 1, 1, 1, 1, 1)
+        assert L.gs_preprocess(C.byref(s), C.byref(c), C.byref(o), C.byref(p), ws, 1 << 20, None) == status
+    s = gs.gs_scene(10, 0, 0, 1, 1, None, 1, 1)
+    assert L.gs_preprocess(C.byref(s), C.byref(c), C.byref(o), C.byref(p), ws, 1 << 20,
+                           None) == gs.GS_ERR_INVALID_ARG
+    # workspace too small
+    s = gs.gs_scene(100000, 0, 0, 1, 1, 1, 1, 1)
+    assert L.gs_preprocess(C.byref(s), C.byref(c), C.byref(o), C.byref(p), ws, 8, None) == gs.GS_ERR_INVALID_ARG
+
+
+def test_sort_argument_checks():
+    L = gs.lib()
+    assert L.gs_radix_sort_u64(None, None, 5, 0, 64, C.c_void_p(1), 1 << 20, None) == gs.GS_ERR_INVALID_ARG
+    assert L.gs_radix_sort_u64(C.c_void_p(1), C.c_void_p(1), 5, 10, 5, C.c_void_p(1), 1 << 20,
+                               None) == gs.GS_ERR_INVALID_ARG
+    assert L.gs_radix_sort_u64(C.c_void_p(1), C.c_void_p(1), 5, 0, 65, C.c_void_p(1), 1 << 20,
+                               None) == gs.GS_ERR_INVALID_ARG
+    # n <= 1 is already sorted: no device work, no workspace needed
+    assert L.gs_radix_sort_u64(C.c_void_p(1), C.c_void_p(1), 1, 0, 64, None, 0, None) == gs.GS_OK
+
+
+def test_workspace_sizes_grow_with_inputs():
+    L = gs.lib()
+    c = _cam(1920, 1080)
+    o = gs.options()
+    a = L.gs_workspace_bytes(1000, 1000, C.byref(c), C.byref(o))
+    b = L.gs_workspace_bytes(1000, 100000, C.byref(c), C.byref(o))
+    assert b > a >= 1000 * 12
+    assert L.gs_sort_workspace_bytes(1 << 20) >= (1 << 20) * 12

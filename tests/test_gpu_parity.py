@@ -1,0 +1,304 @@
+"""GPU parity tests: the HIP library against the FP64 oracle (and, for the sort, against a
+library stable sort of the same seeded keys).  All calls go through the C ABI binding."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2605_17855_amd import gs, scenes
+from gpu_helpers import bins_numpy, note, projected_numpy, psnr, render, tile_mask
+
+pytestmark = pytest.mark.gpu
+
+AUX_ALL = gs.GS_AUX_TFINAL | gs.GS_AUX_WSUM | gs.GS_AUX_NEVAL
+
+
+@pytest.fixture(scope="module")
+def small():
+    sc, cam = scenes.small_camera_space()
+    ref = oracle.render(sc, cam)
+    return sc, cam, ref, gs.DeviceScene(sc)
+
+
+@pytest.fixture(scope="module")
+def big():
+    note("build 1M-Gaussian 1080p scene and its oracle records")
+    sc, cam = scenes.clustered_1m()
+    rec = oracle.preprocess(sc, cam)
+    return sc, cam, rec, gs.DeviceScene(sc)
+
+
+def _compare_records(rec, gp, amb_ok):
+    vis_o = rec["visible"]
+    vis_g = gp["count"] > 0
+    amb = (rec["flags"] & (oracle.AMB_ZNEAR | oracle.AMB_EDGES)) != 0
+    assert np.array_equal(vis_o[~amb], vis_g[~amb])
+    assert amb.sum() <= amb_ok
+    both = vis_o & vis_g & ~amb
+    assert both.sum() > 0
+    assert np.abs(gp["xy"][both] - rec["xy"][both]).max() < 1e-7
+    a, b, c = (rec["conic"][both, i] for i in range(3))
+    ga, gb, gc = (gp["conic"][both, i].astype(np.float64) for i in range(3))
+    scale = np.sqrt(a * c)
+    assert (np.abs(ga - a) / a).max() < 2e-5
+    assert (np.abs(gc - c) / c).max() < 2e-5
+    assert (np.abs(gb - b) / scale).max() < 2e-5
+    assert np.abs(gp["rgb"][both, :3] - rec["rgb"][both]).max() < 2e-5
+    assert (np.abs(gp["rgb"][both, 3] - rec["depth"][both]) / rec["depth"][both]).max() < 1e-7
+    assert np.array_equal(gp["rect"][both], rec["rect"][both])
+    r = rec["rect"][both]
+    assert np.array_equal(gp["count"][both], (r[:, 2] - r[:, 0]) * (r[:, 3] - r[:, 1]))
+    assert int(gp["offset"][-1]) == int(gp["count"].astype(np.uint64).sum())
+
+
+def test_preprocess_small(small):
+    sc, cam, ref, ds = small
+    note("preprocess parity 4096 / 128x128")
+    out = render(ds, cam)
+    gp = projected_numpy(out["renderer"])
+    _compare_records(ref["records"], gp, amb_ok=10)
+    assert out["n_keys"] == int(gp["offset"][-1])
+
+
+def test_preprocess_1m_1080p(big):
+    sc, cam, rec, ds = big
+    note("preprocess parity 1M / 1920x1080")
+    out = render(ds, cam, precision="fp16")
+    gp = projected_numpy(out["renderer"])
+    _compare_records(rec, gp, amb_ok=2000)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 63, 2047, 2048, 2049, 100_003, 3_000_000])
+def test_radix_sort_bit_exact(n):
+    import torch
+    note(f"radix sort n={n}")
+    keys, vals = scenes.random_keys(n, seed=100 + n % 97)
+    kd = torch.from_numpy(keys.view(np.int64).copy()).cuda()
+    vd = torch.from_numpy(vals.view(np.int32).copy()).cuda()
+    gs.gs_radix_sort_u64(kd, vd, 0, 45)
+    torch.cuda.synchronize()
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(kd.cpu().numpy().view(np.uint64), keys[order])
+    assert np.array_equal(vd.cpu().numpy().view(np.uint32), vals[order])
+
+
+@pytest.mark.parametrize("lo,hi", [(0, 8), (3, 17), (32, 45), (0, 64)])
+def test_radix_sort_bit_ranges(lo, hi):
+    import torch
+    note(f"radix sort bits [{lo},{hi})")
+    rng = np.random.default_rng(lo * 100 + hi)
+    n = 50_001
+    keys = rng.integers(0, 1 << 62, n, dtype=np.uint64) * np.uint64(3)
+    vals = np.arange(n, dtype=np.uint32)
+    kd = torch.from_numpy(keys.view(np.int64).copy()).cuda()
+    vd = torch.from_numpy(vals.view(np.int32).copy()).cuda()
+    gs.gs_radix_sort_u64(kd, vd, lo, hi)
+    torch.cuda.synchronize()
+    field = (keys >> np.uint64(lo)) & np.uint64((1 << (hi - lo)) - 1 if hi - lo < 64 else ~0)
+    order = np.argsort(field, kind="stable")
+    assert np.array_equal(vd.cpu().numpy().view(np.uint32), vals[order])
+
+
+def _check_bins(rec, cam, r, n_keys, group):
+    b = bins_numpy(r, n_keys)
+    keys, vals = b["keys"], b["vals"]
+    # ascending keys; key = (bin << 32) | float bits of the GPU depth of its Gaussian
+    assert np.all(keys[1:] >= keys[:-1])
+    gdepth = r.proj.rgb.cpu().numpy()[:, 3]
+    assert np.array_equal(keys & np.uint64(0xFFFFFFFF), gdepth[vals].view(np.uint32).astype(np.uint64))
+    # stable: equal keys keep Gaussian-index order
+    same = keys[1:] == keys[:-1]
+    assert np.all(vals[1:][same] > vals[:-1][same])
+    # ranges equal a linear scan of the sorted keys
+    bins_of = (keys >> np.uint64(32)).astype(np.int64)
+    nb = gs.gs_num_bins(cam, group)
+    want = np.zeros((nb, 2), np.int64)
+    if n_keys:
+        starts = np.r_[0, np.nonzero(bins_of[1:] != bins_of[:-1])[0] + 1]
+        ends = np.r_[starts[1:], n_keys]
+        want[bins_of[starts], 0] = starts
+        want[bins_of[starts], 1] = ends
+    assert np.array_equal(b["ranges"][:nb].astype(np.int64), want)
+    # entries against the oracle's lists (footprint-edge ambiguous Gaussians excluded)
+    st, ids, masks = oracle.lists(rec, cam, group)
+    amb = (rec["flags"] & (oracle.AMB_ZNEAR | oracle.AMB_EDGES)) != 0
+    ob = np.repeat(np.arange(nb), np.diff(st))
+    keep_o = ~amb[ids]
+    keep_g = ~amb[vals]
+    assert np.array_equal(ob[keep_o], bins_of[keep_g])
+    og, gg = ids[keep_o], vals[keep_g].astype(np.int64)
+    mismatch = np.nonzero(og != gg)[0]
+    # order may differ only between Gaussians at (nearly) equal depth
+    for i in mismatch:
+        za, zb = rec["depth"][og[i]], rec["depth"][gg[i]]
+        assert abs(za - zb) <= 1e-6 * za, (i, og[i], gg[i])
+    if group > 1:
+        gm = b["masks"][keep_g].astype(np.uint32)
+        om = masks[keep_o]
+        ok = og == gg
+        assert np.array_equal(gm[ok], om[ok])
+
+
+@pytest.mark.parametrize("group", [1, 2, 4])
+def test_bin_sort_small(small, group):
+    sc, cam, ref, ds = small
+    note(f"bin sort 4096 / 128x128 group {group}")
+    out = render(ds, cam, group=group, precision="fp16")
+    _check_bins(ref["records"], cam, out["renderer"], out["n_keys"], group)
+
+
+@pytest.mark.parametrize("group", [1, 2])
+def test_bin_sort_1m(big, group):
+    sc, cam, rec, ds = big
+    note(f"bin sort 1M / 1080p group {group}")
+    out = render(ds, cam, group=group, precision="fp16")
+    _check_bins(rec, cam, out["renderer"], out["n_keys"], group)
+
+
+def test_fp32_image_small(small):
+    sc, cam, ref, ds = small
+    note("fp32 image 4096 / 128x128")
+    out = render(ds, cam, precision="fp32", aux=AUX_ALL)
+    ok = ref["ambiguous"] == 0
+    assert ok.mean() > 0.999
+    err = np.abs(out["image"] - ref["image"])
+    assert err[:, ok].max() <= 1e-4, err[:, ok].max()
+    assert np.abs(out["tfinal"] - ref["tfinal"])[ok].max() <= 1e-5
+    assert np.abs(out["wsum"] + out["tfinal"] - 1.0).max() <= 1e-5
+    assert np.array_equal(out["neval"][ok], ref["neval"][ok].astype(np.float64))
+
+
+@pytest.mark.parametrize("prec,splits,required", [("fp16", 1, False), ("fp16", 2, True), ("bf16", 1, False),
+                                                  ("bf16", 2, False), ("bf16", 3, True)])
+def test_mfma_image_small(small, prec, splits, required):
+    sc, cam, ref, ds = small
+    note(f"mfma image {prec} splits {splits} 4096 / 128x128")
+    out = render(ds, cam, precision=prec, splits=splits, aux=AUX_ALL)
+    p = psnr(out["image"], ref["image"])
+    mae = float(np.mean(np.abs(out["image"] - ref["image"])))
+    print(f"{prec} splits={splits}: PSNR {p:.2f} dB, MAE {mae:.3e}, max abs "
+          f"{np.abs(out['image'] - ref['image']).max():.3e}")
+    assert np.abs(out["wsum"] + out["tfinal"] - 1.0).max() <= 1e-5
+    if required:
+        assert p >= 45.0 and mae <= 2e-3
+
+
+@pytest.mark.parametrize("prec,splits", [("fp16", 2), ("bf16", 3), ("fp16", 1)])
+@pytest.mark.parametrize("size", [(128, 128), (100, 70)])
+def test_grouping_bit_identical(prec, splits, size):
+    sc, _ = scenes.small_camera_space()
+    cam = scenes.pinhole(size[0], size[1], 60.0)
+    ds = gs.DeviceScene(sc)
+    note(f"grouping identity {prec}/{splits} {size}")
+    base = render(ds, cam, group=1, precision=prec, splits=splits, aux=AUX_ALL)
+    for g in (2, 4):
+        out = render(ds, cam, group=g, precision=prec, splits=splits, aux=AUX_ALL)
+        for k in ("image", "tfinal", "wsum", "neval"):
+            assert np.array_equal(out[k], base[k]), (g, k)
+
+
+def test_fp32_grouped_matches_oracle(small):
+    sc, cam, ref, ds = small
+    ok = ref["ambiguous"] == 0
+    for g in (2, 4):
+        note(f"fp32 grouped {g}")
+        out = render(ds, cam, group=g, precision="fp32")
+        assert np.abs(out["image"] - ref["image"])[:, ok].max() <= 1e-4
+
+
+def test_determinism(small):
+    sc, cam, ref, ds = small
+    note("determinism")
+    a = render(ds, cam, precision="fp16", aux=AUX_ALL)
+    b = render(ds, cam, precision="fp16", aux=AUX_ALL)
+    assert np.array_equal(a["image"], b["image"]) and np.array_equal(a["neval"], b["neval"])
+    c = render(ds, cam, precision="fp32")
+    d = render(ds, cam, precision="fp32")
+    assert np.array_equal(c["image"], d["image"])
+
+
+def test_empty_and_culled_scenes():
+    cam = scenes.pinhole(80, 48, 60.0)
+    bg = (0.25, 0.5, 0.75)
+    sc = scenes.camera_box_scene(0, seed=1)
+    note("empty scene")
+    for prec in ("fp32", "fp16"):
+        out = render(gs.DeviceScene(sc), cam, precision=prec, bg=bg)
+        assert out["n_keys"] == 0
+        assert np.allclose(out["image"], np.asarray(bg)[:, None, None])
+    # everything behind the camera
+    sc = scenes.camera_box_scene(500, seed=2)
+    sc.mean[2] *= -1.0
+    note("culled scene")
+    out = render(gs.DeviceScene(sc), cam, precision="fp16", bg=bg)
+    assert out["n_keys"] == 0
+    assert np.allclose(out["image"], np.asarray(bg)[:, None, None])
+
+
+@pytest.mark.parametrize("size", [(1, 1), (17, 33), (100, 70), (250, 16)])
+def test_ragged_sizes(size):
+    sc = scenes.camera_box_scene(1500, seed=9)
+    cam = scenes.pinhole(size[0], size[1], 60.0)
+    ref = oracle.render(sc, cam, bg=(0.1, 0.2, 0.3))
+    ds = gs.DeviceScene(sc)
+    ok = ref["ambiguous"] == 0
+    for prec, tol in (("fp32", 1e-4), ("fp16", 2e-3)):
+        note(f"ragged {size} {prec}")
+        out = render(ds, cam, precision=prec, bg=(0.1, 0.2, 0.3))
+        assert out["image"].shape == (3, size[1], size[0])
+        assert np.abs(out["image"] - ref["image"])[:, ok].max() <= tol
+
+
+def test_single_gaussian():
+    cam = scenes.pinhole(64, 64, 60.0)
+    sc = scenes.Scene(np.array([[0.01], [-0.02], [2.0]], np.float32), np.full((3, 1), math.log(0.05), np.float32),
+                      np.array([[0.9], [0.1], [0.3], [-0.2]], np.float32), np.array([0.8], np.float32),
+                      np.array([[[0.4], [0.1], [-0.2]]], np.float32), 0)
+    ref = oracle.render(sc, cam)
+    ds = gs.DeviceScene(sc)
+    for prec in ("fp32", "fp16", "bf16"):
+        note(f"single gaussian {prec}")
+        out = render(ds, cam, precision=prec, splits=3 if prec == "bf16" else 2)
+        tol = 1e-4 if prec == "fp32" else 2e-3
+        assert np.abs(out["image"] - ref["image"]).max() <= tol
+
+
+def test_capacity_error_reports_count(small):
+    import torch
+    sc, cam, ref, ds = small
+    note("capacity error")
+    r = gs.Renderer(ds.n, cam.width, cam.height, capacity=100)
+    opt = gs.options()
+    with pytest.raises(gs.GsError) as ei:
+        gs.gs_render(ds, cam, opt, r.proj, r.bins, r.image, None, r.ws)
+    assert ei.value.status == gs.GS_ERR_CAPACITY
+    assert ei.value.n_keys == int(ref["start"][-1])
+    torch.cuda.synchronize()
+
+
+def _sampled_tiles(cam, count, seed):
+    tx, ty = (cam.width + 15) // 16, (cam.height + 15) // 16
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(tx * ty, size=min(count, tx * ty), replace=False))
+
+
+def test_1080p_sampled_tiles(big):
+    sc, cam, rec, ds = big
+    tiles = _sampled_tiles(cam, 400, 7)
+    st, ids, _ = oracle.lists(rec, cam, 1)
+    ref = oracle.composite(rec, cam, st, ids, nthreads=8, tiles=tiles)
+    m = tile_mask(cam, tiles)
+    ok = m & (ref["ambiguous"] == 0)
+    for prec, splits in (("fp32", 2), ("fp16", 2), ("bf16", 3)):
+        note(f"1080p sampled tiles {prec}")
+        out = render(ds, cam, precision=prec, splits=splits, aux=AUX_ALL)
+        err = np.abs(out["image"] - ref["image"])
+        p = psnr(out["image"][:, m], ref["image"][:, m])
+        mae = float(err[:, m].mean())
+        print(f"1080p {prec}: max abs {err[:, ok].max():.3e}, PSNR {p:.2f}, MAE {mae:.3e}, "
+              f"neval match {(out['neval'][ok] == ref['neval'][ok]).mean():.5f}")
+        assert p >= 45.0 and mae <= 2e-3
+        if prec == "fp32":
+            assert err[:, ok].max() <= 1e-3
+        assert np.abs(out["wsum"] + out["tfinal"] - 1.0).max() <= 1e-5
