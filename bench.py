@@ -1,0 +1,219 @@
+"""Frame-rate benchmark of the render path on one MI355X.
+
+Workload: 1M Gaussians (64-cluster mixture, SH degree 3, log-scale N(ln 0.01, 0.7),
+opacity sigmoid(N(0, 1.5))) rendered at 1920x1080 along a 200-pose orbit of the
+radius-4 sphere, 1x1 tile grouping.  One step = one frame of the whole path on the
+resident scene: preprocess + count scan, binning + radix sort + ranges, rasterize.
+
+The chosen form (FP16 MFMA power, hi/lo splits) is timed, then the plain FP32
+rasterizer on the same poses.  The JSON line carries both rates, per-frame p50/p99,
+the raster kernel's ALU roofline (HIP events on the launch stream), the PSNR of the
+chosen form against the FP64 oracle on sampled tiles, and the oracle's own rate on
+the host cores.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "frames/s @1080p 1M Gaussians: MFMA-FP16 vs FP32 plain at PSNR≥45dB; p99 ms"
+# Per Gaussian-pixel evaluation: power as 6 multiply-adds (12 flops), alpha = o exp(power)
+# (2); per blended pair: 1 - alpha, T (1 - alpha), alpha T, 3 colour FMAs (9).
+FLOPS_PER_EVAL = 14
+FLOPS_PER_BLEND = 9
+PEAK_FP32_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (packed) x 2 (FMA) x 2.4 GHz
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp16", choices=["fp16", "bf16", "fp32"])
+    ap.add_argument("--splits", type=int, default=2)
+    ap.add_argument("--group", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP32 plain comparison run")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle compositing time")
+    return ap.parse_args()
+
+
+def timed_frames(gs, torch, ds, cams, rend, opt, steps, warmup):
+    """Returns (elapsed s, per-frame ms list, per-frame raster-kernel ms list)."""
+    st = torch.cuda.current_stream()
+
+    def frame(cam, ev):
+        gs.gs_preprocess(ds, cam, opt, rend.proj, rend.ws)
+        gs.gs_bin_sort(rend.proj, cam, opt, rend.bins, rend.ws)
+        if ev is not None:
+            ev[1].record(st)
+        gs.gs_rasterize(rend.proj, rend.bins, cam, opt, rend.image)
+        if ev is not None:
+            ev[2].record(st)
+
+    # make sure the entry buffers are large enough for every pose (grows outside the timed region)
+    for cam in cams[:max(warmup, 1)]:
+        rend.render(ds, cam, opt)
+    for i in range(warmup):
+        frame(cams[i % len(cams)], None)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record(st)
+        frame(cams[i % len(cams)], evs[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    frame_ms = [e[0].elapsed_time(e[2]) for e in evs]
+    raster_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    return elapsed, frame_ms, raster_ms
+
+
+def work_units(gs, torch, ds, cams, rend, opt_kwargs, steps):
+    """Gaussian-pixel evaluations and blended pairs of the timed frames (aux pass, untimed)."""
+    opt = gs.options(aux_flags=gs.GS_AUX_NEVAL | gs.GS_AUX_NBLEND, **opt_kwargs)
+    e_pix = 0
+    blend = 0
+    seen = {}
+    for i in range(steps):
+        k = i % len(cams)
+        if k not in seen:
+            rend.render(ds, cams[k], opt)
+            torch.cuda.synchronize()
+            a = rend.aux.double()
+            seen[k] = (int(a[0].sum().item()), int(a[1].sum().item()))
+        e_pix += seen[k][0]
+        blend += seen[k][1]
+    return e_pix, blend
+
+
+def cpu_baseline_and_psnr(gs, torch, sc, cam, image_gpu, target_s):
+    from oracle import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    rec = oracle.preprocess(sc, cam)
+    st, ids, _ = oracle.lists(rec, cam, 1)
+    amb = oracle.ambiguous_membership(rec, cam)
+    t_pre = time.perf_counter() - t0
+    tx, ty = (cam.width + 15) // 16, (cam.height + 15) // 16
+    ntiles = tx * ty
+    rng = np.random.default_rng(7)
+    order = rng.permutation(ntiles)
+    # calibrate the tile sample so the compositing takes about target_s
+    t1 = time.perf_counter()
+    probe = np.sort(order[:64])
+    oracle.composite(rec, cam, st, ids, nthreads=threads, tiles=probe, amb=amb)
+    per_tile = (time.perf_counter() - t1) / len(probe)
+    nsel = int(min(ntiles, max(64, target_s / max(per_tile, 1e-6))))
+    sel = np.sort(order[:nsel])
+    t2 = time.perf_counter()
+    ref = oracle.composite(rec, cam, st, ids, nthreads=threads, tiles=sel, amb=amb)
+    t_comp = time.perf_counter() - t2
+    frame_s = t_pre + t_comp * ntiles / nsel
+    mask = np.zeros((cam.height, cam.width), bool)
+    for t in sel:
+        x, y = (t % tx) * 16, (t // tx) * 16
+        mask[y:y + 16, x:x + 16] = True
+    a = np.clip(image_gpu[:, mask], 0, 1)
+    b = np.clip(ref["image"][:, mask], 0, 1)
+    mse = float(np.mean((a - b) ** 2))
+    psnr = float("inf") if mse == 0 else 10 * np.log10(1 / mse)
+    mae = float(np.mean(np.abs(image_gpu[:, mask] - ref["image"][:, mask])))
+    base = {"value": 1.0 / frame_s, "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 oracle on the first pose: preprocess + tile lists of all {sc.n} Gaussians "
+                       f"({t_pre:.1f} s, 1 thread), compositing of {nsel} of {ntiles} random tiles "
+                       f"({t_comp:.1f} s, {threads} threads), extrapolated to the full frame")}
+    return base, psnr, mae, nsel
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2605_17855_amd import gs, scenes
+
+    log("generating the 1M-Gaussian scene")
+    sc, _ = scenes.clustered_1m()
+    cams = scenes.orbit(200, 1920, 1080, seed=2)
+    ds = gs.DeviceScene(sc)
+    okw = dict(group=args.group, precision=args.precision, splits=args.splits)
+    rend = gs.Renderer(sc.n, 1920, 1080, group=args.group)
+
+    opt = gs.options(**okw)
+    log(f"timing {args.precision}: {args.warmup} warm-up + {args.steps} frames")
+    elapsed, frame_ms, raster_ms = timed_frames(gs, torch, ds, cams, rend, opt, args.steps, args.warmup)
+    fps = args.steps / elapsed
+    first_img = None
+    rend.render(ds, cams[0], opt)
+    torch.cuda.synchronize()
+    first_img = rend.image.double().cpu().numpy()
+
+    log("counting evaluations of the timed frames (aux pass)")
+    e_pix, blend = work_units(gs, torch, ds, cams, rend, okw, args.steps)
+    raster_total_s = sum(raster_ms) / 1e3
+    flops = FLOPS_PER_EVAL * e_pix + FLOPS_PER_BLEND * blend
+    achieved = flops / raster_total_s / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "kernel": f"k_raster_mfma (precision {args.precision}, splits {args.splits}, group {args.group})"
+                          if args.precision != "fp32" else "k_raster_fp32",
+                "avg_launch_ms": float(np.mean(raster_ms)),
+                "evals_per_frame": e_pix / args.steps, "blends_per_frame": blend / args.steps}
+
+    compare = None
+    if not args.no_compare and args.precision != "fp32":
+        log("timing fp32 plain on the same poses")
+        opt32 = gs.options(group=1, precision="fp32")
+        rend32 = gs.Renderer(sc.n, 1920, 1080, group=1)
+        el32, fm32, rm32 = timed_frames(gs, torch, ds, cams, rend32, opt32, args.steps, args.warmup)
+        compare = {"precision": "fp32", "frames_per_s": args.steps / el32,
+                   "p50_ms": float(np.percentile(fm32, 50)), "p99_ms": float(np.percentile(fm32, 99)),
+                   "raster_avg_ms": float(np.mean(rm32))}
+
+    cpu = None
+    psnr = mae = None
+    if not args.no_cpu_baseline:
+        log("FP64 oracle: CPU baseline and PSNR on sampled tiles")
+        cpu, psnr, mae, _ = cpu_baseline_and_psnr(gs, torch, sc, cams[0], first_img, args.cpu_seconds)
+
+    line = {
+        "metric": METRIC, "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.precision if args.precision != "fp32" else "fp32",
+        "data": "synthetic",
+        "config": {"workload": "1M Gaussians, 64-cluster mixture, SH degree 3, 1920x1080, 200-pose orbit, "
+                               f"{args.group}x{args.group} tile groups, {args.precision} splits {args.splits}",
+                   "gaussians": sc.n, "width": 1920, "height": 1080, "group": args.group,
+                   "precision": args.precision, "splits": args.splits},
+        "p50_ms": float(np.percentile(frame_ms, 50)), "p99_ms": float(np.percentile(frame_ms, 99)),
+        "raster_avg_ms": float(np.mean(raster_ms)),
+        "mpix_gauss_evals_per_s": e_pix / raster_total_s / 1e6,
+        "psnr_db_vs_oracle": psnr, "mae_vs_oracle": mae,
+        "fp32_plain": compare,
+        "speedup_vs_fp32": (fps / compare["frames_per_s"]) if compare else None,
+        "raster_speedup_vs_fp32": (compare["raster_avg_ms"] / float(np.mean(raster_ms))) if compare else None,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

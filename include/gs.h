@@ -61,7 +61,8 @@ typedef enum {
 enum {
   GS_AUX_TFINAL = 1u,       /* transmittance left after the last blended Gaussian */
   GS_AUX_WSUM = 2u,         /* sum over blended Gaussians of alpha*T (so WSUM + TFINAL = 1) */
-  GS_AUX_NEVAL = 4u         /* Gaussians evaluated before the stop, as a float count */
+  GS_AUX_NEVAL = 4u,        /* Gaussians evaluated before the stop, as a float count */
+  GS_AUX_NBLEND = 8u        /* Gaussians blended (alpha >= 1/255, before the stop), as a float count */
 };
 
 typedef struct {

@@ -59,7 +59,7 @@ gs_status check_options(const gs_options *o) {
     if (o->precision == GS_PREC_FP16_MFMA && o->splits == 3)
       return fail(GS_ERR_UNSUPPORTED, "FP16 supports splits 1..2 (a third FP16 piece would be subnormal)");
   }
-  if (o->aux_flags & ~(uint32_t)(GS_AUX_TFINAL | GS_AUX_WSUM | GS_AUX_NEVAL))
+  if (o->aux_flags & ~(uint32_t)(GS_AUX_TFINAL | GS_AUX_WSUM | GS_AUX_NEVAL | GS_AUX_NBLEND))
     return fail(GS_ERR_INVALID_ARG, "aux_flags 0x%x", o->aux_flags);
   if (o->reserved != 0) return fail(GS_ERR_INVALID_ARG, "reserved must be 0");
   for (int i = 0; i < 3; ++i)

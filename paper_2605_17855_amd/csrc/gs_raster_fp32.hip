@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParam
   const int px = (w & 1) * 8 + (lane & 7), py = (w >> 1) * 8 + (lane >> 3);
 
   float T[NT], C0[NT], C1[NT], C2[NT], Ws[NT], cut[NT];
-  uint32_t nstop[NT], nseen[NT];
+  uint32_t nstop[NT], nseen[NT], nblend[NT];
   float X[NT], Y[NT];
 #pragma unroll
   for (int k = 0; k < NT; ++k) {
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParam
     const bool inside = (ox + lx < J.W) && (oy + ly < J.H);
     T[k] = 1.0f; C0[k] = C1[k] = C2[k] = 0.0f; Ws[k] = 0.0f;
     cut[k] = inside ? kCutLog2 : INFINITY;
-    nstop[k] = 0; nseen[k] = 0;
+    nstop[k] = 0; nseen[k] = 0; nblend[k] = 0;
   }
 
   for (uint32_t cs = start; cs < end; cs += kBlock) {
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParam
             C0[k] = fmaf(wgt, B.z, C0[k]);
             C1[k] = fmaf(wgt, B.w, C1[k]);
             C2[k] = fmaf(wgt, Cc.x, C2[k]);
-            if (AUX) Ws[k] += wgt;
+            if (AUX) { Ws[k] += wgt; nblend[k]++; }
             T[k] = Tn;
           }
         }
@@ -116,6 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParam
         const bool stopped = (cut[k] == INFINITY);
         J.aux[(plane++) * HW + pix] = (float)(stopped ? nstop[k] : nseen[k]);
       }
+      if (P.aux_flags & GS_AUX_NBLEND) J.aux[(plane++) * HW + pix] = (float)nblend[k];
     }
   }
 }

@@ -133,7 +133,7 @@ __device__ __forceinline__ void pad_row(uint16_t *row) {
 
 struct TileState {
   float T, C0, C1, C2, W, cut;
-  uint32_t nstop;
+  uint32_t nstop, nblend;
 };
 
 // Runs the rows [0, nrows) of buffer A/col for one member tile.
@@ -176,7 +176,7 @@ __device__ __forceinline__ void process_rows(const uint16_t *sA, const float4 *s
           st.C0 = fmaf(wgt, cl.x, st.C0);
           st.C1 = fmaf(wgt, cl.y, st.C1);
           st.C2 = fmaf(wgt, cl.z, st.C2);
-          if (AUX) st.W += wgt;
+          if (AUX) { st.W += wgt; st.nblend++; }
           st.T = Tn;
         }
       }
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParam
     const bool inside = (tx0 + px < J.W) && (ty0 + py < J.H);
     st[k].T = 1.0f; st[k].C0 = st[k].C1 = st[k].C2 = 0.0f; st[k].W = 0.0f;
     st[k].cut = inside ? kCutLog2 : INFINITY;
-    st[k].nstop = 0;
+    st[k].nstop = 0; st[k].nblend = 0;
     rows_done[k] = 0;
     if (tx0 < J.W && ty0 < J.H) alive_mask |= 1u << k;
   }
@@ -367,6 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParam
         const bool stopped = st[k].cut == INFINITY;
         J.aux[(plane++) * HW + pix] = (float)(stopped ? st[k].nstop : rows_done[k]);
       }
+      if (P.aux_flags & GS_AUX_NBLEND) J.aux[(plane++) * HW + pix] = (float)st[k].nblend;
     }
   }
 }

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libgs.so")
 
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_UNSUPPORTED, GS_ERR_CAPACITY, GS_ERR_HIP = range(5)
 GS_PREC_FP32, GS_PREC_FP16_MFMA, GS_PREC_BF16_MFMA = range(3)
-GS_AUX_TFINAL, GS_AUX_WSUM, GS_AUX_NEVAL = 1, 2, 4
+GS_AUX_TFINAL, GS_AUX_WSUM, GS_AUX_NEVAL, GS_AUX_NBLEND = 1, 2, 4, 8
 PRECISIONS = {"fp32": GS_PREC_FP32, "fp16": GS_PREC_FP16_MFMA, "bf16": GS_PREC_BF16_MFMA}
 TILE = 16
 
@@ -249,7 +249,7 @@ def gs_radix_sort_u64(keys, vals, lo_bit: int, hi_bit: int, ws=None, stream=None
 
 
 def aux_planes(flags: int) -> int:
-    return bin(flags & 7).count("1")
+    return bin(flags & 15).count("1")
 
 
 class Renderer:

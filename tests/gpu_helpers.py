@@ -22,7 +22,8 @@ def render(dscene, cam, group=1, precision="fp32", splits=2, bg=(0.0, 0.0, 0.0),
     if aux:
         planes = r.aux.cpu().numpy()
         k = 0
-        for flag, name in ((gs.GS_AUX_TFINAL, "tfinal"), (gs.GS_AUX_WSUM, "wsum"), (gs.GS_AUX_NEVAL, "neval")):
+        for flag, name in ((gs.GS_AUX_TFINAL, "tfinal"), (gs.GS_AUX_WSUM, "wsum"), (gs.GS_AUX_NEVAL, "neval"),
+                           (gs.GS_AUX_NBLEND, "nblend")):
             if aux & flag:
                 out[name] = planes[k].astype(np.float64)
                 k += 1

@@ -52,6 +52,7 @@ def test_num_bins():
     ("precision", 7, gs.GS_ERR_INVALID_ARG),
     ("splits", 0, gs.GS_ERR_INVALID_ARG),
     ("aux_flags", 16, gs.GS_ERR_INVALID_ARG),
+    ("aux_flags", 32, gs.GS_ERR_INVALID_ARG),
     ("reserved", 1, gs.GS_ERR_INVALID_ARG),
 ])
 def test_rasterize_rejects_bad_options(field, value, status):

@@ -95,7 +95,7 @@ def test_radix_sort_bit_ranges(lo, hi):
     vd = torch.from_numpy(vals.view(np.int32).copy()).cuda()
     gs.gs_radix_sort_u64(kd, vd, lo, hi)
     torch.cuda.synchronize()
-    field = (keys >> np.uint64(lo)) & np.uint64((1 << (hi - lo)) - 1 if hi - lo < 64 else ~0)
+    field = (keys >> np.uint64(lo)) & np.uint64((1 << (hi - lo)) - 1 if hi - lo < 64 else 0xFFFFFFFFFFFFFFFF)
     order = np.argsort(field, kind="stable")
     assert np.array_equal(vd.cpu().numpy().view(np.uint32), vals[order])
 
