@@ -106,6 +106,9 @@ typedef struct {
   uint16_t *rect;           /* n x 4: (x0, y0, x1, y1) half-open tile ranges */
   uint32_t *count;          /* n: number of bins overlapped (tiles for G = 1, groups otherwise) */
   uint64_t *offset;         /* n + 1: exclusive prefix sum of count; offset[n] = entry count */
+  uint32_t *order;          /* n: the visible Gaussians (count > 0), first *n_visible entries valid;
+                               index order after gs_preprocess, (depth, index) order after gs_bin_sort */
+  uint32_t *n_visible;      /* 1: number of visible Gaussians */
 } gs_projected;
 
 /* Duplicated and sorted entries (capacity entries each) and per-bin ranges. */

@@ -80,7 +80,8 @@ gs_status check_scene(const gs_scene *s) {
 
 gs_status check_projected(const gs_projected *p, int64_t n, bool need_records) {
   if (!p) return fail(GS_ERR_INVALID_ARG, "projected is NULL");
-  if (!p->offset) return fail(GS_ERR_INVALID_ARG, "projected.offset is NULL");
+  if (!p->offset || !p->n_visible) return fail(GS_ERR_INVALID_ARG, "projected.offset or n_visible is NULL");
+  if (n > 0 && !p->order) return fail(GS_ERR_INVALID_ARG, "projected.order is NULL");
   if (n > 0 && (!p->count || !p->rect || (need_records && (!p->xy || !p->conic || !p->rgb))))
     return fail(GS_ERR_INVALID_ARG, "projected array is NULL");
   return GS_OK;
@@ -95,10 +96,15 @@ gs_status check_bins(const gs_bins *b, int group, bool need_keys) {
 }
 
 struct Workspace {
-  void *scan;
-  uint64_t *keys_alt;
-  uint32_t *vals_alt;
-  void *sort;
+  void *scan;            // scan partials (n)
+  uint32_t *dkey;        // depth keys of the visible Gaussians (n)
+  uint32_t *dkey_alt;    // depth sort double buffer (n)
+  uint32_t *dval_alt;    // (n)
+  uint64_t *dpos;        // first entry of each visible Gaussian in depth order (n + 1)
+  uint32_t *bkey;        // bin key of each entry (capacity)
+  uint32_t *bkey_alt;    // bin sort double buffer (capacity)
+  uint32_t *bval_alt;    // (capacity)
+  void *sort;            // digit counts and histograms
   size_t total;
 };
 
@@ -106,14 +112,22 @@ Workspace carve(void *ws, int64_t n, uint64_t capacity) {
   Workspace w;
   char *p = static_cast<char *>(ws);
   size_t off = 0;
-  w.scan = p ? p + off : nullptr;
-  off += align_up(gsi::scan_tmp_bytes(n));
-  w.keys_alt = p ? reinterpret_cast<uint64_t *>(p + off) : nullptr;
-  off += align_up((size_t)capacity * sizeof(uint64_t));
-  w.vals_alt = p ? reinterpret_cast<uint32_t *>(p + off) : nullptr;
-  off += align_up((size_t)capacity * sizeof(uint32_t));
-  w.sort = p ? p + off : nullptr;
-  off += align_up(gsi::sort_tmp_bytes(capacity));
+  auto take = [&](size_t bytes) -> char * {
+    char *q = p ? p + off : nullptr;
+    off += align_up(bytes);
+    return q;
+  };
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  w.scan = take(gsi::scan_tmp_bytes(n));
+  w.dkey = reinterpret_cast<uint32_t *>(take(nn * 4));
+  w.dkey_alt = reinterpret_cast<uint32_t *>(take(nn * 4));
+  w.dval_alt = reinterpret_cast<uint32_t *>(take(nn * 4));
+  w.dpos = reinterpret_cast<uint64_t *>(take((nn + 1) * 8));
+  w.bkey = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
+  w.bkey_alt = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
+  w.bval_alt = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
+  const size_t st_n = gsi::sort_tmp_bytes((uint64_t)nn), st_c = gsi::sort_tmp_bytes(capacity);
+  w.sort = take(st_n > st_c ? st_n : st_c);
   w.total = off;
   return w;
 }
@@ -145,36 +159,44 @@ gsi::RasterParams make_params(const gs_options &o) {
 }
 
 gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam, const gs_options *opt,
-                      const gs_bins *bins, uint64_t *n_keys, void *ws, size_t ws_bytes, hipStream_t st) {
+                      const gs_bins *bins, uint64_t *n_keys, void *ws, hipStream_t st) {
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
   const Workspace w = carve(ws, n, bins->capacity);
   uint64_t K = 0;
+  uint32_t V = 0;
   GS_HIP(hipMemcpyAsync(&K, proj->offset + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  GS_HIP(hipMemcpyAsync(&V, proj->n_visible, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   GS_HIP(hipStreamSynchronize(st));
   *n_keys = K;
   if (K > bins->capacity)
     return fail(GS_ERR_CAPACITY, "%llu entries exceed capacity %llu", (unsigned long long)K,
                 (unsigned long long)bins->capacity);
   if (K >= (1ull << 32)) return fail(GS_ERR_UNSUPPORTED, "%llu entries >= 2^32", (unsigned long long)K);
-  const int hi = 32 + gsi::bits_for((uint64_t)g.nbins);
-  const int passes = gsi::radix_passes(0, hi);
-  // binning writes where an odd number of passes ends in the caller's buffers
-  const bool first_alt = (passes & 1) && K > 1;
-  uint64_t *k0 = first_alt ? w.keys_alt : bins->keys;
-  uint32_t *v0 = first_alt ? w.vals_alt : bins->vals;
-  uint64_t *k1 = first_alt ? bins->keys : w.keys_alt;
-  uint32_t *v1 = first_alt ? bins->vals : w.vals_alt;
-  GS_HIP(gsi::launch_binning(*proj, n, g, bins->capacity, k0, v0, st));
+  if (V > (uint64_t)n) return fail(GS_ERR_HIP, "visible count %u exceeds n", V);
+  // low key digits (depth bits) on the visible Gaussians
+  GS_HIP(gsi::launch_depth_keys(proj->order, reinterpret_cast<const float4 *>(proj->rgb), V, w.dkey, st));
   bool in_alt = false;
-  GS_HIP(gsi::radix_sort(k0, v0, k1, v1, K, 0, hi, w.sort, st, &in_alt));
-  const bool in_caller = first_alt ? in_alt : !in_alt;
-  if (!in_caller && K > 0) {
-    GS_HIP(hipMemcpyAsync(bins->keys, in_alt ? k1 : k0, K * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
-    GS_HIP(hipMemcpyAsync(bins->vals, in_alt ? v1 : v0, K * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
-  }
-  GS_HIP(gsi::launch_ranges(bins->keys, bins->vals, K, proj->rect, g, bins->ranges,
-                            opt->group > 1 ? bins->masks : nullptr, st));
-  (void)ws_bytes;
+  GS_HIP(gsi::radix_sort32(w.dkey, proj->order, w.dkey_alt, w.dval_alt, V, 0, 32, w.sort, st, &in_alt));
+  if (in_alt && V > 0)
+    GS_HIP(hipMemcpyAsync(proj->order, w.dval_alt, (size_t)V * 4, hipMemcpyDeviceToDevice, st));
+  // first entry of each Gaussian in depth order, then one thread per entry
+  GS_HIP(gsi::launch_scan_gather(proj->count, proj->order, w.dpos, V, w.scan, st));
+  const int bin_bits = gsi::bits_for((uint64_t)g.nbins);
+  const int passes = gsi::radix_passes(0, bin_bits);
+  const bool first_alt = (passes & 1) && K > 1;   // an odd pass count ends in the other buffer
+  uint32_t *k0 = first_alt ? w.bkey_alt : w.bkey;
+  uint32_t *v0 = first_alt ? w.bval_alt : bins->vals;
+  uint32_t *k1 = first_alt ? w.bkey : w.bkey_alt;
+  uint32_t *v1 = first_alt ? bins->vals : w.bval_alt;
+  GS_HIP(gsi::launch_binning(proj->order, w.dpos, V, K, proj->rect, g, k0, v0, st));
+  // high key digits (bin) on the entries, stable
+  GS_HIP(gsi::radix_sort32(k0, v0, k1, v1, K, 0, bin_bits, w.sort, st, &in_alt));
+  const bool in_primary = first_alt ? in_alt : !in_alt;
+  const uint32_t *kf = in_alt ? k1 : k0;
+  if (!in_primary && K > 0)
+    GS_HIP(hipMemcpyAsync(bins->vals, in_alt ? v1 : v0, K * 4, hipMemcpyDeviceToDevice, st));
+  GS_HIP(gsi::launch_ranges(kf, bins->vals, K, proj->rect, proj->rgb, g, bins->ranges,
+                            opt->group > 1 ? bins->masks : nullptr, bins->keys, st));
   return GS_OK;
 }
 
@@ -218,7 +240,7 @@ gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_op
   hipStream_t st = static_cast<hipStream_t>(stream);
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
   GS_HIP(gsi::launch_preprocess(*scene, *cam, g, *out, st));
-  GS_HIP(gsi::launch_scan(out->count, out->offset, scene->n, ws, st));
+  GS_HIP(gsi::launch_scan_compact(out->count, out->offset, scene->n, out->order, out->n_visible, ws, st));
   return GS_OK;
 }
 
@@ -233,7 +255,7 @@ gs_status gs_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
   if (!n_keys) return fail(GS_ERR_INVALID_ARG, "n_keys is NULL");
   const size_t need = carve(nullptr, n, bins->capacity).total;
   if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID_ARG, "workspace %zu bytes, need %zu", ws_bytes, need);
-  return do_bin_sort(proj, n, cam, opt, bins, n_keys, ws, ws_bytes, static_cast<hipStream_t>(stream));
+  return do_bin_sort(proj, n, cam, opt, bins, n_keys, ws, static_cast<hipStream_t>(stream));
 }
 
 gs_status gs_rasterize(const gs_projected *proj, const gs_bins *bins, const gs_camera *cam, const gs_options *opt,
@@ -269,8 +291,8 @@ gs_status gs_render(const gs_scene *scene, const gs_camera *cam, const gs_option
   hipStream_t st = static_cast<hipStream_t>(stream);
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
   GS_HIP(gsi::launch_preprocess(*scene, *cam, g, *proj, st));
-  GS_HIP(gsi::launch_scan(proj->count, proj->offset, scene->n, ws, st));
-  if ((s = do_bin_sort(proj, scene->n, cam, opt, bins, n_keys, ws, ws_bytes, st))) return s;
+  GS_HIP(gsi::launch_scan_compact(proj->count, proj->offset, scene->n, proj->order, proj->n_visible, ws, st));
+  if ((s = do_bin_sort(proj, scene->n, cam, opt, bins, n_keys, ws, st))) return s;
   const gsi::RasterJob j = make_job(*proj, *bins, g, image, aux);
   const gsi::RasterParams p = make_params(*opt);
   if (opt->precision == GS_PREC_FP32)

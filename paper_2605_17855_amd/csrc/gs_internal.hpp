@@ -40,23 +40,36 @@ inline int bits_for(uint64_t v) {  // bits needed to represent values 0..v-1 (at
   return b;
 }
 
-// ---- preprocess + scan -----------------------------------------------------
+// ---- preprocess + scans ------------------------------------------------------
 hipError_t launch_preprocess(const gs_scene &s, const gs_camera &c, const Grid &g, const gs_projected &o,
                              hipStream_t st);
 size_t scan_tmp_bytes(int64_t n);
+// out[0..n] = exclusive prefix sum of in[0..n) (out[n] = total)
 hipError_t launch_scan(const uint32_t *in, uint64_t *out, int64_t n, void *tmp, hipStream_t st);
+// as launch_scan, and order[0..*nvis) = indices i with in[i] > 0, in index order
+hipError_t launch_scan_compact(const uint32_t *in, uint64_t *out, int64_t n, uint32_t *order, uint32_t *nvis,
+                               void *tmp, hipStream_t st);
+// out[0..n] = exclusive prefix sum of in[idx[i]]
+hipError_t launch_scan_gather(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n, void *tmp,
+                              hipStream_t st);
 
 // ---- binning, sort, ranges -------------------------------------------------
-hipError_t launch_binning(const gs_projected &p, int64_t n, const Grid &g, uint64_t capacity, uint64_t *keys,
-                          uint32_t *vals, hipStream_t st);
 size_t sort_tmp_bytes(uint64_t n);
-// Sorts (keys, vals) on bits [lo, hi); ping-pongs with (keys_alt, vals_alt).  Returns in
-// *in_alt whether the result ended in the alternate buffers.
+// Stable sort of (keys, vals) on key bits [lo, hi); ping-pongs with (keys_alt, vals_alt) and
+// reports in *in_alt whether the result ended in the alternate buffers.
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
                       int hi, void *tmp, hipStream_t st, bool *in_alt);
+hipError_t radix_sort32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
+                        int hi, void *tmp, hipStream_t st, bool *in_alt);
 int radix_passes(int lo, int hi);
-hipError_t launch_ranges(const uint64_t *keys, const uint32_t *vals, uint64_t n, const uint16_t *rect, const Grid &g,
-                         uint32_t *ranges, uint16_t *masks, hipStream_t st);
+hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, uint32_t nvis, uint32_t *keys,
+                             hipStream_t st);
+// entries of the visible Gaussians order[0..nvis) (depth order), Gaussian i's first entry at dpos[i]
+hipError_t launch_binning(const uint32_t *order, const uint64_t *dpos, uint32_t nvis, uint64_t K,
+                          const uint16_t *rect, const Grid &g, uint32_t *bin_keys, uint32_t *vals, hipStream_t st);
+hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *vals, uint64_t n, const uint16_t *rect,
+                         const float *rgb, const Grid &g, uint32_t *ranges, uint16_t *masks, uint64_t *keys,
+                         hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
 
 // ---- rasterizers -------------------------------------------------------------

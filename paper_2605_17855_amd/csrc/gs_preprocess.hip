@@ -162,73 +162,137 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
 }
 
 // ---- exclusive scan: u32 counts -> u64 offsets (n + 1 entries) ------------------
+// Optionally the values are gathered through an index list (v[i] = in[idx[i]]), and
+// optionally the indices with v[i] > 0 are compacted in index order (the visible list).
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;
 
-__device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t *sh, uint64_t *total) {
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *sh, T *total) {
   const int t = threadIdx.x;
   sh[t] = v;
   __syncthreads();
   for (int off = 1; off < kBlock; off <<= 1) {
-    uint64_t add = t >= off ? sh[t - off] : 0;
+    T add = t >= off ? sh[t - off] : (T)0;
     __syncthreads();
     sh[t] += add;
     __syncthreads();
   }
-  uint64_t incl = sh[t];
+  T incl = sh[t];
   *total = sh[kBlock - 1];
   __syncthreads();
   return incl - v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *in, int64_t n, uint64_t *bsum) {
+template <bool GATHER>
+__device__ __forceinline__ uint32_t scan_value(const uint32_t *in, const uint32_t *idx, int64_t i) {
+  return GATHER ? in[idx[i]] : in[i];
+}
+
+template <bool GATHER, bool COMPACT>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *in, const uint32_t *idx, int64_t n,
+                                                        uint64_t *bsum, uint32_t *bvis) {
   __shared__ uint64_t sh[kBlock];
+  __shared__ uint32_t shv[kBlock];
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   uint64_t s = 0;
+  uint32_t c = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    int64_t idx = base + (int64_t)i * kBlock + threadIdx.x;
-    if (idx < n) s += in[idx];
+    const int64_t k = base + (int64_t)i * kBlock + threadIdx.x;
+    if (k < n) {
+      const uint32_t v = scan_value<GATHER>(in, idx, k);
+      s += v;
+      c += v > 0;
+    }
   }
   uint64_t total;
-  block_exclusive_scan(s, sh, &total);
+  block_exclusive_scan<uint64_t>(s, sh, &total);
   if (threadIdx.x == 0) bsum[blockIdx.x] = total;
-}
-
-// single workgroup: exclusive scan of the block sums in place, grand total to *total_out
-__global__ __launch_bounds__(kBlock) void k_scan_top(uint64_t *bsum, int64_t nb, uint64_t *total_out) {
-  __shared__ uint64_t sh[kBlock];
-  uint64_t carry = 0;
-  for (int64_t base = 0; base < nb; base += kBlock) {
-    int64_t idx = base + threadIdx.x;
-    uint64_t v = idx < nb ? bsum[idx] : 0;
-    uint64_t tot;
-    uint64_t ex = block_exclusive_scan(v, sh, &tot);
-    if (idx < nb) bsum[idx] = carry + ex;
-    carry += tot;
+  if (COMPACT) {
+    uint32_t tv;
+    block_exclusive_scan<uint32_t>(c, shv, &tv);
+    if (threadIdx.x == 0) bvis[blockIdx.x] = tv;
   }
-  if (threadIdx.x == 0) *total_out = carry;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, int64_t n, const uint64_t *bsum,
-                                                      uint64_t *out) {
+// single workgroup: exclusive scan of the block partials in place; totals to *total / *nvis
+template <bool COMPACT>
+__global__ __launch_bounds__(kBlock) void k_scan_top(uint64_t *bsum, uint32_t *bvis, int64_t nb, uint64_t *total,
+                                                     uint32_t *nvis) {
   __shared__ uint64_t sh[kBlock];
+  __shared__ uint32_t shv[kBlock];
+  uint64_t carry = 0;
+  uint32_t carryv = 0;
+  for (int64_t base = 0; base < nb; base += kBlock) {
+    const int64_t i = base + threadIdx.x;
+    uint64_t tot;
+    const uint64_t ex = block_exclusive_scan<uint64_t>(i < nb ? bsum[i] : 0, sh, &tot);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += tot;
+    if (COMPACT) {
+      uint32_t totv;
+      const uint32_t exv = block_exclusive_scan<uint32_t>(i < nb ? bvis[i] : 0u, shv, &totv);
+      if (i < nb) bvis[i] = carryv + exv;
+      carryv += totv;
+    }
+  }
+  if (threadIdx.x == 0) {
+    *total = carry;
+    if (COMPACT) *nvis = carryv;
+  }
+}
+
+template <bool GATHER, bool COMPACT>
+__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, const uint32_t *idx, int64_t n,
+                                                      const uint64_t *bsum, const uint32_t *bvis, uint64_t *out,
+                                                      uint32_t *order) {
+  __shared__ uint64_t sh[kBlock];
+  __shared__ uint32_t shv[kBlock];
   // thread t owns the consecutive items [base + t*kScanItems, base + (t+1)*kScanItems)
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
   uint64_t s = 0;
+  uint32_t c = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    v[i] = (base + i < n) ? in[base + i] : 0u;
+    v[i] = (base + i < n) ? scan_value<GATHER>(in, idx, base + i) : 0u;
     s += v[i];
+    c += v[i] > 0;
   }
   uint64_t tot;
-  uint64_t run = bsum[blockIdx.x] + block_exclusive_scan(s, sh, &tot);
+  uint64_t run = bsum[blockIdx.x] + block_exclusive_scan<uint64_t>(s, sh, &tot);
+  uint32_t runv = 0;
+  if (COMPACT) {
+    uint32_t totv;
+    runv = bvis[blockIdx.x] + block_exclusive_scan<uint32_t>(c, shv, &totv);
+  }
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    if (base + i < n) out[base + i] = run;
+    if (base + i < n) {
+      out[base + i] = run;
+      if (COMPACT && v[i] > 0) order[runv++] = (uint32_t)(base + i);
+    }
     run += v[i];
   }
+}
+
+template <bool GATHER, bool COMPACT>
+hipError_t scan_impl(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n, uint32_t *order,
+                     uint32_t *nvis, void *tmp, hipStream_t st) {
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  uint64_t *bsum = static_cast<uint64_t *>(tmp);
+  uint32_t *bvis = reinterpret_cast<uint32_t *>(bsum + nb + 1);
+  if (nb > 0) {
+    hipLaunchKernelGGL((k_scan_reduce<GATHER, COMPACT>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx, n, bsum,
+                       bvis);
+  }
+  hipLaunchKernelGGL((k_scan_top<COMPACT>), dim3(1), dim3(kBlock), 0, st, bsum, bvis, nb, out + n, nvis);
+  if (nb > 0) {
+    hipLaunchKernelGGL((k_scan_down<GATHER, COMPACT>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx, n, bsum,
+                       bvis, out, order);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -268,22 +332,22 @@ hipError_t launch_preprocess(const gs_scene &s, const gs_camera &c, const Grid &
 }
 
 size_t scan_tmp_bytes(int64_t n) {
-  int64_t nb = (n + kScanTile - 1) / kScanTile;
-  return (size_t)(nb + 1) * sizeof(uint64_t);
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  return (size_t)(nb + 1) * (sizeof(uint64_t) + sizeof(uint32_t)) + 16;
 }
 
 hipError_t launch_scan(const uint32_t *in, uint64_t *out, int64_t n, void *tmp, hipStream_t st) {
-  int64_t nb = (n + kScanTile - 1) / kScanTile;
-  uint64_t *bsum = static_cast<uint64_t *>(tmp);
-  if (nb == 0) {
-    // n == 0: offset[0] = 0
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, st, bsum, (int64_t)0, out);
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, bsum);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, st, bsum, nb, out + n);
-  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kBlock), 0, st, in, n, bsum, out);
-  return hipGetLastError();
+  return scan_impl<false, false>(in, nullptr, out, n, nullptr, nullptr, tmp, st);
+}
+
+hipError_t launch_scan_compact(const uint32_t *in, uint64_t *out, int64_t n, uint32_t *order, uint32_t *nvis,
+                               void *tmp, hipStream_t st) {
+  return scan_impl<false, true>(in, nullptr, out, n, order, nvis, tmp, st);
+}
+
+hipError_t launch_scan_gather(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n, void *tmp,
+                              hipStream_t st) {
+  return scan_impl<true, false>(in, idx, out, n, nullptr, nullptr, tmp, st);
 }
 
 }  // namespace gsi

@@ -6,8 +6,13 @@
 // carries a tile-membership bit mask; entries are ordered by (group, depth).
 //
 // Key = (bin << 32) | bits(float depth): depths are positive, so their IEEE bits order as
-// unsigned integers.  Entries are emitted Gaussian-major and the LSD passes are stable, so
-// equal keys keep Gaussian-index order: the result equals a stable sort on (bin, depth, index).
+// unsigned integers.  An LSD radix sort takes the low (depth) digits first.  Those digits
+// are a property of the Gaussian, not of the entry, so their passes run on the visible
+// Gaussians before duplication (V elements instead of K entries): the visible list is
+// sorted stably by depth bits, entries are emitted in that order (one thread per entry,
+// load-balanced over Gaussians of any footprint), and the remaining passes sort the
+// entries stably on the bin digits.  The result is exactly the stable sort of the 64-bit
+// keys of Gaussian-major emission, i.e. the order (bin, depth bits, Gaussian index).
 #include "gs_internal.hpp"
 
 namespace gsi {
@@ -19,26 +24,6 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint64_t n, ui
   for (; i < n; i += stride) p[i] = v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_binning(int64_t n, const uint32_t *count, const uint64_t *offset,
-                                                    const ushort4 *rect, const float4 *rgb, int G, int GX,
-                                                    uint64_t capacity, uint64_t *keys, uint32_t *vals) {
-  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (g >= n) return;
-  const uint32_t c = count[g];
-  if (c == 0) return;
-  uint64_t o = offset[g];
-  if (o + c > capacity) return;  // the host reports GS_ERR_CAPACITY
-  const uint64_t dbits = __float_as_uint(rgb[g].w);
-  const ushort4 r = rect[g];
-  const int gx0 = r.x / G, gx1 = (r.z - 1) / G, gy0 = r.y / G, gy1 = (r.w - 1) / G;
-  for (int gy = gy0; gy <= gy1; ++gy)
-    for (int gx = gx0; gx <= gx1; ++gx) {
-      keys[o] = ((uint64_t)(gy * GX + gx) << 32) | dbits;
-      vals[o] = (uint32_t)g;
-      ++o;
-    }
-}
-
 // ---- radix sort --------------------------------------------------------------
 // Workgroup tile: 4 waves x 8 rounds x 64 lanes = 2048 keys.  Wave w owns the contiguous
 // sub-tile [w*512, (w+1)*512) and walks it in rounds of 64 consecutive keys, so
@@ -48,17 +33,35 @@ constexpr int kWaveTile = kRounds * 64;
 constexpr int kSortTile = 4 * kWaveTile;
 constexpr int kDigits = 256;
 
-__global__ __launch_bounds__(kBlock) void k_radix_count(const uint64_t *keys, uint64_t n, int shift, uint32_t dmask,
+// lanes of the wave holding the same digit as this lane (among lanes with valid keys)
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nbits) {
+  uint64_t peers = __ballot(valid);
+  for (int b = 0; b < nbits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+template <typename KT>
+__global__ __launch_bounds__(kBlock) void k_radix_count(const KT *keys, uint64_t n, int shift, int nbits,
                                                         uint32_t nblocks, uint32_t *counts, uint32_t *ghist) {
   __shared__ uint32_t h[kDigits];
   h[threadIdx.x] = 0;
   __syncthreads();
-  const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
-  static_assert(kSortTile % kBlock == 0, "tile is a whole number of workgroup strides");
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t dmask = (1u << nbits) - 1u;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const uint64_t base = (uint64_t)blockIdx.x * kSortTile + (uint64_t)w * kWaveTile;
 #pragma unroll
-  for (int r = 0; r < kSortTile / kBlock; ++r) {
-    uint64_t i = base + (uint64_t)r * kBlock + threadIdx.x;
-    if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & dmask], 1u);
+  for (int r = 0; r < kRounds; ++r) {
+    const uint64_t i = base + (uint64_t)r * 64 + lane;
+    const bool valid = i < n;
+    const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & dmask : 0u;
+    const uint64_t peers = match_digit(d, valid, nbits);
+    // one LDS atomic per distinct digit of the round (the group's first lane adds the group size)
+    if (valid && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
   }
   __syncthreads();
   const uint32_t v = h[threadIdx.x];
@@ -70,105 +73,199 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(const uint64_t *keys, ui
 __global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t *counts, uint32_t nblocks,
                                                              const uint32_t *ghist) {
   __shared__ uint32_t sh[kBlock];
-  __shared__ uint32_t sbase;
   const int d = blockIdx.x;
-  if (threadIdx.x == 0) {
-    uint32_t b = 0;
-    for (int k = 0; k < d; ++k) b += ghist[k];
-    sbase = b;
+  const int t = threadIdx.x;
+  // digit base: sum of the global histogram below d (parallel reduction)
+  sh[t] = t < d ? ghist[t] : 0u;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (t < off) sh[t] += sh[t + off];
+    __syncthreads();
   }
+  const uint32_t dbase = sh[0];
   __syncthreads();
   uint32_t *row = counts + (uint64_t)d * nblocks;
   const uint32_t per = (nblocks + kBlock - 1) / kBlock;
-  const uint32_t b0 = threadIdx.x * per;
+  const uint32_t b0 = t * per;
   uint32_t s = 0;
   for (uint32_t i = 0; i < per; ++i)
     if (b0 + i < nblocks) s += row[b0 + i];
-  sh[threadIdx.x] = s;
+  sh[t] = s;
   __syncthreads();
   for (int off = 1; off < kBlock; off <<= 1) {
-    uint32_t add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+    uint32_t add = t >= off ? sh[t - off] : 0;
     __syncthreads();
-    sh[threadIdx.x] += add;
+    sh[t] += add;
     __syncthreads();
   }
-  uint32_t run = sbase + sh[threadIdx.x] - s;
+  uint32_t run = dbase + sh[t] - s;
   for (uint32_t i = 0; i < per; ++i)
     if (b0 + i < nblocks) {
-      uint32_t c = row[b0 + i];
+      const uint32_t c = row[b0 + i];
       row[b0 + i] = run;
       run += c;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
-                                                          uint32_t *vout, uint64_t n, int shift, uint32_t dmask,
-                                                          uint32_t nblocks, const uint32_t *offsets) {
+// Stable scatter: ranks come from per-wave digit counters; keys are first placed in LDS in
+// block-local digit order, then written out so that consecutive lanes write consecutive
+// addresses of the same digit run.
+template <typename KT>
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const uint32_t *vin, KT *kout, uint32_t *vout,
+                                                          uint64_t n, int shift, int nbits, uint32_t nblocks,
+                                                          const uint32_t *offsets) {
   __shared__ uint32_t wcnt[4][kDigits];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ uint32_t bstart[kDigits];
+  __shared__ uint32_t gbase[kDigits];
+  __shared__ KT s_key[kSortTile];
+  __shared__ uint32_t s_val[kSortTile];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const uint32_t dmask = (1u << nbits) - 1u;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) wcnt[k][threadIdx.x] = 0;
+  for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
   __syncthreads();
   const uint64_t lt = (1ull << lane) - 1ull;
-  const uint64_t base = (uint64_t)blockIdx.x * kSortTile + (uint64_t)w * kWaveTile;
-  uint64_t key[kRounds];
+  const uint64_t tile0 = (uint64_t)blockIdx.x * kSortTile;
+  const uint64_t base = tile0 + (uint64_t)w * kWaveTile;
+  KT key[kRounds];
   uint32_t val[kRounds], pos[kRounds], dig[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint64_t i = base + (uint64_t)r * 64 + lane;
     const bool valid = i < n;
-    key[r] = valid ? kin[i] : 0ull;
+    key[r] = valid ? kin[i] : (KT)0;
     val[r] = valid ? vin[i] : 0u;
     const uint32_t d = (uint32_t)(key[r] >> shift) & dmask;
     dig[r] = d;
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
-    }
+    const uint64_t peers = match_digit(d, valid, nbits);
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
     const uint32_t old = wcnt[w][d];
     pos[r] = old + rank;
-    // all lanes of the wave have read wcnt before the group's first lane updates it
+    // every lane of the wave has read the counter before the group's first lane updates it
     __builtin_amdgcn_wave_barrier();
     if (valid && rank == 0) wcnt[w][d] = old + (uint32_t)__popcll(peers);
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  {
-    const int d = threadIdx.x;
-    const uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d];
-    const uint32_t g = offsets[(uint64_t)d * nblocks + blockIdx.x];
+  // per digit: block-local start (exclusive scan over digits) and per-wave starts
+  const uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
+  const uint32_t tot = c0 + c1 + c2 + c3;
+  bstart[t] = tot;
+  gbase[t] = offsets[(uint64_t)t * nblocks + blockIdx.x];
+  __syncthreads();
+  for (int off = 1; off < kDigits; off <<= 1) {
+    const uint32_t add = t >= off ? bstart[t - off] : 0u;
     __syncthreads();
-    wcnt[0][d] = g;
-    wcnt[1][d] = g + c0;
-    wcnt[2][d] = g + c0 + c1;
-    wcnt[3][d] = g + c0 + c1 + c2;
+    bstart[t] += add;
+    __syncthreads();
   }
+  const uint32_t bs = bstart[t] - tot;  // exclusive
+  __syncthreads();
+  bstart[t] = bs;
+  wcnt[0][t] = bs;
+  wcnt[1][t] = bs + c0;
+  wcnt[2][t] = bs + c0 + c1;
+  wcnt[3][t] = bs + c0 + c1 + c2;
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint64_t i = base + (uint64_t)r * 64 + lane;
     if (i < n) {
-      const uint32_t dst = wcnt[w][dig[r]] + pos[r];
-      kout[dst] = key[r];
-      vout[dst] = val[r];
+      const uint32_t lp = wcnt[w][dig[r]] + pos[r];
+      s_key[lp] = key[r];
+      s_val[lp] = val[r];
     }
+  }
+  __syncthreads();
+  const uint32_t nvalid = (uint32_t)((n - tile0) < (uint64_t)kSortTile ? (n - tile0) : (uint64_t)kSortTile);
+  for (uint32_t i = t; i < nvalid; i += kBlock) {
+    const KT k = s_key[i];
+    const uint32_t d = (uint32_t)(k >> shift) & dmask;
+    const uint32_t dst = gbase[d] + (i - bstart[d]);
+    kout[dst] = k;
+    vout[dst] = s_val[i];
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_ranges(const uint64_t *keys, const uint32_t *vals, uint64_t n,
-                                                   const ushort4 *rect, int G, int GX, uint32_t *ranges,
-                                                   uint16_t *masks) {
+// depth keys of the visible Gaussians: key[i] = bits(depth of order[i])
+__global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, const float4 *rgb, uint32_t nvis,
+                                                       uint32_t *keys) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < nvis) keys[i] = __float_as_uint(rgb[order[i]].w);
+}
+
+// ---- binning: one thread per entry -------------------------------------------
+// dpos[i] = first entry of the i-th visible Gaussian in depth order (exclusive scan of its
+// bin count; dpos[V] = K).  Every visible Gaussian owns at least one entry, so a block's
+// kBinItems consecutive entries span at most kBinItems consecutive Gaussians: one
+// wave-wide search finds the first, the block stages their offsets in LDS, and each
+// entry finds its Gaussian by binary search there.
+constexpr int kBinItems = 1024;
+
+__global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const uint64_t *dpos, uint32_t nvis,
+                                                    uint64_t K, const ushort4 *rect, int G, int GX,
+                                                    uint32_t *bin_keys, uint32_t *vals) {
+  __shared__ uint64_t s_pos[kBinItems + 1];
+  __shared__ uint32_t s_first;
+  const uint64_t e0 = (uint64_t)blockIdx.x * kBinItems;
+  const int t = threadIdx.x, lane = t & 63;
+  if (t < 64) {
+    // 64-ary search for the last Gaussian i with dpos[i] <= e0 over [lo, hi)
+    uint32_t lo = 0, hi = nvis;
+    while (hi - lo > 1) {
+      const uint32_t span = hi - lo;
+      const uint32_t step = (span + 63) / 64;
+      const uint32_t probe = lo + (uint32_t)lane * step;
+      const bool le = probe < hi && dpos[probe] <= e0;
+      const uint64_t m = __ballot(le);
+      // m has lanes 0..j set (dpos is non-decreasing); lane j's probe is the new lower bound
+      const int j = 63 - __clzll(m);
+      const uint32_t nlo = lo + (uint32_t)j * step;
+      const uint32_t nhi = (nlo + step < hi) ? nlo + step : hi;
+      lo = nlo;
+      hi = nhi;
+    }
+    if (lane == 0) s_first = lo;
+  }
+  __syncthreads();
+  const uint32_t first = s_first;
+  const uint32_t span = (nvis - first) < (uint32_t)kBinItems ? (nvis - first) : (uint32_t)kBinItems;
+  for (uint32_t i = t; i <= span; i += kBlock) s_pos[i] = dpos[first + i];
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kBinItems / kBlock; ++it) {
+    const uint64_t e = e0 + (uint64_t)it * kBlock + t;
+    if (e >= K) break;
+    // last local index l with s_pos[l] <= e (s_pos[0] <= e0 <= e)
+    uint32_t lo = 0, hi = span;  // invariant: s_pos[lo] <= e < s_pos[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (s_pos[mid] <= e) lo = mid; else hi = mid;
+    }
+    const uint32_t g = order[first + lo];
+    const uint32_t j = (uint32_t)(e - s_pos[lo]);
+    const ushort4 r = rect[g];
+    const int gx0 = r.x / G, gx1 = (r.z - 1) / G, gy0 = r.y / G;
+    const int wdt = gx1 - gx0 + 1;
+    const int gy = gy0 + (int)(j / (uint32_t)wdt), gx = gx0 + (int)(j % (uint32_t)wdt);
+    bin_keys[e] = (uint32_t)(gy * GX + gx);
+    vals[e] = g;
+  }
+}
+
+// Bin ranges, tile-membership masks and the 64-bit keys (bin << 32 | depth bits).
+__global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, const uint32_t *vals, uint64_t n,
+                                                   const ushort4 *rect, const float4 *rgb, int G, int GX,
+                                                   uint32_t *ranges, uint16_t *masks, uint64_t *keys) {
   const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const uint32_t bin = (uint32_t)(keys[i] >> 32);
-  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != bin) ranges[2 * (uint64_t)bin] = (uint32_t)i;
-  if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != bin) ranges[2 * (uint64_t)bin + 1] = (uint32_t)(i + 1);
+  const uint32_t bin = bin_keys[i];
+  const uint32_t g = vals[i];
+  if (i == 0 || bin_keys[i - 1] != bin) ranges[2 * (uint64_t)bin] = (uint32_t)i;
+  if (i == n - 1 || bin_keys[i + 1] != bin) ranges[2 * (uint64_t)bin + 1] = (uint32_t)(i + 1);
+  keys[i] = ((uint64_t)bin << 32) | __float_as_uint(rgb[g].w);
   if (G > 1 && masks) {
-    const ushort4 r = rect[vals[i]];
+    const ushort4 r = rect[g];
     const int gx = (int)(bin % (uint32_t)GX), gy = (int)(bin / (uint32_t)GX);
     uint32_t m = 0;
     for (int ly = 0; ly < G; ++ly)
@@ -180,9 +277,38 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint64_t *keys, const u
   }
 }
 
-inline unsigned grid_for(uint64_t n) {
-  uint64_t b = (n + kBlock - 1) / kBlock;
+inline unsigned grid_for(uint64_t n, uint64_t per = kBlock) {
+  const uint64_t b = (n + per - 1) / per;
   return (unsigned)(b ? b : 1);
+}
+
+template <typename KT>
+hipError_t radix_sort_t(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n, int lo, int hi,
+                        void *tmp, hipStream_t st, bool *in_alt) {
+  *in_alt = false;
+  if (n <= 1 || hi <= lo) return hipSuccess;
+  const uint32_t nblocks = (uint32_t)((n + kSortTile - 1) / kSortTile);
+  uint32_t *counts = static_cast<uint32_t *>(tmp);
+  uint32_t *ghist = counts + (uint64_t)kDigits * nblocks;
+  const int passes = radix_passes(lo, hi);
+  hipError_t e = launch_fill_u32(ghist, (uint64_t)passes * kDigits, 0u, st);
+  if (e != hipSuccess) return e;
+  KT *kin = keys, *kout = keys_alt;
+  uint32_t *vin = vals, *vout = vals_alt;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = lo + 8 * p;
+    const int bits = (hi - shift) < 8 ? (hi - shift) : 8;
+    uint32_t *gh = ghist + p * kDigits;
+    hipLaunchKernelGGL((k_radix_count<KT>), dim3(nblocks), dim3(kBlock), 0, st, kin, n, shift, bits, nblocks, counts,
+                       gh);
+    hipLaunchKernelGGL(k_radix_digit_scan, dim3(kDigits), dim3(kBlock), 0, st, counts, nblocks, gh);
+    hipLaunchKernelGGL((k_radix_scatter<KT>), dim3(nblocks), dim3(kBlock), 0, st, kin, vin, kout, vout, n, shift,
+                       bits, nblocks, counts);
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+    *in_alt = !*in_alt;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -192,15 +318,6 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) 
   uint64_t b = (n + kBlock - 1) / kBlock;
   if (b > 4096) b = 4096;
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)b), dim3(kBlock), 0, st, p, n, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_binning(const gs_projected &p, int64_t n, const Grid &g, uint64_t capacity, uint64_t *keys,
-                          uint32_t *vals, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_binning, dim3(grid_for((uint64_t)n)), dim3(kBlock), 0, st, n, p.count, p.offset,
-                     reinterpret_cast<const ushort4 *>(p.rect), reinterpret_cast<const float4 *>(p.rgb), g.G,
-                     g.GX, capacity, keys, vals);
   return hipGetLastError();
 }
 
@@ -214,38 +331,37 @@ size_t sort_tmp_bytes(uint64_t n) {
 
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
                       int hi, void *tmp, hipStream_t st, bool *in_alt) {
-  *in_alt = false;
-  if (n <= 1 || hi <= lo) return hipSuccess;
-  const uint32_t nblocks = (uint32_t)((n + kSortTile - 1) / kSortTile);
-  uint32_t *counts = static_cast<uint32_t *>(tmp);
-  uint32_t *ghist = counts + (uint64_t)kDigits * nblocks;
-  const int passes = radix_passes(lo, hi);
-  hipError_t e = launch_fill_u32(ghist, (uint64_t)passes * kDigits, 0u, st);
-  if (e != hipSuccess) return e;
-  uint64_t *kin = keys, *kout = keys_alt;
-  uint32_t *vin = vals, *vout = vals_alt;
-  for (int p = 0; p < passes; ++p) {
-    const int shift = lo + 8 * p;
-    const int bits = (hi - shift) < 8 ? (hi - shift) : 8;
-    const uint32_t dmask = (1u << bits) - 1u;
-    uint32_t *gh = ghist + p * kDigits;
-    hipLaunchKernelGGL(k_radix_count, dim3(nblocks), dim3(kBlock), 0, st, kin, n, shift, dmask, nblocks, counts, gh);
-    hipLaunchKernelGGL(k_radix_digit_scan, dim3(kDigits), dim3(kBlock), 0, st, counts, nblocks, gh);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kBlock), 0, st, kin, vin, kout, vout, n, shift, dmask,
-                       nblocks, counts);
-    std::swap(kin, kout);
-    std::swap(vin, vout);
-    *in_alt = !*in_alt;
-  }
+  return radix_sort_t<uint64_t>(keys, vals, keys_alt, vals_alt, n, lo, hi, tmp, st, in_alt);
+}
+
+hipError_t radix_sort32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
+                        int hi, void *tmp, hipStream_t st, bool *in_alt) {
+  return radix_sort_t<uint32_t>(keys, vals, keys_alt, vals_alt, n, lo, hi, tmp, st, in_alt);
+}
+
+hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, uint32_t nvis, uint32_t *keys,
+                             hipStream_t st) {
+  if (nvis == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_depth_keys, dim3(grid_for(nvis)), dim3(kBlock), 0, st, order, rgb, nvis, keys);
   return hipGetLastError();
 }
 
-hipError_t launch_ranges(const uint64_t *keys, const uint32_t *vals, uint64_t n, const uint16_t *rect, const Grid &g,
-                         uint32_t *ranges, uint16_t *masks, hipStream_t st) {
+hipError_t launch_binning(const uint32_t *order, const uint64_t *dpos, uint32_t nvis, uint64_t K,
+                          const uint16_t *rect, const Grid &g, uint32_t *bin_keys, uint32_t *vals, hipStream_t st) {
+  if (K == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_binning, dim3(grid_for(K, kBinItems)), dim3(kBlock), 0, st, order, dpos, nvis, K,
+                     reinterpret_cast<const ushort4 *>(rect), g.G, g.GX, bin_keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *vals, uint64_t n, const uint16_t *rect,
+                         const float *rgb, const Grid &g, uint32_t *ranges, uint16_t *masks, uint64_t *keys,
+                         hipStream_t st) {
   hipError_t e = launch_fill_u32(ranges, (uint64_t)g.nbins * 2, 0u, st);
   if (e != hipSuccess || n == 0) return e;
-  hipLaunchKernelGGL(k_ranges, dim3(grid_for(n)), dim3(kBlock), 0, st, keys, vals, n,
-                     reinterpret_cast<const ushort4 *>(rect), g.G, g.GX, ranges, masks);
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for(n)), dim3(kBlock), 0, st, bin_keys, vals, n,
+                     reinterpret_cast<const ushort4 *>(rect), reinterpret_cast<const float4 *>(rgb), g.G, g.GX,
+                     ranges, masks, keys);
   return hipGetLastError();
 }
 

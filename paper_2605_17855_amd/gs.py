@@ -48,7 +48,7 @@ class gs_scene(C.Structure):
 
 class gs_projected(C.Structure):
     _fields_ = [("xy", C.c_void_p), ("conic", C.c_void_p), ("rgb", C.c_void_p), ("rect", C.c_void_p),
-                ("count", C.c_void_p), ("offset", C.c_void_p)]
+                ("count", C.c_void_p), ("offset", C.c_void_p), ("order", C.c_void_p), ("n_visible", C.c_void_p)]
 
 
 class gs_bins(C.Structure):
@@ -183,9 +183,12 @@ class Projected:
         self.rect = torch.empty((m, 4), dtype=torch.int16, device=device)
         self.count = torch.empty((m,), dtype=torch.int32, device=device)
         self.offset = torch.empty((n + 1,), dtype=torch.int64, device=device)
+        self.order = torch.empty((m,), dtype=torch.int32, device=device)
+        self.n_visible = torch.empty((1,), dtype=torch.int32, device=device)
         p = gs_projected()
         p.xy, p.conic, p.rgb = _ptr(self.xy), _ptr(self.conic), _ptr(self.rgb)
         p.rect, p.count, p.offset = _ptr(self.rect), _ptr(self.count), _ptr(self.offset)
+        p.order, p.n_visible = _ptr(self.order), _ptr(self.n_visible)
         self.struct = p
 
 

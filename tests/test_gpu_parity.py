@@ -133,6 +133,13 @@ def _check_bins(rec, cam, r, n_keys, group):
     for i in mismatch:
         za, zb = rec["depth"][og[i]], rec["depth"][gg[i]]
         assert abs(za - zb) <= 1e-6 * za, (i, og[i], gg[i])
+    # the visible list after sorting: every visible Gaussian once, ordered by (depth bits, index)
+    V = int(r.proj.n_visible.cpu().numpy()[0])
+    order = r.proj.order.cpu().numpy().view(np.uint32)[:V].astype(np.int64)
+    count = r.proj.count.cpu().numpy().view(np.uint32)
+    assert np.array_equal(np.sort(order), np.nonzero(count[: r.proj.n])[0])
+    dbits = gdepth.view(np.uint32)[order]
+    assert np.all((dbits[1:] > dbits[:-1]) | ((dbits[1:] == dbits[:-1]) & (order[1:] > order[:-1])))
     if group > 1:
         gm = b["masks"][keep_g].astype(np.uint32)
         om = masks[keep_o]
