@@ -49,7 +49,21 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 plain comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle compositing time")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (5 times), for HBM counter calibration")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    """A plain copy of known size: FETCH_SIZE / WRITE_SIZE of its dispatches give the counters' scale."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": n * 4, "dispatches": 5}), flush=True)
 
 
 def timed_frames(gs, torch, ds, cams, rend, opt, steps, warmup):
@@ -86,19 +100,21 @@ def timed_frames(gs, torch, ds, cams, rend, opt, steps, warmup):
 def work_units(gs, torch, ds, cams, rend, opt_kwargs, steps):
     """Gaussian-pixel evaluations and blended pairs of the timed frames (aux pass, untimed)."""
     opt = gs.options(aux_flags=gs.GS_AUX_NEVAL | gs.GS_AUX_NBLEND, **opt_kwargs)
-    e_pix = 0
-    blend = 0
+    e_pix = blend = entries = visible = 0
     seen = {}
     for i in range(steps):
         k = i % len(cams)
         if k not in seen:
-            rend.render(ds, cams[k], opt)
+            n_keys = rend.render(ds, cams[k], opt)
             torch.cuda.synchronize()
             a = rend.aux.double()
-            seen[k] = (int(a[0].sum().item()), int(a[1].sum().item()))
+            seen[k] = (int(a[0].sum().item()), int(a[1].sum().item()), n_keys,
+                       int(rend.proj.n_visible.cpu().item()))
         e_pix += seen[k][0]
         blend += seen[k][1]
-    return e_pix, blend
+        entries += seen[k][2]
+        visible += seen[k][3]
+    return e_pix, blend, entries / steps, visible / steps
 
 
 def cpu_baseline_and_psnr(gs, torch, sc, cam, image_gpu, target_s):
@@ -146,6 +162,9 @@ def main():
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy_mib:
+        calibrate_copy(args.calibrate_copy_mib)
+        return
     import torch
     from paper_2605_17855_amd import gs, scenes
 
@@ -166,7 +185,7 @@ def main():
     first_img = rend.image.double().cpu().numpy()
 
     log("counting evaluations of the timed frames (aux pass)")
-    e_pix, blend = work_units(gs, torch, ds, cams, rend, okw, args.steps)
+    e_pix, blend, entries_pf, visible_pf = work_units(gs, torch, ds, cams, rend, okw, args.steps)
     raster_total_s = sum(raster_ms) / 1e3
     flops = FLOPS_PER_EVAL * e_pix + FLOPS_PER_BLEND * blend
     achieved = flops / raster_total_s / 1e12
@@ -175,7 +194,8 @@ def main():
                 "kernel": f"k_raster_mfma (precision {args.precision}, splits {args.splits}, group {args.group})"
                           if args.precision != "fp32" else "k_raster_fp32",
                 "avg_launch_ms": float(np.mean(raster_ms)),
-                "evals_per_frame": e_pix / args.steps, "blends_per_frame": blend / args.steps}
+                "evals_per_frame": e_pix / args.steps, "blends_per_frame": blend / args.steps,
+                "entries_per_frame": entries_pf, "visible_per_frame": visible_pf}
 
     compare = None
     if not args.no_compare and args.precision != "fp32":

@@ -96,7 +96,8 @@ gs_status check_bins(const gs_bins *b, int group, bool need_keys) {
 }
 
 struct Workspace {
-  void *scan;            // scan partials (n)
+  void *scan;            // scan partials (count scan, then the depth-order offset scan)
+  void *sort;            // radix sort scratch (per-tile digit counts and totals)
   uint32_t *dkey;        // depth keys of the visible Gaussians (n)
   uint32_t *dkey_alt;    // depth sort double buffer (n)
   uint32_t *dval_alt;    // (n)
@@ -104,7 +105,6 @@ struct Workspace {
   uint32_t *bkey;        // bin key of each entry (capacity)
   uint32_t *bkey_alt;    // bin sort double buffer (capacity)
   uint32_t *bval_alt;    // (capacity)
-  void *sort;            // digit counts and histograms
   size_t total;
 };
 
@@ -117,8 +117,9 @@ Workspace carve(void *ws, int64_t n, uint64_t capacity) {
     off += align_up(bytes);
     return q;
   };
-  const size_t nn = (size_t)(n > 0 ? n : 1);
+  const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
   w.scan = take(gsi::scan_tmp_bytes(n));
+  w.sort = take(gsi::radix_tmp_bytes(nn > capacity ? nn : capacity));
   w.dkey = reinterpret_cast<uint32_t *>(take(nn * 4));
   w.dkey_alt = reinterpret_cast<uint32_t *>(take(nn * 4));
   w.dval_alt = reinterpret_cast<uint32_t *>(take(nn * 4));
@@ -126,8 +127,6 @@ Workspace carve(void *ws, int64_t n, uint64_t capacity) {
   w.bkey = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
   w.bkey_alt = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
   w.bval_alt = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
-  const size_t st_n = gsi::sort_tmp_bytes((uint64_t)nn), st_c = gsi::sort_tmp_bytes(capacity);
-  w.sort = take(st_n > st_c ? st_n : st_c);
   w.total = off;
   return w;
 }
@@ -163,38 +162,25 @@ gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
   const Workspace w = carve(ws, n, bins->capacity);
   uint64_t K = 0;
-  uint32_t V = 0;
   GS_HIP(hipMemcpyAsync(&K, proj->offset + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-  GS_HIP(hipMemcpyAsync(&V, proj->n_visible, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   GS_HIP(hipStreamSynchronize(st));
   *n_keys = K;
   if (K > bins->capacity)
     return fail(GS_ERR_CAPACITY, "%llu entries exceed capacity %llu", (unsigned long long)K,
                 (unsigned long long)bins->capacity);
   if (K >= (1ull << 32)) return fail(GS_ERR_UNSUPPORTED, "%llu entries >= 2^32", (unsigned long long)K);
-  if (V > (uint64_t)n) return fail(GS_ERR_HIP, "visible count %u exceeds n", V);
-  // low key digits (depth bits) on the visible Gaussians
-  GS_HIP(gsi::launch_depth_keys(proj->order, reinterpret_cast<const float4 *>(proj->rgb), V, w.dkey, st));
+  const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
+  // low key digits (depth bits) on the visible Gaussians; also zeroes the bin ranges
   bool in_alt = false;
-  GS_HIP(gsi::radix_sort32(w.dkey, proj->order, w.dkey_alt, w.dval_alt, V, 0, 32, w.sort, st, &in_alt));
-  if (in_alt && V > 0)
-    GS_HIP(hipMemcpyAsync(proj->order, w.dval_alt, (size_t)V * 4, hipMemcpyDeviceToDevice, st));
-  // first entry of each Gaussian in depth order, then one thread per entry
-  GS_HIP(gsi::launch_scan_gather(proj->count, proj->order, w.dpos, V, w.scan, st));
-  const int bin_bits = gsi::bits_for((uint64_t)g.nbins);
-  const int passes = gsi::radix_passes(0, bin_bits);
-  const bool first_alt = (passes & 1) && K > 1;   // an odd pass count ends in the other buffer
-  uint32_t *k0 = first_alt ? w.bkey_alt : w.bkey;
-  uint32_t *v0 = first_alt ? w.bval_alt : bins->vals;
-  uint32_t *k1 = first_alt ? w.bkey : w.bkey_alt;
-  uint32_t *v1 = first_alt ? bins->vals : w.bval_alt;
-  GS_HIP(gsi::launch_binning(proj->order, w.dpos, V, K, proj->rect, g, k0, v0, st));
-  // high key digits (bin) on the entries, stable
-  GS_HIP(gsi::radix_sort32(k0, v0, k1, v1, K, 0, bin_bits, w.sort, st, &in_alt));
-  const bool in_primary = first_alt ? in_alt : !in_alt;
-  const uint32_t *kf = in_alt ? k1 : k0;
-  if (!in_primary && K > 0)
-    GS_HIP(hipMemcpyAsync(bins->vals, in_alt ? v1 : v0, K * 4, hipMemcpyDeviceToDevice, st));
+  GS_HIP(gsi::sort_depth(proj->order, reinterpret_cast<const float4 *>(proj->rgb), proj->n_visible, nn, w.dkey,
+                         w.dkey_alt, w.dval_alt, w.sort, bins->ranges, 2 * (uint64_t)g.nbins, st, &in_alt));
+  if (in_alt) GS_HIP(hipMemcpyAsync(proj->order, w.dval_alt, nn * 4, hipMemcpyDeviceToDevice, st));
+  // first entry of each Gaussian in depth order, then one thread per entry and the bin digits
+  GS_HIP(gsi::launch_scan_gather(proj->count, proj->order, w.dpos, (int64_t)nn, proj->n_visible, w.scan, st));
+  GS_HIP(gsi::bin_and_sort(proj->order, w.dpos, proj->n_visible, K, proj->rect, g, w.bkey, bins->vals, w.bkey_alt,
+                           w.bval_alt, w.sort, st, &in_alt));
+  const uint32_t *kf = in_alt ? w.bkey_alt : w.bkey;
+  if (in_alt && K > 0) GS_HIP(hipMemcpyAsync(bins->vals, w.bval_alt, K * 4, hipMemcpyDeviceToDevice, st));
   GS_HIP(gsi::launch_ranges(kf, bins->vals, K, proj->rect, proj->rgb, g, bins->ranges,
                             opt->group > 1 ? bins->masks : nullptr, bins->keys, st));
   return GS_OK;
@@ -235,7 +221,7 @@ gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_op
   if ((s = check_scene(scene)) || (s = check_camera(cam)) || (s = check_options(opt)) ||
       (s = check_projected(out, scene->n, true)))
     return s;
-  const size_t need = align_up(gsi::scan_tmp_bytes(scene->n));
+  const size_t need = gsi::scan_tmp_bytes(scene->n);
   if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID_ARG, "workspace %zu bytes, need %zu", ws_bytes, need);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
@@ -304,7 +290,7 @@ gs_status gs_render(const gs_scene *scene, const gs_camera *cam, const gs_option
 
 size_t gs_sort_workspace_bytes(uint64_t n) {
   return align_up((size_t)n * sizeof(uint64_t)) + align_up((size_t)n * sizeof(uint32_t)) +
-         align_up(gsi::sort_tmp_bytes(n));
+         align_up(gsi::radix_tmp_bytes(n));
 }
 
 gs_status gs_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t n, int32_t lo_bit, int32_t hi_bit, void *ws,

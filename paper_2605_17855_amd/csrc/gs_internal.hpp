@@ -16,6 +16,45 @@ constexpr float kLog2e = 1.4426950408889634f;
 // log2(1/255): the 1/255 alpha cut taken on log2(alpha)
 constexpr float kCutLog2 = -7.994353436858858f;
 
+// ---- decoupled look-back (single-pass chained scans) -------------------------
+// A chain of tiles, each with one status word per scanned value: bits 63/62 flag "inclusive
+// prefix" / "aggregate only", bits 61..0 the value.  Tile ids come from an atomic counter in
+// the order workgroups start, so every predecessor a tile waits on is already resident and
+// finishes; the wait still has a spin limit, so an inconsistent chain yields a wrong result
+// (caught by the parity tests) rather than a hang.
+constexpr uint64_t kFlagP = 1ull << 63;
+constexpr uint64_t kFlagA = 1ull << 62;
+constexpr uint64_t kValMask = kFlagA - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ void status_store(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t status_load(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Exclusive prefix of `tile` in the chain status[tile * stride].
+__device__ __forceinline__ uint64_t lookback(const uint64_t *status, int64_t tile, int64_t stride) {
+  uint64_t excl = 0;
+  int64_t p = tile - 1;
+  uint32_t spins = 0;
+  while (p >= 0) {
+    const uint64_t w = status_load(&status[p * stride]);
+    if (w & kFlagP) {
+      excl += w & kValMask;
+      break;
+    }
+    if (w & kFlagA) {
+      excl += w & kValMask;
+      --p;
+      continue;
+    }
+    if (++spins > kSpinLimit) break;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return excl;
+}
+
 struct Grid {
   int W, H, TX, TY, G, GX, GY;
   int64_t nbins;
@@ -43,30 +82,35 @@ inline int bits_for(uint64_t v) {  // bits needed to represent values 0..v-1 (at
 // ---- preprocess + scans ------------------------------------------------------
 hipError_t launch_preprocess(const gs_scene &s, const gs_camera &c, const Grid &g, const gs_projected &o,
                              hipStream_t st);
+// Scans (reduce-then-scan); tmp holds scan_tmp_bytes(n) bytes.
 size_t scan_tmp_bytes(int64_t n);
-// out[0..n] = exclusive prefix sum of in[0..n) (out[n] = total)
-hipError_t launch_scan(const uint32_t *in, uint64_t *out, int64_t n, void *tmp, hipStream_t st);
-// as launch_scan, and order[0..*nvis) = indices i with in[i] > 0, in index order
+// out[0..n] = exclusive prefix sum of in[0..n) (out[n] = total); order[0..*nvis) = indices i
+// with in[i] > 0, in index order
 hipError_t launch_scan_compact(const uint32_t *in, uint64_t *out, int64_t n, uint32_t *order, uint32_t *nvis,
                                void *tmp, hipStream_t st);
-// out[0..n] = exclusive prefix sum of in[idx[i]]
-hipError_t launch_scan_gather(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n, void *tmp,
-                              hipStream_t st);
+// out[0..m] = exclusive prefix sum of in[idx[i]] for i < m = *n_dev (m <= n_max)
+hipError_t launch_scan_gather(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n_max,
+                              const uint32_t *n_dev, void *tmp, hipStream_t st);
 
 // ---- binning, sort, ranges -------------------------------------------------
-size_t sort_tmp_bytes(uint64_t n);
+int radix_passes(int lo, int hi);
+// scratch of a radix sort over at most n keys (per-tile digit counts and digit totals)
+size_t radix_tmp_bytes(uint64_t n);
 // Stable sort of (keys, vals) on key bits [lo, hi); ping-pongs with (keys_alt, vals_alt) and
 // reports in *in_alt whether the result ended in the alternate buffers.
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
                       int hi, void *tmp, hipStream_t st, bool *in_alt);
-hipError_t radix_sort32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
-                        int hi, void *tmp, hipStream_t st, bool *in_alt);
-int radix_passes(int lo, int hi);
-hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, uint32_t nvis, uint32_t *keys,
-                             hipStream_t st);
-// entries of the visible Gaussians order[0..nvis) (depth order), Gaussian i's first entry at dpos[i]
-hipError_t launch_binning(const uint32_t *order, const uint64_t *dpos, uint32_t nvis, uint64_t K,
-                          const uint16_t *rect, const Grid &g, uint32_t *bin_keys, uint32_t *vals, hipStream_t st);
+// Sorts the visible list order[0..*nvis) by depth bits (4 passes, stable), using keys/keys_alt/
+// vals_alt (n_max each) as scratch; also zeroes ranges[0..nranges).
+hipError_t sort_depth(uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max, uint32_t *keys,
+                      uint32_t *keys_alt, uint32_t *vals_alt, void *tmp, uint32_t *ranges, uint64_t nranges,
+                      hipStream_t st, bool *in_alt);
+// Entries of the depth-ordered visible Gaussians (Gaussian i's first entry at dpos[i]) into
+// (bkey, bval), then a stable sort on the bin bits.
+hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, const uint32_t *nvis, uint64_t K,
+                        const uint16_t *rect, const Grid &g, uint32_t *bkey, uint32_t *bval, uint32_t *bkey_alt,
+                        uint32_t *bval_alt, void *tmp, hipStream_t st, bool *in_alt);
+// Bin ranges (zeroed before), masks (group > 1) and the 64-bit keys of the sorted entries.
 hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *vals, uint64_t n, const uint16_t *rect,
                          const float *rgb, const Grid &g, uint32_t *ranges, uint16_t *masks, uint64_t *keys,
                          hipStream_t st);

@@ -162,70 +162,97 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
 }
 
 // ---- exclusive scan: u32 counts -> u64 offsets (n + 1 entries) ------------------
-// Optionally the values are gathered through an index list (v[i] = in[idx[i]]), and
-// optionally the indices with v[i] > 0 are compacted in index order (the visible list).
+// Reduce-then-scan in three launches with no inter-workgroup waits: per-tile sums, one
+// workgroup scanning the tile sums, and a down-sweep that rescans each tile from its
+// offset.  Block scans use wave shuffles (one LDS exchange of the four wave totals).
+// Optionally the values are gathered through an index list (v[i] = in[idx[i]]), the indices
+// with v[i] > 0 are compacted in index order (the visible list), and n is read from device
+// memory (the grid covers an upper bound).
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;
 
 template <typename T>
-__device__ __forceinline__ T block_exclusive_scan(T v, T *sh, T *total) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    T add = t >= off ? sh[t - off] : (T)0;
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
   }
-  T incl = sh[t];
-  *total = sh[kBlock - 1];
+  return v;
+}
+
+// exclusive scan over the workgroup; *total = sum over the workgroup
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *sh4, T *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const T incl = wave_inclusive_scan<T>(v);
+  if (lane == 63) sh4[w] = incl;
   __syncthreads();
-  return incl - v;
+  T before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    const T x = sh4[k];
+    before += k < w ? x : (T)0;
+    all += x;
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - v;
 }
 
 template <bool GATHER>
-__device__ __forceinline__ uint32_t scan_value(const uint32_t *in, const uint32_t *idx, int64_t i) {
-  return GATHER ? in[idx[i]] : in[i];
+__device__ __forceinline__ void load_items(const uint32_t *in, const uint32_t *idx, int64_t base, int64_t n,
+                                           uint32_t *v) {
+  if (!GATHER && base + kScanItems <= n && ((base & 3) == 0)) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(in + base);
+#pragma unroll
+    for (int q = 0; q < kScanItems / 4; ++q) {
+      const uint4 x = p[q];
+      v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) v[i] = (base + i < n) ? (GATHER ? in[idx[base + i]] : in[base + i]) : 0u;
 }
 
 template <bool GATHER, bool COMPACT>
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *in, const uint32_t *idx, int64_t n,
-                                                        uint64_t *bsum, uint32_t *bvis) {
-  __shared__ uint64_t sh[kBlock];
-  __shared__ uint32_t shv[kBlock];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *in, const uint32_t *idx, int64_t n_host,
+                                                        const uint32_t *n_dev, uint64_t *bsum, uint32_t *bvis) {
+  __shared__ uint64_t sh[4];
+  __shared__ uint32_t shv[4];
+  const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  load_items<GATHER>(in, idx, base, n, v);
   uint64_t s = 0;
   uint32_t c = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    const int64_t k = base + (int64_t)i * kBlock + threadIdx.x;
-    if (k < n) {
-      const uint32_t v = scan_value<GATHER>(in, idx, k);
-      s += v;
-      c += v > 0;
-    }
+    s += v[i];
+    c += v[i] > 0;
   }
-  uint64_t total;
-  block_exclusive_scan<uint64_t>(s, sh, &total);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+  uint64_t tot;
+  block_exclusive_scan<uint64_t>(s, sh, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
   if (COMPACT) {
-    uint32_t tv;
-    block_exclusive_scan<uint32_t>(c, shv, &tv);
-    if (threadIdx.x == 0) bvis[blockIdx.x] = tv;
+    uint32_t totv;
+    block_exclusive_scan<uint32_t>(c, shv, &totv);
+    if (threadIdx.x == 0) bvis[blockIdx.x] = totv;
   }
 }
 
-// single workgroup: exclusive scan of the block partials in place; totals to *total / *nvis
+// one workgroup: exclusive scan of the tile sums in place; grand totals to out[n] and *nvis
 template <bool COMPACT>
-__global__ __launch_bounds__(kBlock) void k_scan_top(uint64_t *bsum, uint32_t *bvis, int64_t nb, uint64_t *total,
-                                                     uint32_t *nvis) {
-  __shared__ uint64_t sh[kBlock];
-  __shared__ uint32_t shv[kBlock];
+__global__ __launch_bounds__(kBlock) void k_scan_top(uint64_t *bsum, uint32_t *bvis, int64_t nb, int64_t n_host,
+                                                     const uint32_t *n_dev, uint64_t *out, uint32_t *nvis) {
+  __shared__ uint64_t sh[4];
+  __shared__ uint32_t shv[4];
   uint64_t carry = 0;
   uint32_t carryv = 0;
-  for (int64_t base = 0; base < nb; base += kBlock) {
-    const int64_t i = base + threadIdx.x;
+  for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
+    const int64_t i = b0 + threadIdx.x;
     uint64_t tot;
     const uint64_t ex = block_exclusive_scan<uint64_t>(i < nb ? bsum[i] : 0, sh, &tot);
     if (i < nb) bsum[i] = carry + ex;
@@ -238,25 +265,27 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(uint64_t *bsum, uint32_t *b
     }
   }
   if (threadIdx.x == 0) {
-    *total = carry;
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+    out[n] = carry;
     if (COMPACT) *nvis = carryv;
   }
 }
 
 template <bool GATHER, bool COMPACT>
-__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, const uint32_t *idx, int64_t n,
-                                                      const uint64_t *bsum, const uint32_t *bvis, uint64_t *out,
-                                                      uint32_t *order) {
-  __shared__ uint64_t sh[kBlock];
-  __shared__ uint32_t shv[kBlock];
-  // thread t owns the consecutive items [base + t*kScanItems, base + (t+1)*kScanItems)
+__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, const uint32_t *idx, int64_t n_host,
+                                                      const uint32_t *n_dev, const uint64_t *bsum,
+                                                      const uint32_t *bvis, uint64_t *out, uint32_t *order) {
+  __shared__ uint64_t sh[4];
+  __shared__ uint32_t shv[4];
+  const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+  if ((int64_t)blockIdx.x * kScanTile >= n) return;
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
+  load_items<GATHER>(in, idx, base, n, v);
   uint64_t s = 0;
   uint32_t c = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    v[i] = (base + i < n) ? scan_value<GATHER>(in, idx, base + i) : 0u;
     s += v[i];
     c += v[i] > 0;
   }
@@ -278,20 +307,18 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, const 
 }
 
 template <bool GATHER, bool COMPACT>
-hipError_t scan_impl(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n, uint32_t *order,
-                     uint32_t *nvis, void *tmp, hipStream_t st) {
+hipError_t scan_impl(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n, const uint32_t *n_dev,
+                     uint32_t *order, uint32_t *nvis, void *tmp, hipStream_t st) {
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   uint64_t *bsum = static_cast<uint64_t *>(tmp);
-  uint32_t *bvis = reinterpret_cast<uint32_t *>(bsum + nb + 1);
-  if (nb > 0) {
-    hipLaunchKernelGGL((k_scan_reduce<GATHER, COMPACT>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx, n, bsum,
-                       bvis);
-  }
-  hipLaunchKernelGGL((k_scan_top<COMPACT>), dim3(1), dim3(kBlock), 0, st, bsum, bvis, nb, out + n, nvis);
-  if (nb > 0) {
-    hipLaunchKernelGGL((k_scan_down<GATHER, COMPACT>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx, n, bsum,
-                       bvis, out, order);
-  }
+  uint32_t *bvis = reinterpret_cast<uint32_t *>(bsum + (nb > 0 ? nb : 1));
+  if (nb > 0)
+    hipLaunchKernelGGL((k_scan_reduce<GATHER, COMPACT>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx, n, n_dev,
+                       bsum, bvis);
+  hipLaunchKernelGGL((k_scan_top<COMPACT>), dim3(1), dim3(kBlock), 0, st, bsum, bvis, nb, n, n_dev, out, nvis);
+  if (nb > 0)
+    hipLaunchKernelGGL((k_scan_down<GATHER, COMPACT>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx, n, n_dev,
+                       bsum, bvis, out, order);
   return hipGetLastError();
 }
 
@@ -333,21 +360,17 @@ hipError_t launch_preprocess(const gs_scene &s, const gs_camera &c, const Grid &
 
 size_t scan_tmp_bytes(int64_t n) {
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
-  return (size_t)(nb + 1) * (sizeof(uint64_t) + sizeof(uint32_t)) + 16;
-}
-
-hipError_t launch_scan(const uint32_t *in, uint64_t *out, int64_t n, void *tmp, hipStream_t st) {
-  return scan_impl<false, false>(in, nullptr, out, n, nullptr, nullptr, tmp, st);
+  return (size_t)((nb > 0 ? nb : 1) * (sizeof(uint64_t) + sizeof(uint32_t)) + 16);
 }
 
 hipError_t launch_scan_compact(const uint32_t *in, uint64_t *out, int64_t n, uint32_t *order, uint32_t *nvis,
                                void *tmp, hipStream_t st) {
-  return scan_impl<false, true>(in, nullptr, out, n, order, nvis, tmp, st);
+  return scan_impl<false, true>(in, nullptr, out, n, nullptr, order, nvis, tmp, st);
 }
 
-hipError_t launch_scan_gather(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n, void *tmp,
-                              hipStream_t st) {
-  return scan_impl<true, false>(in, idx, out, n, nullptr, nullptr, tmp, st);
+hipError_t launch_scan_gather(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n_max,
+                              const uint32_t *n_dev, void *tmp, hipStream_t st) {
+  return scan_impl<true, false>(in, idx, out, n_max, n_dev, nullptr, nullptr, tmp, st);
 }
 
 }  // namespace gsi

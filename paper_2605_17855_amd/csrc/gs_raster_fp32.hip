@@ -70,6 +70,13 @@ __global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParam
     for (int k = 0; k < NT; ++k) alive |= cut[k] != INFINITY;
     if (!__syncthreads_or(alive)) break;
     for (int j = 0; j < cnt; ++j) {
+      if ((j & 31) == 0) {
+        // a wave whose pixels have all stopped leaves the chunk early
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) any |= cut[k] != INFINITY;
+        if (__ballot(any) == 0) break;
+      }
       const float4 A = s_a[j];
       const float4 B = s_b[j];
       const float4 Cc = s_c[j];

@@ -145,6 +145,8 @@ __device__ __forceinline__ void process_rows(const uint16_t *sA, const float4 *s
   const int lane = threadIdx.x & 63;
   const int nblk = (nrows + 31) >> 5;
   for (int blk = 0; blk < nblk; ++blk) {
+    // a wave whose 64 pixels have all stopped skips the rest of this tile's rows
+    if (__ballot(st.cut != INFINITY) == 0) break;
     const uint16_t *rp = sA + (size_t)(32 * blk + (lane & 31)) * RS + 8 * (lane >> 5);
     const short8 a = *reinterpret_cast<const short8 *>(rp);
     float16v z = {};

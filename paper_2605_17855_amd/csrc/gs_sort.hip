@@ -13,6 +13,11 @@
 // load-balanced over Gaussians of any footprint), and the remaining passes sort the
 // entries stably on the bin digits.  The result is exactly the stable sort of the 64-bit
 // keys of Gaussian-major emission, i.e. the order (bin, depth bits, Gaussian index).
+//
+// Each pass is three kernels without inter-workgroup waits: per-tile digit counts, one
+// workgroup per digit scanning its row of tile counts (and writing the row total), and a
+// stable scatter that derives the digit bases from the row totals and writes each digit's
+// run through LDS so that lanes store consecutive addresses.
 #include "gs_internal.hpp"
 
 namespace gsi {
@@ -32,6 +37,7 @@ constexpr int kRounds = 8;
 constexpr int kWaveTile = kRounds * 64;
 constexpr int kSortTile = 4 * kWaveTile;
 constexpr int kDigits = 256;
+constexpr int kMaxPasses = 8;
 
 // lanes of the wave holding the same digit as this lane (among lanes with valid keys)
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nbits) {
@@ -44,97 +50,102 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nbit
   return peers;
 }
 
+// Per-tile digit counts: counts[d * tiles + tile].  Keys are loaded up front (8 in flight
+// per lane) and each wave adds one LDS atomic per distinct digit.
 template <typename KT>
-__global__ __launch_bounds__(kBlock) void k_radix_count(const KT *keys, uint64_t n, int shift, int nbits,
-                                                        uint32_t nblocks, uint32_t *counts, uint32_t *ghist) {
+__global__ __launch_bounds__(kBlock) void k_radix_count(const KT *keys, uint64_t n_host, const uint32_t *n_dev,
+                                                        int shift, int nbits, uint32_t tiles_max, uint32_t *counts) {
   __shared__ uint32_t h[kDigits];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  h[t] = 0;
+  const uint64_t n = n_dev ? (uint64_t)*n_dev : n_host;
   const uint32_t dmask = (1u << nbits) - 1u;
   const uint64_t lt = (1ull << lane) - 1ull;
   const uint64_t base = (uint64_t)blockIdx.x * kSortTile + (uint64_t)w * kWaveTile;
+  KT key[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint64_t i = base + (uint64_t)r * 64 + lane;
-    const bool valid = i < n;
-    const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & dmask : 0u;
+    key[r] = i < n ? keys[i] : (KT)0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const bool valid = base + (uint64_t)r * 64 + lane < n;
+    const uint32_t d = (uint32_t)(key[r] >> shift) & dmask;
     const uint64_t peers = match_digit(d, valid, nbits);
-    // one LDS atomic per distinct digit of the round (the group's first lane adds the group size)
     if (valid && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
   }
   __syncthreads();
-  const uint32_t v = h[threadIdx.x];
-  counts[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = v;
-  if (v) atomicAdd(&ghist[threadIdx.x], v);
+  counts[(uint64_t)t * tiles_max + blockIdx.x] = h[t];
 }
 
-// one workgroup per digit: offsets[d][b] = (keys with smaller digit) + (digit-d keys in blocks < b)
-__global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t *counts, uint32_t nblocks,
-                                                             const uint32_t *ghist) {
+// One workgroup per digit d: counts[d][*] becomes the exclusive prefix over tiles (within the
+// digit) and totals[d] the digit's total.
+__global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t *counts, uint32_t tiles_max,
+                                                             uint32_t *totals) {
   __shared__ uint32_t sh[kBlock];
-  const int d = blockIdx.x;
-  const int t = threadIdx.x;
-  // digit base: sum of the global histogram below d (parallel reduction)
-  sh[t] = t < d ? ghist[t] : 0u;
-  __syncthreads();
-  for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if (t < off) sh[t] += sh[t + off];
-    __syncthreads();
-  }
-  const uint32_t dbase = sh[0];
-  __syncthreads();
-  uint32_t *row = counts + (uint64_t)d * nblocks;
-  const uint32_t per = (nblocks + kBlock - 1) / kBlock;
+  const int d = blockIdx.x, t = threadIdx.x;
+  uint32_t *row = counts + (uint64_t)d * tiles_max;
+  const uint32_t per = (tiles_max + kBlock - 1) / kBlock;
   const uint32_t b0 = t * per;
   uint32_t s = 0;
   for (uint32_t i = 0; i < per; ++i)
-    if (b0 + i < nblocks) s += row[b0 + i];
+    if (b0 + i < tiles_max) s += row[b0 + i];
   sh[t] = s;
   __syncthreads();
   for (int off = 1; off < kBlock; off <<= 1) {
-    uint32_t add = t >= off ? sh[t - off] : 0;
+    const uint32_t add = t >= off ? sh[t - off] : 0u;
     __syncthreads();
     sh[t] += add;
     __syncthreads();
   }
-  uint32_t run = dbase + sh[t] - s;
+  uint32_t run = sh[t] - s;
+  if (t == kBlock - 1) totals[d] = sh[t];
   for (uint32_t i = 0; i < per; ++i)
-    if (b0 + i < nblocks) {
+    if (b0 + i < tiles_max) {
       const uint32_t c = row[b0 + i];
       row[b0 + i] = run;
       run += c;
     }
 }
 
-// Stable scatter: ranks come from per-wave digit counters; keys are first placed in LDS in
-// block-local digit order, then written out so that consecutive lanes write consecutive
-// addresses of the same digit run.
+// Stable scatter of one tile: ranks from per-wave digit counters; the tile's start for digit
+// d is (keys with a smaller digit) + offsets[d][tile]; keys are placed in LDS in tile-local
+// digit order and then stored so that consecutive lanes write consecutive addresses.
 template <typename KT>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const uint32_t *vin, KT *kout, uint32_t *vout,
-                                                          uint64_t n, int shift, int nbits, uint32_t nblocks,
-                                                          const uint32_t *offsets) {
+                                                          uint64_t n_host, const uint32_t *n_dev, int shift, int nbits,
+                                                          uint32_t tiles_max, const uint32_t *offsets,
+                                                          const uint32_t *totals) {
   __shared__ uint32_t wcnt[4][kDigits];
   __shared__ uint32_t bstart[kDigits];
   __shared__ uint32_t gbase[kDigits];
   __shared__ KT s_key[kSortTile];
   __shared__ uint32_t s_val[kSortTile];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const uint32_t dmask = (1u << nbits) - 1u;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
-  __syncthreads();
-  const uint64_t lt = (1ull << lane) - 1ull;
+  const uint64_t n = n_dev ? (uint64_t)*n_dev : n_host;
   const uint64_t tile0 = (uint64_t)blockIdx.x * kSortTile;
+  if (tile0 >= n) return;
+  const uint32_t dmask = (1u << nbits) - 1u;
+  const uint64_t lt = (1ull << lane) - 1ull;
   const uint64_t base = tile0 + (uint64_t)w * kWaveTile;
   KT key[kRounds];
   uint32_t val[kRounds], pos[kRounds], dig[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint64_t i = base + (uint64_t)r * 64 + lane;
-    const bool valid = i < n;
-    key[r] = valid ? kin[i] : (KT)0;
-    val[r] = valid ? vin[i] : 0u;
+    key[r] = i < n ? kin[i] : (KT)0;
+    val[r] = i < n ? vin[i] : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
+  const uint32_t tot_d = totals[t];
+  const uint32_t off_d = offsets[(uint64_t)t * tiles_max + blockIdx.x];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const bool valid = base + (uint64_t)r * 64 + lane < n;
     const uint32_t d = (uint32_t)(key[r] >> shift) & dmask;
     dig[r] = d;
     const uint64_t peers = match_digit(d, valid, nbits);
@@ -147,21 +158,26 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // per digit: block-local start (exclusive scan over digits) and per-wave starts
+  // thread t = digit: tile-local start (scan over digits of the tile's counts) and global
+  // start (scan over digits of the totals, plus this tile's offset within the digit)
   const uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
   const uint32_t tot = c0 + c1 + c2 + c3;
   bstart[t] = tot;
-  gbase[t] = offsets[(uint64_t)t * nblocks + blockIdx.x];
+  gbase[t] = tot_d;
   __syncthreads();
   for (int off = 1; off < kDigits; off <<= 1) {
-    const uint32_t add = t >= off ? bstart[t - off] : 0u;
+    const uint32_t a1 = t >= off ? bstart[t - off] : 0u;
+    const uint32_t a2 = t >= off ? gbase[t - off] : 0u;
     __syncthreads();
-    bstart[t] += add;
+    bstart[t] += a1;
+    gbase[t] += a2;
     __syncthreads();
   }
-  const uint32_t bs = bstart[t] - tot;  // exclusive
+  const uint32_t bs = bstart[t] - tot;
+  const uint32_t gb = gbase[t] - tot_d + off_d;
   __syncthreads();
   bstart[t] = bs;
+  gbase[t] = gb;
   wcnt[0][t] = bs;
   wcnt[1][t] = bs + c0;
   wcnt[2][t] = bs + c0 + c1;
@@ -181,17 +197,20 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
   for (uint32_t i = t; i < nvalid; i += kBlock) {
     const KT k = s_key[i];
     const uint32_t d = (uint32_t)(k >> shift) & dmask;
-    const uint32_t dst = gbase[d] + (i - bstart[d]);
-    kout[dst] = k;
-    vout[dst] = s_val[i];
+    kout[gbase[d] + (i - bstart[d])] = k;
+    vout[gbase[d] + (i - bstart[d])] = s_val[i];
   }
 }
 
-// depth keys of the visible Gaussians: key[i] = bits(depth of order[i])
-__global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, const float4 *rgb, uint32_t nvis,
-                                                       uint32_t *keys) {
+// Depth keys of the visible Gaussians (key[i] = bits(depth of order[i]), i < *nvis), and the
+// zeroing of the bin ranges.
+__global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis,
+                                                       uint32_t *keys, uint32_t *ranges, uint64_t nranges) {
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < nranges; i += stride) ranges[i] = 0u;
+  const uint32_t V = *nvis;
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < nvis) keys[i] = __float_as_uint(rgb[order[i]].w);
+  if (i < V) keys[i] = __float_as_uint(rgb[order[i]].w);
 }
 
 // ---- binning: one thread per entry -------------------------------------------
@@ -202,28 +221,27 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, co
 // entry finds its Gaussian by binary search there.
 constexpr int kBinItems = 1024;
 
-__global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const uint64_t *dpos, uint32_t nvis,
+__global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const uint64_t *dpos, const uint32_t *nvis_p,
                                                     uint64_t K, const ushort4 *rect, int G, int GX,
                                                     uint32_t *bin_keys, uint32_t *vals) {
   __shared__ uint64_t s_pos[kBinItems + 1];
   __shared__ uint32_t s_first;
+  const uint32_t nvis = *nvis_p;
   const uint64_t e0 = (uint64_t)blockIdx.x * kBinItems;
   const int t = threadIdx.x, lane = t & 63;
   if (t < 64) {
-    // 64-ary search for the last Gaussian i with dpos[i] <= e0 over [lo, hi)
+    // 64-ary search for the last Gaussian i with dpos[i] <= e0, over [lo, hi)
     uint32_t lo = 0, hi = nvis;
     while (hi - lo > 1) {
-      const uint32_t span = hi - lo;
-      const uint32_t step = (span + 63) / 64;
+      const uint32_t step = (hi - lo + 63) / 64;
       const uint32_t probe = lo + (uint32_t)lane * step;
       const bool le = probe < hi && dpos[probe] <= e0;
       const uint64_t m = __ballot(le);
-      // m has lanes 0..j set (dpos is non-decreasing); lane j's probe is the new lower bound
+      // dpos increases, so the lanes with le set are 0..j; lane j's probe is the new lower bound
       const int j = 63 - __clzll(m);
       const uint32_t nlo = lo + (uint32_t)j * step;
-      const uint32_t nhi = (nlo + step < hi) ? nlo + step : hi;
+      hi = (nlo + step < hi) ? nlo + step : hi;
       lo = nlo;
-      hi = nhi;
     }
     if (lane == 0) s_first = lo;
   }
@@ -235,25 +253,26 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
 #pragma unroll
   for (int it = 0; it < kBinItems / kBlock; ++it) {
     const uint64_t e = e0 + (uint64_t)it * kBlock + t;
-    if (e >= K) break;
-    // last local index l with s_pos[l] <= e (s_pos[0] <= e0 <= e)
-    uint32_t lo = 0, hi = span;  // invariant: s_pos[lo] <= e < s_pos[hi]
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (s_pos[mid] <= e) lo = mid; else hi = mid;
+    if (e < K) {
+      // last local index l with s_pos[l] <= e; invariant s_pos[lo] <= e < s_pos[hi]
+      uint32_t lo = 0, hi = span;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_pos[mid] <= e) lo = mid; else hi = mid;
+      }
+      const uint32_t g = order[first + lo];
+      const uint32_t j = (uint32_t)(e - s_pos[lo]);
+      const ushort4 r = rect[g];
+      const int gx0 = r.x / G, gx1 = (r.z - 1) / G, gy0 = r.y / G;
+      const int wdt = gx1 - gx0 + 1;
+      const int gy = gy0 + (int)(j / (uint32_t)wdt), gx = gx0 + (int)(j % (uint32_t)wdt);
+      bin_keys[e] = (uint32_t)(gy * GX + gx);
+      vals[e] = g;
     }
-    const uint32_t g = order[first + lo];
-    const uint32_t j = (uint32_t)(e - s_pos[lo]);
-    const ushort4 r = rect[g];
-    const int gx0 = r.x / G, gx1 = (r.z - 1) / G, gy0 = r.y / G;
-    const int wdt = gx1 - gx0 + 1;
-    const int gy = gy0 + (int)(j / (uint32_t)wdt), gx = gx0 + (int)(j % (uint32_t)wdt);
-    bin_keys[e] = (uint32_t)(gy * GX + gx);
-    vals[e] = g;
   }
 }
 
-// Bin ranges, tile-membership masks and the 64-bit keys (bin << 32 | depth bits).
+// Bin ranges (zeroed beforehand), tile-membership masks and the 64-bit keys.
 __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, const uint32_t *vals, uint64_t n,
                                                    const ushort4 *rect, const float4 *rgb, int G, int GX,
                                                    uint32_t *ranges, uint16_t *masks, uint64_t *keys) {
@@ -282,28 +301,40 @@ inline unsigned grid_for(uint64_t n, uint64_t per = kBlock) {
   return (unsigned)(b ? b : 1);
 }
 
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  uint64_t b = (n + kBlock - 1) / kBlock;
+  if (b > 8192) b = 8192;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)b), dim3(kBlock), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+int radix_passes(int lo, int hi) { return hi > lo ? (hi - lo + 7) / 8 : 0; }
+
+size_t radix_tmp_bytes(uint64_t n) {
+  const uint64_t tiles = (n + kSortTile - 1) / kSortTile;
+  return ((size_t)kDigits * (tiles ? tiles : 1) + kDigits) * sizeof(uint32_t);
+}
+
 template <typename KT>
-hipError_t radix_sort_t(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n, int lo, int hi,
-                        void *tmp, hipStream_t st, bool *in_alt) {
+hipError_t radix_passes_t(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n_max,
+                          const uint32_t *n_dev, int lo, int hi, void *tmp, hipStream_t st, bool *in_alt) {
   *in_alt = false;
-  if (n <= 1 || hi <= lo) return hipSuccess;
-  const uint32_t nblocks = (uint32_t)((n + kSortTile - 1) / kSortTile);
+  if (hi <= lo || n_max == 0) return hipSuccess;
+  const uint32_t tiles = (uint32_t)((n_max + kSortTile - 1) / kSortTile);
   uint32_t *counts = static_cast<uint32_t *>(tmp);
-  uint32_t *ghist = counts + (uint64_t)kDigits * nblocks;
-  const int passes = radix_passes(lo, hi);
-  hipError_t e = launch_fill_u32(ghist, (uint64_t)passes * kDigits, 0u, st);
-  if (e != hipSuccess) return e;
+  uint32_t *totals = counts + (uint64_t)kDigits * tiles;
   KT *kin = keys, *kout = keys_alt;
   uint32_t *vin = vals, *vout = vals_alt;
-  for (int p = 0; p < passes; ++p) {
-    const int shift = lo + 8 * p;
+  for (int shift = lo; shift < hi; shift += 8) {
     const int bits = (hi - shift) < 8 ? (hi - shift) : 8;
-    uint32_t *gh = ghist + p * kDigits;
-    hipLaunchKernelGGL((k_radix_count<KT>), dim3(nblocks), dim3(kBlock), 0, st, kin, n, shift, bits, nblocks, counts,
-                       gh);
-    hipLaunchKernelGGL(k_radix_digit_scan, dim3(kDigits), dim3(kBlock), 0, st, counts, nblocks, gh);
-    hipLaunchKernelGGL((k_radix_scatter<KT>), dim3(nblocks), dim3(kBlock), 0, st, kin, vin, kout, vout, n, shift,
-                       bits, nblocks, counts);
+    hipLaunchKernelGGL((k_radix_count<KT>), dim3(tiles), dim3(kBlock), 0, st, kin, n_max, n_dev, shift, bits, tiles,
+                       counts);
+    hipLaunchKernelGGL(k_radix_digit_scan, dim3(kDigits), dim3(kBlock), 0, st, counts, tiles, totals);
+    hipLaunchKernelGGL((k_radix_scatter<KT>), dim3(tiles), dim3(kBlock), 0, st, kin, vin, kout, vout, n_max, n_dev,
+                       shift, bits, tiles, counts, totals);
     std::swap(kin, kout);
     std::swap(vin, vout);
     *in_alt = !*in_alt;
@@ -311,54 +342,37 @@ hipError_t radix_sort_t(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_a
   return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  uint64_t b = (n + kBlock - 1) / kBlock;
-  if (b > 4096) b = 4096;
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)b), dim3(kBlock), 0, st, p, n, v);
-  return hipGetLastError();
-}
-
-int radix_passes(int lo, int hi) { return hi > lo ? (hi - lo + 7) / 8 : 0; }
-
-size_t sort_tmp_bytes(uint64_t n) {
-  const uint64_t nblocks = (n + kSortTile - 1) / kSortTile;
-  // digit counts (256 x nblocks) + one 256-bin global histogram per pass (at most 8 passes)
-  return (size_t)(kDigits * (nblocks ? nblocks : 1) + 8 * kDigits) * sizeof(uint32_t);
-}
-
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
                       int hi, void *tmp, hipStream_t st, bool *in_alt) {
-  return radix_sort_t<uint64_t>(keys, vals, keys_alt, vals_alt, n, lo, hi, tmp, st, in_alt);
+  *in_alt = false;
+  if (n <= 1) return hipSuccess;
+  return radix_passes_t<uint64_t>(keys, vals, keys_alt, vals_alt, n, nullptr, lo, hi, tmp, st, in_alt);
 }
 
-hipError_t radix_sort32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
-                        int hi, void *tmp, hipStream_t st, bool *in_alt) {
-  return radix_sort_t<uint32_t>(keys, vals, keys_alt, vals_alt, n, lo, hi, tmp, st, in_alt);
+hipError_t sort_depth(uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max, uint32_t *keys,
+                      uint32_t *keys_alt, uint32_t *vals_alt, void *tmp, uint32_t *ranges, uint64_t nranges,
+                      hipStream_t st, bool *in_alt) {
+  hipLaunchKernelGGL(k_depth_keys, dim3(grid_for(n_max)), dim3(kBlock), 0, st, order, rgb, nvis, keys, ranges,
+                     nranges);
+  return radix_passes_t<uint32_t>(keys, order, keys_alt, vals_alt, n_max, nvis, 0, 32, tmp, st, in_alt);
 }
 
-hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, uint32_t nvis, uint32_t *keys,
-                             hipStream_t st) {
-  if (nvis == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_depth_keys, dim3(grid_for(nvis)), dim3(kBlock), 0, st, order, rgb, nvis, keys);
-  return hipGetLastError();
-}
-
-hipError_t launch_binning(const uint32_t *order, const uint64_t *dpos, uint32_t nvis, uint64_t K,
-                          const uint16_t *rect, const Grid &g, uint32_t *bin_keys, uint32_t *vals, hipStream_t st) {
+hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, const uint32_t *nvis, uint64_t K,
+                        const uint16_t *rect, const Grid &g, uint32_t *bkey, uint32_t *bval, uint32_t *bkey_alt,
+                        uint32_t *bval_alt, void *tmp, hipStream_t st, bool *in_alt) {
+  *in_alt = false;
   if (K == 0) return hipSuccess;
   hipLaunchKernelGGL(k_binning, dim3(grid_for(K, kBinItems)), dim3(kBlock), 0, st, order, dpos, nvis, K,
-                     reinterpret_cast<const ushort4 *>(rect), g.G, g.GX, bin_keys, vals);
-  return hipGetLastError();
+                     reinterpret_cast<const ushort4 *>(rect), g.G, g.GX, bkey, bval);
+  if (K <= 1) return hipGetLastError();
+  return radix_passes_t<uint32_t>(bkey, bval, bkey_alt, bval_alt, K, nullptr, 0, bits_for((uint64_t)g.nbins), tmp, st,
+                                  in_alt);
 }
 
 hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *vals, uint64_t n, const uint16_t *rect,
                          const float *rgb, const Grid &g, uint32_t *ranges, uint16_t *masks, uint64_t *keys,
                          hipStream_t st) {
-  hipError_t e = launch_fill_u32(ranges, (uint64_t)g.nbins * 2, 0u, st);
-  if (e != hipSuccess || n == 0) return e;
+  if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_ranges, dim3(grid_for(n)), dim3(kBlock), 0, st, bin_keys, vals, n,
                      reinterpret_cast<const ushort4 *>(rect), reinterpret_cast<const float4 *>(rgb), g.G, g.GX,
                      ranges, masks, keys);
