@@ -167,13 +167,15 @@ typedef struct {
   float *aux;               /* NULL or planes as in gs_rasterize */
 } gs_job;
 
-/* Rasterizes n_jobs images in one persistent launch: workgroups take (job, bin) items
- * from `work_counter` (device, one uint32, zeroed by the call).  Each image is bit-identical
- * to gs_rasterize of the same job alone.  job_table is device scratch of
- * gs_batch_table_bytes(n_jobs) bytes. */
-size_t gs_batch_table_bytes(int32_t n_jobs);
-gs_status gs_rasterize_batch(const gs_job *jobs, int32_t n_jobs, const gs_options *opt,
-                             void *job_table, uint32_t *work_counter, void *stream);
+/* Rasterizes n_jobs images (at most gs_max_batch()) in one persistent launch: workgroups take
+ * (job, bin) items from `work_counter` (device, one uint32, zeroed by the call) until every
+ * bin of every job is done.  Each image is bit-identical to gs_rasterize of the same job alone
+ * (the per-bin work does not depend on the launch).  All jobs share opt (group, precision,
+ * splits, background, aux).  The job descriptions are copied into the launch, so `jobs` may be
+ * reused when the call returns.  Serving: batches the ready requests of a request loop. */
+int32_t gs_max_batch(void);
+gs_status gs_rasterize_batch(const gs_job *jobs, int32_t n_jobs, const gs_options *opt, uint32_t *work_counter,
+                             void *stream);
 
 const char *gs_status_string(gs_status s);
 const char *gs_last_error(void);

@@ -315,14 +315,48 @@ gs_status gs_radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t n, int32_t 
   return GS_OK;
 }
 
-size_t gs_batch_table_bytes(int32_t n_jobs) {
-  return n_jobs > 0 ? (size_t)n_jobs * sizeof(gsi::RasterJob) : 0;
-}
+int32_t gs_max_batch(void) { return gsi::kMaxBatch; }
 
-gs_status gs_rasterize_batch(const gs_job *jobs, int32_t n_jobs, const gs_options *opt, void *job_table,
-                             uint32_t *work_counter, void *stream) {
-  (void)jobs; (void)n_jobs; (void)opt; (void)job_table; (void)work_counter; (void)stream;
-  return fail(GS_ERR_UNSUPPORTED, "batched rasterization is not built yet");
+gs_status gs_rasterize_batch(const gs_job *jobs, int32_t n_jobs, const gs_options *opt, uint32_t *work_counter,
+                             void *stream) {
+  gs_status s;
+  if ((s = check_options(opt))) return s;
+  if (n_jobs < 0) return fail(GS_ERR_INVALID_ARG, "n_jobs = %d", n_jobs);
+  if (n_jobs > gsi::kMaxBatch) return fail(GS_ERR_UNSUPPORTED, "n_jobs = %d above %d", n_jobs, gsi::kMaxBatch);
+  if (n_jobs == 0) return GS_OK;
+  if (!jobs || !work_counter) return fail(GS_ERR_INVALID_ARG, "jobs or work_counter is NULL");
+  gsi::BatchTable table{};
+  int64_t total = 0;
+  for (int32_t i = 0; i < n_jobs; ++i) {
+    const gs_job &jb = jobs[i];
+    if ((s = check_camera(&jb.cam))) return fail(s, "job %d: camera", i);
+    if ((s = check_bins(jb.bins, opt->group, false))) return fail(s, "job %d: bins", i);
+    if (!jb.proj || !jb.proj->xy || !jb.proj->conic || !jb.proj->rgb)
+      return fail(GS_ERR_INVALID_ARG, "job %d: projected record is NULL", i);
+    if (!jb.image) return fail(GS_ERR_INVALID_ARG, "job %d: image is NULL", i);
+    if (opt->aux_flags && !jb.aux) return fail(GS_ERR_INVALID_ARG, "job %d: aux is NULL with aux_flags set", i);
+    const gsi::Grid g = gsi::make_grid(jb.cam.width, jb.cam.height, opt->group);
+    table.jobs[i] = make_job(*jb.proj, *jb.bins, g, jb.image, jb.aux);
+    table.jobs[i].bin0 = (int)total;
+    total += g.nbins;
+    if (total >= (1ll << 31)) return fail(GS_ERR_UNSUPPORTED, "batch has >= 2^31 bins");
+  }
+  table.n_jobs = n_jobs;
+  table.total = (int)total;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int dev = 0, cus = 0;
+  GS_HIP(hipGetDevice(&dev));
+  GS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const gsi::RasterParams p = make_params(*opt);
+  // persistent grid: enough workgroups to fill every CU several times, never more than items
+  int64_t grid = (int64_t)cus * 8;
+  if (grid > total) grid = total;
+  GS_HIP(gsi::launch_fill_u32(work_counter, 1, 0u, st));
+  if (opt->precision == GS_PREC_FP32)
+    GS_HIP(gsi::launch_raster_fp32_batch(table, (int)grid, p, work_counter, st));
+  else
+    GS_HIP(gsi::launch_raster_mfma_batch(table, (int)grid, p, work_counter, st));
+  return GS_OK;
 }
 
 }  // extern "C"

@@ -139,7 +139,17 @@ struct RasterParams {
 
 hipError_t launch_raster_fp32(const RasterJob &j, const RasterParams &p, hipStream_t st);
 hipError_t launch_raster_mfma(const RasterJob &j, const RasterParams &p, hipStream_t st);
-hipError_t launch_raster_batch(const RasterJob *table_dev, int n_jobs, int total_items, const RasterParams &p,
-                               uint32_t *counter, hipStream_t st);
+// Jobs of one batched launch, passed by value as a kernel argument (copied at launch).
+constexpr int kMaxBatch = 32;
+struct BatchTable {
+  int n_jobs, total;
+  RasterJob jobs[kMaxBatch];   // jobs[j].bin0: first (job, bin) item of job j, ascending
+};
+// Persistent batched launches: `grid` workgroups take items [0, table.total) from *counter
+// (zeroed before).
+hipError_t launch_raster_fp32_batch(const BatchTable &table, int grid, const RasterParams &p, uint32_t *counter,
+                                    hipStream_t st);
+hipError_t launch_raster_mfma_batch(const BatchTable &table, int grid, const RasterParams &p, uint32_t *counter,
+                                    hipStream_t st);
 
 }  // namespace gsi

@@ -23,14 +23,16 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return x * per + (x < rem ? x : rem) + idx;
 }
 
-template <int G, bool AUX>
-__global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParams P) {
-  constexpr int NT = G * G;
-  __shared__ float4 s_a[kBlock];  // (u, v, -a/2 log2e, -b log2e)
-  __shared__ float4 s_b[kBlock];  // (-c/2 log2e, log2 o, r, g)
-  __shared__ float4 s_c[kBlock];  // (b, mask bits, -, -)
+struct Fp32Shared {
+  float4 a[kBlock];  // (u, v, -a/2 log2e, -b log2e)
+  float4 b[kBlock];  // (-c/2 log2e, log2 o, r, g)
+  float4 c[kBlock];  // (b, mask bits, -, -)
+};
 
-  const int bin = xcd_remap(blockIdx.x, J.nbins);
+// Renders bin `bin` of job J (one workgroup).  Shared by the single-image and batched kernels.
+template <int G, bool AUX>
+__device__ __forceinline__ void raster_bin_fp32(const RasterJob &J, const RasterParams &P, int bin, Fp32Shared &sm) {
+  constexpr int NT = G * G;
   const int gx = bin % J.GX, gy = bin / J.GX;
   const int ox = gx * G * kTile, oy = gy * G * kTile;
   const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
@@ -61,9 +63,9 @@ __global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParam
       const float4 co = J.conic[g];
       const float4 cl = J.rgb[g];
       const uint32_t mk = (G > 1) ? (uint32_t)J.masks[e] : 1u;
-      s_a[t] = make_float4((float)(m.x - ox), (float)(m.y - oy), -0.5f * kLog2e * co.x, -kLog2e * co.y);
-      s_b[t] = make_float4(-0.5f * kLog2e * co.z, __log2f(co.w), cl.x, cl.y);
-      s_c[t] = make_float4(cl.z, __uint_as_float(mk), 0.0f, 0.0f);
+      sm.a[t] = make_float4((float)(m.x - ox), (float)(m.y - oy), -0.5f * kLog2e * co.x, -kLog2e * co.y);
+      sm.b[t] = make_float4(-0.5f * kLog2e * co.z, __log2f(co.w), cl.x, cl.y);
+      sm.c[t] = make_float4(cl.z, __uint_as_float(mk), 0.0f, 0.0f);
     }
     bool alive = false;
 #pragma unroll
@@ -77,9 +79,9 @@ __global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParam
         for (int k = 0; k < NT; ++k) any |= cut[k] != INFINITY;
         if (__ballot(any) == 0) break;
       }
-      const float4 A = s_a[j];
-      const float4 B = s_b[j];
-      const float4 Cc = s_c[j];
+      const float4 A = sm.a[j];
+      const float4 B = sm.b[j];
+      const float4 Cc = sm.c[j];
       const uint32_t mk = __float_as_uint(Cc.y);
 #pragma unroll
       for (int k = 0; k < NT; ++k) {
@@ -88,18 +90,21 @@ __global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParam
         const float dx = X[k] - A.x, dy = Y[k] - A.y;
         const float D = fmaf(dx, fmaf(A.z, dx, A.w * dy), fmaf(B.x * dy, dy, B.y));
         if (D >= cut[k]) {
+          // branch-free body: T' = T (1 - alpha) as one FMA; a stop (T' < 1e-4) blends
+          // nothing, keeps T and disables the pixel
           const float al = fminf(kAlphaMax, __builtin_amdgcn_exp2f(D));
-          const float Tn = T[k] * (1.0f - al);
-          if (Tn < kTMin) {
-            cut[k] = INFINITY;
-            if (AUX) nstop[k] = nseen[k];
-          } else {
-            const float wgt = al * T[k];
-            C0[k] = fmaf(wgt, B.z, C0[k]);
-            C1[k] = fmaf(wgt, B.w, C1[k]);
-            C2[k] = fmaf(wgt, Cc.x, C2[k]);
-            if (AUX) { Ws[k] += wgt; nblend[k]++; }
-            T[k] = Tn;
+          const float Tn = fmaf(-T[k], al, T[k]);
+          const bool ok = Tn >= kTMin;
+          const float wgt = ok ? al * T[k] : 0.0f;
+          C0[k] = fmaf(wgt, B.z, C0[k]);
+          C1[k] = fmaf(wgt, B.w, C1[k]);
+          C2[k] = fmaf(wgt, Cc.x, C2[k]);
+          T[k] = ok ? Tn : T[k];
+          cut[k] = ok ? cut[k] : INFINITY;
+          if (AUX) {
+            Ws[k] += wgt;
+            nblend[k] += ok ? 1u : 0u;
+            nstop[k] = ok ? nstop[k] : nseen[k];
           }
         }
       }
@@ -129,22 +134,74 @@ __global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParam
 }
 
 template <int G, bool AUX>
-hipError_t launch_g(const RasterJob &j, const RasterParams &p, hipStream_t st) {
-  hipLaunchKernelGGL((k_raster_fp32<G, AUX>), dim3((unsigned)j.nbins), dim3(kBlock), 0, st, j, p);
+__global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParams P) {
+  __shared__ Fp32Shared sm;
+  raster_bin_fp32<G, AUX>(J, P, xcd_remap(blockIdx.x, J.nbins), sm);
+}
+
+// Persistent batched rasterizer (see the MFMA variant).
+template <int G, bool AUX>
+__global__ __launch_bounds__(kBlock) void k_raster_fp32_batch(const BatchTable tb,
+                                                              RasterParams P, uint32_t *counter) {
+  const int total = tb.total;
+  __shared__ Fp32Shared sm;
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= total) break;
+    int lo = 0, hi = tb.n_jobs;   // last job with bin0 <= item
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (tb.jobs[mid].bin0 <= item) lo = mid; else hi = mid;
+    }
+    const RasterJob J = tb.jobs[lo];
+    raster_bin_fp32<G, AUX>(J, P, item - J.bin0, sm);
+  }
+}
+
+struct BatchArgs {
+  const BatchTable *table;
+  int grid;
+  uint32_t *counter;
+};
+
+template <int G, bool AUX>
+hipError_t launch_g(const RasterJob &j, const RasterParams &p, const BatchArgs *b, hipStream_t st) {
+  if (b) {
+    hipLaunchKernelGGL((k_raster_fp32_batch<G, AUX>), dim3((unsigned)b->grid), dim3(kBlock), 0, st, *b->table, p,
+                       b->counter);
+  } else {
+    hipLaunchKernelGGL((k_raster_fp32<G, AUX>), dim3((unsigned)j.nbins), dim3(kBlock), 0, st, j, p);
+  }
   return hipGetLastError();
+}
+
+hipError_t dispatch(const RasterJob &j, const RasterParams &p, const BatchArgs *b, hipStream_t st) {
+  const bool aux = p.aux_flags != 0;
+  switch (p.G) {
+    case 1: return aux ? launch_g<1, true>(j, p, b, st) : launch_g<1, false>(j, p, b, st);
+    case 2: return aux ? launch_g<2, true>(j, p, b, st) : launch_g<2, false>(j, p, b, st);
+    case 4: return aux ? launch_g<4, true>(j, p, b, st) : launch_g<4, false>(j, p, b, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
 hipError_t launch_raster_fp32(const RasterJob &j, const RasterParams &p, hipStream_t st) {
   if (j.nbins == 0) return hipSuccess;
-  const bool aux = p.aux_flags != 0;
-  switch (p.G) {
-    case 1: return aux ? launch_g<1, true>(j, p, st) : launch_g<1, false>(j, p, st);
-    case 2: return aux ? launch_g<2, true>(j, p, st) : launch_g<2, false>(j, p, st);
-    case 4: return aux ? launch_g<4, true>(j, p, st) : launch_g<4, false>(j, p, st);
-    default: return hipErrorInvalidValue;
-  }
+  return dispatch(j, p, nullptr, st);
+}
+
+hipError_t launch_raster_fp32_batch(const BatchTable &table, int grid, const RasterParams &p, uint32_t *counter,
+                                    hipStream_t st) {
+  if (table.total == 0) return hipSuccess;
+  BatchArgs b{&table, grid, counter};
+  RasterJob dummy{};
+  return dispatch(dummy, p, &b, st);
 }
 
 }  // namespace gsi

@@ -167,48 +167,47 @@ __device__ __forceinline__ void process_rows(const uint16_t *sA, const float4 *s
 #pragma unroll
     for (int m = 0; m < 32; ++m) {
       if (D[m] >= st.cut) {
+        // branch-free body: T' = T (1 - alpha) as one FMA; a stop (T' < 1e-4) blends nothing,
+        // keeps T and disables the pixel
         const float4 cl = scol[32 * blk + m];
         const float al = fminf(kAlphaMax, __builtin_amdgcn_exp2f(D[m]));
-        const float Tn = st.T * (1.0f - al);
-        if (Tn < kTMin) {
-          st.cut = INFINITY;
-          if (AUX) st.nstop = row_base + 32 * blk + m + 1;
-        } else {
-          const float wgt = al * st.T;
-          st.C0 = fmaf(wgt, cl.x, st.C0);
-          st.C1 = fmaf(wgt, cl.y, st.C1);
-          st.C2 = fmaf(wgt, cl.z, st.C2);
-          if (AUX) { st.W += wgt; st.nblend++; }
-          st.T = Tn;
+        const float Tn = fmaf(-st.T, al, st.T);
+        const bool ok = Tn >= kTMin;
+        const float wgt = ok ? al * st.T : 0.0f;
+        st.C0 = fmaf(wgt, cl.x, st.C0);
+        st.C1 = fmaf(wgt, cl.y, st.C1);
+        st.C2 = fmaf(wgt, cl.z, st.C2);
+        st.T = ok ? Tn : st.T;
+        st.cut = ok ? st.cut : INFINITY;
+        if (AUX) {
+          st.W += wgt;
+          st.nblend += ok ? 1u : 0u;
+          st.nstop = ok ? st.nstop : row_base + 32 * blk + m + 1;
         }
       }
     }
   }
 }
 
-template <int G, int PREC, int S, bool AUX>
-__global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParams P) {
-  constexpr int NT = G * G;
-  constexpr int RS = (S == 3) ? 32 : 16;
-  __shared__ __align__(16) uint16_t s_A[2][kBlock * RS];
-  __shared__ float4 s_col[2][kBlock];
-  __shared__ double2 s_r0[G > 1 ? kBlock : 1];  // FP64 centre; every tile rounds its own offset
-  __shared__ float4 s_r1[G > 1 ? kBlock : 1];   // (a, b, c, ln o)
-  __shared__ float4 s_r2[G > 1 ? kBlock : 1];   // (r, g, b, -)
-  __shared__ uint32_t s_wcnt[2][NT][4];          // by chunk parity: a wave may stage chunk c+1 while
-                                                 // another still reads chunk c's counts
-  __shared__ uint32_t s_alive[2][4];
+template <int G, int S>
+struct MfmaShared {
+  static constexpr int NT = G * G;
+  static constexpr int RS = (S == 3) ? 32 : 16;
+  __align__(16) uint16_t A[2][kBlock * RS];
+  float4 col[2][kBlock];
+  double2 r0[G > 1 ? kBlock : 1];  // FP64 centre; every tile rounds its own offset
+  float4 r1[G > 1 ? kBlock : 1];   // (a, b, c, ln o)
+  float4 r2[G > 1 ? kBlock : 1];   // (r, g, b, -)
+  uint32_t wcnt[2][NT][4];         // by chunk parity: a wave may stage chunk c+1 while
+                                   // another still reads chunk c's counts
+  uint32_t alive[2][4];
+};
 
-  const int bin = xcd_remap(blockIdx.x, J.nbins);
-  const int gx = bin % J.GX, gy = bin / J.GX;
-  const int ox = gx * G * kTile, oy = gy * G * kTile;
-  const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+// Pixel-side operand: phi of this lane's panel pixel (n = lane % 32) in both panels.
+template <int PREC>
+__device__ __forceinline__ void make_pixel_operand(short8 &B0, short8 &B1, short8 &B20, short8 &B21) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int qx0 = (w & 1) * 8, qy0 = (w >> 1) * 8;
-  const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
-
-  // pixel-side operand: phi of this lane's panel pixel (n = lane % 32) in both panels
-  short8 B0, B1, B20, B21;
   {
     using N = Narrow<PREC>;
     const int n = lane & 31, h = lane >> 5;
@@ -238,6 +237,22 @@ __global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParam
     }
   }
 
+}
+
+// Renders bin `bin` of job J (one workgroup).  Shared by the single-image and batched kernels.
+template <int G, int PREC, int S, bool AUX>
+__device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const RasterParams &P, int bin,
+                                                MfmaShared<G, S> &sm, short8 B0, short8 B1, short8 B20,
+                                                short8 B21) {
+  constexpr int NT = G * G;
+  constexpr int RS = (S == 3) ? 32 : 16;
+  const int gx = bin % J.GX, gy = bin / J.GX;
+  const int ox = gx * G * kTile, oy = gy * G * kTile;
+  const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int qx0 = (w & 1) * 8, qy0 = (w >> 1) * 8;
+  const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
+
   TileState st[NT];
   uint32_t alive_mask = 0;       // uniform: member tiles with pixels still blending
   uint32_t rows_done[NT];        // uniform: entries of each tile consumed so far
@@ -265,24 +280,24 @@ __global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParam
         const double2 m = J.xy[g];
         const float4 co = J.conic[g];
         const float4 cl = J.rgb[g];
-        build_row<PREC, S>(&s_A[buf][t * RS], (float)(m.x - ((double)ox + 8.5)), (float)(m.y - ((double)oy + 8.5)),
+        build_row<PREC, S>(&sm.A[buf][t * RS], (float)(m.x - ((double)ox + 8.5)), (float)(m.y - ((double)oy + 8.5)),
                            co.x, co.y, co.z, __logf(co.w));
-        s_col[buf][t] = cl;
+        sm.col[buf][t] = cl;
       } else if (t < ((cnt + 31) & ~31)) {
-        pad_row<PREC, S>(&s_A[buf][t * RS]);
+        pad_row<PREC, S>(&sm.A[buf][t * RS]);
       }
       __syncthreads();
       if (last_k >= 0) {
-        const uint32_t any = s_alive[(it - 1) & 1][0] | s_alive[(it - 1) & 1][1] | s_alive[(it - 1) & 1][2] |
-                             s_alive[(it - 1) & 1][3];
+        const uint32_t any = sm.alive[(it - 1) & 1][0] | sm.alive[(it - 1) & 1][1] | sm.alive[(it - 1) & 1][2] |
+                             sm.alive[(it - 1) & 1][3];
         if (!any) alive_mask = 0;
         last_k = -1;
         if (!alive_mask) break;
       }
-      process_rows<PREC, S, AUX>(s_A[buf], s_col[buf], cnt, B0, B1, B20, B21, st[0], rows_done[0]);
+      process_rows<PREC, S, AUX>(sm.A[buf], sm.col[buf], cnt, B0, B1, B20, B21, st[0], rows_done[0]);
       rows_done[0] += cnt;
       const uint64_t bal = __ballot(st[0].cut != INFINITY);
-      if (lane == 0) s_alive[it & 1][w] = bal != 0;
+      if (lane == 0) sm.alive[it & 1][w] = bal != 0;
       last_k = 0;
       ++it;
     } else {
@@ -295,27 +310,27 @@ __global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParam
         const float4 co = J.conic[g];
         const float4 cl = J.rgb[g];
         mk = J.masks[e];
-        s_r0[t] = m;
-        s_r1[t] = make_float4(co.x, co.y, co.z, __logf(co.w));
-        s_r2[t] = cl;
+        sm.r0[t] = m;
+        sm.r1[t] = make_float4(co.x, co.y, co.z, __logf(co.w));
+        sm.r2[t] = cl;
       }
       uint64_t bal[NT];
 #pragma unroll
       for (int k = 0; k < NT; ++k) {
         bal[k] = __ballot((mk >> k) & 1u);
-        if (lane == 0) s_wcnt[cp][k][w] = (uint32_t)__popcll(bal[k]);
+        if (lane == 0) sm.wcnt[cp][k][w] = (uint32_t)__popcll(bal[k]);
       }
       __syncthreads();
       if (last_k >= 0) {
-        const uint32_t any = s_alive[(it - 1) & 1][0] | s_alive[(it - 1) & 1][1] | s_alive[(it - 1) & 1][2] |
-                             s_alive[(it - 1) & 1][3];
+        const uint32_t any = sm.alive[(it - 1) & 1][0] | sm.alive[(it - 1) & 1][1] | sm.alive[(it - 1) & 1][2] |
+                             sm.alive[(it - 1) & 1][3];
         if (!any) alive_mask &= ~(1u << last_k);
         last_k = -1;
       }
       uint32_t nk[NT], woff[NT];
 #pragma unroll
       for (int k = 0; k < NT; ++k) {
-        const uint32_t c0 = s_wcnt[cp][k][0], c1 = s_wcnt[cp][k][1], c2 = s_wcnt[cp][k][2], c3 = s_wcnt[cp][k][3];
+        const uint32_t c0 = sm.wcnt[cp][k][0], c1 = sm.wcnt[cp][k][1], c2 = sm.wcnt[cp][k][2], c3 = sm.wcnt[cp][k][3];
         nk[k] = c0 + c1 + c2 + c3;
         woff[k] = (w > 0 ? c0 : 0) + (w > 1 ? c1 : 0) + (w > 2 ? c2 : 0);
       }
@@ -328,23 +343,23 @@ __global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParam
         if ((mk >> k) & 1u) {
           const uint32_t pos =
               woff[k] + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[k] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal[k], 0u));
-          const double2 r0 = s_r0[t];
-          const float4 r1 = s_r1[t];
-          build_row<PREC, S>(&s_A[buf][pos * RS], (float)(r0.x - fx0), (float)(r0.y - fy0), r1.x, r1.y, r1.z, r1.w);
-          s_col[buf][pos] = s_r2[t];
+          const double2 r0 = sm.r0[t];
+          const float4 r1 = sm.r1[t];
+          build_row<PREC, S>(&sm.A[buf][pos * RS], (float)(r0.x - fx0), (float)(r0.y - fy0), r1.x, r1.y, r1.z, r1.w);
+          sm.col[buf][pos] = sm.r2[t];
         }
         const uint32_t padn = ((nk[k] + 31) & ~31u) - nk[k];
-        if ((uint32_t)t < padn) pad_row<PREC, S>(&s_A[buf][(nk[k] + t) * RS]);
+        if ((uint32_t)t < padn) pad_row<PREC, S>(&sm.A[buf][(nk[k] + t) * RS]);
         __syncthreads();
         if (last_k >= 0) {
-          const uint32_t any = s_alive[(it - 1) & 1][0] | s_alive[(it - 1) & 1][1] | s_alive[(it - 1) & 1][2] |
-                               s_alive[(it - 1) & 1][3];
+          const uint32_t any = sm.alive[(it - 1) & 1][0] | sm.alive[(it - 1) & 1][1] | sm.alive[(it - 1) & 1][2] |
+                               sm.alive[(it - 1) & 1][3];
           if (!any) alive_mask &= ~(1u << last_k);
         }
-        process_rows<PREC, S, AUX>(s_A[buf], s_col[buf], (int)nk[k], B0, B1, B20, B21, st[k], rows_done[k]);
+        process_rows<PREC, S, AUX>(sm.A[buf], sm.col[buf], (int)nk[k], B0, B1, B20, B21, st[k], rows_done[k]);
         rows_done[k] += nk[k];
         const uint64_t ab = __ballot(st[k].cut != INFINITY);
-        if (lane == 0) s_alive[it & 1][w] = ab != 0;
+        if (lane == 0) sm.alive[it & 1][w] = ab != 0;
         last_k = k;
         ++it;
       }
@@ -375,41 +390,98 @@ __global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParam
 }
 
 template <int G, int PREC, int S, bool AUX>
-hipError_t launch_t(const RasterJob &j, const RasterParams &p, hipStream_t st) {
-  hipLaunchKernelGGL((k_raster_mfma<G, PREC, S, AUX>), dim3((unsigned)j.nbins), dim3(kBlock), 0, st, j, p);
+__global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParams P) {
+  __shared__ MfmaShared<G, S> sm;
+  short8 B0, B1, B20, B21;
+  make_pixel_operand<PREC>(B0, B1, B20, B21);
+  raster_bin_mfma<G, PREC, S, AUX>(J, P, xcd_remap(blockIdx.x, J.nbins), sm, B0, B1, B20, B21);
+}
+
+// Persistent batched rasterizer: workgroups take (job, bin) items from *counter until all
+// `total` items are done; job j owns items [jobs[j].bin0, jobs[j].bin0 + jobs[j].nbins).
+template <int G, int PREC, int S, bool AUX>
+__global__ __launch_bounds__(kBlock) void k_raster_mfma_batch(const BatchTable tb,
+                                                              RasterParams P, uint32_t *counter) {
+  const int total = tb.total;
+  __shared__ MfmaShared<G, S> sm;
+  __shared__ int s_item;
+  short8 B0, B1, B20, B21;
+  make_pixel_operand<PREC>(B0, B1, B20, B21);
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= total) break;
+    int lo = 0, hi = tb.n_jobs;   // last job with bin0 <= item
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (tb.jobs[mid].bin0 <= item) lo = mid; else hi = mid;
+    }
+    const RasterJob J = tb.jobs[lo];
+    raster_bin_mfma<G, PREC, S, AUX>(J, P, item - J.bin0, sm, B0, B1, B20, B21);
+  }
+}
+
+struct BatchArgs {
+  const BatchTable *table;
+  int grid;
+  uint32_t *counter;
+};
+
+template <int G, int PREC, int S, bool AUX>
+hipError_t launch_t(const RasterJob &j, const RasterParams &p, const BatchArgs *b, hipStream_t st) {
+  if (b) {
+    hipLaunchKernelGGL((k_raster_mfma_batch<G, PREC, S, AUX>), dim3((unsigned)b->grid), dim3(kBlock), 0, st, *b->table, p,
+                       b->counter);
+  } else {
+    hipLaunchKernelGGL((k_raster_mfma<G, PREC, S, AUX>), dim3((unsigned)j.nbins), dim3(kBlock), 0, st, j, p);
+  }
   return hipGetLastError();
 }
 
 template <int G, int PREC>
-hipError_t launch_s(const RasterJob &j, const RasterParams &p, hipStream_t st) {
+hipError_t launch_s(const RasterJob &j, const RasterParams &p, const BatchArgs *b, hipStream_t st) {
   const bool aux = p.aux_flags != 0;
   switch (p.splits) {
-    case 1: return aux ? launch_t<G, PREC, 1, true>(j, p, st) : launch_t<G, PREC, 1, false>(j, p, st);
-    case 2: return aux ? launch_t<G, PREC, 2, true>(j, p, st) : launch_t<G, PREC, 2, false>(j, p, st);
+    case 1: return aux ? launch_t<G, PREC, 1, true>(j, p, b, st) : launch_t<G, PREC, 1, false>(j, p, b, st);
+    case 2: return aux ? launch_t<G, PREC, 2, true>(j, p, b, st) : launch_t<G, PREC, 2, false>(j, p, b, st);
     case 3:
       if (PREC == GS_PREC_FP16_MFMA) return hipErrorInvalidValue;
-      return aux ? launch_t<G, PREC, 3, true>(j, p, st) : launch_t<G, PREC, 3, false>(j, p, st);
+      return aux ? launch_t<G, PREC, 3, true>(j, p, b, st) : launch_t<G, PREC, 3, false>(j, p, b, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int PREC>
-hipError_t launch_p(const RasterJob &j, const RasterParams &p, hipStream_t st) {
+hipError_t launch_p(const RasterJob &j, const RasterParams &p, const BatchArgs *b, hipStream_t st) {
   switch (p.G) {
-    case 1: return launch_s<1, PREC>(j, p, st);
-    case 2: return launch_s<2, PREC>(j, p, st);
-    case 4: return launch_s<4, PREC>(j, p, st);
+    case 1: return launch_s<1, PREC>(j, p, b, st);
+    case 2: return launch_s<2, PREC>(j, p, b, st);
+    case 4: return launch_s<4, PREC>(j, p, b, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t dispatch(const RasterJob &j, const RasterParams &p, const BatchArgs *b, hipStream_t st) {
+  if (p.prec == GS_PREC_FP16_MFMA) return launch_p<GS_PREC_FP16_MFMA>(j, p, b, st);
+  if (p.prec == GS_PREC_BF16_MFMA) return launch_p<GS_PREC_BF16_MFMA>(j, p, b, st);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
 hipError_t launch_raster_mfma(const RasterJob &j, const RasterParams &p, hipStream_t st) {
   if (j.nbins == 0) return hipSuccess;
-  if (p.prec == GS_PREC_FP16_MFMA) return launch_p<GS_PREC_FP16_MFMA>(j, p, st);
-  if (p.prec == GS_PREC_BF16_MFMA) return launch_p<GS_PREC_BF16_MFMA>(j, p, st);
-  return hipErrorInvalidValue;
+  return dispatch(j, p, nullptr, st);
+}
+
+hipError_t launch_raster_mfma_batch(const BatchTable &table, int grid, const RasterParams &p, uint32_t *counter,
+                                    hipStream_t st) {
+  if (table.total == 0) return hipSuccess;
+  BatchArgs b{&table, grid, counter};
+  RasterJob dummy{};
+  return dispatch(dummy, p, &b, st);
 }
 
 }  // namespace gsi

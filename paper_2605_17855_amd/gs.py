@@ -62,7 +62,7 @@ class gs_job(C.Structure):
 
 
 EXPORTS = ["gs_num_bins", "gs_workspace_bytes", "gs_preprocess", "gs_bin_sort", "gs_rasterize", "gs_render",
-           "gs_sort_workspace_bytes", "gs_radix_sort_u64", "gs_batch_table_bytes", "gs_rasterize_batch",
+           "gs_sort_workspace_bytes", "gs_radix_sort_u64", "gs_max_batch", "gs_rasterize_batch",
            "gs_status_string", "gs_last_error"]
 
 _lib = None
@@ -94,9 +94,9 @@ def lib():
     L.gs_sort_workspace_bytes.restype = C.c_size_t
     L.gs_radix_sort_u64.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.c_int32, C.c_int32, C.c_void_p,
                                     C.c_size_t, C.c_void_p]
-    L.gs_batch_table_bytes.argtypes = [C.c_int32]
-    L.gs_batch_table_bytes.restype = C.c_size_t
-    L.gs_rasterize_batch.argtypes = [P(gs_job), C.c_int32, P(gs_options), C.c_void_p, C.c_void_p, C.c_void_p]
+    L.gs_max_batch.argtypes = []
+    L.gs_max_batch.restype = C.c_int32
+    L.gs_rasterize_batch.argtypes = [P(gs_job), C.c_int32, P(gs_options), C.c_void_p, C.c_void_p]
     for f in ("gs_preprocess", "gs_bin_sort", "gs_rasterize", "gs_render", "gs_radix_sort_u64",
               "gs_rasterize_batch"):
         getattr(L, f).restype = C.c_int
@@ -249,6 +249,19 @@ def gs_radix_sort_u64(keys, vals, lo_bit: int, hi_bit: int, ws=None, stream=None
         ws = torch.empty((max(need, 1),), dtype=torch.uint8, device=keys.device)
     _check(lib().gs_radix_sort_u64(_ptr(keys), _ptr(vals), n, lo_bit, hi_bit, _ptr(ws), ws.numel(),
                                    _stream(stream)))
+
+
+def gs_rasterize_batch(items, opt: gs_options, counter, stream=None):
+    """items: list of (Projected, Bins, camera, image, aux-or-None).  One persistent launch."""
+    n = len(items)
+    arr = (gs_job * max(n, 1))()
+    for i, (proj, bins, cam, image, aux) in enumerate(items):
+        arr[i].proj = C.pointer(proj.struct)
+        arr[i].bins = C.pointer(bins.struct)
+        arr[i].cam = camera(cam)
+        arr[i].image = _ptr(image)
+        arr[i].aux = _ptr(aux)
+    _check(lib().gs_rasterize_batch(arr, n, C.byref(opt), _ptr(counter), _stream(stream)))
 
 
 def aux_planes(flags: int) -> int:

@@ -59,7 +59,7 @@ def test_rasterize_rejects_bad_options(field, value, status):
     L = gs.lib()
     o = gs.options(precision="fp16")
     setattr(o, field, value)
-    p = gs.gs_projected(1, 1, 1, 1, 1, 1)
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1, 1, 1)
     b = gs.gs_bins(1, 1, 1, 16, 1)
     img = C.c_void_p(1)
     assert L.gs_rasterize(C.byref(p), C.byref(b), C.byref(_cam()), C.byref(o), img, None, None) == status
@@ -69,7 +69,7 @@ def test_rasterize_rejects_bad_options(field, value, status):
 def test_fp16_three_splits_unsupported():
     L = gs.lib()
     o = gs.options(precision="fp16", splits=3)
-    p = gs.gs_projected(1, 1, 1, 1, 1, 1)
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1, 1, 1)
     b = gs.gs_bins(1, 1, 1, 16, 1)
     assert L.gs_rasterize(C.byref(p), C.byref(b), C.byref(_cam()), C.byref(o), C.c_void_p(1), None,
                           None) == gs.GS_ERR_UNSUPPORTED
@@ -81,7 +81,7 @@ def test_rasterize_rejects_bad_camera(w, h, status):
     L = gs.lib()
     c = _cam()
     c.width, c.height = w, h
-    p = gs.gs_projected(1, 1, 1, 1, 1, 1)
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1, 1, 1)
     b = gs.gs_bins(1, 1, 1, 16, 1)
     assert L.gs_rasterize(C.byref(p), C.byref(b), C.byref(c), C.byref(gs.options()), C.c_void_p(1), None,
                           None) == status
@@ -89,7 +89,7 @@ def test_rasterize_rejects_bad_camera(w, h, status):
 
 def test_camera_value_checks():
     L = gs.lib()
-    p = gs.gs_projected(1, 1, 1, 1, 1, 1)
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1, 1, 1)
     b = gs.gs_bins(1, 1, 1, 16, 1)
     for field, value in (("fx", 0.0), ("fy", -1.0), ("znear", 0.0), ("fx", float("nan"))):
         c = _cam()
@@ -102,7 +102,7 @@ def test_null_arguments():
     L = gs.lib()
     o = gs.options()
     c = _cam()
-    p = gs.gs_projected(1, 1, 1, 1, 1, 1)
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1, 1, 1)
     b = gs.gs_bins(1, 1, 1, 16, 1)
     assert L.gs_rasterize(None, C.byref(b), C.byref(c), C.byref(o), C.c_void_p(1), None, None) == gs.GS_ERR_INVALID_ARG
     assert L.gs_rasterize(C.byref(p), None, C.byref(c), C.byref(o), C.c_void_p(1), None, None) == gs.GS_ERR_INVALID_ARG
@@ -122,7 +122,7 @@ def test_scene_checks():
     L = gs.lib()
     o = gs.options()
     c = _cam()
-    p = gs.gs_projected(1, 1, 1, 1, 1, 1)
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1, 1, 1)
     ws = C.c_void_p(1)
     for n, deg, status in ((-1, 0, gs.GS_ERR_INVALID_ARG), (1 << 31, 0, gs.GS_ERR_UNSUPPORTED),
                            (10, 4, gs.GS_ERR_UNSUPPORTED), (10, -1, gs.GS_ERR_INVALID_ARG)):
@@ -155,3 +155,26 @@ def test_workspace_sizes_grow_with_inputs():
     b = L.gs_workspace_bytes(1000, 100000, C.byref(c), C.byref(o))
     assert b > a >= 1000 * 12
     assert L.gs_sort_workspace_bytes(1 << 20) >= (1 << 20) * 12
+
+
+def test_batch_argument_checks():
+    L = gs.lib()
+    assert L.gs_max_batch() == 32
+    o = gs.options()
+    jobs = (gs.gs_job * 40)()
+    counter = C.c_void_p(1)
+    assert L.gs_rasterize_batch(jobs, 0, C.byref(o), counter, None) == gs.GS_OK
+    assert L.gs_rasterize_batch(jobs, -1, C.byref(o), counter, None) == gs.GS_ERR_INVALID_ARG
+    assert L.gs_rasterize_batch(jobs, 33, C.byref(o), counter, None) == gs.GS_ERR_UNSUPPORTED
+    assert L.gs_rasterize_batch(None, 2, C.byref(o), counter, None) == gs.GS_ERR_INVALID_ARG
+    # a job without projected records is rejected before any device work
+    jobs[0].cam = _cam()
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1, 1, 1)
+    b = gs.gs_bins(1, 1, 1, 16, 1)
+    jobs[0].bins = C.pointer(b)
+    assert L.gs_rasterize_batch(jobs, 1, C.byref(o), counter, None) == gs.GS_ERR_INVALID_ARG
+    jobs[0].proj = C.pointer(p)
+    jobs[0].image = None
+    assert L.gs_rasterize_batch(jobs, 1, C.byref(o), counter, None) == gs.GS_ERR_INVALID_ARG
+    bad = gs.options(group=3)
+    assert L.gs_rasterize_batch(jobs, 1, C.byref(bad), counter, None) == gs.GS_ERR_UNSUPPORTED

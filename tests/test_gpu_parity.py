@@ -309,3 +309,42 @@ def test_1080p_sampled_tiles(big):
         if prec == "fp32":
             assert err[:, ok].max() <= 1e-3
         assert np.abs(out["wsum"] + out["tfinal"] - 1.0).max() <= 1e-5
+
+
+@pytest.mark.parametrize("prec,group", [("fp16", 1), ("fp32", 1), ("bf16", 2)])
+def test_batch_matches_single_renders(prec, group):
+    """Persistent batched rasterization: every image equals rendering its job alone (bit-identical)."""
+    import torch
+    jobs = []
+    specs = [(scenes.camera_box_scene(3000, seed=21), scenes.pinhole(128, 96, 60.0)),
+             (scenes.camera_box_scene(1500, seed=22), scenes.pinhole(70, 33, 50.0)),
+             (scenes.clustered_scene(20000, seed=23, clusters=8), scenes.look_at([3.0, 1.0, 1.5], 160, 90)),
+             (scenes.camera_box_scene(10, seed=24), scenes.pinhole(16, 16, 60.0))]
+    aux = AUX_ALL | gs.GS_AUX_NBLEND
+    opt = gs.options(group=group, precision=prec, splits=3 if prec == "bf16" else 2, bg=(0.2, 0.1, 0.0),
+                     aux_flags=aux)
+    singles = []
+    for sc, cam in specs:
+        ds = gs.DeviceScene(sc)
+        r = gs.Renderer(sc.n, cam.width, cam.height, group=group)
+        note(f"batch reference {prec} g{group} {cam.width}x{cam.height}")
+        r.render(ds, cam, opt)
+        torch.cuda.synchronize()
+        singles.append((r.image.clone(), r.aux.clone()))
+        img = torch.full_like(r.image, -1.0)
+        ax = torch.full_like(r.aux, -1.0)
+        jobs.append((r.proj, r.bins, cam, img, ax, r, ds))
+    counter = torch.zeros(1, dtype=torch.int32, device="cuda")
+    note(f"batch launch {prec} g{group}")
+    gs.gs_rasterize_batch([(j[0], j[1], j[2], j[3], j[4]) for j in jobs], opt, counter)
+    torch.cuda.synchronize()
+    for (img, ax), j in zip(singles, jobs):
+        assert torch.equal(img, j[3]) and torch.equal(ax, j[4])
+    # the same jobs twice in one launch, in another order
+    order = [2, 0, 3, 1, 2]
+    outs = [(torch.full_like(jobs[k][3], -1.0), torch.full_like(jobs[k][4], -1.0)) for k in order]
+    gs.gs_rasterize_batch([(jobs[k][0], jobs[k][1], jobs[k][2], o[0], o[1]) for k, o in zip(order, outs)], opt,
+                          counter)
+    torch.cuda.synchronize()
+    for k, o in zip(order, outs):
+        assert torch.equal(o[0], singles[k][0]) and torch.equal(o[1], singles[k][1])
