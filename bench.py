@@ -8,10 +8,12 @@ resident scene: preprocess + count scan, binning + radix sort + ranges, rasteriz
 The chosen form (FP16 MFMA power, hi/lo splits) is timed, then the plain FP32
 rasterizer on the same poses.  The JSON line carries both rates, per-frame p50/p99,
 the raster kernel's ALU roofline (HIP events on the launch stream), the PSNR of the
-chosen form against the FP64 oracle on sampled tiles, and the oracle's own rate on
-the host cores.
+chosen form against the FP64 oracle on sampled tiles, the oracle's own rate on
+the host cores, and a serving run (8 resident scenes, mixed resolutions, continuous
+batching; p50/p99 latency of an open-loop Poisson stream) under "serving".
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-serve]
+       python bench.py --serve-only [--serve-requests R] [--serve-load F]
 """
 from __future__ import annotations
 
@@ -49,6 +51,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 plain comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle compositing time")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving workload")
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-load", type=float, default=0.7, help="offered rate / saturated throughput")
+    ap.add_argument("--serve-pool-gib", type=float, default=4.0)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times), for HBM counter calibration")
     return ap.parse_args()
@@ -156,6 +163,57 @@ def cpu_baseline_and_psnr(gs, torch, sc, cam, image_gpu, target_s):
     return base, psnr, mae, nsel
 
 
+def serve(gs, torch, args):
+    """Serving workload: 8 resident scenes (N = 0.5M..3M), requests of mixed resolution and pose.
+    A closed burst measures saturated throughput; then an open-loop Poisson stream at
+    `serve_load` of it gives p50/p99 latency (completion - scheduled arrival)."""
+    from paper_2605_17855_amd import scenes, server
+    log("serving: generating 8 resident scenes (0.5M..3M Gaussians)")
+    scs = scenes.serving_scenes()
+    dss = [gs.DeviceScene(s) for s in scs]
+    opt = gs.options(group=1, precision=args.precision, splits=args.splits)
+    # per-scene duplicated entries per pixel, from one 1080p render each
+    kpp = {}
+    for i, sc in enumerate(scs):
+        cam = scenes.random_pose(np.random.default_rng(900 + i), 1920, 1080)
+        r = gs.Renderer(sc.n, 1920, 1080)
+        kpp[i] = r.render(dss[i], cam, opt) / (1920 * 1080)
+        del r
+    torch.cuda.synchronize()
+    max_px = max(w * h for w, h in scenes.SERVE_RESOLUTIONS)
+    pool = int(args.serve_pool_gib * (1 << 30))
+    slots = 16
+
+    def run(reqs):
+        be = server.GpuBackend(dss, slots=slots, pool_bytes=pool, opt=opt, max_pixels=max_px,
+                               keys_per_pixel=kpp)
+        try:
+            st = server.Server(be, pool, slots=slots, max_batch=32).run(reqs)
+        finally:
+            be.close()
+        torch.cuda.synchronize()
+        return st
+
+    log("serving: warm-up")
+    run(scenes.serving_requests(64, rate_hz=1e7, seed=48))
+    log("serving: saturated burst of 1000 requests")
+    sat = run(scenes.serving_requests(1000, rate_hz=1e7, seed=47))
+    rate = args.serve_load * sat.frames_per_s
+    log(f"serving: saturated {sat.frames_per_s:.0f} frames/s; open loop at {rate:.0f} req/s, "
+        f"{args.serve_requests} requests")
+    st = run(scenes.serving_requests(args.serve_requests, rate_hz=rate, seed=49))
+    return {"workload": "8 resident scenes, N = linspace(0.5M, 3M), 64-cluster mixture, SH degree 3; "
+                        "resolution uniform over 640x360..2560x1440, poses on the radius-4 sphere",
+            "requests": args.serve_requests, "offered_rate_hz": rate, "load": args.serve_load,
+            "frames_per_s": st.frames_per_s, "p50_ms": st.latency_p50_ms, "p99_ms": st.latency_p99_ms,
+            "mean_ms": st.latency_mean_ms, "saturated_frames_per_s": sat.frames_per_s,
+            "saturated_p99_ms": sat.latency_p99_ms, "completed": st.completed, "failed": st.failed,
+            "retries": st.retries, "batches": st.batches, "mean_batch": st.mean_batch,
+            "max_inflight_jobs": st.max_inflight_jobs, "pool_bytes": pool,
+            "max_reserved_bytes": st.max_reserved_bytes, "slots": slots,
+            "precision": args.precision, "resident_gaussians": int(sum(s.n for s in scs))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -167,6 +225,10 @@ def main():
         return
     import torch
     from paper_2605_17855_amd import gs, scenes
+
+    if args.serve_only:
+        print(json.dumps({"serving": serve(gs, torch, args)}), flush=True)
+        return
 
     log("generating the 1M-Gaussian scene")
     sc, _ = scenes.clustered_1m()
@@ -213,6 +275,10 @@ def main():
         log("FP64 oracle: CPU baseline and PSNR on sampled tiles")
         cpu, psnr, mae, _ = cpu_baseline_and_psnr(gs, torch, sc, cams[0], first_img, args.cpu_seconds)
 
+    serving = None
+    if not args.no_serve:
+        serving = serve(gs, torch, args)
+
     line = {
         "metric": METRIC, "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
@@ -231,6 +297,7 @@ def main():
         "raster_speedup_vs_fp32": (compare["raster_avg_ms"] / float(np.mean(raster_ms))) if compare else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

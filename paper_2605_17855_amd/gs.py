@@ -209,6 +209,19 @@ class Bins:
         b.ranges = _ptr(self.ranges)
         self.struct = b
 
+    @classmethod
+    def from_tensors(cls, keys, vals, masks, ranges, capacity: int) -> "Bins":
+        """Bins over caller-provided device tensors (e.g. views of a memory pool)."""
+        self = cls.__new__(cls)
+        self.capacity = int(capacity)
+        self.keys, self.vals, self.masks, self.ranges = keys, vals, masks, ranges
+        b = gs_bins()
+        b.keys, b.vals, b.masks = _ptr(keys), _ptr(vals), _ptr(masks)
+        b.capacity = self.capacity
+        b.ranges = _ptr(ranges)
+        self.struct = b
+        return self
+
 
 def gs_preprocess(scene: DeviceScene, cam, opt: gs_options, proj: Projected, ws, stream=None):
     _check(lib().gs_preprocess(C.byref(scene.struct), C.byref(camera(cam)), C.byref(opt), C.byref(proj.struct),
@@ -216,9 +229,14 @@ def gs_preprocess(scene: DeviceScene, cam, opt: gs_options, proj: Projected, ws,
 
 
 def gs_bin_sort(proj: Projected, cam, opt: gs_options, bins: Bins, ws, stream=None) -> int:
+    """Returns the entry count; raises GsError (status GS_ERR_CAPACITY with .n_keys) when bins is too small."""
     n_keys = C.c_uint64(0)
-    _check(lib().gs_bin_sort(C.byref(proj.struct), proj.n, C.byref(camera(cam)), C.byref(opt), C.byref(bins.struct),
-                             C.byref(n_keys), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+    st = lib().gs_bin_sort(C.byref(proj.struct), proj.n, C.byref(camera(cam)), C.byref(opt), C.byref(bins.struct),
+                           C.byref(n_keys), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
+    if st != GS_OK:
+        err = GsError(st, lib().gs_last_error().decode())
+        err.n_keys = int(n_keys.value)
+        raise err
     return int(n_keys.value)
 
 
