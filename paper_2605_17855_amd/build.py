@@ -22,8 +22,11 @@ HEADERS = ["gs_internal.hpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC,
-    # packed FP32 instructions stay off (see the build notes in the design document)
+    # no packed FP32 (v_pk_*_f32) instructions are formed from float code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: no AGPR read-back before the lane swaps, and the
+    # rasterizer's register budget is not split between the two files
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-result",
 ]
 

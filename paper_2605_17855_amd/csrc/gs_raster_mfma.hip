@@ -246,6 +246,7 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
                                                 short8 B21) {
   constexpr int NT = G * G;
   constexpr int RS = (S == 3) ? 32 : 16;
+  constexpr int kTileUnroll = G == 4 ? 1 : NT;
   const int gx = bin % J.GX, gy = bin / J.GX;
   const int ox = gx * G * kTile, oy = gy * G * kTile;
   const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
@@ -334,7 +335,9 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
         nk[k] = c0 + c1 + c2 + c3;
         woff[k] = (w > 0 ? c0 : 0) + (w > 1 ? c1 : 0) + (w > 2 ? c2 : 0);
       }
-#pragma unroll
+      // G = 2: fully unrolled, all state in registers.  G = 4: one copy of the step; the
+      // sixteen tiles' state lives in private memory and the step works on a register copy
+#pragma unroll kTileUnroll
       for (int k = 0; k < NT; ++k) {
         if (!((alive_mask >> k) & 1u) || nk[k] == 0) continue;
         const int buf = it & 1;
@@ -356,9 +359,11 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
                                sm.alive[(it - 1) & 1][3];
           if (!any) alive_mask &= ~(1u << last_k);
         }
-        process_rows<PREC, S, AUX>(sm.A[buf], sm.col[buf], (int)nk[k], B0, B1, B20, B21, st[k], rows_done[k]);
+        TileState cur = st[k];
+        process_rows<PREC, S, AUX>(sm.A[buf], sm.col[buf], (int)nk[k], B0, B1, B20, B21, cur, rows_done[k]);
+        st[k] = cur;
         rows_done[k] += nk[k];
-        const uint64_t ab = __ballot(st[k].cut != INFINITY);
+        const uint64_t ab = __ballot(cur.cut != INFINITY);
         if (lane == 0) sm.alive[it & 1][w] = ab != 0;
         last_k = k;
         ++it;

@@ -109,7 +109,9 @@ class Server:
             # admission: FIFO, a slot and pool room for the head of the queue
             while pending and free_slots:
                 job = pending[0]
-                need = job.reserve_hint or be.estimate_bytes(job)
+                # an estimate above the pool is tried at the pool's size; only an exact size
+                # (known after a first attempt) can reject the request
+                need = job.reserve_hint or min(be.estimate_bytes(job), self.pool)
                 if need > self.pool:
                     pending.popleft()
                     job.failed = f"needs {need} bytes, pool is {self.pool}"
@@ -118,6 +120,15 @@ class Server:
                     progressed = True
                     continue
                 if reserved + need > self.pool or not be.try_reserve(job, need):
+                    if reserved == 0:
+                        # nothing is held, so nothing will be released: the request can never
+                        # be placed (the backend refused a reservation within the pool)
+                        pending.popleft()
+                        job.failed = f"backend could not reserve {need} bytes in an empty pool"
+                        job.t_done = now - t_start
+                        done += 1
+                        progressed = True
+                        continue
                     break
                 pending.popleft()
                 job.slot = free_slots.pop()
@@ -202,8 +213,10 @@ def entry_capacity(reserve: int, n_gaussians: int, pixels: int) -> int:
 class FakeBackend:
     """Virtual-clock backend: scripted entry counts and durations (no GPU)."""
 
-    def __init__(self, scene_sizes, keys_fn, est_fn=None, prepare_s=lambda j: 1e-3, raster_s=lambda js: 2e-3):
+    def __init__(self, scene_sizes, keys_fn, est_fn=None, prepare_s=lambda j: 1e-3, raster_s=lambda js: 2e-3,
+                 arena_bytes: Optional[int] = None):
         self.scene_sizes = list(scene_sizes)
+        self.arena = _Arena(arena_bytes) if arena_bytes is not None else None   # as the GPU backend places them
         self.keys_fn = keys_fn            # job -> true entry count
         self.est_fn = est_fn or keys_fn   # job -> estimated entry count
         self.prepare_s = prepare_s
@@ -223,6 +236,12 @@ class FakeBackend:
         return job_bytes(self.scene_sizes[job.scene], n_keys, job.width * job.height)
 
     def try_reserve(self, job, need):
+        if self.arena is None:
+            return True
+        off = self.arena.alloc(need)
+        if off is None:
+            return False
+        job.payload = off
         return True
 
     def _push(self, dt, kind, payload):
@@ -244,6 +263,8 @@ class FakeBackend:
         for _, _, _, job in self._due("prepared"):
             k = self.keys_fn(job)
             cap = entry_capacity(job.reserve, self.scene_sizes[job.scene], job.width * job.height)
+            if k > cap:
+                self.release(job)
             res.append((job, k, k <= cap))
         return res
 
@@ -258,7 +279,9 @@ class FakeBackend:
         return [h for _, _, _, h in self._due("raster")]
 
     def release(self, job):
-        pass
+        if self.arena is not None and job.payload is not None:
+            self.arena.release(job.payload, job.reserve)
+            job.payload = None
 
     def wait(self, until):
         nxt = self.events[0][0] if self.events else None
@@ -271,8 +294,11 @@ class _Arena:
     """First-fit allocator of byte ranges inside one device buffer (the memory pool)."""
 
     def __init__(self, nbytes: int, align: int = 256):
+        # sized to the pool rounded up to the alignment, so that any single reservation
+        # of at most `nbytes` fits an empty arena
         self.align = align
-        self.free = [(0, nbytes)]
+        self.size = (int(nbytes) + align - 1) // align * align
+        self.free = [(0, self.size)]
 
     def alloc(self, size: int) -> Optional[int]:
         size = (size + self.align - 1) // self.align * self.align
@@ -311,10 +337,11 @@ class GpuBackend:
         self.scenes = device_scenes
         self.opt = opt
         self.safety = safety
-        self.kpp = dict(keys_per_pixel)      # per-scene calibration, raised by observed counts
+        self.kpp = dict(keys_per_pixel)      # per-scene calibration
+        self.kpp_seen = {}                   # (scene, width, height) -> largest observed entries/pixel
         self.lock = threading.Lock()
-        self.arena_buf = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
         self.arena = _Arena(pool_bytes)
+        self.arena_buf = torch.empty(self.arena.size, dtype=torch.uint8, device="cuda")
         nmax = max(s.n for s in device_scenes)
         self.slot_state = []
         for _ in range(slots):
@@ -334,8 +361,11 @@ class GpuBackend:
         return time.perf_counter() - self.t0
 
     def estimate_bytes(self, job):
+        # entries per pixel fall as the resolution grows (a splat's tile count grows slower
+        # than its pixel area), so observations are kept per resolution
         px = job.width * job.height
-        return job_bytes(self.scenes[job.scene].n, self.safety * self.kpp[job.scene] * px, px)
+        kpp = self.kpp_seen.get((job.scene, job.width, job.height), self.kpp[job.scene])
+        return job_bytes(self.scenes[job.scene].n, self.safety * kpp * px, px)
 
     def exact_bytes(self, job, n_keys):
         return job_bytes(self.scenes[job.scene].n, int(n_keys * 1.02) + 1024, job.width * job.height)
@@ -414,8 +444,8 @@ class GpuBackend:
         for f in self.futures:
             if f.done():
                 job, n_keys, ok = f.result()
-                with self.lock:   # the exact count, also from a failed attempt, refines the estimate
-                    self.kpp[job.scene] = max(self.kpp[job.scene], n_keys / (job.width * job.height))
+                key = (job.scene, job.width, job.height)   # exact counts, also of failed attempts
+                self.kpp_seen[key] = max(self.kpp_seen.get(key, 0.0), n_keys / (job.width * job.height))
                 if not ok:
                     self.release(job)
                 out.append((job, n_keys, ok))

@@ -50,6 +50,8 @@ def test_serving_rejects_request_larger_than_pool():
     scs = scenes.serving_scenes(count=2, scale=0.02)
     dss = [gs.DeviceScene(s) for s in scs]
     reqs = scenes.serving_requests(6, rate_hz=1e5, n_scenes=2, seed=50, resolutions=((320, 180),))
+    for r in reqs:
+        r.scene = 1                                            # the larger scene only
     opt = gs.options(group=1, precision="fp16", splits=2)
     pool = server.job_bytes(scs[1].n, 0, 320 * 180) + 4096    # room for per-Gaussian scratch only
     be = server.GpuBackend(dss, slots=4, pool_bytes=pool, opt=opt, max_pixels=320 * 180,
@@ -61,3 +63,4 @@ def test_serving_rejects_request_larger_than_pool():
         be.close()
     torch.cuda.synchronize()
     assert st.failed == 6 and st.completed == 0
+    assert st.retries == 6          # each tried once at the pool's size, then rejected on its exact size

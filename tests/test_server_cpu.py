@@ -11,7 +11,9 @@ def make_requests(times, n_scenes=2, size=(64, 64)):
 
 
 def run(times, pool, slots=4, keys=lambda j: 1000, est=None, prep=1e-3, rast=2e-3, scene_n=(1000, 2000), **kw):
-    be = server.FakeBackend(scene_n, keys, est, prepare_s=lambda j: prep, raster_s=lambda js: rast)
+    # reservations are placed in an arena of the pool's size, as on the device
+    be = server.FakeBackend(scene_n, keys, est, prepare_s=lambda j: prep, raster_s=lambda js: rast,
+                            arena_bytes=pool)
     srv = server.Server(be, pool, slots=slots, **kw)
     st = srv.run(make_requests(times, len(scene_n)))
     return st, be
@@ -116,3 +118,31 @@ def test_request_generator_is_open_loop_poisson():
     assert np.mean(gaps) == pytest.approx(1e-3, rel=0.1)
     assert set(r.scene for r in reqs) == set(range(8))
     assert set((r.width, r.height) for r in reqs) == set(scenes.SERVE_RESOLUTIONS)
+
+
+def test_estimate_above_pool_is_tried_not_rejected():
+    # the estimate overshoots the pool; the exact size fits, so the request must complete
+    pool = server.job_bytes(2000, 1000, 64 * 64) * 2
+    st, be = run(np.linspace(0, 0.01, 6), pool=pool, slots=4, keys=lambda j: 1000, est=lambda j: 10**8)
+    assert st.completed == 6 and st.failed == 0
+    # each request reserves the whole pool, which holds its entries: one at a time, no retries
+    assert st.retries == 0 and st.max_inflight_jobs == 1
+    assert st.max_reserved_bytes == pool
+
+
+def test_unaligned_pool_with_oversized_estimates_terminates():
+    # a pool that is not a multiple of the arena alignment, estimates above it and exact sizes
+    # above it too: every request is tried once at the pool's size, then rejected
+    pool = server.job_bytes(2000, 0, 320 * 180) + 4096 + 7
+    st, be = run(np.linspace(0, 0.01, 6), pool=pool, slots=4, keys=lambda j: 10**6, est=lambda j: 10**6)
+    assert st.completed == 0 and st.failed == 6
+    assert st.retries == 6
+
+
+def test_reservation_refused_in_empty_pool_fails_the_request():
+    class Refusing(server.FakeBackend):
+        def try_reserve(self, job, need):
+            return job.rid != 2 and super().try_reserve(job, need)
+    be = Refusing((1000, 2000), lambda j: 1000, prepare_s=lambda j: 1e-3, raster_s=lambda js: 1e-3)
+    st = server.Server(be, 10**9, slots=1).run(make_requests(np.linspace(0, 0.01, 5)))
+    assert st.completed == 4 and st.failed == 1
