@@ -21,7 +21,6 @@ namespace {
 
 struct PreArgs {
   int64_t n;
-  int deg;
   const float *mean, *log_scale, *quat, *opacity, *sh;
   double R[9], t[3];
   float Rf[9];
@@ -43,14 +42,15 @@ struct PreArgs {
 //   l=1: sqrt(3/(4 pi))
 //   l=2: sqrt(15/(4 pi)), sqrt(5/(16 pi)), sqrt(15/(16 pi))
 //   l=3: sqrt(35/(32 pi)), sqrt(105/(4 pi)), sqrt(21/(32 pi)), sqrt(7/(16 pi)), sqrt(105/(16 pi))
-__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float *b) {
+template <int DEG>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float *b) {
   b[0] = 0.28209479177387814f;
-  if (deg < 1) return;
+  if (DEG < 1) return;
   const float c1 = 0.4886025119029199f;
   b[1] = -c1 * y;
   b[2] = c1 * z;
   b[3] = -c1 * x;
-  if (deg < 2) return;
+  if (DEG < 2) return;
   const float xx = x * x, yy = y * y, zz = z * z;
   const float xy = x * y, yz = y * z, xz = x * z;
   b[4] = 1.0925484305920792f * xy;
@@ -58,7 +58,7 @@ __device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, flo
   b[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);
   b[7] = -1.0925484305920792f * xz;
   b[8] = 0.5462742152960396f * (xx - yy);
-  if (deg < 3) return;
+  if (DEG < 3) return;
   b[9] = -0.5900435899266435f * y * (3.0f * xx - yy);
   b[10] = 2.890611442640554f * xy * z;
   b[11] = -0.4570457994644658f * y * (5.0f * zz - 1.0f);
@@ -68,7 +68,13 @@ __device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, flo
   b[15] = -0.5900435899266435f * x * (xx - 3.0f * yy);
 }
 
+// The SH degree is a template argument so that every coefficient load of a lane is issued
+// before the first multiply-add uses one (a runtime-bounded loop would wait on each load in
+// turn).  The per-Gaussian parameters are loaded before the near-plane test for the same
+// reason: one round trip to memory instead of two.
+template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
+  constexpr int NB = (DEG + 1) * (DEG + 1);
   const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= a.n) return;
   const int64_t n = a.n;
@@ -76,14 +82,16 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
   ushort4 rc = make_ushort4(0, 0, 0, 0);
 
   const double px = a.mean[g], py = a.mean[n + g], pz = a.mean[2 * n + g];
+  const float ls0 = a.log_scale[g], ls1 = a.log_scale[n + g], ls2 = a.log_scale[2 * n + g];
+  float qw = a.quat[g], qx = a.quat[n + g], qy = a.quat[2 * n + g], qz = a.quat[3 * n + g];
+  const float opac = a.opacity[g];
   const double tx = fma(a.R[0], px, fma(a.R[1], py, fma(a.R[2], pz, a.t[0])));
   const double ty = fma(a.R[3], px, fma(a.R[4], py, fma(a.R[5], pz, a.t[1])));
   const double tz = fma(a.R[6], px, fma(a.R[7], py, fma(a.R[8], pz, a.t[2])));
 
   if (tz > a.znear) {
     // scales and rotation
-    const float s0 = expf(a.log_scale[g]), s1 = expf(a.log_scale[n + g]), s2 = expf(a.log_scale[2 * n + g]);
-    float qw = a.quat[g], qx = a.quat[n + g], qy = a.quat[2 * n + g], qz = a.quat[3 * n + g];
+    const float s0 = expf(ls0), s1 = expf(ls1), s2 = expf(ls2);
     const float qi = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
     qw *= qi; qx *= qi; qy *= qi; qz *= qi;
     const float M[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
@@ -141,18 +149,21 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
         float dx = (float)px - a.campos[0], dy = (float)py - a.campos[1], dz = (float)pz - a.campos[2];
         const float di = rsqrtf(dx * dx + dy * dy + dz * dz);
         dx *= di; dy *= di; dz *= di;
+        float coef[NB * 3];
+#pragma unroll
+        for (int k = 0; k < NB * 3; ++k) coef[k] = a.sh[(int64_t)k * n + g];
         float b[16];
-        sh_basis(a.deg, dx, dy, dz, b);
-        const int nb = (a.deg + 1) * (a.deg + 1);
+        sh_basis<DEG>(dx, dy, dz, b);
         float col[3];
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
           float acc = 0.0f;
-          for (int k = 0; k < nb; ++k) acc = fmaf(a.sh[((int64_t)k * 3 + ch) * n + g], b[k], acc);
+#pragma unroll
+          for (int k = 0; k < NB; ++k) acc = fmaf(coef[k * 3 + ch], b[k], acc);
           col[ch] = fmaxf(acc + 0.5f, 0.0f);
         }
         a.xy[g] = make_double2(mx, my);
-        a.conic[g] = make_float4(ca, cb, cc, a.opacity[g]);
+        a.conic[g] = make_float4(ca, cb, cc, opac);
         a.rgb[g] = make_float4(col[0], col[1], col[2], tzf);
       }
     }
@@ -329,7 +340,6 @@ hipError_t launch_preprocess(const gs_scene &s, const gs_camera &c, const Grid &
   if (s.n == 0) return hipSuccess;
   PreArgs a;
   a.n = s.n;
-  a.deg = s.sh_degree;
   a.mean = s.mean;
   a.log_scale = s.log_scale;
   a.quat = s.quat;
@@ -354,7 +364,13 @@ hipError_t launch_preprocess(const gs_scene &s, const gs_camera &c, const Grid &
   a.rect = reinterpret_cast<ushort4 *>(o.rect);
   a.count = o.count;
   const unsigned blocks = (unsigned)((s.n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(kBlock), 0, st, a);
+  switch (s.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3(blocks), dim3(kBlock), 0, st, a); break;
+    case 1: hipLaunchKernelGGL(k_preprocess<1>, dim3(blocks), dim3(kBlock), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_preprocess<2>, dim3(blocks), dim3(kBlock), 0, st, a); break;
+    case 3: hipLaunchKernelGGL(k_preprocess<3>, dim3(blocks), dim3(kBlock), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
