@@ -161,24 +161,27 @@ gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
                       const gs_bins *bins, uint64_t *n_keys, void *ws, hipStream_t st) {
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
   const Workspace w = carve(ws, n, bins->capacity);
+  // the one host synchronization: entry count K and visible count V (V sizes the depth sort)
   uint64_t K = 0;
+  uint32_t V = 0;
   GS_HIP(hipMemcpyAsync(&K, proj->offset + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  GS_HIP(hipMemcpyAsync(&V, proj->n_visible, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   GS_HIP(hipStreamSynchronize(st));
   *n_keys = K;
   if (K > bins->capacity)
     return fail(GS_ERR_CAPACITY, "%llu entries exceed capacity %llu", (unsigned long long)K,
                 (unsigned long long)bins->capacity);
   if (K >= (1ull << 32)) return fail(GS_ERR_UNSUPPORTED, "%llu entries >= 2^32", (unsigned long long)K);
-  const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
+  if ((int64_t)V > n) return fail(GS_ERR_INVALID_ARG, "visible count %u exceeds n", V);
   // low key digits (depth bits) on the visible Gaussians; also zeroes the bin ranges
   bool in_alt = false;
-  GS_HIP(gsi::sort_depth(proj->order, reinterpret_cast<const float4 *>(proj->rgb), proj->n_visible, nn, w.dkey,
-                         w.dkey_alt, w.dval_alt, w.sort, bins->ranges, 2 * (uint64_t)g.nbins, st, &in_alt));
-  if (in_alt) GS_HIP(hipMemcpyAsync(proj->order, w.dval_alt, nn * 4, hipMemcpyDeviceToDevice, st));
+  GS_HIP(gsi::sort_depth(proj->order, reinterpret_cast<const float4 *>(proj->rgb), V, w.dkey, w.dkey_alt, w.dval_alt,
+                         w.sort, bins->ranges, 2 * (uint64_t)g.nbins, st, &in_alt));
+  if (in_alt && V > 0) GS_HIP(hipMemcpyAsync(proj->order, w.dval_alt, (size_t)V * 4, hipMemcpyDeviceToDevice, st));
   // first entry of each Gaussian in depth order, then one thread per entry and the bin digits
-  GS_HIP(gsi::launch_scan_gather(proj->count, proj->order, w.dpos, (int64_t)nn, proj->n_visible, w.scan, st));
-  GS_HIP(gsi::bin_and_sort(proj->order, w.dpos, proj->n_visible, K, proj->rect, g, w.bkey, bins->vals, w.bkey_alt,
-                           w.bval_alt, w.sort, st, &in_alt));
+  GS_HIP(gsi::launch_scan_gather(proj->count, proj->order, w.dpos, (int64_t)V, nullptr, w.scan, st));
+  GS_HIP(gsi::bin_and_sort(proj->order, w.dpos, V, K, proj->rect, g, w.bkey, bins->vals, w.bkey_alt, w.bval_alt,
+                           w.sort, st, &in_alt));
   const uint32_t *kf = in_alt ? w.bkey_alt : w.bkey;
   if (in_alt && K > 0) GS_HIP(hipMemcpyAsync(bins->vals, w.bval_alt, K * 4, hipMemcpyDeviceToDevice, st));
   GS_HIP(gsi::launch_ranges(kf, bins->vals, K, proj->rect, proj->rgb, g, bins->ranges,

@@ -100,16 +100,16 @@ size_t radix_tmp_bytes(uint64_t n);
 // reports in *in_alt whether the result ended in the alternate buffers.
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
                       int hi, void *tmp, hipStream_t st, bool *in_alt);
-// Sorts the visible list order[0..*nvis) by depth bits (4 passes, stable), using keys/keys_alt/
-// vals_alt (n_max each) as scratch; also zeroes ranges[0..nranges).
-hipError_t sort_depth(uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max, uint32_t *keys,
-                      uint32_t *keys_alt, uint32_t *vals_alt, void *tmp, uint32_t *ranges, uint64_t nranges,
-                      hipStream_t st, bool *in_alt);
-// Entries of the depth-ordered visible Gaussians (Gaussian i's first entry at dpos[i]) into
+// Sorts the visible list order[0..V) by depth bits (4 passes, stable), using keys/keys_alt/
+// vals_alt (V each) as scratch; also zeroes ranges[0..nranges).
+hipError_t sort_depth(uint32_t *order, const float4 *rgb, uint32_t V, uint32_t *keys, uint32_t *keys_alt,
+                      uint32_t *vals_alt, void *tmp, uint32_t *ranges, uint64_t nranges, hipStream_t st,
+                      bool *in_alt);
+// Entries of the V depth-ordered visible Gaussians (Gaussian i's first entry at dpos[i]) into
 // (bkey, bval), then a stable sort on the bin bits.
-hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, const uint32_t *nvis, uint64_t K,
-                        const uint16_t *rect, const Grid &g, uint32_t *bkey, uint32_t *bval, uint32_t *bkey_alt,
-                        uint32_t *bval_alt, void *tmp, hipStream_t st, bool *in_alt);
+hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V, uint64_t K, const uint16_t *rect,
+                        const Grid &g, uint32_t *bkey, uint32_t *bval, uint32_t *bkey_alt, uint32_t *bval_alt,
+                        void *tmp, hipStream_t st, bool *in_alt);
 // Bin ranges (zeroed before), masks (group > 1) and the 64-bit keys of the sorted entries.
 hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *vals, uint64_t n, const uint16_t *rect,
                          const float *rgb, const Grid &g, uint32_t *ranges, uint16_t *masks, uint64_t *keys,

@@ -30,14 +30,18 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint64_t n, ui
 }
 
 // ---- radix sort --------------------------------------------------------------
-// Workgroup tile: 4 waves x 8 rounds x 64 lanes = 2048 keys.  Wave w owns the contiguous
-// sub-tile [w*512, (w+1)*512) and walks it in rounds of 64 consecutive keys, so
-// (wave, round, lane) order is input order and per-digit ranks are stable.
-constexpr int kRounds = 8;
-constexpr int kWaveTile = kRounds * 64;
-constexpr int kSortTile = 4 * kWaveTile;
+// Workgroup tile: 4 waves x R rounds x 64 lanes.  Wave w owns the contiguous sub-tile
+// [w*64R, (w+1)*64R) and walks it in rounds of 64 consecutive keys, so (wave, round, lane)
+// order is input order and per-digit ranks are stable.  Small sorts use R = 2 (512-key
+// tiles, so that they still spread over every CU); large ones R = 8 (2048 keys).
 constexpr int kDigits = 256;
-constexpr int kMaxPasses = 8;
+constexpr uint64_t kSmallSort = 1ull << 20;   // sorts up to this size use 512-key tiles
+template <int R>
+struct SortTile {
+  static constexpr int kRounds = R;
+  static constexpr int kWaveTile = R * 64;
+  static constexpr int kTile = 4 * kWaveTile;
+};
 
 // lanes of the wave holding the same digit as this lane (among lanes with valid keys)
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nbits) {
@@ -52,13 +56,13 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nbit
 
 // Per-tile digit counts: counts[d * tiles + tile].  Keys are loaded up front (8 in flight
 // per lane) and each wave adds one LDS atomic per distinct digit.
-template <typename KT>
-__global__ __launch_bounds__(kBlock) void k_radix_count(const KT *keys, uint64_t n_host, const uint32_t *n_dev,
-                                                        int shift, int nbits, uint32_t tiles_max, uint32_t *counts) {
+template <typename KT, int R>
+__global__ __launch_bounds__(kBlock) void k_radix_count(const KT *keys, uint64_t n, int shift, int nbits,
+                                                        uint32_t tiles_max, uint32_t *counts) {
+  constexpr int kRounds = SortTile<R>::kRounds, kWaveTile = SortTile<R>::kWaveTile, kSortTile = SortTile<R>::kTile;
   __shared__ uint32_t h[kDigits];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   h[t] = 0;
-  const uint64_t n = n_dev ? (uint64_t)*n_dev : n_host;
   const uint32_t dmask = (1u << nbits) - 1u;
   const uint64_t lt = (1ull << lane) - 1ull;
   const uint64_t base = (uint64_t)blockIdx.x * kSortTile + (uint64_t)w * kWaveTile;
@@ -113,20 +117,18 @@ __global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t *counts, u
 // Stable scatter of one tile: ranks from per-wave digit counters; the tile's start for digit
 // d is (keys with a smaller digit) + offsets[d][tile]; keys are placed in LDS in tile-local
 // digit order and then stored so that consecutive lanes write consecutive addresses.
-template <typename KT>
+template <typename KT, int R>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const uint32_t *vin, KT *kout, uint32_t *vout,
-                                                          uint64_t n_host, const uint32_t *n_dev, int shift, int nbits,
-                                                          uint32_t tiles_max, const uint32_t *offsets,
-                                                          const uint32_t *totals) {
+                                                          uint64_t n, int shift, int nbits, uint32_t tiles_max,
+                                                          const uint32_t *offsets, const uint32_t *totals) {
+  constexpr int kRounds = SortTile<R>::kRounds, kWaveTile = SortTile<R>::kWaveTile, kSortTile = SortTile<R>::kTile;
   __shared__ uint32_t wcnt[4][kDigits];
   __shared__ uint32_t bstart[kDigits];
   __shared__ uint32_t gbase[kDigits];
   __shared__ KT s_key[kSortTile];
   __shared__ uint32_t s_val[kSortTile];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const uint64_t n = n_dev ? (uint64_t)*n_dev : n_host;
   const uint64_t tile0 = (uint64_t)blockIdx.x * kSortTile;
-  if (tile0 >= n) return;
   const uint32_t dmask = (1u << nbits) - 1u;
   const uint64_t lt = (1ull << lane) - 1ull;
   const uint64_t base = tile0 + (uint64_t)w * kWaveTile;
@@ -204,13 +206,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
 
 // Depth keys of the visible Gaussians (key[i] = bits(depth of order[i]), i < *nvis), and the
 // zeroing of the bin ranges.
-__global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis,
+__global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, const float4 *rgb, uint32_t V,
                                                        uint32_t *keys, uint32_t *ranges, uint64_t nranges) {
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < nranges; i += stride) ranges[i] = 0u;
-  const uint32_t V = *nvis;
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < V) keys[i] = __float_as_uint(rgb[order[i]].w);
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < V; i += stride)
+    keys[i] = __float_as_uint(rgb[order[i]].w);
 }
 
 // ---- binning: one thread per entry -------------------------------------------
@@ -221,12 +222,11 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, co
 // entry finds its Gaussian by binary search there.
 constexpr int kBinItems = 1024;
 
-__global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const uint64_t *dpos, const uint32_t *nvis_p,
+__global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const uint64_t *dpos, uint32_t nvis,
                                                     uint64_t K, const ushort4 *rect, int G, int GX,
                                                     uint32_t *bin_keys, uint32_t *vals) {
   __shared__ uint64_t s_pos[kBinItems + 1];
   __shared__ uint32_t s_first;
-  const uint32_t nvis = *nvis_p;
   const uint64_t e0 = (uint64_t)blockIdx.x * kBinItems;
   const int t = threadIdx.x, lane = t & 63;
   if (t < 64) {
@@ -313,28 +313,32 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) 
 
 int radix_passes(int lo, int hi) { return hi > lo ? (hi - lo + 7) / 8 : 0; }
 
+// tiles of a sort of n keys, and the most tiles of any sort of at most n keys
+inline uint64_t sort_tiles(uint64_t n) {
+  return n <= kSmallSort ? (n + SortTile<2>::kTile - 1) / SortTile<2>::kTile
+                         : (n + SortTile<8>::kTile - 1) / SortTile<8>::kTile;
+}
+
 size_t radix_tmp_bytes(uint64_t n) {
-  const uint64_t tiles = (n + kSortTile - 1) / kSortTile;
+  uint64_t tiles = sort_tiles(n < kSmallSort ? n : kSmallSort);
+  if (sort_tiles(n) > tiles) tiles = sort_tiles(n);
   return ((size_t)kDigits * (tiles ? tiles : 1) + kDigits) * sizeof(uint32_t);
 }
 
-template <typename KT>
-hipError_t radix_passes_t(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n_max,
-                          const uint32_t *n_dev, int lo, int hi, void *tmp, hipStream_t st, bool *in_alt) {
-  *in_alt = false;
-  if (hi <= lo || n_max == 0) return hipSuccess;
-  const uint32_t tiles = (uint32_t)((n_max + kSortTile - 1) / kSortTile);
+template <typename KT, int R>
+hipError_t radix_passes_r(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n, int lo, int hi,
+                          void *tmp, hipStream_t st, bool *in_alt) {
+  const uint32_t tiles = (uint32_t)((n + SortTile<R>::kTile - 1) / SortTile<R>::kTile);
   uint32_t *counts = static_cast<uint32_t *>(tmp);
   uint32_t *totals = counts + (uint64_t)kDigits * tiles;
   KT *kin = keys, *kout = keys_alt;
   uint32_t *vin = vals, *vout = vals_alt;
   for (int shift = lo; shift < hi; shift += 8) {
     const int bits = (hi - shift) < 8 ? (hi - shift) : 8;
-    hipLaunchKernelGGL((k_radix_count<KT>), dim3(tiles), dim3(kBlock), 0, st, kin, n_max, n_dev, shift, bits, tiles,
-                       counts);
+    hipLaunchKernelGGL((k_radix_count<KT, R>), dim3(tiles), dim3(kBlock), 0, st, kin, n, shift, bits, tiles, counts);
     hipLaunchKernelGGL(k_radix_digit_scan, dim3(kDigits), dim3(kBlock), 0, st, counts, tiles, totals);
-    hipLaunchKernelGGL((k_radix_scatter<KT>), dim3(tiles), dim3(kBlock), 0, st, kin, vin, kout, vout, n_max, n_dev,
-                       shift, bits, tiles, counts, totals);
+    hipLaunchKernelGGL((k_radix_scatter<KT, R>), dim3(tiles), dim3(kBlock), 0, st, kin, vin, kout, vout, n, shift,
+                       bits, tiles, counts, totals);
     std::swap(kin, kout);
     std::swap(vin, vout);
     *in_alt = !*in_alt;
@@ -342,31 +346,38 @@ hipError_t radix_passes_t(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals
   return hipGetLastError();
 }
 
+template <typename KT>
+hipError_t radix_passes_t(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n, int lo, int hi,
+                          void *tmp, hipStream_t st, bool *in_alt) {
+  *in_alt = false;
+  if (hi <= lo || n <= 1) return hipSuccess;
+  if (n <= kSmallSort) return radix_passes_r<KT, 2>(keys, vals, keys_alt, vals_alt, n, lo, hi, tmp, st, in_alt);
+  return radix_passes_r<KT, 8>(keys, vals, keys_alt, vals_alt, n, lo, hi, tmp, st, in_alt);
+}
+
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
                       int hi, void *tmp, hipStream_t st, bool *in_alt) {
-  *in_alt = false;
-  if (n <= 1) return hipSuccess;
-  return radix_passes_t<uint64_t>(keys, vals, keys_alt, vals_alt, n, nullptr, lo, hi, tmp, st, in_alt);
+  return radix_passes_t<uint64_t>(keys, vals, keys_alt, vals_alt, n, lo, hi, tmp, st, in_alt);
 }
 
-hipError_t sort_depth(uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max, uint32_t *keys,
-                      uint32_t *keys_alt, uint32_t *vals_alt, void *tmp, uint32_t *ranges, uint64_t nranges,
-                      hipStream_t st, bool *in_alt) {
-  hipLaunchKernelGGL(k_depth_keys, dim3(grid_for(n_max)), dim3(kBlock), 0, st, order, rgb, nvis, keys, ranges,
-                     nranges);
-  return radix_passes_t<uint32_t>(keys, order, keys_alt, vals_alt, n_max, nvis, 0, 32, tmp, st, in_alt);
+hipError_t sort_depth(uint32_t *order, const float4 *rgb, uint32_t V, uint32_t *keys, uint32_t *keys_alt,
+                      uint32_t *vals_alt, void *tmp, uint32_t *ranges, uint64_t nranges, hipStream_t st,
+                      bool *in_alt) {
+  const uint64_t m = V > nranges ? V : nranges;
+  const unsigned blocks = grid_for(m) < 8192u ? grid_for(m) : 8192u;   // grid-stride beyond
+  hipLaunchKernelGGL(k_depth_keys, dim3(blocks), dim3(kBlock), 0, st, order, rgb, V, keys, ranges, nranges);
+  return radix_passes_t<uint32_t>(keys, order, keys_alt, vals_alt, V, 0, 32, tmp, st, in_alt);
 }
 
-hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, const uint32_t *nvis, uint64_t K,
-                        const uint16_t *rect, const Grid &g, uint32_t *bkey, uint32_t *bval, uint32_t *bkey_alt,
-                        uint32_t *bval_alt, void *tmp, hipStream_t st, bool *in_alt) {
+hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V, uint64_t K, const uint16_t *rect,
+                        const Grid &g, uint32_t *bkey, uint32_t *bval, uint32_t *bkey_alt, uint32_t *bval_alt,
+                        void *tmp, hipStream_t st, bool *in_alt) {
   *in_alt = false;
   if (K == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_binning, dim3(grid_for(K, kBinItems)), dim3(kBlock), 0, st, order, dpos, nvis, K,
+  hipLaunchKernelGGL(k_binning, dim3(grid_for(K, kBinItems)), dim3(kBlock), 0, st, order, dpos, V, K,
                      reinterpret_cast<const ushort4 *>(rect), g.G, g.GX, bkey, bval);
   if (K <= 1) return hipGetLastError();
-  return radix_passes_t<uint32_t>(bkey, bval, bkey_alt, bval_alt, K, nullptr, 0, bits_for((uint64_t)g.nbins), tmp, st,
-                                  in_alt);
+  return radix_passes_t<uint32_t>(bkey, bval, bkey_alt, bval_alt, K, 0, bits_for((uint64_t)g.nbins), tmp, st, in_alt);
 }
 
 hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *vals, uint64_t n, const uint16_t *rect,
