@@ -121,6 +121,30 @@ def lists(rec: dict, cam, group: int = 1):
     return start, ids[:total], masks[:total]
 
 
+def tile_lists(rec: dict, cam, tiles):
+    """The tile lists of `lists(rec, cam, 1)` for the tiles in `tiles` only, as the same CSR
+    layout with every other tile empty (Background, Gaussian sorting: a tile's list holds
+    the visible Gaussians whose tile rectangle contains it, ordered by depth, ties by index).
+    Written in numpy from the definition, for workloads whose full lists are too large."""
+    tx, ty, _, _ = grid(cam, 1)
+    vis = np.nonzero(rec["visible"])[0]
+    vis = vis[np.lexsort((vis, rec["depth"][vis]))]
+    rect = rec["rect"][vis]
+    counts = np.zeros(tx * ty, np.int64)
+    per = {}
+    for t in np.unique(np.asarray(tiles, np.int64)):
+        x, y = int(t % tx), int(t // tx)
+        inside = (rect[:, 0] <= x) & (x < rect[:, 2]) & (rect[:, 1] <= y) & (y < rect[:, 3])
+        per[int(t)] = vis[inside]
+        counts[t] = per[int(t)].size
+    start = np.zeros(tx * ty + 1, np.int64)
+    start[1:] = np.cumsum(counts)
+    ids = np.zeros(max(int(start[-1]), 1), np.int64)
+    for t, g in per.items():
+        ids[start[t]:start[t + 1]] = g
+    return start, ids[:int(start[-1])]
+
+
 def ambiguous_membership(rec: dict, cam):
     """Per tile, the Gaussians whose membership flips inside the footprint-edge (1e-3 px) or
     near-plane (1e-6) guard band.  Returns CSR (start, ids)."""

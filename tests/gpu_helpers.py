@@ -3,6 +3,7 @@ import sys
 
 import numpy as np
 
+from oracle import oracle
 from paper_2605_17855_amd import gs
 
 
@@ -57,3 +58,56 @@ def tile_mask(cam, tiles):
         x, y = (t % tx) * 16, (t // tx) * 16
         m[y:y + 16, x:x + 16] = True
     return m
+
+
+def sampled_tiles(cam, count, seed):
+    tx, ty = (cam.width + 15) // 16, (cam.height + 15) // 16
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(tx * ty, size=min(count, tx * ty), replace=False))
+
+
+def check_bins(rec, cam, r, n_keys, group):
+    b = bins_numpy(r, n_keys)
+    keys, vals = b["keys"], b["vals"]
+    # ascending keys; key = (bin << 32) | float bits of the GPU depth of its Gaussian
+    assert np.all(keys[1:] >= keys[:-1])
+    gdepth = r.proj.rgb.cpu().numpy()[:, 3]
+    assert np.array_equal(keys & np.uint64(0xFFFFFFFF), gdepth[vals].view(np.uint32).astype(np.uint64))
+    # stable: equal keys keep Gaussian-index order
+    same = keys[1:] == keys[:-1]
+    assert np.all(vals[1:][same] > vals[:-1][same])
+    # ranges equal a linear scan of the sorted keys
+    bins_of = (keys >> np.uint64(32)).astype(np.int64)
+    nb = gs.gs_num_bins(cam, group)
+    want = np.zeros((nb, 2), np.int64)
+    if n_keys:
+        starts = np.r_[0, np.nonzero(bins_of[1:] != bins_of[:-1])[0] + 1]
+        ends = np.r_[starts[1:], n_keys]
+        want[bins_of[starts], 0] = starts
+        want[bins_of[starts], 1] = ends
+    assert np.array_equal(b["ranges"][:nb].astype(np.int64), want)
+    # entries against the oracle's lists (footprint-edge ambiguous Gaussians excluded)
+    st, ids, masks = oracle.lists(rec, cam, group)
+    amb = (rec["flags"] & (oracle.AMB_ZNEAR | oracle.AMB_EDGES)) != 0
+    ob = np.repeat(np.arange(nb), np.diff(st))
+    keep_o = ~amb[ids]
+    keep_g = ~amb[vals]
+    assert np.array_equal(ob[keep_o], bins_of[keep_g])
+    og, gg = ids[keep_o], vals[keep_g].astype(np.int64)
+    mismatch = np.nonzero(og != gg)[0]
+    # order may differ only between Gaussians at (nearly) equal depth
+    for i in mismatch:
+        za, zb = rec["depth"][og[i]], rec["depth"][gg[i]]
+        assert abs(za - zb) <= 1e-6 * za, (i, og[i], gg[i])
+    # the visible list after sorting: every visible Gaussian once, ordered by (depth bits, index)
+    V = int(r.proj.n_visible.cpu().numpy()[0])
+    order = r.proj.order.cpu().numpy().view(np.uint32)[:V].astype(np.int64)
+    count = r.proj.count.cpu().numpy().view(np.uint32)
+    assert np.array_equal(np.sort(order), np.nonzero(count[: r.proj.n])[0])
+    dbits = gdepth.view(np.uint32)[order]
+    assert np.all((dbits[1:] > dbits[:-1]) | ((dbits[1:] == dbits[:-1]) & (order[1:] > order[:-1])))
+    if group > 1:
+        gm = b["masks"][keep_g].astype(np.uint32)
+        om = masks[keep_o]
+        ok = og == gg
+        assert np.array_equal(gm[ok], om[ok])

@@ -298,6 +298,31 @@ def test_lists_sorted_by_depth_then_index():
         assert np.array_equal(ids[start[t]:start[t + 1]], want)
 
 
+def test_tile_lists_equal_full_lists_on_their_tiles():
+    # the numpy per-tile builder against the C list builder: every tile of the small workload,
+    # and sampled tiles of a world-space scene (all other tiles empty)
+    sc, cam = scenes.small_camera_space()
+    rec = oracle.preprocess(sc, cam)
+    start, ids, _ = oracle.lists(rec, cam, 1)
+    tx, ty, _, _ = oracle.grid(cam)
+    s2, i2 = oracle.tile_lists(rec, cam, np.arange(tx * ty))
+    assert np.array_equal(start, s2) and np.array_equal(ids, i2)
+    sc = scenes.clustered_scene(60_000, seed=31, clusters=16)
+    cam = scenes.look_at([3.0, -2.0, 1.0], 640, 360)
+    rec = oracle.preprocess(sc, cam)
+    start, ids, _ = oracle.lists(rec, cam, 1)
+    tx, ty, _, _ = oracle.grid(cam)
+    tiles = np.random.default_rng(5).choice(tx * ty, 60, replace=False)
+    s2, i2 = oracle.tile_lists(rec, cam, tiles)
+    assert int(s2[-1]) > 1000
+    for t in range(tx * ty):
+        seg = i2[s2[t]:s2[t + 1]]
+        if t in set(tiles.tolist()):
+            assert np.array_equal(seg, ids[start[t]:start[t + 1]])
+        else:
+            assert seg.size == 0
+
+
 @pytest.mark.parametrize("G", [2, 4])
 def test_group_lists_filter_to_tile_lists(G):
     # Filtering a depth-sorted group list by a member tile's mask bit gives that tile's list.
