@@ -14,6 +14,7 @@ batching; p50/p99 latency of an open-loop Poisson stream) under "serving".
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-serve]
        python bench.py --serve-only [--serve-requests R] [--serve-load F]
+       python bench.py --sweep [--sweep-steps K]
 """
 from __future__ import annotations
 
@@ -56,6 +57,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered rate / saturated throughput")
     ap.add_argument("--serve-pool-gib", type=float, default=4.0)
+    ap.add_argument("--sweep", action="store_true",
+                    help="only the sensitivity sweep: 3M at 1080p/2160p and dense 6M, groups 1/2/4, all precisions")
+    ap.add_argument("--sweep-steps", type=int, default=30)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times), for HBM counter calibration")
     return ap.parse_args()
@@ -87,7 +91,7 @@ def timed_frames(gs, torch, ds, cams, rend, opt, steps, warmup):
             ev[2].record(st)
 
     # make sure the entry buffers are large enough for every pose (grows outside the timed region)
-    for cam in cams[:max(warmup, 1)]:
+    for cam in cams[:max(steps, warmup, 1)]:
         rend.render(ds, cam, opt)
     for i in range(warmup):
         frame(cams[i % len(cams)], None)
@@ -214,6 +218,40 @@ def serve(gs, torch, args):
             "precision": args.precision, "resident_gaussians": int(sum(s.n for s in scs))}
 
 
+def sweep(gs, torch, args):
+    """Frame rate of every (precision, tile group) variant on the sensitivity and stress
+    workloads, with the entry counts behind the load reduction 1 - K(G)/K(1)."""
+    from paper_2605_17855_amd import scenes
+    work = [("3M Gaussians, 256 clusters, 1920x1080", lambda: scenes.clustered_3m(width=1920, height=1080), 1920, 1080, 3),
+            ("3M Gaussians, 256 clusters, 3840x2160", lambda: scenes.clustered_3m(width=3840, height=2160), 3840, 2160, 3),
+            ("dense 6M Gaussians, log-scale N(ln 0.05, 0.5), opacity sigmoid(N(-1,1)), 1920x1080",
+             lambda: scenes.dense_6m(), 1920, 1080, 5)]
+    rows, lr = [], []
+    for name, make, w, h, seed in work:
+        log(f"sweep: {name}")
+        sc, _ = make()
+        ds = gs.DeviceScene(sc)
+        cams = scenes.orbit(max(args.sweep_steps, 1), w, h, seed=seed)
+        keys = {}
+        for group in (1, 2, 4):
+            rend = gs.Renderer(sc.n, w, h, group=group)
+            for prec in ("fp32", "fp16", "bf16"):
+                splits = 3 if prec == "bf16" else 2
+                opt = gs.options(group=group, precision=prec, splits=splits)
+                el, fm, rm = timed_frames(gs, torch, ds, cams, rend, opt, args.sweep_steps, 3)
+                rows.append({"workload": name, "precision": prec, "splits": splits, "group": group,
+                             "frames_per_s": args.sweep_steps / el, "p99_ms": float(np.percentile(fm, 99)),
+                             "raster_avg_ms": float(np.mean(rm))})
+                log(f"  G{group} {prec}: {rows[-1]['frames_per_s']:.1f} frames/s, raster {rows[-1]['raster_avg_ms']:.3f} ms")
+            keys[group] = np.mean([rend.render(ds, c, gs.options(group=group)) for c in cams[:5]])
+            del rend
+        lr.append({"workload": name, "entries": {str(g): float(k) for g, k in keys.items()},
+                   "load_reduction": {str(g): 1.0 - keys[g] / keys[1] for g in (2, 4)}})
+        del ds
+        torch.cuda.empty_cache()
+    return {"rows": rows, "load_reduction": lr, "steps": args.sweep_steps}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -228,6 +266,9 @@ def main():
 
     if args.serve_only:
         print(json.dumps({"serving": serve(gs, torch, args)}), flush=True)
+        return
+    if args.sweep:
+        print(json.dumps({"sweep": sweep(gs, torch, args)}), flush=True)
         return
 
     log("generating the 1M-Gaussian scene")

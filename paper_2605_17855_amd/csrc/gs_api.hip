@@ -177,14 +177,15 @@ gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
   bool in_alt = false;
   GS_HIP(gsi::sort_depth(proj->order, reinterpret_cast<const float4 *>(proj->rgb), V, w.dkey, w.dkey_alt, w.dval_alt,
                          w.sort, bins->ranges, 2 * (uint64_t)g.nbins, st, &in_alt));
+  const uint32_t *dkeys = in_alt ? w.dkey_alt : w.dkey;   // depth bits in depth order
   if (in_alt && V > 0) GS_HIP(hipMemcpyAsync(proj->order, w.dval_alt, (size_t)V * 4, hipMemcpyDeviceToDevice, st));
   // first entry of each Gaussian in depth order, then one thread per entry and the bin digits
   GS_HIP(gsi::launch_scan_gather(proj->count, proj->order, w.dpos, (int64_t)V, nullptr, w.scan, st));
   GS_HIP(gsi::bin_and_sort(proj->order, w.dpos, V, K, proj->rect, g, w.bkey, bins->vals, w.bkey_alt, w.bval_alt,
                            w.sort, st, &in_alt));
   const uint32_t *kf = in_alt ? w.bkey_alt : w.bkey;
-  if (in_alt && K > 0) GS_HIP(hipMemcpyAsync(bins->vals, w.bval_alt, K * 4, hipMemcpyDeviceToDevice, st));
-  GS_HIP(gsi::launch_ranges(kf, bins->vals, K, proj->rect, proj->rgb, g, bins->ranges,
+  const uint32_t *ranks = in_alt ? w.bval_alt : bins->vals;
+  GS_HIP(gsi::launch_ranges(kf, ranks, K, proj->order, dkeys, proj->rect, g, bins->vals, bins->ranges,
                             opt->group > 1 ? bins->masks : nullptr, bins->keys, st));
   return GS_OK;
 }

@@ -105,15 +105,17 @@ hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32
 hipError_t sort_depth(uint32_t *order, const float4 *rgb, uint32_t V, uint32_t *keys, uint32_t *keys_alt,
                       uint32_t *vals_alt, void *tmp, uint32_t *ranges, uint64_t nranges, hipStream_t st,
                       bool *in_alt);
-// Entries of the V depth-ordered visible Gaussians (Gaussian i's first entry at dpos[i]) into
-// (bkey, bval), then a stable sort on the bin bits.
+// Entries of the V depth-ordered visible Gaussians (the i-th one's first entry at dpos[i])
+// into (bkey, bval = the Gaussian's rank i in depth order), then a stable sort on the bin bits.
 hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V, uint64_t K, const uint16_t *rect,
                         const Grid &g, uint32_t *bkey, uint32_t *bval, uint32_t *bkey_alt, uint32_t *bval_alt,
                         void *tmp, hipStream_t st, bool *in_alt);
-// Bin ranges (zeroed before), masks (group > 1) and the 64-bit keys of the sorted entries.
-hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *vals, uint64_t n, const uint16_t *rect,
-                         const float *rgb, const Grid &g, uint32_t *ranges, uint16_t *masks, uint64_t *keys,
-                         hipStream_t st);
+// Bin ranges (zeroed before), masks (group > 1), the 64-bit keys and the Gaussian indices
+// (vals[i] = order[ranks[i]]; ranks may alias vals) of the sorted entries; dkeys[r] are the
+// depth bits of the r-th Gaussian in depth order.
+hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n, const uint32_t *order,
+                         const uint32_t *dkeys, const uint16_t *rect, const Grid &g, uint32_t *vals, uint32_t *ranges,
+                         uint16_t *masks, uint64_t *keys, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
 
 // ---- rasterizers -------------------------------------------------------------

@@ -260,37 +260,44 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
         const uint32_t mid = (lo + hi) >> 1;
         if (s_pos[mid] <= e) lo = mid; else hi = mid;
       }
-      const uint32_t g = order[first + lo];
+      const uint32_t rank = first + lo;
+      const uint32_t g = order[rank];
       const uint32_t j = (uint32_t)(e - s_pos[lo]);
       const ushort4 r = rect[g];
       const int gx0 = r.x / G, gx1 = (r.z - 1) / G, gy0 = r.y / G;
       const int wdt = gx1 - gx0 + 1;
       const int gy = gy0 + (int)(j / (uint32_t)wdt), gx = gx0 + (int)(j % (uint32_t)wdt);
       bin_keys[e] = (uint32_t)(gy * GX + gx);
-      vals[e] = g;
+      vals[e] = rank;   // the Gaussian's rank in depth order; k_ranges turns it into its index
     }
   }
 }
 
-// Bin ranges (zeroed beforehand), tile-membership masks and the 64-bit keys.
-__global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, const uint32_t *vals, uint64_t n,
-                                                   const ushort4 *rect, const float4 *rgb, int G, int GX,
-                                                   uint32_t *ranges, uint16_t *masks, uint64_t *keys) {
+// Bin ranges (zeroed beforehand), tile-membership masks and the 64-bit keys.  Entry i holds
+// its Gaussian's rank r in the depth-sorted visible list; the Gaussian index order[r] and the
+// depth bits dkeys[r] come from those two V-sized arrays (cache-resident), not from the
+// per-Gaussian records.
+__global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n,
+                                                   const uint32_t *order, const uint32_t *dkeys, const ushort4 *rect,
+                                                   int G, int GX, uint32_t *vals, uint32_t *ranges, uint16_t *masks,
+                                                   uint64_t *keys) {
   const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const uint32_t bin = bin_keys[i];
-  const uint32_t g = vals[i];
+  const uint32_t r = ranks[i];
+  const uint32_t g = order[r];
   if (i == 0 || bin_keys[i - 1] != bin) ranges[2 * (uint64_t)bin] = (uint32_t)i;
   if (i == n - 1 || bin_keys[i + 1] != bin) ranges[2 * (uint64_t)bin + 1] = (uint32_t)(i + 1);
-  keys[i] = ((uint64_t)bin << 32) | __float_as_uint(rgb[g].w);
+  keys[i] = ((uint64_t)bin << 32) | dkeys[r];
+  vals[i] = g;
   if (G > 1 && masks) {
-    const ushort4 r = rect[g];
+    const ushort4 rc = rect[g];
     const int gx = (int)(bin % (uint32_t)GX), gy = (int)(bin / (uint32_t)GX);
     uint32_t m = 0;
     for (int ly = 0; ly < G; ++ly)
       for (int lx = 0; lx < G; ++lx) {
         const int tx = gx * G + lx, ty = gy * G + ly;
-        if (tx >= r.x && tx < r.z && ty >= r.y && ty < r.w) m |= 1u << (ly * G + lx);
+        if (tx >= rc.x && tx < rc.z && ty >= rc.y && ty < rc.w) m |= 1u << (ly * G + lx);
       }
     masks[i] = (uint16_t)m;
   }
@@ -380,13 +387,12 @@ hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V,
   return radix_passes_t<uint32_t>(bkey, bval, bkey_alt, bval_alt, K, 0, bits_for((uint64_t)g.nbins), tmp, st, in_alt);
 }
 
-hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *vals, uint64_t n, const uint16_t *rect,
-                         const float *rgb, const Grid &g, uint32_t *ranges, uint16_t *masks, uint64_t *keys,
-                         hipStream_t st) {
+hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n, const uint32_t *order,
+                         const uint32_t *dkeys, const uint16_t *rect, const Grid &g, uint32_t *vals, uint32_t *ranges,
+                         uint16_t *masks, uint64_t *keys, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ranges, dim3(grid_for(n)), dim3(kBlock), 0, st, bin_keys, vals, n,
-                     reinterpret_cast<const ushort4 *>(rect), reinterpret_cast<const float4 *>(rgb), g.G, g.GX,
-                     ranges, masks, keys);
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for(n)), dim3(kBlock), 0, st, bin_keys, ranks, n, order, dkeys,
+                     reinterpret_cast<const ushort4 *>(rect), g.G, g.GX, vals, ranges, masks, keys);
   return hipGetLastError();
 }
 
