@@ -36,6 +36,34 @@ FLOPS_PER_EVAL = 14
 FLOPS_PER_BLEND = 9
 PEAK_FP32_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (packed) x 2 (FMA) x 2.4 GHz
 
+# HBM bytes per launch of the rasterizer on this workload (FP16, splits 2, 1x1 groups): rocprofv3
+# FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by what the same counters read for a plain
+# device copy of known size (x2 and x1).  They describe the kernel built from the source and
+# compiler flags hashed in `sha256`; after any change to either the traffic is reported as null.
+RASTER_COUNTERS = dict(sha256="50798a1122752d11cf4b596e5020215fc57c5576ffa66d91d494ee7052f9d41f",
+                       fetch_kib=55225, write_kib=25204, fetch_scale=2.0, write_scale=1.0,
+                       precision="fp16", splits=2, group=1)
+
+
+def raster_source_hash():
+    import hashlib
+    from paper_2605_17855_amd import build
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2605_17855_amd", "csrc", "gs_raster_mfma.hip"), "rb") as f:
+        h.update(f.read())
+    h.update(" ".join(f for f in build.FLAGS if not os.path.isabs(f)).encode())
+    return h.hexdigest()
+
+
+def raster_traffic(args):
+    """Measured HBM bytes per launch, or None when they do not describe this kernel and workload."""
+    c = RASTER_COUNTERS
+    if (args.precision, args.splits, args.group) != (c["precision"], c["splits"], c["group"]):
+        return None
+    if raster_source_hash() != c["sha256"]:
+        return None
+    return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -293,7 +321,7 @@ def main():
     flops = FLOPS_PER_EVAL * e_pix + FLOPS_PER_BLEND * blend
     achieved = flops / raster_total_s / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": raster_traffic(args),
                 "kernel": f"k_raster_mfma (precision {args.precision}, splits {args.splits}, group {args.group})"
                           if args.precision != "fp32" else "k_raster_fp32",
                 "avg_launch_ms": float(np.mean(raster_ms)),
