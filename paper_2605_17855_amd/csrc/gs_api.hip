@@ -105,6 +105,7 @@ struct Workspace {
   uint32_t *bkey;        // bin key of each entry (capacity)
   uint32_t *bkey_alt;    // bin sort double buffer (capacity)
   uint32_t *bval_alt;    // (capacity)
+  uint64_t *counts;      // {K, V}: packed for the one device-to-host copy
   size_t total;
 };
 
@@ -127,6 +128,7 @@ Workspace carve(void *ws, int64_t n, uint64_t capacity) {
   w.bkey = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
   w.bkey_alt = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
   w.bval_alt = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
+  w.counts = reinterpret_cast<uint64_t *>(take(2 * sizeof(uint64_t)));
   w.total = off;
   return w;
 }
@@ -162,11 +164,12 @@ gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
   const Workspace w = carve(ws, n, bins->capacity);
   // the one host synchronization: entry count K and visible count V (V sizes the depth sort)
-  uint64_t K = 0;
-  uint32_t V = 0;
-  GS_HIP(hipMemcpyAsync(&K, proj->offset + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-  GS_HIP(hipMemcpyAsync(&V, proj->n_visible, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  uint64_t kv[2] = {0, 0};
+  GS_HIP(gsi::launch_pack_counts(proj->offset + n, proj->n_visible, w.counts, st));
+  GS_HIP(hipMemcpyAsync(kv, w.counts, sizeof(kv), hipMemcpyDeviceToHost, st));
   GS_HIP(hipStreamSynchronize(st));
+  const uint64_t K = kv[0];
+  const uint32_t V = (uint32_t)kv[1];
   *n_keys = K;
   if (K > bins->capacity)
     return fail(GS_ERR_CAPACITY, "%llu entries exceed capacity %llu", (unsigned long long)K,

@@ -117,6 +117,8 @@ hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64
                          const uint32_t *dkeys, const uint16_t *rect, const Grid &g, uint32_t *vals, uint32_t *ranges,
                          uint16_t *masks, uint64_t *keys, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
+// out[0] = *K, out[1] = *V (one thread): the entry and visible counts side by side
+hipError_t launch_pack_counts(const uint64_t *K, const uint32_t *V, uint64_t *out, hipStream_t st);
 
 // ---- rasterizers -------------------------------------------------------------
 struct RasterJob {

@@ -179,8 +179,11 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
 // Optionally the values are gathered through an index list (v[i] = in[idx[i]]), the indices
 // with v[i] > 0 are compacted in index order (the visible list), and n is read from device
 // memory (the grid covers an upper bound).
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kBlock * kScanItems;
+// Items per thread: 4 for scans of up to 2^20 values (1,024-value tiles, so that small scans
+// still spread over every CU), 16 above that.
+constexpr int64_t kSmallScan = 1ll << 20;
+template <int ITEMS>
+constexpr int64_t scan_tile() { return (int64_t)kBlock * ITEMS; }
 
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T v) {
@@ -212,7 +215,7 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *sh4, T *total) {
   return before + incl - v;
 }
 
-template <bool GATHER>
+template <bool GATHER, int kScanItems>
 __device__ __forceinline__ void load_items(const uint32_t *in, const uint32_t *idx, int64_t base, int64_t n,
                                            uint32_t *v) {
   if (!GATHER && base + kScanItems <= n && ((base & 3) == 0)) {
@@ -228,15 +231,16 @@ __device__ __forceinline__ void load_items(const uint32_t *in, const uint32_t *i
   for (int i = 0; i < kScanItems; ++i) v[i] = (base + i < n) ? (GATHER ? in[idx[base + i]] : in[base + i]) : 0u;
 }
 
-template <bool GATHER, bool COMPACT>
+template <bool GATHER, bool COMPACT, int kScanItems>
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *in, const uint32_t *idx, int64_t n_host,
                                                         const uint32_t *n_dev, uint64_t *bsum, uint32_t *bvis) {
+  constexpr int64_t kScanTile = scan_tile<kScanItems>();
   __shared__ uint64_t sh[4];
   __shared__ uint32_t shv[4];
   const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
-  load_items<GATHER>(in, idx, base, n, v);
+  load_items<GATHER, kScanItems>(in, idx, base, n, v);
   uint64_t s = 0;
   uint32_t c = 0;
 #pragma unroll
@@ -282,17 +286,18 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(uint64_t *bsum, uint32_t *b
   }
 }
 
-template <bool GATHER, bool COMPACT>
+template <bool GATHER, bool COMPACT, int kScanItems>
 __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, const uint32_t *idx, int64_t n_host,
                                                       const uint32_t *n_dev, const uint64_t *bsum,
                                                       const uint32_t *bvis, uint64_t *out, uint32_t *order) {
+  constexpr int64_t kScanTile = scan_tile<kScanItems>();
   __shared__ uint64_t sh[4];
   __shared__ uint32_t shv[4];
   const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
   if ((int64_t)blockIdx.x * kScanTile >= n) return;
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
-  load_items<GATHER>(in, idx, base, n, v);
+  load_items<GATHER, kScanItems>(in, idx, base, n, v);
   uint64_t s = 0;
   uint32_t c = 0;
 #pragma unroll
@@ -317,20 +322,27 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, const 
   }
 }
 
-template <bool GATHER, bool COMPACT>
-hipError_t scan_impl(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n, const uint32_t *n_dev,
-                     uint32_t *order, uint32_t *nvis, void *tmp, hipStream_t st) {
-  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+template <bool GATHER, bool COMPACT, int ITEMS>
+hipError_t scan_impl_t(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n, const uint32_t *n_dev,
+                       uint32_t *order, uint32_t *nvis, void *tmp, hipStream_t st) {
+  const int64_t nb = (n + scan_tile<ITEMS>() - 1) / scan_tile<ITEMS>();
   uint64_t *bsum = static_cast<uint64_t *>(tmp);
   uint32_t *bvis = reinterpret_cast<uint32_t *>(bsum + (nb > 0 ? nb : 1));
   if (nb > 0)
-    hipLaunchKernelGGL((k_scan_reduce<GATHER, COMPACT>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx, n, n_dev,
-                       bsum, bvis);
+    hipLaunchKernelGGL((k_scan_reduce<GATHER, COMPACT, ITEMS>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx, n,
+                       n_dev, bsum, bvis);
   hipLaunchKernelGGL((k_scan_top<COMPACT>), dim3(1), dim3(kBlock), 0, st, bsum, bvis, nb, n, n_dev, out, nvis);
   if (nb > 0)
-    hipLaunchKernelGGL((k_scan_down<GATHER, COMPACT>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx, n, n_dev,
-                       bsum, bvis, out, order);
+    hipLaunchKernelGGL((k_scan_down<GATHER, COMPACT, ITEMS>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx, n,
+                       n_dev, bsum, bvis, out, order);
   return hipGetLastError();
+}
+
+template <bool GATHER, bool COMPACT>
+hipError_t scan_impl(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n, const uint32_t *n_dev,
+                     uint32_t *order, uint32_t *nvis, void *tmp, hipStream_t st) {
+  if (n <= kSmallScan) return scan_impl_t<GATHER, COMPACT, 4>(in, idx, out, n, n_dev, order, nvis, tmp, st);
+  return scan_impl_t<GATHER, COMPACT, 16>(in, idx, out, n, n_dev, order, nvis, tmp, st);
 }
 
 }  // namespace
@@ -375,7 +387,11 @@ hipError_t launch_preprocess(const gs_scene &s, const gs_camera &c, const Grid &
 }
 
 size_t scan_tmp_bytes(int64_t n) {
-  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  // the most tile sums of any scan of at most n values
+  const int64_t small = n < kSmallScan ? n : kSmallScan;
+  int64_t nb = (small + scan_tile<4>() - 1) / scan_tile<4>();
+  const int64_t nb_large = (n + scan_tile<16>() - 1) / scan_tile<16>();
+  if (nb_large > nb) nb = nb_large;
   return (size_t)((nb > 0 ? nb : 1) * (sizeof(uint64_t) + sizeof(uint32_t)) + 16);
 }
 

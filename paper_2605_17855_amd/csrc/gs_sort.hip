@@ -23,6 +23,13 @@
 namespace gsi {
 namespace {
 
+__global__ void k_pack_counts(const uint64_t *K, const uint32_t *V, uint64_t *out) {
+  if (threadIdx.x == 0) {
+    out[0] = *K;
+    out[1] = *V;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
   uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
@@ -276,30 +283,52 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
 // Bin ranges (zeroed beforehand), tile-membership masks and the 64-bit keys.  Entry i holds
 // its Gaussian's rank r in the depth-sorted visible list; the Gaussian index order[r] and the
 // depth bits dkeys[r] come from those two V-sized arrays (cache-resident), not from the
-// per-Gaussian records.
+// per-Gaussian records.  Each thread takes kRangeItems consecutive entries and issues all
+// their loads before the dependent gathers, so several round trips are in flight at once.
+constexpr int kRangeItems = 4;
+
 __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n,
                                                    const uint32_t *order, const uint32_t *dkeys, const ushort4 *rect,
                                                    int G, int GX, uint32_t *vals, uint32_t *ranges, uint16_t *masks,
                                                    uint64_t *keys) {
-  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t bin = bin_keys[i];
-  const uint32_t r = ranks[i];
-  const uint32_t g = order[r];
-  if (i == 0 || bin_keys[i - 1] != bin) ranges[2 * (uint64_t)bin] = (uint32_t)i;
-  if (i == n - 1 || bin_keys[i + 1] != bin) ranges[2 * (uint64_t)bin + 1] = (uint32_t)(i + 1);
-  keys[i] = ((uint64_t)bin << 32) | dkeys[r];
-  vals[i] = g;
-  if (G > 1 && masks) {
-    const ushort4 rc = rect[g];
-    const int gx = (int)(bin % (uint32_t)GX), gy = (int)(bin / (uint32_t)GX);
-    uint32_t m = 0;
-    for (int ly = 0; ly < G; ++ly)
-      for (int lx = 0; lx < G; ++lx) {
-        const int tx = gx * G + lx, ty = gy * G + ly;
-        if (tx >= rc.x && tx < rc.z && ty >= rc.y && ty < rc.w) m |= 1u << (ly * G + lx);
-      }
-    masks[i] = (uint16_t)m;
+  const uint64_t i0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * kRangeItems;
+  if (i0 >= n) return;
+  uint32_t bin[kRangeItems + 2], r[kRangeItems];
+  // bin[0] = key before the first item (or ~0), bin[kRangeItems + 1] = key after the last
+  bin[0] = i0 > 0 ? bin_keys[i0 - 1] : 0xFFFFFFFFu;
+#pragma unroll
+  for (int j = 0; j < kRangeItems; ++j) {
+    const bool in = i0 + j < n;
+    bin[j + 1] = in ? bin_keys[i0 + j] : 0xFFFFFFFFu;
+    r[j] = in ? ranks[i0 + j] : 0u;
+  }
+  bin[kRangeItems + 1] = i0 + kRangeItems < n ? bin_keys[i0 + kRangeItems] : 0xFFFFFFFFu;
+  uint32_t g[kRangeItems], d[kRangeItems];
+#pragma unroll
+  for (int j = 0; j < kRangeItems; ++j) {
+    g[j] = i0 + j < n ? order[r[j]] : 0u;
+    d[j] = i0 + j < n ? dkeys[r[j]] : 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < kRangeItems; ++j) {
+    const uint64_t i = i0 + j;
+    if (i >= n) break;
+    const uint32_t b = bin[j + 1];
+    if (bin[j] != b) ranges[2 * (uint64_t)b] = (uint32_t)i;
+    if (i == n - 1 || bin[j + 2] != b) ranges[2 * (uint64_t)b + 1] = (uint32_t)(i + 1);
+    keys[i] = ((uint64_t)b << 32) | d[j];
+    vals[i] = g[j];
+    if (G > 1 && masks) {
+      const ushort4 rc = rect[g[j]];
+      const int gx = (int)(b % (uint32_t)GX), gy = (int)(b / (uint32_t)GX);
+      uint32_t m = 0;
+      for (int ly = 0; ly < G; ++ly)
+        for (int lx = 0; lx < G; ++lx) {
+          const int tx = gx * G + lx, ty = gy * G + ly;
+          if (tx >= rc.x && tx < rc.z && ty >= rc.y && ty < rc.w) m |= 1u << (ly * G + lx);
+        }
+      masks[i] = (uint16_t)m;
+    }
   }
 }
 
@@ -315,6 +344,11 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) 
   uint64_t b = (n + kBlock - 1) / kBlock;
   if (b > 8192) b = 8192;
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)b), dim3(kBlock), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_counts(const uint64_t *K, const uint32_t *V, uint64_t *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_counts, dim3(1), dim3(64), 0, st, K, V, out);
   return hipGetLastError();
 }
 
@@ -391,7 +425,8 @@ hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64
                          const uint32_t *dkeys, const uint16_t *rect, const Grid &g, uint32_t *vals, uint32_t *ranges,
                          uint16_t *masks, uint64_t *keys, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ranges, dim3(grid_for(n)), dim3(kBlock), 0, st, bin_keys, ranks, n, order, dkeys,
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for(n, (uint64_t)kBlock * kRangeItems)), dim3(kBlock), 0, st, bin_keys,
+                     ranks, n, order, dkeys,
                      reinterpret_cast<const ushort4 *>(rect), g.G, g.GX, vals, ranges, masks, keys);
   return hipGetLastError();
 }
