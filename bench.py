@@ -220,7 +220,7 @@ def serve(gs, torch, args):
         be = server.GpuBackend(dss, slots=slots, pool_bytes=pool, opt=opt, max_pixels=max_px,
                                keys_per_pixel=kpp)
         try:
-            st = server.Server(be, pool, slots=slots, max_batch=32).run(reqs)
+            st = server.Server(be, pool, slots=slots, max_batch=32, max_inflight_batches=3).run(reqs)
         finally:
             be.close()
         torch.cuda.synchronize()

@@ -3,7 +3,7 @@
 Requests (scene, resolution, pose, scheduled arrival) enter a FIFO.  A request is
 admitted when a slot is free and its estimated memory (duplicated entries plus
 per-Gaussian scratch) fits the pool next to every reservation already held.  An
-admitted request runs preprocess + bin sort on its own stream; when its entries
+admitted request runs preprocess + bin sort on a preparation stream; when its entries
 are ready it joins the next batched raster launch, which renders every ready
 request in one persistent kernel while other requests keep preparing on their
 streams.  A request whose entry count exceeds its reservation gives the memory
@@ -51,6 +51,7 @@ class Job:
     t_done: float = math.nan
     failed: str = ""
     payload: object = None   # backend-owned (buffers, events)
+    cam: object = None       # backend-owned camera struct (built when the request is attached)
 
 
 @dataclasses.dataclass
@@ -86,6 +87,9 @@ class Server:
         be = self.backend
         reqs = sorted(requests, key=lambda r: r.arrival)
         jobs = [Job(r.rid, r.scene, r.width, r.height, np.asarray(r.position), r.arrival) for r in reqs]
+        if hasattr(be, "attach"):
+            be.attach(jobs)
+        max_inflight = min(self.max_inflight, getattr(be, "max_inflight", self.max_inflight))
         pending: collections.deque = collections.deque()
         ready: List[Job] = []
         inflight: Dict[object, List[Job]] = {}
@@ -155,7 +159,7 @@ class Server:
                     job.reserve_hint = be.exact_bytes(job, n_keys)
                     job.retries += 1
                     pending.appendleft(job)
-            while ready and len(inflight) < self.max_inflight:
+            while ready and len(inflight) < max_inflight:
                 batch = ready[: self.max_batch]
                 ready = ready[self.max_batch:]
                 handle = be.start_raster(batch)
@@ -324,16 +328,69 @@ class _Arena:
         self.free = merged
 
 
+class _Hip:
+    """The few HIP runtime calls the backend needs for its events (ctypes releases the GIL
+    while a call blocks, so a waiting thread never stalls the others)."""
+
+    def __init__(self):
+        import ctypes as C
+        self.C = C
+        self.lib = C.CDLL("libamdhip64.so")
+        for name, args in (("hipEventCreateWithFlags", [C.c_void_p, C.c_uint]),
+                           ("hipEventRecord", [C.c_void_p, C.c_void_p]),
+                           ("hipStreamWaitEvent", [C.c_void_p, C.c_void_p, C.c_uint]),
+                           ("hipEventSynchronize", [C.c_void_p]),
+                           ("hipEventDestroy", [C.c_void_p])):
+            f = getattr(self.lib, name)
+            f.argtypes = args
+            f.restype = C.c_int
+
+    def _ok(self, rc, what):
+        if rc != 0:
+            raise RuntimeError(f"{what} failed with HIP error {rc}")
+
+    def event(self):
+        ev = self.C.c_void_p()
+        self._ok(self.lib.hipEventCreateWithFlags(self.C.byref(ev), 0x2), "hipEventCreateWithFlags")  # no timing
+        return ev.value
+
+    def record(self, ev, stream):
+        self._ok(self.lib.hipEventRecord(ev, stream), "hipEventRecord")
+
+    def wait_event(self, stream, ev):
+        self._ok(self.lib.hipStreamWaitEvent(stream, ev, 0), "hipStreamWaitEvent")
+
+    def synchronize(self, ev):
+        self._ok(self.lib.hipEventSynchronize(ev), "hipEventSynchronize")
+
+    def destroy(self, ev):
+        self.lib.hipEventDestroy(ev)
+
+
 class GpuBackend:
-    """Drives the HIP library: per-slot streams for preprocess + sort, one stream for batched
-    raster launches; every request's entries and workspace live in one device arena."""
+    """Drives the HIP library: a few preparation streams for preprocess + sort (slots map onto
+    them round-robin) and one stream for batched raster launches; every request's entries and
+    workspace live in one device arena.  The stream count matches the process's hardware
+    queues (4 by default): more streams than queues would share queues, and in-order queues
+    would then hold a request's preparation, and the host synchronization inside it, behind
+    unrelated raster batches.
+
+    Host work per request is kept small: the camera struct is built when the request is
+    attached, buffers are raw pointers into the arena, and completions (a prepared request, a
+    finished raster launch) arrive through a queue that wakes the scheduler instead of being
+    polled."""
 
     def __init__(self, device_scenes, slots: int, pool_bytes: int, opt, max_pixels: int,
-                 keys_per_pixel: Dict[int, float], safety: float = 1.3, keep_results: bool = False):
+                 keys_per_pixel: Dict[int, float], safety: float = 1.3, keep_results: bool = False,
+                 prep_streams: int = 3, max_inflight_batches: int = 4):
+        import queue
         import torch
         from paper_2605_17855_amd import gs
         self.gs = gs
+        self.C = gs.C
+        self.L = gs.lib()
         self.torch = torch
+        self.hip = _Hip()
         self.scenes = device_scenes
         self.opt = opt
         self.safety = safety
@@ -342,23 +399,43 @@ class GpuBackend:
         self.lock = threading.Lock()
         self.arena = _Arena(pool_bytes)
         self.arena_buf = torch.empty(self.arena.size, dtype=torch.uint8, device="cuda")
+        self.base = self.arena_buf.data_ptr()
         nmax = max(s.n for s in device_scenes)
+        self.prep_streams = [torch.cuda.Stream() for _ in range(max(1, prep_streams))]
         self.slot_state = []
-        for _ in range(slots):
-            self.slot_state.append(dict(stream=torch.cuda.Stream(), proj=gs.Projected(nmax),
-                                        image=torch.empty(3 * max_pixels, dtype=torch.float32, device="cuda")))
+        for i in range(slots):
+            self.slot_state.append(dict(proj=gs.Projected(nmax),
+                                        image=torch.empty(3 * max_pixels, dtype=torch.float32, device="cuda"),
+                                        stream=self.prep_streams[i % len(self.prep_streams)],
+                                        event=self.hip.event()))
+        for st in self.slot_state:
+            st["stream_h"] = st["stream"].cuda_stream
+            st["image_ptr"] = st["image"].data_ptr()
         self.raster_stream = torch.cuda.Stream()
-        self.counters = [torch.zeros(1, dtype=torch.int32, device="cuda") for _ in range(8)]
+        self.raster_h = self.raster_stream.cuda_stream
+        self.max_inflight = max_inflight_batches
+        self.counters = torch.zeros(2 * max_inflight_batches, dtype=torch.int32, device="cuda")
         self.counter_i = 0
+        self.raster_events = [self.hip.event() for _ in range(2 * max_inflight_batches)]
         self.pool = cf.ThreadPoolExecutor(max_workers=slots)
-        self.futures = []
-        self.raster_events = []
+        self.done = queue.Queue()            # ("prepared", job, n_keys, ok) | ("raster", handle) | ("error", e)
+        self.pending = []
+        self.signal = threading.Event()
+        self.raster_fifo = queue.Queue()     # (handle, event) in launch order, for the waiter
+        self.waiter = threading.Thread(target=self._raster_waiter, daemon=True)
+        self.waiter.start()
         self.keep_results = keep_results
         self.results = {}                    # rid -> (3, H, W) image, when keep_results
         self.t0 = time.perf_counter()
 
     def now(self):
         return time.perf_counter() - self.t0
+
+    def attach(self, jobs):
+        """Per-request host work that belongs to the client: the camera struct of each pose."""
+        from paper_2605_17855_amd import scenes
+        for job in jobs:
+            job.cam = self.gs.camera(scenes.look_at(job.position, job.width, job.height))
 
     def estimate_bytes(self, job):
         # entries per pixel fall as the resolution grows (a splat's tile count grows slower
@@ -379,105 +456,128 @@ class GpuBackend:
         return True
 
     def _buffers(self, job, off):
-        """Bins and workspace views carved from the arena at `off`."""
-        gs = self.gs
+        """gs_bins and workspace carved from the arena at `off` (raw device pointers)."""
+        gs, C = self.gs, self.C
         n = self.scenes[job.scene].n
         cap = entry_capacity(job.reserve, n, job.width * job.height)
-        cam = self._camera(job)
         tx, ty = (job.width + 15) // 16, (job.height + 15) // 16
         g = self.opt.group
         nbins = ((tx + g - 1) // g) * ((ty + g - 1) // g)
-        ws_bytes = int(gs.lib().gs_workspace_bytes(n, cap, gs.C.byref(gs.camera(cam)), gs.C.byref(self.opt)))
-        buf = self.arena_buf
+        ws_bytes = int(self.L.gs_workspace_bytes(n, cap, C.byref(job.cam), C.byref(self.opt)))
         o = off
 
-        def take(nb, dtype, count):
+        def take(nb):
             nonlocal o
-            t = buf[o:o + nb].view(dtype)[:count]
+            ptr = self.base + o
             o += (nb + 255) // 256 * 256
-            return t
+            return ptr
 
         c = max(cap, 1)
-        torch = self.torch
-        keys = take(8 * c, torch.int64, c)
-        vals = take(4 * c, torch.int32, c)
-        masks = take(2 * c + 2, torch.int16, c)
-        ranges = take(8 * nbins, torch.int32, 2 * nbins).view(nbins, 2)
-        ws = take(ws_bytes, torch.uint8, ws_bytes)
+        b = gs.gs_bins()
+        b.keys = take(8 * c)
+        b.vals = take(4 * c)
+        b.masks = take(2 * c + 2)
+        b.capacity = cap
+        b.ranges = take(8 * nbins)
+        ws = take(ws_bytes)
         if o - off > job.reserve:
             raise RuntimeError("reservation layout overflow")
-        return gs.Bins.from_tensors(keys, vals, masks, ranges, cap), ws, cam
-
-    def _camera(self, job):
-        from paper_2605_17855_amd import scenes
-        return scenes.look_at(job.position, job.width, job.height)
+        return b, ws, ws_bytes
 
     def start_prepare(self, job):
-        self.futures.append(self.pool.submit(self._prepare, job))
+        self.pool.submit(self._prepare, job)
 
     def _prepare(self, job):
-        gs, torch = self.gs, self.torch
-        st = self.slot_state[job.slot]
-        bins, ws, cam = self._buffers(job, job.payload["off"])
-        job.payload.update(bins=bins, ws=ws, cam=cam)
-        ds = self.scenes[job.scene]
-        proj = st["proj"]
-        proj_n = gs.Projected.__new__(gs.Projected)
-        proj_n.__dict__.update(proj.__dict__)
-        proj_n.n = ds.n
-        with torch.cuda.stream(st["stream"]):
-            gs.gs_preprocess(ds, cam, self.opt, proj_n, ws, stream=st["stream"])
+        gs, C, L = self.gs, self.C, self.L
+        try:
+            st = self.slot_state[job.slot]
+            bins, ws, ws_bytes = self._buffers(job, job.payload["off"])
+            job.payload.update(bins=bins)
+            ds = self.scenes[job.scene]
+            proj = st["proj"].struct
+            rc = L.gs_preprocess(C.byref(ds.struct), C.byref(job.cam), C.byref(self.opt), C.byref(proj), ws,
+                                 ws_bytes, st["stream_h"])
+            if rc != gs.GS_OK:
+                raise gs.GsError(rc, L.gs_last_error().decode())
+            n_keys = C.c_uint64(0)
+            rc = L.gs_bin_sort(C.byref(proj), ds.n, C.byref(job.cam), C.byref(self.opt), C.byref(bins),
+                               C.byref(n_keys), ws, ws_bytes, st["stream_h"])
+            if rc == gs.GS_ERR_CAPACITY:
+                self.done.put(("prepared", job, int(n_keys.value), False))
+            elif rc != gs.GS_OK:
+                raise gs.GsError(rc, L.gs_last_error().decode())
+            else:
+                self.hip.record(st["event"], st["stream_h"])
+                self.done.put(("prepared", job, int(n_keys.value), True))
+        except BaseException as e:                 # surfaced by the scheduler thread
+            self.done.put(("error", e))
+        self.signal.set()
+
+    def _raster_waiter(self):
+        while True:
+            item = self.raster_fifo.get()
+            if item is None:
+                return
+            handle, ev = item
+            self.hip.synchronize(ev)
+            self.done.put(("raster", handle))
+            self.signal.set()
+
+    def _take(self, kind):
+        """Completions of one kind; the rest stay pending for the other poll."""
+        import queue
+        while True:
             try:
-                n_keys = gs.gs_bin_sort(proj_n, cam, self.opt, bins, ws, stream=st["stream"])
-            except gs.GsError as e:
-                if e.status != gs.GS_ERR_CAPACITY:
-                    raise
-                return job, int(getattr(e, "n_keys", 0)), False
-            ev = torch.cuda.Event()
-            ev.record(st["stream"])
-        job.payload.update(proj=proj_n, event=ev)
-        return job, n_keys, True
+                self.pending.append(self.done.get_nowait())
+            except queue.Empty:
+                break
+        out = [it for it in self.pending if it[0] == kind or it[0] == "error"]
+        self.pending = [it for it in self.pending if not (it[0] == kind or it[0] == "error")]
+        for it in out:
+            if it[0] == "error":
+                raise it[1]
+        return out
 
     def poll_prepared(self):
         out = []
-        keep = []
-        for f in self.futures:
-            if f.done():
-                job, n_keys, ok = f.result()
-                key = (job.scene, job.width, job.height)   # exact counts, also of failed attempts
-                self.kpp_seen[key] = max(self.kpp_seen.get(key, 0.0), n_keys / (job.width * job.height))
-                if not ok:
-                    self.release(job)
-                out.append((job, n_keys, ok))
-            else:
-                keep.append(f)
-        self.futures = keep
+        for _, job, n_keys, ok in self._take("prepared"):
+            key = (job.scene, job.width, job.height)   # exact counts, also of failed attempts
+            self.kpp_seen[key] = max(self.kpp_seen.get(key, 0.0), n_keys / (job.width * job.height))
+            if not ok:
+                self.release(job)
+            out.append((job, n_keys, ok))
         return out
 
     def start_raster(self, jobs):
-        gs, torch = self.gs, self.torch
-        rs = self.raster_stream
-        items = []
-        for j in jobs:
-            rs.wait_event(j.payload["event"])
-            img = self.slot_state[j.slot]["image"][: 3 * j.width * j.height]
-            items.append((j.payload["proj"], j.payload["bins"], j.payload["cam"], img, None))
-        counter = self.counters[self.counter_i % len(self.counters)]
+        gs, C = self.gs, self.C
+        arr = (gs.gs_job * len(jobs))()
+        for i, j in enumerate(jobs):
+            st = self.slot_state[j.slot]
+            self.hip.wait_event(self.raster_h, st["event"])
+            arr[i].proj = C.pointer(st["proj"].struct)
+            arr[i].bins = C.pointer(j.payload["bins"])
+            arr[i].cam = j.cam
+            arr[i].image = st["image_ptr"]
+            arr[i].aux = None
+        k = self.counter_i % len(self.raster_events)
         self.counter_i += 1
-        gs.gs_rasterize_batch(items, self.opt, counter, stream=rs)
+        rc = self.L.gs_rasterize_batch(arr, len(jobs), C.byref(self.opt), self.counters[k:].data_ptr(),
+                                       self.raster_h)
+        if rc != gs.GS_OK:
+            raise gs.GsError(rc, self.L.gs_last_error().decode())
         if self.keep_results:
-            with torch.cuda.stream(rs):
-                for j, it in zip(jobs, items):
-                    self.results[j.rid] = it[3].view(3, j.height, j.width).clone()
-        ev = torch.cuda.Event()
-        ev.record(rs)
-        self.raster_events.append(ev)
-        return ev
+            with self.torch.cuda.stream(self.raster_stream):
+                for j in jobs:
+                    img = self.slot_state[j.slot]["image"][: 3 * j.width * j.height]
+                    self.results[j.rid] = img.view(3, j.height, j.width).clone()
+        ev = self.raster_events[k]
+        self.hip.record(ev, self.raster_h)
+        handle = ("batch", self.counter_i)
+        self.raster_fifo.put((handle, ev))
+        return handle
 
     def poll_rasters(self):
-        out = [e for e in self.raster_events if e.query()]
-        self.raster_events = [e for e in self.raster_events if e not in out]
-        return out
+        return [it[1] for it in self._take("raster")]
 
     def release(self, job):
         if job.payload and "off" in job.payload:
@@ -486,12 +586,16 @@ class GpuBackend:
             job.payload = None
 
     def wait(self, until):
-        if until is None:
-            time.sleep(0)
-        else:
-            dt = until - self.now()
-            if dt > 0:
-                time.sleep(min(dt, 5e-4))
+        timeout = 0.002 if until is None else max(0.0, min(until - self.now(), 0.002))
+        if self.signal.wait(timeout):
+            self.signal.clear()
 
     def close(self):
         self.pool.shutdown(wait=True)
+        self.raster_fifo.put(None)
+        self.waiter.join()
+        self.torch.cuda.synchronize()
+        for st in self.slot_state:
+            self.hip.destroy(st["event"])
+        for ev in self.raster_events:
+            self.hip.destroy(ev)
