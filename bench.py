@@ -111,6 +111,8 @@ def timed_frames(gs, torch, ds, cams, rend, opt, steps, warmup):
 
     def frame(cam, ev):
         gs.gs_preprocess(ds, cam, opt, rend.proj, rend.ws)
+        if ev is not None:
+            ev[3].record(st)
         gs.gs_bin_sort(rend.proj, cam, opt, rend.bins, rend.ws)
         if ev is not None:
             ev[1].record(st)
@@ -123,7 +125,7 @@ def timed_frames(gs, torch, ds, cams, rend, opt, steps, warmup):
         rend.render(ds, cam, opt)
     for i in range(warmup):
         frame(cams[i % len(cams)], None)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
@@ -133,13 +135,16 @@ def timed_frames(gs, torch, ds, cams, rend, opt, steps, warmup):
     elapsed = time.perf_counter() - t0
     frame_ms = [e[0].elapsed_time(e[2]) for e in evs]
     raster_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    timed_frames.stages = {"preprocess_ms": float(np.mean([e[0].elapsed_time(e[3]) for e in evs])),
+                           "bin_sort_ms": float(np.mean([e[3].elapsed_time(e[1]) for e in evs])),
+                           "rasterize_ms": float(np.mean(raster_ms))}
     return elapsed, frame_ms, raster_ms
 
 
 def work_units(gs, torch, ds, cams, rend, opt_kwargs, steps):
     """Gaussian-pixel evaluations and blended pairs of the timed frames (aux pass, untimed)."""
     opt = gs.options(aux_flags=gs.GS_AUX_NEVAL | gs.GS_AUX_NBLEND, **opt_kwargs)
-    e_pix = blend = entries = visible = 0
+    e_pix = blend = entries = visible = e_tile = e_wave = 0
     seen = {}
     for i in range(steps):
         k = i % len(cams)
@@ -147,12 +152,24 @@ def work_units(gs, torch, ds, cams, rend, opt_kwargs, steps):
             n_keys = rend.render(ds, cams[k], opt)
             torch.cuda.synchronize()
             a = rend.aux.double()
-            seen[k] = (int(a[0].sum().item()), int(a[1].sum().item()), n_keys,
-                       int(rend.proj.n_visible.cpu().item()))
+            ne = a[0]
+            # what a tile-synchronous (256 pixels) and a wave-synchronous (8x8) kernel execute:
+            # every pixel of the unit runs as many evaluations as its longest pixel
+            h, w = ne.shape
+            pad = torch.zeros(((h + 15) // 16 * 16, (w + 15) // 16 * 16), dtype=ne.dtype, device=ne.device)
+            pad[:h, :w] = ne
+            tile_max = pad.view(pad.shape[0] // 16, 16, pad.shape[1] // 16, 16).amax(dim=(1, 3))
+            wave_max = pad.view(pad.shape[0] // 8, 8, pad.shape[1] // 8, 8).amax(dim=(1, 3))
+            seen[k] = (int(ne.sum().item()), int(a[1].sum().item()), n_keys,
+                       int(rend.proj.n_visible.cpu().item()), int(tile_max.sum().item()) * 256,
+                       int(wave_max.sum().item()) * 64)
         e_pix += seen[k][0]
         blend += seen[k][1]
         entries += seen[k][2]
         visible += seen[k][3]
+        e_tile += seen[k][4]
+        e_wave += seen[k][5]
+    work_units.executed = {"e_tile": e_tile, "e_wave": e_wave}
     return e_pix, blend, entries / steps, visible / steps
 
 
@@ -179,6 +196,11 @@ def cpu_baseline_and_psnr(gs, torch, sc, cam, image_gpu, target_s):
     ref = oracle.composite(rec, cam, st, ids, nthreads=threads, tiles=sel, amb=amb)
     t_comp = time.perf_counter() - t2
     frame_s = t_pre + t_comp * ntiles / nsel
+    # one thread on a sample of tiles, extrapolated
+    one = np.sort(order[:min(ntiles, 256)])
+    t3 = time.perf_counter()
+    oracle.composite(rec, cam, st, ids, nthreads=1, tiles=one, amb=amb)
+    single_s = t_pre + (time.perf_counter() - t3) * ntiles / len(one)
     mask = np.zeros((cam.height, cam.width), bool)
     for t in sel:
         x, y = (t % tx) * 16, (t // tx) * 16
@@ -188,11 +210,26 @@ def cpu_baseline_and_psnr(gs, torch, sc, cam, image_gpu, target_s):
     mse = float(np.mean((a - b) ** 2))
     psnr = float("inf") if mse == 0 else 10 * np.log10(1 / mse)
     mae = float(np.mean(np.abs(image_gpu[:, mask] - ref["image"][:, mask])))
+    ok = mask & (ref["ambiguous"] == 0)
+    quality = {"psnr_db": psnr, "mae": mae, "max_abs": float(np.abs(image_gpu[:, ok] - ref["image"][:, ok]).max()),
+               "ambiguous_pixel_frac": float(1.0 - ok.sum() / max(mask.sum(), 1)), "tiles": int(nsel)}
     base = {"value": 1.0 / frame_s, "unit": "frames/s", "cores": threads, "kind": "oracle",
             "sample": (f"FP64 oracle on the first pose: preprocess + tile lists of all {sc.n} Gaussians "
                        f"({t_pre:.1f} s, 1 thread), compositing of {nsel} of {ntiles} random tiles "
-                       f"({t_comp:.1f} s, {threads} threads), extrapolated to the full frame")}
-    return base, psnr, mae, nsel
+                       f"({t_comp:.1f} s, {threads} threads), extrapolated to the full frame"),
+            "single_thread_s_per_frame": single_s, "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
+    return base, quality
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def serve(gs, torch, args):
@@ -309,6 +346,7 @@ def main():
     opt = gs.options(**okw)
     log(f"timing {args.precision}: {args.warmup} warm-up + {args.steps} frames")
     elapsed, frame_ms, raster_ms = timed_frames(gs, torch, ds, cams, rend, opt, args.steps, args.warmup)
+    stages = timed_frames.stages
     fps = args.steps / elapsed
     first_img = None
     rend.render(ds, cams[0], opt)
@@ -317,6 +355,7 @@ def main():
 
     log("counting evaluations of the timed frames (aux pass)")
     e_pix, blend, entries_pf, visible_pf = work_units(gs, torch, ds, cams, rend, okw, args.steps)
+    exe = work_units.executed
     raster_total_s = sum(raster_ms) / 1e3
     flops = FLOPS_PER_EVAL * e_pix + FLOPS_PER_BLEND * blend
     achieved = flops / raster_total_s / 1e12
@@ -336,13 +375,13 @@ def main():
         el32, fm32, rm32 = timed_frames(gs, torch, ds, cams, rend32, opt32, args.steps, args.warmup)
         compare = {"precision": "fp32", "frames_per_s": args.steps / el32,
                    "p50_ms": float(np.percentile(fm32, 50)), "p99_ms": float(np.percentile(fm32, 99)),
-                   "raster_avg_ms": float(np.mean(rm32))}
+                   "raster_avg_ms": float(np.mean(rm32)), "stage_ms": timed_frames.stages}
 
     cpu = None
-    psnr = mae = None
+    quality = {}
     if not args.no_cpu_baseline:
         log("FP64 oracle: CPU baseline and PSNR on sampled tiles")
-        cpu, psnr, mae, _ = cpu_baseline_and_psnr(gs, torch, sc, cams[0], first_img, args.cpu_seconds)
+        cpu, quality = cpu_baseline_and_psnr(gs, torch, sc, cams[0], first_img, args.cpu_seconds)
 
     serving = None
     if not args.no_serve:
@@ -360,7 +399,11 @@ def main():
         "p50_ms": float(np.percentile(frame_ms, 50)), "p99_ms": float(np.percentile(frame_ms, 99)),
         "raster_avg_ms": float(np.mean(raster_ms)),
         "mpix_gauss_evals_per_s": e_pix / raster_total_s / 1e6,
-        "psnr_db_vs_oracle": psnr, "mae_vs_oracle": mae,
+        "psnr_db_vs_oracle": quality.get("psnr_db"), "mae_vs_oracle": quality.get("mae"),
+        "max_abs_vs_oracle": quality.get("max_abs"), "ambiguous_pixel_frac": quality.get("ambiguous_pixel_frac"),
+        "stage_ms": stages,
+        "executed_work_efficiency": {"e_pix_over_e_tile": e_pix / max(exe["e_tile"], 1),
+                                     "e_pix_over_e_wave": e_pix / max(exe["e_wave"], 1)},
         "fp32_plain": compare,
         "speedup_vs_fp32": (fps / compare["frames_per_s"]) if compare else None,
         "raster_speedup_vs_fp32": (compare["raster_avg_ms"] / float(np.mean(raster_ms))) if compare else None,
