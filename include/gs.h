@@ -134,8 +134,10 @@ gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_op
 
 /* Duplicated entries sorted by (bin, depth, Gaussian index) and bin ranges (Background:
  * "Gaussian sorting"; Algorithm 1's group-level entries when opt->group > 1).
- * *n_keys (host) receives the entry count.  If it exceeds bins->capacity nothing is
- * sorted and GS_ERR_CAPACITY is returned: grow the buffers and call again. */
+ * Also sorts proj->order[0 .. visible count) by depth (ties by Gaussian index).
+ * *n_keys (host) receives the entry count; the call waits once on the host, for that count.
+ * If it exceeds bins->capacity nothing is written to *bins and GS_ERR_CAPACITY is returned
+ * (proj->order may already be in depth order): grow the buffers and call again. */
 gs_status gs_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam, const gs_options *opt,
                       const gs_bins *bins, uint64_t *n_keys, void *ws, size_t ws_bytes, void *stream);
 

@@ -159,15 +159,54 @@ gsi::RasterParams make_params(const gs_options &o) {
   return p;
 }
 
+// One event per host thread for the count readback (created on first use, destroyed when
+// the thread ends); calls on different threads may run concurrently on different streams.
+struct CountsEvent {
+  hipEvent_t ev = nullptr;
+  ~CountsEvent() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
+hipEvent_t counts_event() {
+  thread_local CountsEvent holder;
+  if (!holder.ev && hipEventCreateWithFlags(&holder.ev, hipEventDisableTiming) != hipSuccess) holder.ev = nullptr;
+  return holder.ev;
+}
+
 gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam, const gs_options *opt,
                       const gs_bins *bins, uint64_t *n_keys, void *ws, hipStream_t st) {
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
   const Workspace w = carve(ws, n, bins->capacity);
-  // the one host synchronization: entry count K and visible count V (V sizes the depth sort)
+  // The one host synchronization reads the entry count K and the visible count V.  The copy is
+  // followed by an event, and the depth sort and depth-order offset scan (which read V on the
+  // device) are enqueued before the host waits on that event, so the GPU keeps working while
+  // the counts travel to the host.
   uint64_t kv[2] = {0, 0};
+  hipEvent_t ev = counts_event();
+  if (!ev) return fail(GS_ERR_HIP, "hipEventCreateWithFlags failed");
   GS_HIP(gsi::launch_pack_counts(proj->offset + n, proj->n_visible, w.counts, st));
   GS_HIP(hipMemcpyAsync(kv, w.counts, sizeof(kv), hipMemcpyDeviceToHost, st));
-  GS_HIP(hipStreamSynchronize(st));
+  // from here on the copy into kv may be in flight: every exit waits for it first
+  hipError_t e = hipEventRecord(ev, st);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(st);
+    return hip_fail(e, "hipEventRecord");
+  }
+  const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
+  bool in_alt = false;
+  e = gsi::sort_depth(proj->order, reinterpret_cast<const float4 *>(proj->rgb), proj->n_visible, nn, w.dkey,
+                      w.dkey_alt, w.dval_alt, w.sort, st, &in_alt);
+  const uint32_t *dkeys = in_alt ? w.dkey_alt : w.dkey;   // depth bits in depth order
+  if (e == hipSuccess && in_alt) e = hipMemcpyAsync(proj->order, w.dval_alt, nn * 4, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess)
+    e = gsi::launch_scan_gather(proj->count, proj->order, w.dpos, (int64_t)nn, proj->n_visible, w.scan, st);
+  const hipError_t es = hipEventSynchronize(ev);
+  if (es != hipSuccess) {
+    (void)hipStreamSynchronize(st);
+    return hip_fail(es, "hipEventSynchronize");
+  }
+  if (e != hipSuccess) return hip_fail(e, "depth sort");
   const uint64_t K = kv[0];
   const uint32_t V = (uint32_t)kv[1];
   *n_keys = K;
@@ -176,16 +215,9 @@ gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
                 (unsigned long long)bins->capacity);
   if (K >= (1ull << 32)) return fail(GS_ERR_UNSUPPORTED, "%llu entries >= 2^32", (unsigned long long)K);
   if ((int64_t)V > n) return fail(GS_ERR_INVALID_ARG, "visible count %u exceeds n", V);
-  // low key digits (depth bits) on the visible Gaussians; also zeroes the bin ranges
-  bool in_alt = false;
-  GS_HIP(gsi::sort_depth(proj->order, reinterpret_cast<const float4 *>(proj->rgb), V, w.dkey, w.dkey_alt, w.dval_alt,
-                         w.sort, bins->ranges, 2 * (uint64_t)g.nbins, st, &in_alt));
-  const uint32_t *dkeys = in_alt ? w.dkey_alt : w.dkey;   // depth bits in depth order
-  if (in_alt && V > 0) GS_HIP(hipMemcpyAsync(proj->order, w.dval_alt, (size_t)V * 4, hipMemcpyDeviceToDevice, st));
-  // first entry of each Gaussian in depth order, then one thread per entry and the bin digits
-  GS_HIP(gsi::launch_scan_gather(proj->count, proj->order, w.dpos, (int64_t)V, nullptr, w.scan, st));
+  // one thread per entry and the bin digits (also clears the bin ranges)
   GS_HIP(gsi::bin_and_sort(proj->order, w.dpos, V, K, proj->rect, g, w.bkey, bins->vals, w.bkey_alt, w.bval_alt,
-                           w.sort, st, &in_alt));
+                           bins->ranges, w.sort, st, &in_alt));
   const uint32_t *kf = in_alt ? w.bkey_alt : w.bkey;
   const uint32_t *ranks = in_alt ? w.bval_alt : bins->vals;
   GS_HIP(gsi::launch_ranges(kf, ranks, K, proj->order, dkeys, proj->rect, g, bins->vals, bins->ranges,

@@ -100,16 +100,17 @@ size_t radix_tmp_bytes(uint64_t n);
 // reports in *in_alt whether the result ended in the alternate buffers.
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
                       int hi, void *tmp, hipStream_t st, bool *in_alt);
-// Sorts the visible list order[0..V) by depth bits (4 passes, stable), using keys/keys_alt/
-// vals_alt (V each) as scratch; also zeroes ranges[0..nranges).
-hipError_t sort_depth(uint32_t *order, const float4 *rgb, uint32_t V, uint32_t *keys, uint32_t *keys_alt,
-                      uint32_t *vals_alt, void *tmp, uint32_t *ranges, uint64_t nranges, hipStream_t st,
-                      bool *in_alt);
+// Sorts the visible list order[0..*nvis) by depth bits (4 passes, stable), using keys/keys_alt/
+// vals_alt (n_max >= *nvis each) as scratch.  Reads the visible count on the device, so it can
+// be enqueued before the host knows it.
+hipError_t sort_depth(uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max, uint32_t *keys,
+                      uint32_t *keys_alt, uint32_t *vals_alt, void *tmp, hipStream_t st, bool *in_alt);
 // Entries of the V depth-ordered visible Gaussians (the i-th one's first entry at dpos[i])
 // into (bkey, bval = the Gaussian's rank i in depth order), then a stable sort on the bin bits.
+// Also clears the bin ranges ranges[0 .. 2 nbins) before k_ranges fills the non-empty ones.
 hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V, uint64_t K, const uint16_t *rect,
                         const Grid &g, uint32_t *bkey, uint32_t *bval, uint32_t *bkey_alt, uint32_t *bval_alt,
-                        void *tmp, hipStream_t st, bool *in_alt);
+                        uint32_t *ranges, void *tmp, hipStream_t st, bool *in_alt);
 // Bin ranges (zeroed before), masks (group > 1), the 64-bit keys and the Gaussian indices
 // (vals[i] = order[ranks[i]]; ranks may alias vals) of the sorted entries; dkeys[r] are the
 // depth bits of the r-th Gaussian in depth order.

@@ -63,11 +63,19 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nbit
 
 // Per-tile digit counts: counts[d * tiles + tile].  Keys are loaded up front (8 in flight
 // per lane) and each wave adds one LDS atomic per distinct digit.
+// n is *n_dev when n_dev is given (the grid then covers an upper bound and the surplus
+// workgroups return at once), else n_host.
+__device__ __forceinline__ uint64_t count_of(uint64_t n_host, const uint32_t *n_dev) {
+  return n_dev ? (uint64_t)*n_dev : n_host;
+}
+
 template <typename KT, int R>
-__global__ __launch_bounds__(kBlock) void k_radix_count(const KT *keys, uint64_t n, int shift, int nbits,
-                                                        uint32_t tiles_max, uint32_t *counts) {
+__global__ __launch_bounds__(kBlock) void k_radix_count(const KT *keys, uint64_t n_host, const uint32_t *n_dev,
+                                                        int shift, int nbits, uint32_t tiles_max, uint32_t *counts) {
   constexpr int kRounds = SortTile<R>::kRounds, kWaveTile = SortTile<R>::kWaveTile, kSortTile = SortTile<R>::kTile;
   __shared__ uint32_t h[kDigits];
+  const uint64_t n = count_of(n_host, n_dev);
+  if ((uint64_t)blockIdx.x * kSortTile >= n) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   h[t] = 0;
   const uint32_t dmask = (1u << nbits) - 1u;
@@ -94,15 +102,19 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(const KT *keys, uint64_t
 // One workgroup per digit d: counts[d][*] becomes the exclusive prefix over tiles (within the
 // digit) and totals[d] the digit's total.
 __global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t *counts, uint32_t tiles_max,
-                                                             uint32_t *totals) {
+                                                             uint32_t *totals, uint64_t n_host, const uint32_t *n_dev,
+                                                             uint32_t tile_size) {
   __shared__ uint32_t sh[kBlock];
   const int d = blockIdx.x, t = threadIdx.x;
   uint32_t *row = counts + (uint64_t)d * tiles_max;
-  const uint32_t per = (tiles_max + kBlock - 1) / kBlock;
+  // tiles holding keys (the count kernel wrote no counts for the others)
+  const uint64_t n = count_of(n_host, n_dev);
+  const uint32_t tiles = (uint32_t)((n + tile_size - 1) / tile_size);
+  const uint32_t per = (tiles + kBlock - 1) / kBlock;
   const uint32_t b0 = t * per;
   uint32_t s = 0;
   for (uint32_t i = 0; i < per; ++i)
-    if (b0 + i < tiles_max) s += row[b0 + i];
+    if (b0 + i < tiles) s += row[b0 + i];
   sh[t] = s;
   __syncthreads();
   for (int off = 1; off < kBlock; off <<= 1) {
@@ -114,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t *counts, u
   uint32_t run = sh[t] - s;
   if (t == kBlock - 1) totals[d] = sh[t];
   for (uint32_t i = 0; i < per; ++i)
-    if (b0 + i < tiles_max) {
+    if (b0 + i < tiles) {
       const uint32_t c = row[b0 + i];
       row[b0 + i] = run;
       run += c;
@@ -126,8 +138,9 @@ __global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t *counts, u
 // digit order and then stored so that consecutive lanes write consecutive addresses.
 template <typename KT, int R>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const uint32_t *vin, KT *kout, uint32_t *vout,
-                                                          uint64_t n, int shift, int nbits, uint32_t tiles_max,
-                                                          const uint32_t *offsets, const uint32_t *totals) {
+                                                          uint64_t n_host, const uint32_t *n_dev, int shift, int nbits,
+                                                          uint32_t tiles_max, const uint32_t *offsets,
+                                                          const uint32_t *totals) {
   constexpr int kRounds = SortTile<R>::kRounds, kWaveTile = SortTile<R>::kWaveTile, kSortTile = SortTile<R>::kTile;
   __shared__ uint32_t wcnt[4][kDigits];
   __shared__ uint32_t bstart[kDigits];
@@ -135,7 +148,9 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
   __shared__ KT s_key[kSortTile];
   __shared__ uint32_t s_val[kSortTile];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const uint64_t n = count_of(n_host, n_dev);
   const uint64_t tile0 = (uint64_t)blockIdx.x * kSortTile;
+  if (tile0 >= n) return;
   const uint32_t dmask = (1u << nbits) - 1u;
   const uint64_t lt = (1ull << lane) - 1ull;
   const uint64_t base = tile0 + (uint64_t)w * kWaveTile;
@@ -213,10 +228,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
 
 // Depth keys of the visible Gaussians (key[i] = bits(depth of order[i]), i < *nvis), and the
 // zeroing of the bin ranges.
-__global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, const float4 *rgb, uint32_t V,
-                                                       uint32_t *keys, uint32_t *ranges, uint64_t nranges) {
+__global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis,
+                                                       uint32_t *keys) {
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < nranges; i += stride) ranges[i] = 0u;
+  const uint32_t V = *nvis;
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < V; i += stride)
     keys[i] = __float_as_uint(rgb[order[i]].w);
 }
@@ -231,9 +246,13 @@ constexpr int kBinItems = 1024;
 
 __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const uint64_t *dpos, uint32_t nvis,
                                                     uint64_t K, const ushort4 *rect, int G, int GX,
-                                                    uint32_t *bin_keys, uint32_t *vals) {
+                                                    uint32_t *bin_keys, uint32_t *vals, uint32_t *ranges,
+                                                    uint64_t nranges) {
   __shared__ uint64_t s_pos[kBinItems + 1];
   __shared__ uint32_t s_first;
+  // the bin ranges start empty (k_ranges writes the non-empty ones, two kernels later)
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < nranges; i += (uint64_t)gridDim.x * kBlock)
+    ranges[i] = 0u;
   const uint64_t e0 = (uint64_t)blockIdx.x * kBinItems;
   const int t = threadIdx.x, lane = t & 63;
   if (t < 64) {
@@ -367,8 +386,8 @@ size_t radix_tmp_bytes(uint64_t n) {
 }
 
 template <typename KT, int R>
-hipError_t radix_passes_r(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n, int lo, int hi,
-                          void *tmp, hipStream_t st, bool *in_alt) {
+hipError_t radix_passes_r(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n,
+                          const uint32_t *n_dev, int lo, int hi, void *tmp, hipStream_t st, bool *in_alt) {
   const uint32_t tiles = (uint32_t)((n + SortTile<R>::kTile - 1) / SortTile<R>::kTile);
   uint32_t *counts = static_cast<uint32_t *>(tmp);
   uint32_t *totals = counts + (uint64_t)kDigits * tiles;
@@ -376,10 +395,12 @@ hipError_t radix_passes_r(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals
   uint32_t *vin = vals, *vout = vals_alt;
   for (int shift = lo; shift < hi; shift += 8) {
     const int bits = (hi - shift) < 8 ? (hi - shift) : 8;
-    hipLaunchKernelGGL((k_radix_count<KT, R>), dim3(tiles), dim3(kBlock), 0, st, kin, n, shift, bits, tiles, counts);
-    hipLaunchKernelGGL(k_radix_digit_scan, dim3(kDigits), dim3(kBlock), 0, st, counts, tiles, totals);
-    hipLaunchKernelGGL((k_radix_scatter<KT, R>), dim3(tiles), dim3(kBlock), 0, st, kin, vin, kout, vout, n, shift,
-                       bits, tiles, counts, totals);
+    hipLaunchKernelGGL((k_radix_count<KT, R>), dim3(tiles), dim3(kBlock), 0, st, kin, n, n_dev, shift, bits, tiles,
+                       counts);
+    hipLaunchKernelGGL(k_radix_digit_scan, dim3(kDigits), dim3(kBlock), 0, st, counts, tiles, totals, n, n_dev,
+                       (uint32_t)SortTile<R>::kTile);
+    hipLaunchKernelGGL((k_radix_scatter<KT, R>), dim3(tiles), dim3(kBlock), 0, st, kin, vin, kout, vout, n, n_dev,
+                       shift, bits, tiles, counts, totals);
     std::swap(kin, kout);
     std::swap(vin, vout);
     *in_alt = !*in_alt;
@@ -387,38 +408,39 @@ hipError_t radix_passes_r(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals
   return hipGetLastError();
 }
 
+// n: the number of keys, or (with n_dev) an upper bound of *n_dev
 template <typename KT>
-hipError_t radix_passes_t(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n, int lo, int hi,
-                          void *tmp, hipStream_t st, bool *in_alt) {
+hipError_t radix_passes_t(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n,
+                          const uint32_t *n_dev, int lo, int hi, void *tmp, hipStream_t st, bool *in_alt) {
   *in_alt = false;
   if (hi <= lo || n <= 1) return hipSuccess;
-  if (n <= kSmallSort) return radix_passes_r<KT, 2>(keys, vals, keys_alt, vals_alt, n, lo, hi, tmp, st, in_alt);
-  return radix_passes_r<KT, 8>(keys, vals, keys_alt, vals_alt, n, lo, hi, tmp, st, in_alt);
+  if (n <= kSmallSort) return radix_passes_r<KT, 2>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt);
+  return radix_passes_r<KT, 8>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt);
 }
 
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
                       int hi, void *tmp, hipStream_t st, bool *in_alt) {
-  return radix_passes_t<uint64_t>(keys, vals, keys_alt, vals_alt, n, lo, hi, tmp, st, in_alt);
+  return radix_passes_t<uint64_t>(keys, vals, keys_alt, vals_alt, n, nullptr, lo, hi, tmp, st, in_alt);
 }
 
-hipError_t sort_depth(uint32_t *order, const float4 *rgb, uint32_t V, uint32_t *keys, uint32_t *keys_alt,
-                      uint32_t *vals_alt, void *tmp, uint32_t *ranges, uint64_t nranges, hipStream_t st,
-                      bool *in_alt) {
-  const uint64_t m = V > nranges ? V : nranges;
-  const unsigned blocks = grid_for(m) < 8192u ? grid_for(m) : 8192u;   // grid-stride beyond
-  hipLaunchKernelGGL(k_depth_keys, dim3(blocks), dim3(kBlock), 0, st, order, rgb, V, keys, ranges, nranges);
-  return radix_passes_t<uint32_t>(keys, order, keys_alt, vals_alt, V, 0, 32, tmp, st, in_alt);
+hipError_t sort_depth(uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max, uint32_t *keys,
+                      uint32_t *keys_alt, uint32_t *vals_alt, void *tmp, hipStream_t st, bool *in_alt) {
+  const unsigned blocks = grid_for(n_max) < 2048u ? grid_for(n_max) : 2048u;   // grid-stride beyond
+  hipLaunchKernelGGL(k_depth_keys, dim3(blocks), dim3(kBlock), 0, st, order, rgb, nvis, keys);
+  return radix_passes_t<uint32_t>(keys, order, keys_alt, vals_alt, n_max, nvis, 0, 32, tmp, st, in_alt);
 }
 
 hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V, uint64_t K, const uint16_t *rect,
                         const Grid &g, uint32_t *bkey, uint32_t *bval, uint32_t *bkey_alt, uint32_t *bval_alt,
-                        void *tmp, hipStream_t st, bool *in_alt) {
+                        uint32_t *ranges, void *tmp, hipStream_t st, bool *in_alt) {
   *in_alt = false;
-  if (K == 0) return hipSuccess;
+  const uint64_t nranges = 2 * (uint64_t)g.nbins;
+  if (K == 0) return launch_fill_u32(ranges, nranges, 0u, st);
   hipLaunchKernelGGL(k_binning, dim3(grid_for(K, kBinItems)), dim3(kBlock), 0, st, order, dpos, V, K,
-                     reinterpret_cast<const ushort4 *>(rect), g.G, g.GX, bkey, bval);
+                     reinterpret_cast<const ushort4 *>(rect), g.G, g.GX, bkey, bval, ranges, nranges);
   if (K <= 1) return hipGetLastError();
-  return radix_passes_t<uint32_t>(bkey, bval, bkey_alt, bval_alt, K, 0, bits_for((uint64_t)g.nbins), tmp, st, in_alt);
+  return radix_passes_t<uint32_t>(bkey, bval, bkey_alt, bval_alt, K, nullptr, 0, bits_for((uint64_t)g.nbins), tmp,
+                                  st, in_alt);
 }
 
 hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n, const uint32_t *order,
