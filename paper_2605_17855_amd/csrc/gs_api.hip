@@ -102,6 +102,7 @@ struct Workspace {
   uint32_t *dkey_alt;    // depth sort double buffer (n)
   uint32_t *dval_alt;    // (n)
   uint64_t *dpos;        // first entry of each visible Gaussian in depth order (n + 1)
+  uint32_t *csort;       // entry count of each visible Gaussian in depth order (n)
   uint32_t *bkey;        // bin key of each entry (capacity)
   uint32_t *bkey_alt;    // bin sort double buffer (capacity)
   uint32_t *bval_alt;    // (capacity)
@@ -125,6 +126,7 @@ Workspace carve(void *ws, int64_t n, uint64_t capacity) {
   w.dkey_alt = reinterpret_cast<uint32_t *>(take(nn * 4));
   w.dval_alt = reinterpret_cast<uint32_t *>(take(nn * 4));
   w.dpos = reinterpret_cast<uint64_t *>(take((nn + 1) * 8));
+  w.csort = reinterpret_cast<uint32_t *>(take(nn * 4));
   w.bkey = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
   w.bkey_alt = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
   w.bval_alt = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
@@ -196,11 +198,14 @@ gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
   const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
   bool in_alt = false;
   e = gsi::sort_depth(proj->order, reinterpret_cast<const float4 *>(proj->rgb), proj->n_visible, nn, w.dkey,
-                      w.dkey_alt, w.dval_alt, w.sort, st, &in_alt);
+                      w.dkey_alt, w.dval_alt, w.sort, st, &in_alt, proj->count, w.csort);
   const uint32_t *dkeys = in_alt ? w.dkey_alt : w.dkey;   // depth bits in depth order
   if (e == hipSuccess && in_alt) e = hipMemcpyAsync(proj->order, w.dval_alt, nn * 4, hipMemcpyDeviceToDevice, st);
+  // first entry of each Gaussian in depth order (the sort placed the counts in that order when
+  // it ran; a single Gaussian needs no sort)
   if (e == hipSuccess)
-    e = gsi::launch_scan_gather(proj->count, proj->order, w.dpos, (int64_t)nn, proj->n_visible, w.scan, st);
+    e = nn > 1 ? gsi::launch_scan_dev(w.csort, w.dpos, (int64_t)nn, proj->n_visible, w.scan, st)
+               : gsi::launch_scan_gather(proj->count, proj->order, w.dpos, (int64_t)nn, proj->n_visible, w.scan, st);
   const hipError_t es = hipEventSynchronize(ev);
   if (es != hipSuccess) {
     (void)hipStreamSynchronize(st);

@@ -91,9 +91,11 @@ hipError_t launch_scan_compact(const uint32_t *in, uint64_t *out, int64_t n, uin
 // out[0..m] = exclusive prefix sum of in[idx[i]] for i < m = *n_dev (m <= n_max)
 hipError_t launch_scan_gather(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n_max,
                               const uint32_t *n_dev, void *tmp, hipStream_t st);
+// out[0..m] = exclusive prefix sum of in[i] for i < m = *n_dev (m <= n_max)
+hipError_t launch_scan_dev(const uint32_t *in, uint64_t *out, int64_t n_max, const uint32_t *n_dev, void *tmp,
+                           hipStream_t st);
 
 // ---- binning, sort, ranges -------------------------------------------------
-int radix_passes(int lo, int hi);
 // scratch of a radix sort over at most n keys (per-tile digit counts and digit totals)
 size_t radix_tmp_bytes(uint64_t n);
 // Stable sort of (keys, vals) on key bits [lo, hi); ping-pongs with (keys_alt, vals_alt) and
@@ -101,10 +103,12 @@ size_t radix_tmp_bytes(uint64_t n);
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
                       int hi, void *tmp, hipStream_t st, bool *in_alt);
 // Sorts the visible list order[0..*nvis) by depth bits (4 passes, stable), using keys/keys_alt/
-// vals_alt (n_max >= *nvis each) as scratch.  Reads the visible count on the device, so it can
-// be enqueued before the host knows it.
+// vals_alt (n_max >= *nvis each) as scratch, and writes count_sorted[i] = count[order[i]] for
+// the sorted list (n_max > 1).  Reads the visible count on the device, so it can be enqueued
+// before the host knows it.
 hipError_t sort_depth(uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max, uint32_t *keys,
-                      uint32_t *keys_alt, uint32_t *vals_alt, void *tmp, hipStream_t st, bool *in_alt);
+                      uint32_t *keys_alt, uint32_t *vals_alt, void *tmp, hipStream_t st, bool *in_alt,
+                      const uint32_t *count, uint32_t *count_sorted);
 // Entries of the V depth-ordered visible Gaussians (the i-th one's first entry at dpos[i])
 // into (bkey, bval = the Gaussian's rank i in depth order), then a stable sort on the bin bits.
 // Also clears the bin ranges ranges[0 .. 2 nbins) before k_ranges fills the non-empty ones.

@@ -400,6 +400,11 @@ hipError_t launch_scan_compact(const uint32_t *in, uint64_t *out, int64_t n, uin
   return scan_impl<false, true>(in, nullptr, out, n, nullptr, order, nvis, tmp, st);
 }
 
+hipError_t launch_scan_dev(const uint32_t *in, uint64_t *out, int64_t n_max, const uint32_t *n_dev, void *tmp,
+                           hipStream_t st) {
+  return scan_impl<false, false>(in, nullptr, out, n_max, n_dev, nullptr, nullptr, tmp, st);
+}
+
 hipError_t launch_scan_gather(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n_max,
                               const uint32_t *n_dev, void *tmp, hipStream_t st) {
   return scan_impl<true, false>(in, idx, out, n_max, n_dev, nullptr, nullptr, tmp, st);

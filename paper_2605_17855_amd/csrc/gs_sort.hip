@@ -140,7 +140,8 @@ template <typename KT, int R>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const uint32_t *vin, KT *kout, uint32_t *vout,
                                                           uint64_t n_host, const uint32_t *n_dev, int shift, int nbits,
                                                           uint32_t tiles_max, const uint32_t *offsets,
-                                                          const uint32_t *totals) {
+                                                          const uint32_t *totals, const uint32_t *aux_in,
+                                                          uint32_t *aux_out) {
   constexpr int kRounds = SortTile<R>::kRounds, kWaveTile = SortTile<R>::kWaveTile, kSortTile = SortTile<R>::kTile;
   __shared__ uint32_t wcnt[4][kDigits];
   __shared__ uint32_t bstart[kDigits];
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
-  const uint32_t tot_d = totals[t];
+  const uint32_t tot_d = t < (1 << nbits) ? totals[t] : 0u;   // the digit scan covers 2^nbits digits
   const uint32_t off_d = offsets[(uint64_t)t * tiles_max + blockIdx.x];
   __syncthreads();
 #pragma unroll
@@ -221,8 +222,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
   for (uint32_t i = t; i < nvalid; i += kBlock) {
     const KT k = s_key[i];
     const uint32_t d = (uint32_t)(k >> shift) & dmask;
+    const uint32_t v = s_val[i];
     kout[gbase[d] + (i - bstart[d])] = k;
-    vout[gbase[d] + (i - bstart[d])] = s_val[i];
+    vout[gbase[d] + (i - bstart[d])] = v;
+    if (aux_out) aux_out[gbase[d] + (i - bstart[d])] = aux_in[v];   // a payload gathered through the value
   }
 }
 
@@ -371,8 +374,6 @@ hipError_t launch_pack_counts(const uint64_t *K, const uint32_t *V, uint64_t *ou
   return hipGetLastError();
 }
 
-int radix_passes(int lo, int hi) { return hi > lo ? (hi - lo + 7) / 8 : 0; }
-
 // tiles of a sort of n keys, and the most tiles of any sort of at most n keys
 inline uint64_t sort_tiles(uint64_t n) {
   return n <= kSmallSort ? (n + SortTile<2>::kTile - 1) / SortTile<2>::kTile
@@ -387,20 +388,25 @@ size_t radix_tmp_bytes(uint64_t n) {
 
 template <typename KT, int R>
 hipError_t radix_passes_r(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n,
-                          const uint32_t *n_dev, int lo, int hi, void *tmp, hipStream_t st, bool *in_alt) {
+                          const uint32_t *n_dev, int lo, int hi, void *tmp, hipStream_t st, bool *in_alt,
+                          const uint32_t *aux_in, uint32_t *aux_out) {
   const uint32_t tiles = (uint32_t)((n + SortTile<R>::kTile - 1) / SortTile<R>::kTile);
   uint32_t *counts = static_cast<uint32_t *>(tmp);
   uint32_t *totals = counts + (uint64_t)kDigits * tiles;
   KT *kin = keys, *kout = keys_alt;
   uint32_t *vin = vals, *vout = vals_alt;
-  for (int shift = lo; shift < hi; shift += 8) {
-    const int bits = (hi - shift) < 8 ? (hi - shift) : 8;
+  // passes of (nearly) equal width, at most 8 bits each: 13 bits -> 7 + 6, 32 -> 4 x 8
+  const int passes = (hi - lo + 7) / 8;
+  const int width = (hi - lo + passes - 1) / passes;
+  for (int shift = lo; shift < hi; shift += width) {
+    const int bits = (hi - shift) < width ? (hi - shift) : width;
+    const bool last = shift + width >= hi;
     hipLaunchKernelGGL((k_radix_count<KT, R>), dim3(tiles), dim3(kBlock), 0, st, kin, n, n_dev, shift, bits, tiles,
                        counts);
-    hipLaunchKernelGGL(k_radix_digit_scan, dim3(kDigits), dim3(kBlock), 0, st, counts, tiles, totals, n, n_dev,
+    hipLaunchKernelGGL(k_radix_digit_scan, dim3(1u << bits), dim3(kBlock), 0, st, counts, tiles, totals, n, n_dev,
                        (uint32_t)SortTile<R>::kTile);
     hipLaunchKernelGGL((k_radix_scatter<KT, R>), dim3(tiles), dim3(kBlock), 0, st, kin, vin, kout, vout, n, n_dev,
-                       shift, bits, tiles, counts, totals);
+                       shift, bits, tiles, counts, totals, aux_in, last ? aux_out : nullptr);
     std::swap(kin, kout);
     std::swap(vin, vout);
     *in_alt = !*in_alt;
@@ -408,14 +414,17 @@ hipError_t radix_passes_r(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals
   return hipGetLastError();
 }
 
-// n: the number of keys, or (with n_dev) an upper bound of *n_dev
+// n: the number of keys, or (with n_dev) an upper bound of *n_dev.  With aux_out, the last
+// pass also writes aux_out[i] = aux_in[value of the i-th sorted key].
 template <typename KT>
 hipError_t radix_passes_t(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n,
-                          const uint32_t *n_dev, int lo, int hi, void *tmp, hipStream_t st, bool *in_alt) {
+                          const uint32_t *n_dev, int lo, int hi, void *tmp, hipStream_t st, bool *in_alt,
+                          const uint32_t *aux_in = nullptr, uint32_t *aux_out = nullptr) {
   *in_alt = false;
   if (hi <= lo || n <= 1) return hipSuccess;
-  if (n <= kSmallSort) return radix_passes_r<KT, 2>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt);
-  return radix_passes_r<KT, 8>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt);
+  if (n <= kSmallSort)
+    return radix_passes_r<KT, 2>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt, aux_in, aux_out);
+  return radix_passes_r<KT, 8>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt, aux_in, aux_out);
 }
 
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
@@ -424,10 +433,12 @@ hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32
 }
 
 hipError_t sort_depth(uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max, uint32_t *keys,
-                      uint32_t *keys_alt, uint32_t *vals_alt, void *tmp, hipStream_t st, bool *in_alt) {
+                      uint32_t *keys_alt, uint32_t *vals_alt, void *tmp, hipStream_t st, bool *in_alt,
+                      const uint32_t *count, uint32_t *count_sorted) {
   const unsigned blocks = grid_for(n_max) < 2048u ? grid_for(n_max) : 2048u;   // grid-stride beyond
   hipLaunchKernelGGL(k_depth_keys, dim3(blocks), dim3(kBlock), 0, st, order, rgb, nvis, keys);
-  return radix_passes_t<uint32_t>(keys, order, keys_alt, vals_alt, n_max, nvis, 0, 32, tmp, st, in_alt);
+  return radix_passes_t<uint32_t>(keys, order, keys_alt, vals_alt, n_max, nvis, 0, 32, tmp, st, in_alt, count,
+                                  count_sorted);
 }
 
 hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V, uint64_t K, const uint16_t *rect,

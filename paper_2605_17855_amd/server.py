@@ -26,11 +26,12 @@ from typing import Dict, List, Optional
 import numpy as np
 
 # bytes per duplicated entry: key 8 + value 4 + mask 2, plus the workspace's bin key and
-# the two sort double buffers (4 + 4 + 4) and the sort's per-tile digit counts
-BYTES_PER_ENTRY = 27
-# per-Gaussian workspace bytes: scan partials, depth keys and their double buffers, and
-# each visible Gaussian's first-entry offset
-BYTES_PER_GAUSSIAN = 24
+# the two sort double buffers (4 + 4 + 4) and the sort's per-tile digit counts (up to 2 B
+# per key for sorts of at most 2^20 keys, whose tiles hold 512 keys)
+BYTES_PER_ENTRY = 28
+# per-Gaussian workspace bytes: scan partials, depth keys and their double buffers, each
+# visible Gaussian's entry count and first-entry offset in depth order
+BYTES_PER_GAUSSIAN = 28
 
 
 @dataclasses.dataclass

@@ -146,3 +146,22 @@ def test_reservation_refused_in_empty_pool_fails_the_request():
     be = Refusing((1000, 2000), lambda j: 1000, prepare_s=lambda j: 1e-3, raster_s=lambda js: 1e-3)
     st = server.Server(be, 10**9, slots=1).run(make_requests(np.linspace(0, 0.01, 5)))
     assert st.completed == 4 and st.failed == 1
+
+
+def test_reservation_covers_the_library_workspace():
+    # the serving reservation of a request must hold its bins and the workspace that
+    # gs_workspace_bytes asks for, at the capacity the reservation implies
+    import ctypes as C
+    from paper_2605_17855_amd import gs
+    L = gs.lib()
+    for n in [1, 1000, 500_000, 1_048_576, 1_200_000, 3_000_000, 6_000_000]:
+        for (w, h) in [(16, 16), (640, 360), (1920, 1080), (3840, 2160)]:
+            for k in [0, 1000, 1_048_576, 1_100_000, 20_000_000]:
+                for g in (1, 2, 4):
+                    reserve = server.job_bytes(n, k, w * h)
+                    cap = server.entry_capacity(reserve, n, w * h)
+                    assert cap >= k
+                    ws = int(L.gs_workspace_bytes(n, cap, C.byref(gs.camera_stub(w, h)), C.byref(gs.options(group=g))))
+                    nb = int(L.gs_num_bins(C.byref(gs.camera_stub(w, h)), g))
+                    parts = [8 * max(cap, 1), 4 * max(cap, 1), 2 * max(cap, 1) + 2, 8 * nb, ws]
+                    assert sum((x + 255) // 256 * 256 for x in parts) <= reserve, (n, w, h, k, g)
