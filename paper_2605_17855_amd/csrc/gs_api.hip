@@ -187,7 +187,9 @@ gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
   uint64_t kv[2] = {0, 0};
   hipEvent_t ev = counts_event();
   if (!ev) return fail(GS_ERR_HIP, "hipEventCreateWithFlags failed");
-  GS_HIP(gsi::launch_pack_counts(proj->offset + n, proj->n_visible, w.counts, st));
+  const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
+  GS_HIP(gsi::launch_depth_keys(proj->order, reinterpret_cast<const float4 *>(proj->rgb), proj->n_visible, nn, w.dkey,
+                                proj->offset + n, w.counts, st));
   GS_HIP(hipMemcpyAsync(kv, w.counts, sizeof(kv), hipMemcpyDeviceToHost, st));
   // from here on the copy into kv may be in flight: every exit waits for it first
   hipError_t e = hipEventRecord(ev, st);
@@ -195,10 +197,9 @@ gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
     (void)hipStreamSynchronize(st);
     return hip_fail(e, "hipEventRecord");
   }
-  const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
   bool in_alt = false;
-  e = gsi::sort_depth(proj->order, reinterpret_cast<const float4 *>(proj->rgb), proj->n_visible, nn, w.dkey,
-                      w.dkey_alt, w.dval_alt, w.sort, st, &in_alt, proj->count, w.csort);
+  e = gsi::sort_depth(proj->order, proj->n_visible, nn, w.dkey, w.dkey_alt, w.dval_alt, w.sort, st, &in_alt,
+                      proj->count, w.csort);
   const uint32_t *dkeys = in_alt ? w.dkey_alt : w.dkey;   // depth bits in depth order
   if (e == hipSuccess && in_alt) e = hipMemcpyAsync(proj->order, w.dval_alt, nn * 4, hipMemcpyDeviceToDevice, st);
   // first entry of each Gaussian in depth order (the sort placed the counts in that order when

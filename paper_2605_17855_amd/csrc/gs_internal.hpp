@@ -102,13 +102,17 @@ size_t radix_tmp_bytes(uint64_t n);
 // reports in *in_alt whether the result ended in the alternate buffers.
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
                       int hi, void *tmp, hipStream_t st, bool *in_alt);
-// Sorts the visible list order[0..*nvis) by depth bits (4 passes, stable), using keys/keys_alt/
-// vals_alt (n_max >= *nvis each) as scratch, and writes count_sorted[i] = count[order[i]] for
-// the sorted list (n_max > 1).  Reads the visible count on the device, so it can be enqueued
+// keys[i] = depth bits of order[i] for i < *nvis (n_max >= *nvis), and counts = {*K, *nvis}
+// (the entry and visible counts side by side, for one copy to the host).
+hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max,
+                             uint32_t *keys, const uint64_t *K, uint64_t *counts, hipStream_t st);
+// Sorts the visible list order[0..*nvis) by the depth keys (4 passes, stable), using keys_alt/
+// vals_alt (n_max each) as scratch, and writes count_sorted[i] = count[order[i]] for the
+// sorted list (n_max > 1).  Reads the visible count on the device, so it can be enqueued
 // before the host knows it.
-hipError_t sort_depth(uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max, uint32_t *keys,
-                      uint32_t *keys_alt, uint32_t *vals_alt, void *tmp, hipStream_t st, bool *in_alt,
-                      const uint32_t *count, uint32_t *count_sorted);
+hipError_t sort_depth(uint32_t *order, const uint32_t *nvis, uint64_t n_max, uint32_t *keys, uint32_t *keys_alt,
+                      uint32_t *vals_alt, void *tmp, hipStream_t st, bool *in_alt, const uint32_t *count,
+                      uint32_t *count_sorted);
 // Entries of the V depth-ordered visible Gaussians (the i-th one's first entry at dpos[i])
 // into (bkey, bval = the Gaussian's rank i in depth order), then a stable sort on the bin bits.
 // Also clears the bin ranges ranges[0 .. 2 nbins) before k_ranges fills the non-empty ones.
@@ -122,8 +126,6 @@ hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64
                          const uint32_t *dkeys, const uint16_t *rect, const Grid &g, uint32_t *vals, uint32_t *ranges,
                          uint16_t *masks, uint64_t *keys, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
-// out[0] = *K, out[1] = *V (one thread): the entry and visible counts side by side
-hipError_t launch_pack_counts(const uint64_t *K, const uint32_t *V, uint64_t *out, hipStream_t st);
 
 // ---- rasterizers -------------------------------------------------------------
 struct RasterJob {

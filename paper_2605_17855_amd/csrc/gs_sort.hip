@@ -23,13 +23,6 @@
 namespace gsi {
 namespace {
 
-__global__ void k_pack_counts(const uint64_t *K, const uint32_t *V, uint64_t *out) {
-  if (threadIdx.x == 0) {
-    out[0] = *K;
-    out[1] = *V;
-  }
-}
-
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
   uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
@@ -232,9 +225,13 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
 // Depth keys of the visible Gaussians (key[i] = bits(depth of order[i]), i < *nvis), and the
 // zeroing of the bin ranges.
 __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis,
-                                                       uint32_t *keys) {
+                                                       uint32_t *keys, const uint64_t *K, uint64_t *counts) {
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   const uint32_t V = *nvis;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {   // the entry and visible counts, side by side
+    counts[0] = *K;
+    counts[1] = V;
+  }
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < V; i += stride)
     keys[i] = __float_as_uint(rgb[order[i]].w);
 }
@@ -302,42 +299,43 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
   }
 }
 
-// Bin ranges (zeroed beforehand), tile-membership masks and the 64-bit keys.  Entry i holds
+// Bin ranges (cleared beforehand), tile-membership masks and the 64-bit keys.  Entry i holds
 // its Gaussian's rank r in the depth-sorted visible list; the Gaussian index order[r] and the
 // depth bits dkeys[r] come from those two V-sized arrays (cache-resident), not from the
-// per-Gaussian records.  Each thread takes kRangeItems consecutive entries and issues all
-// their loads before the dependent gathers, so several round trips are in flight at once.
+// per-Gaussian records.  A workgroup takes kRangeItems x 256 consecutive entries, thread t
+// the entries t, t + 256, ... (coalesced), and issues all their loads before the dependent
+// gathers, so several round trips are in flight at once.
 constexpr int kRangeItems = 4;
 
 __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n,
                                                    const uint32_t *order, const uint32_t *dkeys, const ushort4 *rect,
                                                    int G, int GX, uint32_t *vals, uint32_t *ranges, uint16_t *masks,
                                                    uint64_t *keys) {
-  const uint64_t i0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * kRangeItems;
-  if (i0 >= n) return;
-  uint32_t bin[kRangeItems + 2], r[kRangeItems];
-  // bin[0] = key before the first item (or ~0), bin[kRangeItems + 1] = key after the last
-  bin[0] = i0 > 0 ? bin_keys[i0 - 1] : 0xFFFFFFFFu;
+  const uint64_t base = (uint64_t)blockIdx.x * kBlock * kRangeItems + threadIdx.x;
+  uint32_t bin[kRangeItems], prev[kRangeItems], next[kRangeItems], r[kRangeItems];
 #pragma unroll
   for (int j = 0; j < kRangeItems; ++j) {
-    const bool in = i0 + j < n;
-    bin[j + 1] = in ? bin_keys[i0 + j] : 0xFFFFFFFFu;
-    r[j] = in ? ranks[i0 + j] : 0u;
+    const uint64_t i = base + (uint64_t)j * kBlock;
+    const bool in = i < n;
+    bin[j] = in ? bin_keys[i] : 0u;
+    prev[j] = (in && i > 0) ? bin_keys[i - 1] : 0xFFFFFFFFu;
+    next[j] = (in && i + 1 < n) ? bin_keys[i + 1] : 0xFFFFFFFFu;
+    r[j] = in ? ranks[i] : 0u;
   }
-  bin[kRangeItems + 1] = i0 + kRangeItems < n ? bin_keys[i0 + kRangeItems] : 0xFFFFFFFFu;
   uint32_t g[kRangeItems], d[kRangeItems];
 #pragma unroll
   for (int j = 0; j < kRangeItems; ++j) {
-    g[j] = i0 + j < n ? order[r[j]] : 0u;
-    d[j] = i0 + j < n ? dkeys[r[j]] : 0u;
+    const bool in = base + (uint64_t)j * kBlock < n;
+    g[j] = in ? order[r[j]] : 0u;
+    d[j] = in ? dkeys[r[j]] : 0u;
   }
 #pragma unroll
   for (int j = 0; j < kRangeItems; ++j) {
-    const uint64_t i = i0 + j;
+    const uint64_t i = base + (uint64_t)j * kBlock;
     if (i >= n) break;
-    const uint32_t b = bin[j + 1];
-    if (bin[j] != b) ranges[2 * (uint64_t)b] = (uint32_t)i;
-    if (i == n - 1 || bin[j + 2] != b) ranges[2 * (uint64_t)b + 1] = (uint32_t)(i + 1);
+    const uint32_t b = bin[j];
+    if (prev[j] != b) ranges[2 * (uint64_t)b] = (uint32_t)i;
+    if (next[j] != b) ranges[2 * (uint64_t)b + 1] = (uint32_t)(i + 1);
     keys[i] = ((uint64_t)b << 32) | d[j];
     vals[i] = g[j];
     if (G > 1 && masks) {
@@ -366,11 +364,6 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) 
   uint64_t b = (n + kBlock - 1) / kBlock;
   if (b > 8192) b = 8192;
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)b), dim3(kBlock), 0, st, p, n, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_pack_counts(const uint64_t *K, const uint32_t *V, uint64_t *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_pack_counts, dim3(1), dim3(64), 0, st, K, V, out);
   return hipGetLastError();
 }
 
@@ -432,11 +425,16 @@ hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32
   return radix_passes_t<uint64_t>(keys, vals, keys_alt, vals_alt, n, nullptr, lo, hi, tmp, st, in_alt);
 }
 
-hipError_t sort_depth(uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max, uint32_t *keys,
-                      uint32_t *keys_alt, uint32_t *vals_alt, void *tmp, hipStream_t st, bool *in_alt,
-                      const uint32_t *count, uint32_t *count_sorted) {
+hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max,
+                             uint32_t *keys, const uint64_t *K, uint64_t *counts, hipStream_t st) {
   const unsigned blocks = grid_for(n_max) < 2048u ? grid_for(n_max) : 2048u;   // grid-stride beyond
-  hipLaunchKernelGGL(k_depth_keys, dim3(blocks), dim3(kBlock), 0, st, order, rgb, nvis, keys);
+  hipLaunchKernelGGL(k_depth_keys, dim3(blocks), dim3(kBlock), 0, st, order, rgb, nvis, keys, K, counts);
+  return hipGetLastError();
+}
+
+hipError_t sort_depth(uint32_t *order, const uint32_t *nvis, uint64_t n_max, uint32_t *keys, uint32_t *keys_alt,
+                      uint32_t *vals_alt, void *tmp, hipStream_t st, bool *in_alt, const uint32_t *count,
+                      uint32_t *count_sorted) {
   return radix_passes_t<uint32_t>(keys, order, keys_alt, vals_alt, n_max, nvis, 0, 32, tmp, st, in_alt, count,
                                   count_sorted);
 }
