@@ -60,7 +60,10 @@ def raster_traffic(args):
     c = RASTER_COUNTERS
     if (args.precision, args.splits, args.group) != (c["precision"], c["splits"], c["group"]):
         return None
-    if raster_source_hash() != c["sha256"]:
+    try:
+        if raster_source_hash() != c["sha256"]:
+            return None
+    except OSError:          # sources not shipped beside the library
         return None
     return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
 

@@ -49,10 +49,22 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 template <int PREC>
 struct Narrow;
 
+// The encoders take their argument as a materialised FP32 value (the empty asm pins it to a
+// register): otherwise the compiler may fuse the FP32 multiply that produced it with the
+// conversion into one mixed-precision FMA, which rounds once instead of twice, and may do so
+// in one kernel and not in another, so the same Gaussian's row would differ between the
+// ungrouped, grouped and batched rasterizers.
+__device__ __forceinline__ float as_fp32(float x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 template <>
 struct Narrow<GS_PREC_FP16_MFMA> {
   static constexpr float kScale = 2048.0f;            // 2^11
-  __device__ static __forceinline__ uint16_t enc(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+  __device__ static __forceinline__ uint16_t enc(float x) {
+    return __builtin_bit_cast(uint16_t, (_Float16)as_fp32(x));
+  }
   __device__ static __forceinline__ float dec(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
   __device__ static __forceinline__ float16v mma(short8 a, short8 b, float16v c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a), __builtin_bit_cast(half8, b), c, 0,
@@ -63,7 +75,7 @@ struct Narrow<GS_PREC_FP16_MFMA> {
 template <>
 struct Narrow<GS_PREC_BF16_MFMA> {
   static constexpr float kScale = 256.0f;             // 2^8
-  __device__ static __forceinline__ uint16_t enc(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+  __device__ static __forceinline__ uint16_t enc(float x) { return __builtin_bit_cast(uint16_t, (__bf16)as_fp32(x)); }
   __device__ static __forceinline__ float dec(uint16_t h) { return (float)__builtin_bit_cast(__bf16, h); }
   __device__ static __forceinline__ float16v mma(short8 a, short8 b, float16v c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,

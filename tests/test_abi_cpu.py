@@ -178,3 +178,22 @@ def test_batch_argument_checks():
     assert L.gs_rasterize_batch(jobs, 1, C.byref(o), counter, None) == gs.GS_ERR_INVALID_ARG
     bad = gs.options(group=3)
     assert L.gs_rasterize_batch(jobs, 1, C.byref(bad), counter, None) == gs.GS_ERR_UNSUPPORTED
+
+
+def test_rasterizer_operands_rounded_from_fp32(tmp_path):
+    """The MFMA rasterizer's FP16/BF16 operands are rounded from materialised FP32 values: the
+    gfx950 code holds no mixed-precision FMA with a 16-bit result (those round once, straight
+    from the unrounded product, and the compiler may form them in one kernel and not another,
+    so the grouped, ungrouped and batched rasterizers would disagree)."""
+    import re
+    import subprocess
+    from paper_2605_17855_amd import build
+    src = os.path.join(build.CSRC, "gs_raster_mfma.hip")
+    out = tmp_path / "raster.s"
+    flags = [f for f in build.FLAGS]
+    r = subprocess.run([build.HIPCC, *flags, "--offload-device-only", "-S", "-c", src, "-o", str(out)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    asm = out.read_text()
+    assert "v_mfma_f32_32x32x16_f16" in asm
+    assert not re.search(r"v_(fma|mad)_mix(lo|hi)_(f16|bf16)", asm)
