@@ -40,8 +40,8 @@ PEAK_FP32_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (packed) x 2 (FMA) x
 # FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by what the same counters read for a plain
 # device copy of known size (x2 and x1).  They describe the kernel built from the source and
 # compiler flags hashed in `sha256`; after any change to either the traffic is reported as null.
-RASTER_COUNTERS = dict(sha256="50798a1122752d11cf4b596e5020215fc57c5576ffa66d91d494ee7052f9d41f",
-                       fetch_kib=55225, write_kib=25204, fetch_scale=2.0, write_scale=1.0,
+RASTER_COUNTERS = dict(sha256="ae9e1b4bbf2a360f681c162b06f98ed9a79e82ad385b05d1962e9c7c553640ea",
+                       fetch_kib=55166, write_kib=25219, fetch_scale=2.0, write_scale=1.0,
                        precision="fp16", splits=2, group=1)
 
 
