@@ -65,13 +65,25 @@ enum {
   GS_AUX_NBLEND = 8u        /* Gaussians blended (alpha >= 1/255, before the stop), as a float count */
 };
 
+/* gs_options.flags */
+enum {
+  /* Opacity-aware tile culling (the tighter ellipse-tile intersection the paper's method is
+   * combined with; group 1 only): a Gaussian is listed in a tile of its footprint square only
+   * while some point of the rectangle spanned by the tile's pixel centres satisfies
+   * q(p) = (p - mu')^T conic (p - mu') <= 2 ln(255 o) + 0.01, i.e. while its alpha can reach
+   * the 1/255 cut there (the 0.01 margin covers FP32/FP16 rounding).  Every dropped pair has
+   * alpha below the cut at every pixel of the tile, so the image, T_final and the weight sum
+   * are those of the full lists; entry counts and GS_AUX_NEVAL counts are smaller. */
+  GS_OPT_TIGHT = 1u
+};
+
 typedef struct {
   int32_t group;            /* tile-group side G: 1, 2 or 4 (cross-tile grouping) */
   int32_t precision;        /* gs_precision */
   int32_t splits;           /* MFMA paths: 1..3 FP16/BF16 pieces per Gaussian coefficient (hi, lo, lo2) */
   float bg[3];              /* background colour added with the final transmittance */
   uint32_t aux_flags;       /* GS_AUX_* */
-  int32_t reserved;         /* must be 0 */
+  uint32_t flags;           /* GS_OPT_* (other bits must be 0) */
 } gs_options;
 
 /* Pinhole camera.  World -> camera: p_cam = R p + t, x right, y down, z forward.

@@ -31,6 +31,13 @@ VISIBLE = 1
 AMB_ZNEAR = 2
 AMB_EDGES = 4 | 8 | 16 | 32
 PIX_ALPHA, PIX_T, PIX_TIE, PIX_MEMBER = 1, 2, 4, 8
+# Opacity-aware tile culling (the tighter ellipse-tile intersection the paper combines its
+# method with): a Gaussian stays in a tile's list while the minimum of its quadratic form over
+# the rectangle spanned by the tile's pixel centres is at most 2 ln(255 o) + TIGHT_MARGIN.  The
+# margin keeps every pair whose alpha could reach the 1/255 cut under FP32/FP16 rounding;
+# TIGHT_GUARD is the band around the boundary inside which FP32 inputs may decide differently.
+TIGHT_MARGIN = 0.01
+TIGHT_GUARD = 1e-3
 
 _dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
 _fp = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
@@ -143,6 +150,52 @@ def tile_lists(rec: dict, cam, tiles):
     for t, g in per.items():
         ids[start[t]:start[t + 1]] = g
     return start, ids[:int(start[-1])]
+
+
+def tile_qmin(rec: dict, gids, tiles, cam):
+    """Minimum over the rectangle of pixel centres of tile t of q(p) = (p - mu')^T conic
+    (p - mu'), for each (Gaussian gids[i], tile tiles[i]).  Zero when the centre lies in
+    the rectangle; otherwise the minimum lies on an edge, where q is a convex parabola in the
+    free coordinate, minimised by clamping its vertex to the edge."""
+    tx_n = (cam.width + TILE - 1) // TILE
+    gids = np.asarray(gids, np.int64)
+    tiles = np.asarray(tiles, np.int64)
+    a, b, c = rec["conic"][gids, 0], rec["conic"][gids, 1], rec["conic"][gids, 2]
+    ux, uy = rec["xy"][gids, 0], rec["xy"][gids, 1]
+    x0 = (tiles % tx_n) * TILE + 0.5
+    y0 = (tiles // tx_n) * TILE + 0.5
+    x1, y1 = x0 + TILE - 1, y0 + TILE - 1
+    q = np.full(gids.shape, np.inf)
+    for ey in (y0, y1):
+        dy = ey - uy
+        dx = np.clip(-b * dy / a, x0 - ux, x1 - ux)
+        q = np.minimum(q, a * dx * dx + 2 * b * dx * dy + c * dy * dy)
+    for ex in (x0, x1):
+        dx = ex - ux
+        dy = np.clip(-b * dx / c, y0 - uy, y1 - uy)
+        q = np.minimum(q, a * dx * dx + 2 * b * dx * dy + c * dy * dy)
+    inside = (ux >= x0) & (ux <= x1) & (uy >= y0) & (uy <= y1)
+    return np.where(inside, 0.0, q)
+
+
+def tight_keep(rec: dict, gids, tiles, cam):
+    """(keep, ambiguous) for each (Gaussian, tile) pair under opacity-aware culling."""
+    gids = np.asarray(gids, np.int64)
+    bound = 2.0 * np.log(255.0 * rec["opacity"][gids]) + TIGHT_MARGIN
+    q = tile_qmin(rec, gids, tiles, cam)
+    return q <= bound, np.abs(q - bound) < TIGHT_GUARD
+
+
+def tight_lists(rec: dict, cam, start, ids):
+    """The tile lists (start, ids) of `lists(rec, cam, 1)` without the pairs that
+    opacity-aware culling drops; also the per-entry ambiguity of the decision."""
+    tx, ty, _, _ = grid(cam, 1)
+    tiles = np.repeat(np.arange(tx * ty), np.diff(start))
+    keep, amb = tight_keep(rec, ids, tiles, cam)
+    counts = np.bincount(tiles[keep], minlength=tx * ty)
+    st = np.zeros(tx * ty + 1, np.int64)
+    st[1:] = np.cumsum(counts)
+    return st, ids[keep], amb, keep
 
 
 def ambiguous_membership(rec: dict, cam):

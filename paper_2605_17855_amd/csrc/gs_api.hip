@@ -61,7 +61,9 @@ gs_status check_options(const gs_options *o) {
   }
   if (o->aux_flags & ~(uint32_t)(GS_AUX_TFINAL | GS_AUX_WSUM | GS_AUX_NEVAL | GS_AUX_NBLEND))
     return fail(GS_ERR_INVALID_ARG, "aux_flags 0x%x", o->aux_flags);
-  if (o->reserved != 0) return fail(GS_ERR_INVALID_ARG, "reserved must be 0");
+  if (o->flags & ~(uint32_t)GS_OPT_TIGHT) return fail(GS_ERR_INVALID_ARG, "flags 0x%x", o->flags);
+  if ((o->flags & GS_OPT_TIGHT) && o->group != 1)
+    return fail(GS_ERR_UNSUPPORTED, "opacity-aware tile culling needs group 1");
   for (int i = 0; i < 3; ++i)
     if (!std::isfinite(o->bg[i])) return fail(GS_ERR_INVALID_ARG, "background non-finite");
   return GS_OK;
@@ -222,7 +224,8 @@ gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
   if (K >= (1ull << 32)) return fail(GS_ERR_UNSUPPORTED, "%llu entries >= 2^32", (unsigned long long)K);
   if ((int64_t)V > n) return fail(GS_ERR_INVALID_ARG, "visible count %u exceeds n", V);
   // one thread per entry and the bin digits (also clears the bin ranges)
-  GS_HIP(gsi::bin_and_sort(proj->order, w.dpos, V, K, proj->rect, g, w.bkey, bins->vals, w.bkey_alt, w.bval_alt,
+  GS_HIP(gsi::bin_and_sort(proj->order, w.dpos, V, K, proj->rect, proj->xy, proj->conic,
+                           (opt->flags & GS_OPT_TIGHT) != 0, g, w.bkey, bins->vals, w.bkey_alt, w.bval_alt,
                            bins->ranges, w.sort, st, &in_alt));
   const uint32_t *kf = in_alt ? w.bkey_alt : w.bkey;
   const uint32_t *ranks = in_alt ? w.bval_alt : bins->vals;
@@ -270,7 +273,7 @@ gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_op
   if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID_ARG, "workspace %zu bytes, need %zu", ws_bytes, need);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
-  GS_HIP(gsi::launch_preprocess(*scene, *cam, g, *out, st));
+  GS_HIP(gsi::launch_preprocess(*scene, *cam, g, *out, (opt->flags & GS_OPT_TIGHT) != 0, st));
   GS_HIP(gsi::launch_scan_compact(out->count, out->offset, scene->n, out->order, out->n_visible, ws, st));
   return GS_OK;
 }
@@ -321,7 +324,7 @@ gs_status gs_render(const gs_scene *scene, const gs_camera *cam, const gs_option
   if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID_ARG, "workspace %zu bytes, need %zu", ws_bytes, need);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
-  GS_HIP(gsi::launch_preprocess(*scene, *cam, g, *proj, st));
+  GS_HIP(gsi::launch_preprocess(*scene, *cam, g, *proj, (opt->flags & GS_OPT_TIGHT) != 0, st));
   GS_HIP(gsi::launch_scan_compact(proj->count, proj->offset, scene->n, proj->order, proj->n_visible, ws, st));
   if ((s = do_bin_sort(proj, scene->n, cam, opt, bins, n_keys, ws, st))) return s;
   const gsi::RasterJob j = make_job(*proj, *bins, g, image, aux);

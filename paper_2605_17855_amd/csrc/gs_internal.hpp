@@ -79,9 +79,49 @@ inline int bits_for(uint64_t v) {  // bits needed to represent values 0..v-1 (at
   return b;
 }
 
+// ---- opacity-aware tile culling (GS_OPT_TIGHT) ---------------------------------
+// A Gaussian with centre (mx, my), conic (a, b, c) and opacity o stays in a tile while the
+// ellipse q(p) = (p - mu')^T conic (p - mu') <= Q, Q = 2 ln(255 o) + kTightMargin, meets the
+// rectangle spanned by the tile's pixel centres.  Per tile row the ellipse's part inside the
+// row's band of pixel-centre rows is convex, so the tiles it meets are one contiguous span:
+// its x-extent runs from the left boundary at the band height nearest the ellipse's leftmost
+// point to the right boundary at the height nearest its rightmost point.  The preprocess
+// counts entries and the binning places them with this one function, in FP64, from the same
+// stored values, so both agree exactly.
+constexpr double kTightMargin = 0.01;
+
+__device__ __forceinline__ double tight_bound(float opacity) {
+  return 2.0 * log(255.0 * (double)opacity) + kTightMargin;
+}
+
+// Tiles [*lo, *hi] of tile row ty within the footprint columns [x0, x1] that the ellipse meets
+// (*lo > *hi when none).
+__device__ __forceinline__ void tight_row_span(double mx, double my, double a, double b, double c, double Q, int ty,
+                                               int x0, int x1, int *lo, int *hi) {
+  *lo = x0;
+  *hi = x0 - 1;
+  const double det = a * c - b * b;
+  if (!(Q >= 0.0) || !(det > 0.0) || !(a > 0.0) || !(c > 0.0)) return;
+  const double ymax = sqrt(Q * a / det);                           // the ellipse's half-height
+  const double dy0 = fmax((double)(ty * kTile) + 0.5 - my, -ymax);
+  const double dy1 = fmin((double)(ty * kTile) + (kTile - 0.5) - my, ymax);
+  if (dy0 > dy1) return;
+  const double ys = b * sqrt(Q / (c * det));                      // height of the leftmost point
+  const double dl = fmin(fmax(ys, dy0), dy1), dr = fmin(fmax(-ys, dy0), dy1);
+  const double xl = mx + (-b * dl - sqrt(fmax(a * Q - det * dl * dl, 0.0))) / a;
+  const double xr = mx + (-b * dr + sqrt(fmax(a * Q - det * dr * dr, 0.0))) / a;
+  // tile tx meets [xl, xr] when 16 tx + 0.5 <= xr and 16 tx + 15.5 >= xl
+  const double l = fmax(ceil((xl - (kTile - 0.5)) / kTile), (double)x0);
+  const double h = fmin(floor((xr - 0.5) / kTile), (double)x1);
+  if (l <= h) {
+    *lo = (int)l;
+    *hi = (int)h;
+  }
+}
+
 // ---- preprocess + scans ------------------------------------------------------
 hipError_t launch_preprocess(const gs_scene &s, const gs_camera &c, const Grid &g, const gs_projected &o,
-                             hipStream_t st);
+                             bool tight, hipStream_t st);
 // Scans (reduce-then-scan); tmp holds scan_tmp_bytes(n) bytes.
 size_t scan_tmp_bytes(int64_t n);
 // out[0..n] = exclusive prefix sum of in[0..n) (out[n] = total); order[0..*nvis) = indices i
@@ -116,9 +156,11 @@ hipError_t sort_depth(uint32_t *order, const uint32_t *nvis, uint64_t n_max, uin
 // Entries of the V depth-ordered visible Gaussians (the i-th one's first entry at dpos[i])
 // into (bkey, bval = the Gaussian's rank i in depth order), then a stable sort on the bin bits.
 // Also clears the bin ranges ranges[0 .. 2 nbins) before k_ranges fills the non-empty ones.
+// With tight (group 1), entries follow the culled spans of tight_row_span.
 hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V, uint64_t K, const uint16_t *rect,
-                        const Grid &g, uint32_t *bkey, uint32_t *bval, uint32_t *bkey_alt, uint32_t *bval_alt,
-                        uint32_t *ranges, void *tmp, hipStream_t st, bool *in_alt);
+                        const double *xy, const float *conic, bool tight, const Grid &g, uint32_t *bkey,
+                        uint32_t *bval, uint32_t *bkey_alt, uint32_t *bval_alt, uint32_t *ranges, void *tmp,
+                        hipStream_t st, bool *in_alt);
 // Bin ranges (zeroed before), masks (group > 1), the 64-bit keys and the Gaussian indices
 // (vals[i] = order[ranks[i]]; ranks may alias vals) of the sorted entries; dkeys[r] are the
 // depth bits of the r-th Gaussian in depth order.

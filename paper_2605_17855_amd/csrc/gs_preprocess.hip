@@ -28,6 +28,7 @@ struct PreArgs {
   float fxf, fyf, limx, limy;
   float campos[3];
   int TX, TY, G;
+  int tight;   // opacity-aware tile culling (group 1)
   double2 *xy;
   float4 *conic;
   float4 *rgb;
@@ -143,6 +144,16 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
       if (x0 <= x1 && y0 <= y1) {
         const int G = a.G;
         cnt = (uint32_t)((x1 / G - x0 / G + 1) * (y1 / G - y0 / G + 1));
+        if (a.tight) {
+          // entries of the tiles the alpha-cut ellipse meets (the binning walks the same spans)
+          const double Q = tight_bound(opac);
+          cnt = 0;
+          for (int ty = y0; ty <= y1; ++ty) {
+            int lo, hi;
+            tight_row_span(mx, my, (double)ca, (double)cb, (double)cc, Q, ty, x0, x1, &lo, &hi);
+            cnt += (uint32_t)(hi - lo + 1);
+          }
+        }
         rc = make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)(x1 + 1),
                           (unsigned short)(y1 + 1));
         // colour
@@ -348,7 +359,7 @@ hipError_t scan_impl(const uint32_t *in, const uint32_t *idx, uint64_t *out, int
 }  // namespace
 
 hipError_t launch_preprocess(const gs_scene &s, const gs_camera &c, const Grid &g, const gs_projected &o,
-                             hipStream_t st) {
+                             bool tight, hipStream_t st) {
   if (s.n == 0) return hipSuccess;
   PreArgs a;
   a.n = s.n;
@@ -370,6 +381,7 @@ hipError_t launch_preprocess(const gs_scene &s, const gs_camera &c, const Grid &
   for (int i = 0; i < 3; ++i)
     a.campos[i] = (float)(-((double)c.R[i] * c.t[0] + (double)c.R[3 + i] * c.t[1] + (double)c.R[6 + i] * c.t[2]));
   a.TX = g.TX; a.TY = g.TY; a.G = g.G;
+  a.tight = tight ? 1 : 0;
   a.xy = reinterpret_cast<double2 *>(o.xy);
   a.conic = reinterpret_cast<float4 *>(o.conic);
   a.rgb = reinterpret_cast<float4 *>(o.rgb);

@@ -244,10 +244,11 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, co
 // entry finds its Gaussian by binary search there.
 constexpr int kBinItems = 1024;
 
+template <bool TIGHT>
 __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const uint64_t *dpos, uint32_t nvis,
-                                                    uint64_t K, const ushort4 *rect, int G, int GX,
-                                                    uint32_t *bin_keys, uint32_t *vals, uint32_t *ranges,
-                                                    uint64_t nranges) {
+                                                    uint64_t K, const ushort4 *rect, const double2 *xy,
+                                                    const float4 *conic, int G, int GX, uint32_t *bin_keys,
+                                                    uint32_t *vals, uint32_t *ranges, uint64_t nranges) {
   __shared__ uint64_t s_pos[kBinItems + 1];
   __shared__ uint32_t s_first;
   // the bin ranges start empty (k_ranges writes the non-empty ones, two kernels later)
@@ -290,9 +291,32 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
       const uint32_t g = order[rank];
       const uint32_t j = (uint32_t)(e - s_pos[lo]);
       const ushort4 r = rect[g];
-      const int gx0 = r.x / G, gx1 = (r.z - 1) / G, gy0 = r.y / G;
-      const int wdt = gx1 - gx0 + 1;
-      const int gy = gy0 + (int)(j / (uint32_t)wdt), gx = gx0 + (int)(j % (uint32_t)wdt);
+      int gx, gy;
+      if (TIGHT) {
+        // the j-th tile of the culled footprint, walking the per-row spans (group 1)
+        const double2 m = xy[g];
+        const float4 co = conic[g];
+        const double Q = tight_bound(co.w);
+        uint32_t left = j;
+        gx = r.x;
+        gy = r.w - 1;
+        for (int ty = r.y; ty < r.w; ++ty) {
+          int lo, hi;
+          tight_row_span(m.x, m.y, (double)co.x, (double)co.y, (double)co.z, Q, ty, r.x, r.z - 1, &lo, &hi);
+          const uint32_t cnt = (uint32_t)(hi - lo + 1);
+          if (left < cnt) {
+            gx = lo + (int)left;
+            gy = ty;
+            break;
+          }
+          left -= cnt;
+        }
+      } else {
+        const int gx0 = r.x / G, gx1 = (r.z - 1) / G, gy0 = r.y / G;
+        const int wdt = gx1 - gx0 + 1;
+        gy = gy0 + (int)(j / (uint32_t)wdt);
+        gx = gx0 + (int)(j % (uint32_t)wdt);
+      }
       bin_keys[e] = (uint32_t)(gy * GX + gx);
       vals[e] = rank;   // the Gaussian's rank in depth order; k_ranges turns it into its index
     }
@@ -440,13 +464,21 @@ hipError_t sort_depth(uint32_t *order, const uint32_t *nvis, uint64_t n_max, uin
 }
 
 hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V, uint64_t K, const uint16_t *rect,
-                        const Grid &g, uint32_t *bkey, uint32_t *bval, uint32_t *bkey_alt, uint32_t *bval_alt,
-                        uint32_t *ranges, void *tmp, hipStream_t st, bool *in_alt) {
+                        const double *xy, const float *conic, bool tight, const Grid &g, uint32_t *bkey,
+                        uint32_t *bval, uint32_t *bkey_alt, uint32_t *bval_alt, uint32_t *ranges, void *tmp,
+                        hipStream_t st, bool *in_alt) {
   *in_alt = false;
   const uint64_t nranges = 2 * (uint64_t)g.nbins;
   if (K == 0) return launch_fill_u32(ranges, nranges, 0u, st);
-  hipLaunchKernelGGL(k_binning, dim3(grid_for(K, kBinItems)), dim3(kBlock), 0, st, order, dpos, V, K,
-                     reinterpret_cast<const ushort4 *>(rect), g.G, g.GX, bkey, bval, ranges, nranges);
+  const ushort4 *r4 = reinterpret_cast<const ushort4 *>(rect);
+  const double2 *m2 = reinterpret_cast<const double2 *>(xy);
+  const float4 *c4 = reinterpret_cast<const float4 *>(conic);
+  if (tight)
+    hipLaunchKernelGGL(k_binning<true>, dim3(grid_for(K, kBinItems)), dim3(kBlock), 0, st, order, dpos, V, K, r4, m2,
+                       c4, g.G, g.GX, bkey, bval, ranges, nranges);
+  else
+    hipLaunchKernelGGL(k_binning<false>, dim3(grid_for(K, kBinItems)), dim3(kBlock), 0, st, order, dpos, V, K, r4,
+                       m2, c4, g.G, g.GX, bkey, bval, ranges, nranges);
   if (K <= 1) return hipGetLastError();
   return radix_passes_t<uint32_t>(bkey, bval, bkey_alt, bval_alt, K, nullptr, 0, bits_for((uint64_t)g.nbins), tmp,
                                   st, in_alt);

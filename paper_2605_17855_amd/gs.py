@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgs.so")
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_UNSUPPORTED, GS_ERR_CAPACITY, GS_ERR_HIP = range(5)
 GS_PREC_FP32, GS_PREC_FP16_MFMA, GS_PREC_BF16_MFMA = range(3)
 GS_AUX_TFINAL, GS_AUX_WSUM, GS_AUX_NEVAL, GS_AUX_NBLEND = 1, 2, 4, 8
+GS_OPT_TIGHT = 1
 PRECISIONS = {"fp32": GS_PREC_FP32, "fp16": GS_PREC_FP16_MFMA, "bf16": GS_PREC_BF16_MFMA}
 TILE = 16
 
@@ -31,7 +32,7 @@ class GsError(RuntimeError):
 
 class gs_options(C.Structure):
     _fields_ = [("group", C.c_int32), ("precision", C.c_int32), ("splits", C.c_int32),
-                ("bg", C.c_float * 3), ("aux_flags", C.c_uint32), ("reserved", C.c_int32)]
+                ("bg", C.c_float * 3), ("aux_flags", C.c_uint32), ("flags", C.c_uint32)]
 
 
 class gs_camera(C.Structure):
@@ -113,14 +114,15 @@ def _check(status: int):
         raise GsError(status, lib().gs_last_error().decode())
 
 
-def options(group: int = 1, precision="fp32", splits: int = 2, bg=(0.0, 0.0, 0.0), aux_flags: int = 0) -> gs_options:
+def options(group: int = 1, precision="fp32", splits: int = 2, bg=(0.0, 0.0, 0.0), aux_flags: int = 0,
+            tight: bool = False) -> gs_options:
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     o = gs_options()
     o.group, o.precision, o.splits = group, precision, splits
     o.bg = (C.c_float * 3)(*bg)
     o.aux_flags = aux_flags
-    o.reserved = 0
+    o.flags = GS_OPT_TIGHT if tight else 0
     return o
 
 

@@ -66,7 +66,7 @@ def sampled_tiles(cam, count, seed):
     return np.sort(rng.choice(tx * ty, size=min(count, tx * ty), replace=False))
 
 
-def check_bins(rec, cam, r, n_keys, group):
+def check_bins(rec, cam, r, n_keys, group, tight=False):
     b = bins_numpy(r, n_keys)
     keys, vals = b["keys"], b["vals"]
     # ascending keys; key = (bin << 32) | float bits of the GPU depth of its Gaussian
@@ -92,6 +92,13 @@ def check_bins(rec, cam, r, n_keys, group):
     ob = np.repeat(np.arange(nb), np.diff(st))
     keep_o = ~amb[ids]
     keep_g = ~amb[vals]
+    if tight:
+        # the culled lists; (Gaussian, tile) pairs whose culling decision lies in the guard band
+        # are left out on both sides
+        keep_t, amb_t = oracle.tight_keep(rec, ids, ob, cam)
+        bad = set(zip(ids[amb_t].tolist(), ob[amb_t].tolist()))
+        keep_o &= keep_t & ~amb_t
+        keep_g &= np.array([(int(g), int(b)) not in bad for g, b in zip(vals, bins_of)], bool) if bad else True
     assert np.array_equal(ob[keep_o], bins_of[keep_g])
     og, gg = ids[keep_o], vals[keep_g].astype(np.int64)
     mismatch = np.nonzero(og != gg)[0]

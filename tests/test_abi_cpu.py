@@ -53,7 +53,8 @@ def test_num_bins():
     ("splits", 0, gs.GS_ERR_INVALID_ARG),
     ("aux_flags", 16, gs.GS_ERR_INVALID_ARG),
     ("aux_flags", 32, gs.GS_ERR_INVALID_ARG),
-    ("reserved", 1, gs.GS_ERR_INVALID_ARG),
+    ("flags", 2, gs.GS_ERR_INVALID_ARG),
+    ("flags", 0x80000000, gs.GS_ERR_INVALID_ARG),
 ])
 def test_rasterize_rejects_bad_options(field, value, status):
     L = gs.lib()
@@ -64,6 +65,16 @@ def test_rasterize_rejects_bad_options(field, value, status):
     img = C.c_void_p(1)
     assert L.gs_rasterize(C.byref(p), C.byref(b), C.byref(_cam()), C.byref(o), img, None, None) == status
     assert L.gs_last_error()
+
+
+def test_tight_culling_needs_group_one():
+    L = gs.lib()
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1, 1, 1)
+    b = gs.gs_bins(1, 1, 1, 16, 1)
+    for group, status in ((2, gs.GS_ERR_UNSUPPORTED), (4, gs.GS_ERR_UNSUPPORTED)):
+        o = gs.options(precision="fp16", group=group, tight=True)
+        assert L.gs_rasterize(C.byref(p), C.byref(b), C.byref(_cam()), C.byref(o), C.c_void_p(1), None,
+                              None) == status
 
 
 def test_fp16_three_splits_unsupported():

@@ -501,3 +501,83 @@ def test_separable_power_expansion_is_exact():
             dx, dy = x - u, y - v
             want = -(a * dx * dx + 2 * b * dx * dy + c * dy * dy) / 2 + lno
             assert sum(p * q for p, q in zip(k, phi)) == want
+
+
+# ------------------------------------------- opacity-aware tile culling ---
+
+def test_tight_qmin_is_the_rectangle_minimum():
+    """tile_qmin against a bounded numerical minimiser of the same quadratic over the
+    rectangle of the tile's pixel centres."""
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(11)
+    n = 60
+    L = rng.normal(0, 1, (n, 2, 2)) * rng.uniform(0.02, 0.5, (n, 1, 1))
+    conic = np.einsum("nij,nkj->nik", L, L) + 1e-3 * np.eye(2)
+    rec = {"conic": np.stack([conic[:, 0, 0], conic[:, 0, 1], conic[:, 1, 1]], 1),
+           "xy": rng.uniform(-20, 84, (n, 2))}
+    cam = scenes.pinhole(64, 64, 60.0)
+    tiles = rng.integers(0, 16, n)
+    q = oracle.tile_qmin(rec, np.arange(n), tiles, cam)
+    for i in range(n):
+        x0, y0 = (tiles[i] % 4) * 16 + 0.5, (tiles[i] // 4) * 16 + 0.5
+        a, b, c = rec["conic"][i]
+        f = lambda p: a * (p[0] - rec["xy"][i, 0]) ** 2 + 2 * b * (p[0] - rec["xy"][i, 0]) * (p[1] - rec["xy"][i, 1]) \
+            + c * (p[1] - rec["xy"][i, 1]) ** 2
+        best = min(minimize(f, s, bounds=[(x0, x0 + 15), (y0, y0 + 15)], method="L-BFGS-B",
+                            options=dict(ftol=1e-15, gtol=1e-12)).fun
+                   for s in ([x0, y0], [x0 + 15, y0 + 15], [x0 + 7.5, y0 + 7.5]))
+        assert q[i] <= best + 1e-9 * (1 + best)
+        assert best - q[i] <= 1e-6 * (1 + best)
+
+
+def test_tight_culling_drops_only_pairs_below_the_cut_everywhere():
+    """Every dropped (Gaussian, tile) pair has alpha < 1/255 at all 256 pixel centres (the
+    compositing would skip each of them), and every kept pair is close to the cut somewhere."""
+    sc, cam = scenes.small_camera_space()
+    rec = oracle.preprocess(sc, cam)
+    start, ids, _ = oracle.lists(rec, cam, 1)
+    tx, _, _, _ = oracle.grid(cam)
+    tiles = np.repeat(np.arange(len(start) - 1), np.diff(start))
+    keep, _ = oracle.tight_keep(rec, ids, tiles, cam)
+    assert 0.2 < keep.mean() < 0.95
+    px, py = np.meshgrid(np.arange(16) + 0.5, np.arange(16) + 0.5)
+    for g, t, k in zip(ids, tiles, keep):
+        dx = (t % tx) * 16 + px - rec["xy"][g, 0]
+        dy = (t // tx) * 16 + py - rec["xy"][g, 1]
+        a, b, c = rec["conic"][g]
+        q = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+        alpha = np.minimum(0.99, rec["opacity"][g] * np.exp(-0.5 * q))
+        if not k:
+            assert alpha.max() < 1.0 / 255.0
+        else:
+            assert q.min() <= 2 * np.log(255 * rec["opacity"][g]) + oracle.TIGHT_MARGIN + 2 * (abs(a) + abs(b) + abs(c)) * 16
+
+
+def test_tight_lists_leave_the_image_unchanged():
+    sc, cam = scenes.small_camera_space()
+    rec = oracle.preprocess(sc, cam)
+    start, ids, _ = oracle.lists(rec, cam, 1)
+    full = oracle.composite(rec, cam, start, ids, nthreads=4)
+    st2, ids2, _, keep = oracle.tight_lists(rec, cam, start, ids)
+    assert ids2.size < 0.9 * ids.size
+    tight = oracle.composite(rec, cam, st2, ids2, nthreads=4)
+    for k in ("image", "tfinal", "wsum"):
+        assert np.array_equal(full[k], tight[k])
+    assert (tight["neval"] <= full["neval"]).all() and tight["neval"].sum() < full["neval"].sum()
+
+
+def test_tight_isotropic_closed_form():
+    """An isotropic Gaussian keeps exactly the tiles whose pixel-centre rectangle lies within
+    rho = sigma sqrt(2 ln(255 o) + margin) of its centre (distance from a point to a box)."""
+    sigma, o = 9.0, 0.6
+    cam = scenes.pinhole(160, 128, 60.0)
+    rec = {"conic": np.array([[1 / sigma ** 2, 0.0, 1 / sigma ** 2]]), "xy": np.array([[70.3, 57.9]]),
+           "opacity": np.array([o])}
+    tiles = np.arange(10 * 8)
+    keep, _ = oracle.tight_keep(rec, np.zeros(tiles.size, np.int64), tiles, cam)
+    rho = sigma * np.sqrt(2 * np.log(255 * o) + oracle.TIGHT_MARGIN)
+    x0, y0 = (tiles % 10) * 16 + 0.5, (tiles // 10) * 16 + 0.5
+    ddx = np.maximum(np.maximum(x0 - 70.3, 70.3 - (x0 + 15)), 0)
+    ddy = np.maximum(np.maximum(y0 - 57.9, 57.9 - (y0 + 15)), 0)
+    assert np.array_equal(keep, np.hypot(ddx, ddy) <= rho)
+    assert 4 < keep.sum() < 40
