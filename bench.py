@@ -81,6 +81,7 @@ def parse():
     ap.add_argument("--splits", type=int, default=2)
     ap.add_argument("--group", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tight", action="store_true", help="skip the opacity-aware tile culling variant")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 plain comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle compositing time")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
@@ -243,7 +244,8 @@ def serve(gs, torch, args):
     log("serving: generating 8 resident scenes (0.5M..3M Gaussians)")
     scs = scenes.serving_scenes()
     dss = [gs.DeviceScene(s) for s in scs]
-    opt = gs.options(group=1, precision=args.precision, splits=args.splits)
+    # opacity-aware tile culling unless disabled: the images are those of the full lists
+    opt = gs.options(group=1, precision=args.precision, splits=args.splits, tight=not args.no_tight)
     # per-scene duplicated entries per pixel, from one 1080p render each
     kpp = {}
     for i, sc in enumerate(scs):
@@ -283,7 +285,8 @@ def serve(gs, torch, args):
             "retries": st.retries, "batches": st.batches, "mean_batch": st.mean_batch,
             "max_inflight_jobs": st.max_inflight_jobs, "pool_bytes": pool,
             "max_reserved_bytes": st.max_reserved_bytes, "slots": slots,
-            "precision": args.precision, "resident_gaussians": int(sum(s.n for s in scs))}
+            "precision": args.precision, "tight_culling": not args.no_tight,
+            "resident_gaussians": int(sum(s.n for s in scs))}
 
 
 def sweep(gs, torch, args):
@@ -380,6 +383,28 @@ def main():
                    "p50_ms": float(np.percentile(fm32, 50)), "p99_ms": float(np.percentile(fm32, 99)),
                    "raster_avg_ms": float(np.mean(rm32)), "stage_ms": timed_frames.stages}
 
+    tight = None
+    if not args.no_tight and args.group == 1:
+        # the same frames with opacity-aware tile culling (identical images, fewer entries)
+        log("timing the opacity-aware tile culling variant")
+        rend_t = gs.Renderer(sc.n, 1920, 1080, group=1)
+        res = {}
+        for prec, splits in ((args.precision, args.splits), ("fp32", 2)):
+            el, fm, rm = timed_frames(gs, torch, ds, cams, rend_t, gs.options(precision=prec, splits=splits,
+                                                                               tight=True),
+                                      args.steps, args.warmup)
+            res[prec] = {"frames_per_s": args.steps / el, "p50_ms": float(np.percentile(fm, 50)),
+                         "p99_ms": float(np.percentile(fm, 99)), "raster_avg_ms": float(np.mean(rm)),
+                         "stage_ms": timed_frames.stages}
+        ek, eb, ent, _ = work_units(gs, torch, ds, cams, rend_t, dict(precision=args.precision, splits=args.splits,
+                                                                       tight=True), args.steps)
+        t_raster_s = res[args.precision]["raster_avg_ms"] * args.steps / 1e3
+        tight = {"option": "GS_OPT_TIGHT", **res[args.precision],
+                 "fp32_plain_frames_per_s": res["fp32"]["frames_per_s"],
+                 "speedup_vs_fp32": res[args.precision]["frames_per_s"] / res["fp32"]["frames_per_s"],
+                 "entries_per_frame": ent, "evals_per_frame": ek / args.steps,
+                 "roofline_frac": (FLOPS_PER_EVAL * ek + FLOPS_PER_BLEND * eb) / t_raster_s / 1e12 / PEAK_FP32_TFLOPS}
+
     cpu = None
     quality = {}
     if not args.no_cpu_baseline:
@@ -412,6 +437,7 @@ def main():
         "raster_speedup_vs_fp32": (compare["raster_avg_ms"] / float(np.mean(raster_ms))) if compare else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "tight_culling": tight,
         "serving": serving,
     }
     print(json.dumps(line), flush=True)

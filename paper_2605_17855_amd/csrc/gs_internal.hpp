@@ -85,37 +85,68 @@ inline int bits_for(uint64_t v) {  // bits needed to represent values 0..v-1 (at
 // rectangle spanned by the tile's pixel centres.  Per tile row the ellipse's part inside the
 // row's band of pixel-centre rows is convex, so the tiles it meets are one contiguous span:
 // its x-extent runs from the left boundary at the band height nearest the ellipse's leftmost
-// point to the right boundary at the height nearest its rightmost point.  The preprocess
-// counts entries and the binning places them with this one function, in FP64, from the same
-// stored values, so both agree exactly.
+// point to the right boundary at the height nearest its rightmost point.
+//
+// The preprocess counts entries and the binning places them with these functions, from the
+// same stored values, so both agree exactly; contraction into FMAs is off inside them, so
+// that agreement does not depend on how each kernel is compiled.  The arithmetic is FP32 in
+// coordinates relative to the footprint's top-left tile (|values| of a few hundred pixels at
+// most), with the hardware square root and reciprocal (a few ulp, one instruction each), which
+// keeps the error in q near 1e-4 or below.
 constexpr double kTightMargin = 0.01;
 
-__device__ __forceinline__ double tight_bound(float opacity) {
-  return 2.0 * log(255.0 * (double)opacity) + kTightMargin;
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+struct TightEllipse {
+  float mxr, myr;          // centre relative to (16 x0, 16 y0)
+  float a, b, c, det, Q, inv_a;
+  float ymax, ys;          // half-height of the ellipse; height of its leftmost point
+  int x0, x1, y0;          // footprint columns [x0, x1], first row y0
+  bool empty;
+};
+
+__device__ __forceinline__ TightEllipse tight_ellipse(double mx, double my, float a, float b, float c, float opacity,
+                                                      int x0, int x1, int y0) {
+#pragma clang fp contract(off)
+  TightEllipse e;
+  e.mxr = (float)(mx - 16.0 * x0);
+  e.myr = (float)(my - 16.0 * y0);
+  e.a = a;
+  e.b = b;
+  e.c = c;
+  e.det = a * c - b * b;
+  e.Q = (float)(2.0 * log(255.0 * (double)opacity) + kTightMargin);
+  e.x0 = x0;
+  e.x1 = x1;
+  e.y0 = y0;
+  e.empty = !(e.Q >= 0.0f) || !(e.det > 0.0f) || !(a > 0.0f) || !(c > 0.0f);
+  const float inv_det = e.empty ? 0.0f : hw_rcp(e.det);
+  e.inv_a = e.empty ? 0.0f : hw_rcp(a);
+  e.ymax = e.empty ? 0.0f : hw_sqrt(e.Q * a * inv_det);
+  e.ys = e.empty ? 0.0f : b * hw_sqrt(e.Q * hw_rcp(c) * inv_det);
+  return e;
 }
 
-// Tiles [*lo, *hi] of tile row ty within the footprint columns [x0, x1] that the ellipse meets
-// (*lo > *hi when none).
-__device__ __forceinline__ void tight_row_span(double mx, double my, double a, double b, double c, double Q, int ty,
-                                               int x0, int x1, int *lo, int *hi) {
-  *lo = x0;
-  *hi = x0 - 1;
-  const double det = a * c - b * b;
-  if (!(Q >= 0.0) || !(det > 0.0) || !(a > 0.0) || !(c > 0.0)) return;
-  const double ymax = sqrt(Q * a / det);                           // the ellipse's half-height
-  const double dy0 = fmax((double)(ty * kTile) + 0.5 - my, -ymax);
-  const double dy1 = fmin((double)(ty * kTile) + (kTile - 0.5) - my, ymax);
+// Tiles [*lo, *hi] of tile row ty that the ellipse meets (*lo > *hi when none).
+__device__ __forceinline__ void tight_row_span(const TightEllipse &e, int ty, int *lo, int *hi) {
+#pragma clang fp contract(off)
+  *lo = e.x0;
+  *hi = e.x0 - 1;
+  if (e.empty) return;
+  const float top = (float)((ty - e.y0) * kTile) + 0.5f - e.myr;   // first pixel-centre row of the band
+  const float dy0 = fmaxf(top, -e.ymax), dy1 = fminf(top + (float)(kTile - 1), e.ymax);
   if (dy0 > dy1) return;
-  const double ys = b * sqrt(Q / (c * det));                      // height of the leftmost point
-  const double dl = fmin(fmax(ys, dy0), dy1), dr = fmin(fmax(-ys, dy0), dy1);
-  const double xl = mx + (-b * dl - sqrt(fmax(a * Q - det * dl * dl, 0.0))) / a;
-  const double xr = mx + (-b * dr + sqrt(fmax(a * Q - det * dr * dr, 0.0))) / a;
-  // tile tx meets [xl, xr] when 16 tx + 0.5 <= xr and 16 tx + 15.5 >= xl
-  const double l = fmax(ceil((xl - (kTile - 0.5)) / kTile), (double)x0);
-  const double h = fmin(floor((xr - 0.5) / kTile), (double)x1);
-  if (l <= h) {
-    *lo = (int)l;
-    *hi = (int)h;
+  const float dl = fminf(fmaxf(e.ys, dy0), dy1), dr = fminf(fmaxf(-e.ys, dy0), dy1);
+  const float aQ = e.a * e.Q;
+  const float xl = e.mxr + (-e.b * dl - hw_sqrt(fmaxf(aQ - e.det * dl * dl, 0.0f))) * e.inv_a;
+  const float xr = e.mxr + (-e.b * dr + hw_sqrt(fmaxf(aQ - e.det * dr * dr, 0.0f))) * e.inv_a;
+  // tile x0 + k meets [xl, xr] (relative) when 16 k + 0.5 <= xr and 16 k + 15.5 >= xl
+  const float kl = fmaxf(ceilf((xl - (kTile - 0.5f)) * (1.0f / kTile)), 0.0f);
+  const float kh = fminf(floorf((xr - 0.5f) * (1.0f / kTile)), (float)(e.x1 - e.x0));
+  if (kl <= kh) {
+    *lo = e.x0 + (int)kl;
+    *hi = e.x0 + (int)kh;
   }
 }
 

@@ -146,11 +146,11 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
         cnt = (uint32_t)((x1 / G - x0 / G + 1) * (y1 / G - y0 / G + 1));
         if (a.tight) {
           // entries of the tiles the alpha-cut ellipse meets (the binning walks the same spans)
-          const double Q = tight_bound(opac);
+          const TightEllipse el = tight_ellipse(mx, my, ca, cb, cc, opac, x0, x1, y0);
           cnt = 0;
           for (int ty = y0; ty <= y1; ++ty) {
             int lo, hi;
-            tight_row_span(mx, my, (double)ca, (double)cb, (double)cc, Q, ty, x0, x1, &lo, &hi);
+            tight_row_span(el, ty, &lo, &hi);
             cnt += (uint32_t)(hi - lo + 1);
           }
         }
