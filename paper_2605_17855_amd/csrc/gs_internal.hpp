@@ -16,45 +16,6 @@ constexpr float kLog2e = 1.4426950408889634f;
 // log2(1/255): the 1/255 alpha cut taken on log2(alpha)
 constexpr float kCutLog2 = -7.994353436858858f;
 
-// ---- decoupled look-back (single-pass chained scans) -------------------------
-// A chain of tiles, each with one status word per scanned value: bits 63/62 flag "inclusive
-// prefix" / "aggregate only", bits 61..0 the value.  Tile ids come from an atomic counter in
-// the order workgroups start, so every predecessor a tile waits on is already resident and
-// finishes; the wait still has a spin limit, so an inconsistent chain yields a wrong result
-// (caught by the parity tests) rather than a hang.
-constexpr uint64_t kFlagP = 1ull << 63;
-constexpr uint64_t kFlagA = 1ull << 62;
-constexpr uint64_t kValMask = kFlagA - 1;
-constexpr uint32_t kSpinLimit = 1u << 22;
-
-__device__ __forceinline__ void status_store(uint64_t *p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t status_load(const uint64_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// Exclusive prefix of `tile` in the chain status[tile * stride].
-__device__ __forceinline__ uint64_t lookback(const uint64_t *status, int64_t tile, int64_t stride) {
-  uint64_t excl = 0;
-  int64_t p = tile - 1;
-  uint32_t spins = 0;
-  while (p >= 0) {
-    const uint64_t w = status_load(&status[p * stride]);
-    if (w & kFlagP) {
-      excl += w & kValMask;
-      break;
-    }
-    if (w & kFlagA) {
-      excl += w & kValMask;
-      --p;
-      continue;
-    }
-    if (++spins > kSpinLimit) break;
-    __builtin_amdgcn_s_sleep(1);
-  }
-  return excl;
-}
-
 struct Grid {
   int W, H, TX, TY, G, GX, GY;
   int64_t nbins;
