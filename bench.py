@@ -304,20 +304,22 @@ def sweep(gs, torch, args):
         ds = gs.DeviceScene(sc)
         cams = scenes.orbit(max(args.sweep_steps, 1), w, h, seed=seed)
         keys = {}
-        for group in (1, 2, 4):
+        for group, tight in ((1, False), (1, True), (2, False), (4, False)):
             rend = gs.Renderer(sc.n, w, h, group=group)
             for prec in ("fp32", "fp16", "bf16"):
                 splits = 3 if prec == "bf16" else 2
-                opt = gs.options(group=group, precision=prec, splits=splits)
+                opt = gs.options(group=group, precision=prec, splits=splits, tight=tight)
                 el, fm, rm = timed_frames(gs, torch, ds, cams, rend, opt, args.sweep_steps, 3)
-                rows.append({"workload": name, "precision": prec, "splits": splits, "group": group,
+                rows.append({"workload": name, "precision": prec, "splits": splits, "group": group, "tight": tight,
                              "frames_per_s": args.sweep_steps / el, "p99_ms": float(np.percentile(fm, 99)),
-                             "raster_avg_ms": float(np.mean(rm))})
-                log(f"  G{group} {prec}: {rows[-1]['frames_per_s']:.1f} frames/s, raster {rows[-1]['raster_avg_ms']:.3f} ms")
-            keys[group] = np.mean([rend.render(ds, c, gs.options(group=group)) for c in cams[:5]])
+                             "raster_avg_ms": float(np.mean(rm)), "stage_ms": timed_frames.stages})
+                log(f"  G{group}{' tight' if tight else ''} {prec}: {rows[-1]['frames_per_s']:.1f} frames/s, "
+                    f"raster {rows[-1]['raster_avg_ms']:.3f} ms")
+            keys["1t" if tight else group] = np.mean([rend.render(ds, c, gs.options(group=group, tight=tight))
+                                                      for c in cams[:5]])
             del rend
         lr.append({"workload": name, "entries": {str(g): float(k) for g, k in keys.items()},
-                   "load_reduction": {str(g): 1.0 - keys[g] / keys[1] for g in (2, 4)}})
+                   "load_reduction": {str(g): 1.0 - keys[g] / keys[1] for g in (2, 4, "1t")}})
         del ds
         torch.cuda.empty_cache()
     return {"rows": rows, "load_reduction": lr, "steps": args.sweep_steps}
