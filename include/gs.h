@@ -74,7 +74,13 @@ enum {
    * the 1/255 cut there (the 0.01 margin covers FP32/FP16 rounding).  Every dropped pair has
    * alpha below the cut at every pixel of the tile, so the image, T_final and the weight sum
    * are those of the full lists; entry counts and GS_AUX_NEVAL counts are smaller. */
-  GS_OPT_TIGHT = 1u
+  GS_OPT_TIGHT = 1u,
+  /* The MFMA rasterizers leave out of each 8x8 quadrant's MFMA blocks the rows whose alpha
+   * cannot reach the 1/255 cut at any pixel centre of that quadrant (the test is taken with a
+   * margin of 1 in q, far above its own and the split operands' rounding, so the image and
+   * every aux plane are those of the full rows).  This flag makes every quadrant run every row
+   * of its tile, the plain tile loop; it exists to check that equality and changes no result. */
+  GS_OPT_ALL_ROWS = 2u
 };
 
 typedef struct {

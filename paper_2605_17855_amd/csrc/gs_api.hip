@@ -61,7 +61,7 @@ gs_status check_options(const gs_options *o) {
   }
   if (o->aux_flags & ~(uint32_t)(GS_AUX_TFINAL | GS_AUX_WSUM | GS_AUX_NEVAL | GS_AUX_NBLEND))
     return fail(GS_ERR_INVALID_ARG, "aux_flags 0x%x", o->aux_flags);
-  if (o->flags & ~(uint32_t)GS_OPT_TIGHT) return fail(GS_ERR_INVALID_ARG, "flags 0x%x", o->flags);
+  if (o->flags & ~(uint32_t)(GS_OPT_TIGHT | GS_OPT_ALL_ROWS)) return fail(GS_ERR_INVALID_ARG, "flags 0x%x", o->flags);
   if ((o->flags & GS_OPT_TIGHT) && o->group != 1)
     return fail(GS_ERR_UNSUPPORTED, "opacity-aware tile culling needs group 1");
   for (int i = 0; i < 3; ++i)
@@ -160,6 +160,7 @@ gsi::RasterParams make_params(const gs_options &o) {
   p.splits = o.splits;
   for (int i = 0; i < 3; ++i) p.bg[i] = o.bg[i];
   p.aux_flags = o.aux_flags;
+  p.all_rows = (o.flags & GS_OPT_ALL_ROWS) != 0;
   return p;
 }
 

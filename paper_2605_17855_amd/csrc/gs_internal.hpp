@@ -180,6 +180,7 @@ struct RasterParams {
   int G, prec, splits;
   float bg[3];
   uint32_t aux_flags;
+  bool all_rows;               // every quadrant runs every row (no quadrant culling)
 };
 
 hipError_t launch_raster_fp32(const RasterJob &j, const RasterParams &p, hipStream_t st);

@@ -24,6 +24,8 @@
 // lane l >= 32 with all 32 rows of panel-1 pixel l-32.  Each lane then runs the exact
 // sequential front-to-back recurrence over those rows in depth order (VALU: exp2, 1/255
 // cut as a compare on D, clamp, FP32 transmittance product, stop test, colour FMA).
+// Rows are staged for the whole tile; each wave then runs only the rows whose alpha can reach
+// the cut somewhere in its quadrant (quadrant culling, below), gathered from LDS by index.
 //
 // Grouping.  For G > 1 a chunk of the group's list is staged in LDS once; for every member
 // tile the entries whose mask bit is set are compacted in order (ballot + mbcnt) and their
@@ -127,20 +129,70 @@ __device__ __forceinline__ void build_row(uint16_t *row, float u, float v, float
   }
 }
 
-// A row whose D is -1000 at every pixel (never passes the 1/255 cut): pads the last block.
-template <int PREC, int S>
-__device__ __forceinline__ void pad_row(uint16_t *row) {
-  using N = Narrow<PREC>;
-  short8 v0, z;
+// Quadrant culling.  Wave w blends the pixels of quadrant (w & 1, w >> 1) only, so a row that
+// cannot pass the 1/255 alpha cut at any pixel centre of that quadrant is left out of the
+// wave's MFMA blocks.  Bit qx + 2 qy of the mask is set unless the minimum of the conic's
+// quadratic form q(d) = a dx^2 + 2 b dx dy + c dy^2 over the quadrant's pixel centres exceeds
+// 2 ln(255 o) + kQuadMargin (alpha >= 1/255 reads q <= 2 ln(255 o)).  The margin in q, 0.72
+// in log2(alpha), is far above the rounding of this test and of the split 16-bit power, so a
+// left-out row is one whose D stays below the cut at every pixel of the quadrant: the blended
+// result is the one every row would give.
+//
+// A rectangle that does not hold the centre has its minimum on an edge that faces the
+// centre.  Along the facing horizontal edge y = ey the minimum is at dx = -b dy / a clamped
+// into the edge, and q = a (dx + b dy / a)^2 + (det / a) dy^2 holds only non-negative terms;
+// likewise along the facing vertical edge.  Clamping the centre into the rectangle picks the
+// facing edges; a centre inside gives q = 0.
+constexpr float kQuadMargin = 1.0f;
+constexpr float kQuadQ0 = 11.0825270f + kQuadMargin;   // 2 ln 255 + margin
+
+__device__ __forceinline__ uint32_t quad_mask(float u, float v, float a, float b, float c, float lno) {
+  const float Q = fmaf(2.0f, lno, kQuadQ0);
+  if (!(Q > 0.0f)) return 0u;               // o < 1/255 e^{-margin/2}: never reaches the cut
+  const float det = (float)((double)a * c - (double)b * b);
+  if (!(a > 0.0f && c > 0.0f && det > 0.0f)) return 0xFu;
+  const float ia = __builtin_amdgcn_rcpf(a), ic = __builtin_amdgcn_rcpf(c);
+  const float ba = b * ia, bc = b * ic, ga = det * ia, gc = det * ic;
+  uint32_t mask = 0;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) { v0[i] = 0; z[i] = 0; }
-  v0[5] = (short)N::enc(-1000.0f);
-  *reinterpret_cast<short8 *>(row) = v0;
-  *reinterpret_cast<short8 *>(row + 8) = z;
-  if (S == 3) {
-    *reinterpret_cast<short8 *>(row + 16) = z;
-    *reinterpret_cast<short8 *>(row + 24) = z;
+  for (int qy = 0; qy < 2; ++qy) {
+#pragma unroll
+    for (int qx = 0; qx < 2; ++qx) {
+      const float xl = (float)(8 * qx - 8), xh = (float)(8 * qx - 1);
+      const float yl = (float)(8 * qy - 8), yh = (float)(8 * qy - 1);
+      // facing horizontal edge
+      const float dy = fminf(fmaxf(v, yl), yh) - v;
+      const float th = -ba * dy;
+      const float sh = fminf(fmaxf(th, xl - u), xh - u) - th;
+      const float qh = fmaf(a * sh, sh, ga * dy * dy);
+      // facing vertical edge
+      const float dx = fminf(fmaxf(u, xl), xh) - u;
+      const float tv = -bc * dx;
+      const float sv = fminf(fmaxf(tv, yl - v), yh - v) - tv;
+      const float qv = fmaf(c * sv, sv, gc * dx * dx);
+      if (fminf(qh, qv) <= Q) mask |= 1u << (qx + 2 * qy);
+    }
   }
+  return mask;
+}
+
+// Compacts, in order, the rows [0, nrows) whose quadrant mask holds this wave's bit into the
+// wave's own list; returns its length (uniform).
+__device__ __forceinline__ int wave_list(const uint8_t *qm, int nrows, uint8_t *wl) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int n = 0;
+  for (int r0 = 0; r0 < nrows; r0 += 64) {
+    const int r = r0 + lane;
+    const bool in = r < nrows && ((qm[r] >> w) & 1u);
+    const uint64_t b = __ballot(in);
+    if (in) wl[n + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u))] = (uint8_t)r;
+    n += __popcll(b);
+  }
+  // the list is written and read by lanes of this wave only
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  return n;
 }
 
 struct TileState {
@@ -148,27 +200,41 @@ struct TileState {
   uint32_t nstop, nblend;
 };
 
-// Runs the rows [0, nrows) of buffer A/col for one member tile.
+// Runs the rows wl[0, n) of buffer A/col (ascending indices) for one member tile.  Rows are
+// gathered from LDS by index; the slots past n in the last block take a row whose D is -1000
+// at every pixel, so they never pass the cut.  The block's 32 colours (and row indices) are
+// copied to the wave's own buffer wc, so the blend reads them at fixed offsets.
 template <int PREC, int S, bool AUX>
-__device__ __forceinline__ void process_rows(const uint16_t *sA, const float4 *scol, int nrows, short8 B0, short8 B1,
-                                             short8 B20, short8 B21, TileState &st, uint32_t row_base) {
+__device__ __forceinline__ void process_rows(const uint16_t *sA, const float *scol, const uint8_t *wl, int n,
+                                             float4 *wc, short8 B0, short8 B1, short8 B20, short8 B21,
+                                             TileState &st, uint32_t row_base) {
   using N = Narrow<PREC>;
   constexpr int RS = (S == 3) ? 32 : 16;
   const int lane = threadIdx.x & 63;
-  const int nblk = (nrows + 31) >> 5;
+  const int nblk = (n + 31) >> 5;
+  short8 pad = {}, zero = {};
+  if (lane < 32) pad[5] = (short)N::enc(-1000.0f);
   for (int blk = 0; blk < nblk; ++blk) {
     // a wave whose 64 pixels have all stopped skips the rest of this tile's rows
     if (__ballot(st.cut != INFINITY) == 0) break;
-    const uint16_t *rp = sA + (size_t)(32 * blk + (lane & 31)) * RS + 8 * (lane >> 5);
-    const short8 a = *reinterpret_cast<const short8 *>(rp);
+    const int slot = 32 * blk + (lane & 31);
+    const bool real = slot < n;
+    const int ri = real ? (int)wl[slot] : 0;
+    const uint16_t *rp = sA + (size_t)ri * RS + 8 * (lane >> 5);
+    const short8 a = real ? *reinterpret_cast<const short8 *>(rp) : pad;
+    const float4 gc = make_float4(scol[ri], scol[kBlock + ri], scol[2 * kBlock + ri], __int_as_float(ri));
     float16v z = {};
     float16v d0 = N::mma(a, B0, z);
     float16v d1 = N::mma(a, B1, z);
     if (S == 3) {
-      const short8 a2 = *reinterpret_cast<const short8 *>(rp + 16);
+      const short8 a2 = real ? *reinterpret_cast<const short8 *>(rp + 16) : zero;
       d0 = N::mma(a2, B20, d0);
       d1 = N::mma(a2, B21, d1);
     }
+    if (lane < 32) wc[lane] = gc;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     float D[32];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
@@ -181,7 +247,7 @@ __device__ __forceinline__ void process_rows(const uint16_t *sA, const float4 *s
       if (D[m] >= st.cut) {
         // branch-free body: T' = T (1 - alpha) as one FMA; a stop (T' < 1e-4) blends nothing,
         // keeps T and disables the pixel
-        const float4 cl = scol[32 * blk + m];
+        const float4 cl = wc[m];
         const float al = fminf(kAlphaMax, __builtin_amdgcn_exp2f(D[m]));
         const float Tn = fmaf(-st.T, al, st.T);
         const bool ok = Tn >= kTMin;
@@ -194,7 +260,7 @@ __device__ __forceinline__ void process_rows(const uint16_t *sA, const float4 *s
         if (AUX) {
           st.W += wgt;
           st.nblend += ok ? 1u : 0u;
-          st.nstop = ok ? st.nstop : row_base + 32 * blk + m + 1;
+          st.nstop = ok ? st.nstop : row_base + (uint32_t)__float_as_int(cl.w) + 1;
         }
       }
     }
@@ -206,13 +272,16 @@ struct MfmaShared {
   static constexpr int NT = G * G;
   static constexpr int RS = (S == 3) ? 32 : 16;
   __align__(16) uint16_t A[2][kBlock * RS];
-  float4 col[2][kBlock];
+  float col[2][3][kBlock];          // colour planes r, g, b of the staged rows
   double2 r0[G > 1 ? kBlock : 1];  // FP64 centre; every tile rounds its own offset
   float4 r1[G > 1 ? kBlock : 1];   // (a, b, c, ln o)
   float4 r2[G > 1 ? kBlock : 1];   // (r, g, b, -)
   uint32_t wcnt[2][NT][4];         // by chunk parity: a wave may stage chunk c+1 while
                                    // another still reads chunk c's counts
   uint32_t alive[2][4];
+  uint8_t qm[2][kBlock];           // quadrant masks of the staged rows
+  uint8_t wl[4][kBlock];           // each wave's row list (wave-private)
+  float4 wc[4][32];                // each wave's colours of its current block (wave-private)
 };
 
 // Pixel-side operand: phi of this lane's panel pixel (n = lane % 32) in both panels.
@@ -293,11 +362,13 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
         const double2 m = J.xy[g];
         const float4 co = J.conic[g];
         const float4 cl = J.rgb[g];
-        build_row<PREC, S>(&sm.A[buf][t * RS], (float)(m.x - ((double)ox + 8.5)), (float)(m.y - ((double)oy + 8.5)),
-                           co.x, co.y, co.z, __logf(co.w));
-        sm.col[buf][t] = cl;
-      } else if (t < ((cnt + 31) & ~31)) {
-        pad_row<PREC, S>(&sm.A[buf][t * RS]);
+        const float u = (float)(m.x - ((double)ox + 8.5)), v = (float)(m.y - ((double)oy + 8.5));
+        const float lno = __logf(co.w);
+        build_row<PREC, S>(&sm.A[buf][t * RS], u, v, co.x, co.y, co.z, lno);
+        sm.col[buf][0][t] = cl.x;
+        sm.col[buf][1][t] = cl.y;
+        sm.col[buf][2][t] = cl.z;
+        sm.qm[buf][t] = P.all_rows ? (uint8_t)0xF : (uint8_t)quad_mask(u, v, co.x, co.y, co.z, lno);
       }
       __syncthreads();
       if (last_k >= 0) {
@@ -307,7 +378,9 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
         last_k = -1;
         if (!alive_mask) break;
       }
-      process_rows<PREC, S, AUX>(sm.A[buf], sm.col[buf], cnt, B0, B1, B20, B21, st[0], rows_done[0]);
+      const int nw = wave_list(sm.qm[buf], cnt, sm.wl[w]);
+      process_rows<PREC, S, AUX>(sm.A[buf], &sm.col[buf][0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, st[0],
+                                 rows_done[0]);
       rows_done[0] += cnt;
       const uint64_t bal = __ballot(st[0].cut != INFINITY);
       if (lane == 0) sm.alive[it & 1][w] = bal != 0;
@@ -360,11 +433,14 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
               woff[k] + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[k] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal[k], 0u));
           const double2 r0 = sm.r0[t];
           const float4 r1 = sm.r1[t];
-          build_row<PREC, S>(&sm.A[buf][pos * RS], (float)(r0.x - fx0), (float)(r0.y - fy0), r1.x, r1.y, r1.z, r1.w);
-          sm.col[buf][pos] = sm.r2[t];
+          const float u = (float)(r0.x - fx0), v = (float)(r0.y - fy0);
+          build_row<PREC, S>(&sm.A[buf][pos * RS], u, v, r1.x, r1.y, r1.z, r1.w);
+          const float4 r2 = sm.r2[t];
+          sm.col[buf][0][pos] = r2.x;
+          sm.col[buf][1][pos] = r2.y;
+          sm.col[buf][2][pos] = r2.z;
+          sm.qm[buf][pos] = P.all_rows ? (uint8_t)0xF : (uint8_t)quad_mask(u, v, r1.x, r1.y, r1.z, r1.w);
         }
-        const uint32_t padn = ((nk[k] + 31) & ~31u) - nk[k];
-        if ((uint32_t)t < padn) pad_row<PREC, S>(&sm.A[buf][(nk[k] + t) * RS]);
         __syncthreads();
         if (last_k >= 0) {
           const uint32_t any = sm.alive[(it - 1) & 1][0] | sm.alive[(it - 1) & 1][1] | sm.alive[(it - 1) & 1][2] |
@@ -372,7 +448,9 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
           if (!any) alive_mask &= ~(1u << last_k);
         }
         TileState cur = st[k];
-        process_rows<PREC, S, AUX>(sm.A[buf], sm.col[buf], (int)nk[k], B0, B1, B20, B21, cur, rows_done[k]);
+        const int nw = wave_list(sm.qm[buf], (int)nk[k], sm.wl[w]);
+        process_rows<PREC, S, AUX>(sm.A[buf], &sm.col[buf][0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, cur,
+                                   rows_done[k]);
         st[k] = cur;
         rows_done[k] += nk[k];
         const uint64_t ab = __ballot(cur.cut != INFINITY);

@@ -20,6 +20,7 @@ GS_OK, GS_ERR_INVALID_ARG, GS_ERR_UNSUPPORTED, GS_ERR_CAPACITY, GS_ERR_HIP = ran
 GS_PREC_FP32, GS_PREC_FP16_MFMA, GS_PREC_BF16_MFMA = range(3)
 GS_AUX_TFINAL, GS_AUX_WSUM, GS_AUX_NEVAL, GS_AUX_NBLEND = 1, 2, 4, 8
 GS_OPT_TIGHT = 1
+GS_OPT_ALL_ROWS = 2
 PRECISIONS = {"fp32": GS_PREC_FP32, "fp16": GS_PREC_FP16_MFMA, "bf16": GS_PREC_BF16_MFMA}
 TILE = 16
 
@@ -115,14 +116,14 @@ def _check(status: int):
 
 
 def options(group: int = 1, precision="fp32", splits: int = 2, bg=(0.0, 0.0, 0.0), aux_flags: int = 0,
-            tight: bool = False) -> gs_options:
+            tight: bool = False, all_rows: bool = False) -> gs_options:
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     o = gs_options()
     o.group, o.precision, o.splits = group, precision, splits
     o.bg = (C.c_float * 3)(*bg)
     o.aux_flags = aux_flags
-    o.flags = GS_OPT_TIGHT if tight else 0
+    o.flags = (GS_OPT_TIGHT if tight else 0) | (GS_OPT_ALL_ROWS if all_rows else 0)
     return o
 
 

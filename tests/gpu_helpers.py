@@ -13,10 +13,12 @@ def note(msg: str):
     sys.stdout.flush()
 
 
-def render(dscene, cam, group=1, precision="fp32", splits=2, bg=(0.0, 0.0, 0.0), aux=0, capacity=0):
+def render(dscene, cam, group=1, precision="fp32", splits=2, bg=(0.0, 0.0, 0.0), aux=0, capacity=0, tight=False,
+           all_rows=False):
     import torch
     r = gs.Renderer(dscene.n, cam.width, cam.height, group=group, capacity=capacity)
-    opt = gs.options(group=group, precision=precision, splits=splits, bg=bg, aux_flags=aux)
+    opt = gs.options(group=group, precision=precision, splits=splits, bg=bg, aux_flags=aux, tight=tight,
+                     all_rows=all_rows)
     n_keys = r.render(dscene, cam, opt)
     torch.cuda.synchronize()
     out = dict(image=r.image.cpu().numpy().astype(np.float64), n_keys=n_keys, renderer=r)

@@ -53,7 +53,7 @@ def test_num_bins():
     ("splits", 0, gs.GS_ERR_INVALID_ARG),
     ("aux_flags", 16, gs.GS_ERR_INVALID_ARG),
     ("aux_flags", 32, gs.GS_ERR_INVALID_ARG),
-    ("flags", 2, gs.GS_ERR_INVALID_ARG),
+    ("flags", 4, gs.GS_ERR_INVALID_ARG),
     ("flags", 0x80000000, gs.GS_ERR_INVALID_ARG),
 ])
 def test_rasterize_rejects_bad_options(field, value, status):
