@@ -245,22 +245,28 @@ __device__ __forceinline__ void process_rows(const uint16_t *sA, const float *sc
 #pragma unroll
     for (int m = 0; m < 32; ++m) {
       if (D[m] >= st.cut) {
-        // branch-free body: T' = T (1 - alpha) as one FMA; a stop (T' < 1e-4) blends nothing,
-        // keeps T and disables the pixel
+        // T' = T (1 - alpha) as one FMA.  A stop (T' < 1e-4) blends nothing, keeps T and
+        // disables the pixel; it comes at most once per pixel, so the blend without the
+        // stop's selects runs whenever no active lane stops on this row
         const float4 cl = wc[m];
         const float al = fminf(kAlphaMax, __builtin_amdgcn_exp2f(D[m]));
-        const float Tn = fmaf(-st.T, al, st.T);
-        const bool ok = Tn >= kTMin;
-        const float wgt = ok ? al * st.T : 0.0f;
+        float Tn = fmaf(-st.T, al, st.T);
+        float wgt = al * st.T;
+        if (__builtin_expect(__ballot(!(Tn >= kTMin)) != 0, 0)) {
+          const bool ok = Tn >= kTMin;
+          wgt = ok ? wgt : 0.0f;
+          Tn = ok ? Tn : st.T;
+          st.cut = ok ? st.cut : INFINITY;
+          if (AUX) st.nstop = ok ? st.nstop : row_base + (uint32_t)__float_as_int(cl.w) + 1;
+          if (AUX) st.nblend += ok ? 0u : ~0u;
+        }
         st.C0 = fmaf(wgt, cl.x, st.C0);
         st.C1 = fmaf(wgt, cl.y, st.C1);
         st.C2 = fmaf(wgt, cl.z, st.C2);
-        st.T = ok ? Tn : st.T;
-        st.cut = ok ? st.cut : INFINITY;
+        st.T = Tn;
         if (AUX) {
           st.W += wgt;
-          st.nblend += ok ? 1u : 0u;
-          st.nstop = ok ? st.nstop : row_base + (uint32_t)__float_as_int(cl.w) + 1;
+          st.nblend += 1u;
         }
       }
     }
