@@ -304,9 +304,9 @@ def sweep(gs, torch, args):
         ds = gs.DeviceScene(sc)
         cams = scenes.orbit(max(args.sweep_steps, 1), w, h, seed=seed)
         keys = {}
-        for group, tight in ((1, False), (1, True), (2, False), (4, False)):
+        for group, tight in ((1, False), (1, True), (2, False), (4, False), (8, False)):
             rend = gs.Renderer(sc.n, w, h, group=group)
-            for prec in ("fp32", "fp16", "bf16"):
+            for prec in ("fp32", "fp16", "bf16") if group != 8 else ("fp16", "bf16"):
                 splits = 3 if prec == "bf16" else 2
                 opt = gs.options(group=group, precision=prec, splits=splits, tight=tight)
                 el, fm, rm = timed_frames(gs, torch, ds, cams, rend, opt, args.sweep_steps, 3)
@@ -319,7 +319,7 @@ def sweep(gs, torch, args):
                                                       for c in cams[:5]])
             del rend
         lr.append({"workload": name, "entries": {str(g): float(k) for g, k in keys.items()},
-                   "load_reduction": {str(g): 1.0 - keys[g] / keys[1] for g in (2, 4, "1t")}})
+                   "load_reduction": {str(g): 1.0 - keys[g] / keys[1] for g in (2, 4, 8, "1t")}})
         del ds
         torch.cuda.empty_cache()
     return {"rows": rows, "load_reduction": lr, "steps": args.sweep_steps}

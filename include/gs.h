@@ -84,7 +84,7 @@ enum {
 };
 
 typedef struct {
-  int32_t group;            /* tile-group side G: 1, 2 or 4 (cross-tile grouping) */
+  int32_t group;            /* tile-group side G: 1, 2, 4 or 8 (cross-tile grouping; 8 with the MFMA precisions only) */
   int32_t precision;        /* gs_precision */
   int32_t splits;           /* MFMA paths: 1..3 FP16/BF16 pieces per Gaussian coefficient (hi, lo, lo2) */
   float bg[3];              /* background colour added with the final transmittance */
@@ -133,7 +133,8 @@ typedef struct {
 typedef struct {
   uint64_t *keys;           /* (bin << 32) | float bits of depth; ascending after gs_bin_sort */
   uint32_t *vals;           /* Gaussian index of each entry */
-  uint16_t *masks;          /* tile-membership mask of each entry (used when group > 1, may be NULL for group 1) */
+  void *masks;              /* tile-membership mask of each entry: uint16_t for G = 2 and 4, uint64_t for G = 8
+                               (used when group > 1, may be NULL for group 1) */
   uint64_t capacity;        /* entries the three arrays can hold */
   uint32_t *ranges;         /* n_bins x 2: [start, end) of each bin in the sorted arrays; (0, 0) if empty */
 } gs_bins;

@@ -257,7 +257,7 @@ void oracle_preprocess(int64_t n, int deg, const float *mean, const float *log_s
 /* ------------------------------------------------------------------------ */
 /* Lists per bin (tile when G == 1, group of GxG tiles otherwise).           */
 /* ------------------------------------------------------------------------ */
-typedef struct { double z; int64_t id; uint32_t mask; } or_entry;
+typedef struct { double z; int64_t id; uint64_t mask; } or_entry;
 
 static int cmp_entry(const void *pa, const void *pb) {
   const or_entry *a = (const or_entry *)pa, *b = (const or_entry *)pb;
@@ -269,7 +269,7 @@ static int cmp_entry(const void *pa, const void *pb) {
 /* Returns the total entry count.  With start == NULL only counts.
  * start[nbins+1], ids[count], masks[count] (bit (ty%G)*G + (tx%G) per member tile). */
 int64_t oracle_lists(int64_t n, const int32_t *rect, const double *depth, const uint8_t *flags,
-                     int W, int H, int G, int64_t *start, int64_t *ids, uint32_t *masks) {
+                     int W, int H, int G, int64_t *start, int64_t *ids, uint64_t *masks) {
   int TX = (W + OR_TILE - 1) / OR_TILE, TY = (H + OR_TILE - 1) / OR_TILE;
   int GX = (TX + G - 1) / G, GY = (TY + G - 1) / G;
   int64_t nbins = (int64_t)GX * GY;
@@ -293,10 +293,10 @@ int64_t oracle_lists(int64_t n, const int32_t *rect, const double *depth, const 
     int gx0 = x0 / G, gx1 = (x1 - 1) / G, gy0 = y0 / G, gy1 = (y1 - 1) / G;
     for (int gy = gy0; gy <= gy1; ++gy)
       for (int gx = gx0; gx <= gx1; ++gx) {
-        uint32_t m = 0;
+        uint64_t m = 0;
         for (int ty = gy * G; ty < gy * G + G; ++ty)
           for (int tx = gx * G; tx < gx * G + G; ++tx)
-            if (tx >= x0 && tx < x1 && ty >= y0 && ty < y1) m |= 1u << ((ty % G) * G + (tx % G));
+            if (tx >= x0 && tx < x1 && ty >= y0 && ty < y1) m |= (uint64_t)1 << ((ty % G) * G + (tx % G));
         int64_t b = (int64_t)gy * GX + gx;
         or_entry *e = &tmp[start[b] + fill[b]++];
         e->z = depth[g]; e->id = g; e->mask = m;

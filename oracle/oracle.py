@@ -122,7 +122,7 @@ def lists(rec: dict, cam, group: int = 1):
                            None, None, None)
     start = np.zeros(gx * gy + 1, np.int64)
     ids = np.zeros(max(total, 1), np.int64)
-    masks = np.zeros(max(total, 1), np.uint32)
+    masks = np.zeros(max(total, 1), np.uint64)
     L.oracle_lists(n, rec["rect"], rec["depth"], rec["flags"], cam.width, cam.height, group,
                    start.ctypes.data, ids.ctypes.data, masks.ctypes.data)
     return start, ids[:total], masks[:total]

@@ -51,13 +51,16 @@ gs_status check_camera(const gs_camera *c) {
 gs_status check_options(const gs_options *o) {
   if (!o) return fail(GS_ERR_INVALID_ARG, "options is NULL");
   if (o->group < 1) return fail(GS_ERR_INVALID_ARG, "group %d", o->group);
-  if (o->group != 1 && o->group != 2 && o->group != 4) return fail(GS_ERR_UNSUPPORTED, "group %d not in {1,2,4}", o->group);
+  if (o->group != 1 && o->group != 2 && o->group != 4 && o->group != 8)
+    return fail(GS_ERR_UNSUPPORTED, "group %d not in {1,2,4,8}", o->group);
   if (o->precision < GS_PREC_FP32 || o->precision > GS_PREC_BF16_MFMA)
     return fail(GS_ERR_INVALID_ARG, "precision %d", o->precision);
   if (o->precision != GS_PREC_FP32) {
     if (o->splits < 1 || o->splits > 3) return fail(GS_ERR_INVALID_ARG, "splits %d not in 1..3", o->splits);
     if (o->precision == GS_PREC_FP16_MFMA && o->splits == 3)
       return fail(GS_ERR_UNSUPPORTED, "FP16 supports splits 1..2 (a third FP16 piece would be subnormal)");
+  } else if (o->group == 8) {
+    return fail(GS_ERR_UNSUPPORTED, "group 8 needs an MFMA precision (the FP32 rasterizer keeps every member tile in registers)");
   }
   if (o->aux_flags & ~(uint32_t)(GS_AUX_TFINAL | GS_AUX_WSUM | GS_AUX_NEVAL | GS_AUX_NBLEND))
     return fail(GS_ERR_INVALID_ARG, "aux_flags 0x%x", o->aux_flags);

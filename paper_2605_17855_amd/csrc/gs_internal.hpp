@@ -158,7 +158,7 @@ hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V,
 // depth bits of the r-th Gaussian in depth order.
 hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n, const uint32_t *order,
                          const uint32_t *dkeys, const uint16_t *rect, const Grid &g, uint32_t *vals, uint32_t *ranges,
-                         uint16_t *masks, uint64_t *keys, hipStream_t st);
+                         void *masks, uint64_t *keys, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
 
 // ---- rasterizers -------------------------------------------------------------
@@ -167,7 +167,7 @@ struct RasterJob {
   const float4 *conic;
   const float4 *rgb;
   const uint32_t *vals;
-  const uint16_t *masks;
+  const void *masks;       // uint16_t per entry for G = 2, 4; uint64_t for G = 8
   const uint32_t *ranges;
   float *image;
   float *aux;

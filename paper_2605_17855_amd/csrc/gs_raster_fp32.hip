@@ -62,7 +62,7 @@ __device__ __forceinline__ void raster_bin_fp32(const RasterJob &J, const Raster
       const double2 m = J.xy[g];
       const float4 co = J.conic[g];
       const float4 cl = J.rgb[g];
-      const uint32_t mk = (G > 1) ? (uint32_t)J.masks[e] : 1u;
+      const uint32_t mk = (G > 1) ? (uint32_t) static_cast<const uint16_t *>(J.masks)[e] : 1u;
       sm.a[t] = make_float4((float)(m.x - ox), (float)(m.y - oy), -0.5f * kLog2e * co.x, -kLog2e * co.y);
       sm.b[t] = make_float4(-0.5f * kLog2e * co.z, __log2f(co.w), cl.x, cl.y);
       sm.c[t] = make_float4(cl.z, __uint_as_float(mk), 0.0f, 0.0f);

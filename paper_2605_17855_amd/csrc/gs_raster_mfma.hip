@@ -32,6 +32,8 @@
 // A rows are built in that tile's frame.  Per-tile blending state lives in registers.  Each
 // tile sees the same Gaussians in the same order with the same arithmetic as with G = 1, so
 // grouped and ungrouped images are bit-identical.
+#include <type_traits>
+
 #include "gs_internal.hpp"
 
 namespace gsi {
@@ -282,7 +284,7 @@ struct MfmaShared {
   double2 r0[G > 1 ? kBlock : 1];  // FP64 centre; every tile rounds its own offset
   float4 r1[G > 1 ? kBlock : 1];   // (a, b, c, ln o)
   float4 r2[G > 1 ? kBlock : 1];   // (r, g, b, -)
-  uint32_t wcnt[2][NT][4];         // by chunk parity: a wave may stage chunk c+1 while
+  __align__(16) uint32_t wcnt[2][NT][4];   // by chunk parity: a wave may stage chunk c+1 while
                                    // another still reads chunk c's counts
   uint32_t alive[2][4];
   uint8_t qm[2][kBlock];           // quadrant masks of the staged rows
@@ -333,7 +335,8 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
                                                 short8 B21) {
   constexpr int NT = G * G;
   constexpr int RS = (S == 3) ? 32 : 16;
-  constexpr int kTileUnroll = G == 4 ? 1 : NT;
+  constexpr int kTileUnroll = G >= 4 ? 1 : NT;
+  using TileMask = typename std::conditional<(NT > 32), uint64_t, uint32_t>::type;
   const int gx = bin % J.GX, gy = bin / J.GX;
   const int ox = gx * G * kTile, oy = gy * G * kTile;
   const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
@@ -342,9 +345,9 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
   const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
 
   TileState st[NT];
-  uint32_t alive_mask = 0;       // uniform: member tiles with pixels still blending
+  TileMask alive_mask = 0;       // uniform: member tiles with pixels still blending
   uint32_t rows_done[NT];        // uniform: entries of each tile consumed so far
-#pragma unroll
+#pragma unroll kTileUnroll
   for (int k = 0; k < NT; ++k) {
     const int tx0 = ox + (k % G) * kTile, ty0 = oy + (k / G) * kTile;
     const bool inside = (tx0 + px < J.W) && (ty0 + py < J.H);
@@ -352,7 +355,7 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
     st[k].cut = inside ? kCutLog2 : INFINITY;
     st[k].nstop = 0; st[k].nblend = 0;
     rows_done[k] = 0;
-    if (tx0 < J.W && ty0 < J.H) alive_mask |= 1u << k;
+    if (tx0 < J.W && ty0 < J.H) alive_mask |= (TileMask)1 << k;
   }
 
   int it = 0;          // processing steps so far (LDS double-buffer parity)
@@ -394,49 +397,46 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
       ++it;
     } else {
       // stage the chunk once for every member tile (Algorithm 1: load the chunk into shared memory)
-      uint32_t mk = 0;
+      TileMask mk = 0;
       if (t < cnt) {
         const uint32_t e = cs + t;
         const uint32_t g = J.vals[e];
         const double2 m = J.xy[g];
         const float4 co = J.conic[g];
         const float4 cl = J.rgb[g];
-        mk = J.masks[e];
+        mk = G == 8 ? (TileMask) static_cast<const uint64_t *>(J.masks)[e]
+                    : (TileMask) static_cast<const uint16_t *>(J.masks)[e];
         sm.r0[t] = m;
         sm.r1[t] = make_float4(co.x, co.y, co.z, __logf(co.w));
         sm.r2[t] = cl;
       }
-      uint64_t bal[NT];
-#pragma unroll
+#pragma unroll kTileUnroll
       for (int k = 0; k < NT; ++k) {
-        bal[k] = __ballot((mk >> k) & 1u);
-        if (lane == 0) sm.wcnt[cp][k][w] = (uint32_t)__popcll(bal[k]);
+        const uint64_t bk = __ballot((mk >> k) & 1u);
+        if (lane == 0) sm.wcnt[cp][k][w] = (uint32_t)__popcll(bk);
       }
       __syncthreads();
       if (last_k >= 0) {
         const uint32_t any = sm.alive[(it - 1) & 1][0] | sm.alive[(it - 1) & 1][1] | sm.alive[(it - 1) & 1][2] |
                              sm.alive[(it - 1) & 1][3];
-        if (!any) alive_mask &= ~(1u << last_k);
+        if (!any) alive_mask &= ~((TileMask)1 << last_k);
         last_k = -1;
       }
-      uint32_t nk[NT], woff[NT];
-#pragma unroll
-      for (int k = 0; k < NT; ++k) {
-        const uint32_t c0 = sm.wcnt[cp][k][0], c1 = sm.wcnt[cp][k][1], c2 = sm.wcnt[cp][k][2], c3 = sm.wcnt[cp][k][3];
-        nk[k] = c0 + c1 + c2 + c3;
-        woff[k] = (w > 0 ? c0 : 0) + (w > 1 ? c1 : 0) + (w > 2 ? c2 : 0);
-      }
-      // G = 2: fully unrolled, all state in registers.  G = 4: one copy of the step; the
-      // sixteen tiles' state lives in private memory and the step works on a register copy
+      // G = 2: fully unrolled, all state in registers.  G = 4 and 8: one copy of the step; the
+      // member tiles' state lives in private memory and the step works on a register copy
 #pragma unroll kTileUnroll
       for (int k = 0; k < NT; ++k) {
-        if (!((alive_mask >> k) & 1u) || nk[k] == 0) continue;
+        const uint4 ck = *reinterpret_cast<const uint4 *>(sm.wcnt[cp][k]);
+        const uint32_t nk = ck.x + ck.y + ck.z + ck.w;
+        if (!((alive_mask >> k) & 1u) || nk == 0) continue;
         const int buf = it & 1;
         // tile-frame origin in absolute pixels, exactly as the G = 1 path forms it
         const double fx0 = (double)(ox + (k % G) * kTile) + 8.5, fy0 = (double)(oy + (k / G) * kTile) + 8.5;
+        const uint64_t bk = __ballot((mk >> k) & 1u);
         if ((mk >> k) & 1u) {
+          const uint32_t woff = (w > 0 ? ck.x : 0u) + (w > 1 ? ck.y : 0u) + (w > 2 ? ck.z : 0u);
           const uint32_t pos =
-              woff[k] + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[k] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal[k], 0u));
+              woff + __builtin_amdgcn_mbcnt_hi((uint32_t)(bk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bk, 0u));
           const double2 r0 = sm.r0[t];
           const float4 r1 = sm.r1[t];
           const float u = (float)(r0.x - fx0), v = (float)(r0.y - fy0);
@@ -451,14 +451,14 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
         if (last_k >= 0) {
           const uint32_t any = sm.alive[(it - 1) & 1][0] | sm.alive[(it - 1) & 1][1] | sm.alive[(it - 1) & 1][2] |
                                sm.alive[(it - 1) & 1][3];
-          if (!any) alive_mask &= ~(1u << last_k);
+          if (!any) alive_mask &= ~((TileMask)1 << last_k);
         }
         TileState cur = st[k];
-        const int nw = wave_list(sm.qm[buf], (int)nk[k], sm.wl[w]);
+        const int nw = wave_list(sm.qm[buf], (int)nk, sm.wl[w]);
         process_rows<PREC, S, AUX>(sm.A[buf], &sm.col[buf][0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, cur,
                                    rows_done[k]);
         st[k] = cur;
-        rows_done[k] += nk[k];
+        rows_done[k] += nk;
         const uint64_t ab = __ballot(cur.cut != INFINITY);
         if (lane == 0) sm.alive[it & 1][w] = ab != 0;
         last_k = k;
@@ -469,7 +469,7 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
   }
 
   const int64_t HW = (int64_t)J.W * J.H;
-#pragma unroll
+#pragma unroll kTileUnroll
   for (int k = 0; k < NT; ++k) {
     const int xx = ox + (k % G) * kTile + px, yy = oy + (k / G) * kTile + py;
     if (xx >= J.W || yy >= J.H) continue;
@@ -560,6 +560,7 @@ hipError_t launch_p(const RasterJob &j, const RasterParams &p, const BatchArgs *
     case 1: return launch_s<1, PREC>(j, p, b, st);
     case 2: return launch_s<2, PREC>(j, p, b, st);
     case 4: return launch_s<4, PREC>(j, p, b, st);
+    case 8: return launch_s<8, PREC>(j, p, b, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -365,7 +365,7 @@ constexpr int kRangeItems = 4;
 
 __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n,
                                                    const uint32_t *order, const uint32_t *dkeys, const ushort4 *rect,
-                                                   int G, int GX, uint32_t *vals, uint32_t *ranges, uint16_t *masks,
+                                                   int G, int GX, uint32_t *vals, uint32_t *ranges, void *masks,
                                                    uint64_t *keys) {
   const uint64_t base = (uint64_t)blockIdx.x * kBlock * kRangeItems + threadIdx.x;
   uint32_t bin[kRangeItems], prev[kRangeItems], next[kRangeItems], r[kRangeItems];
@@ -397,13 +397,14 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, con
     if (G > 1 && masks) {
       const ushort4 rc = rect[g[j]];
       const int gx = (int)(b % (uint32_t)GX), gy = (int)(b / (uint32_t)GX);
-      uint32_t m = 0;
-      for (int ly = 0; ly < G; ++ly)
-        for (int lx = 0; lx < G; ++lx) {
-          const int tx = gx * G + lx, ty = gy * G + ly;
-          if (tx >= rc.x && tx < rc.z && ty >= rc.y && ty < rc.w) m |= 1u << (ly * G + lx);
-        }
-      masks[i] = (uint16_t)m;
+      // member tiles inside the footprint: a rectangle of rows [y0, y1) and columns [x0, x1)
+      const int x0 = max((int)rc.x - gx * G, 0), x1 = min((int)rc.z - gx * G, G);
+      const int y0 = max((int)rc.y - gy * G, 0), y1 = min((int)rc.w - gy * G, G);
+      const uint64_t row = ((1ull << (x1 - x0)) - 1ull) << x0;   // x1 - x0 <= G <= 8
+      uint64_t m = 0;
+      for (int ly = y0; ly < y1; ++ly) m |= row << (ly * G);
+      if (G == 8) static_cast<uint64_t *>(masks)[i] = m;
+      else static_cast<uint16_t *>(masks)[i] = (uint16_t)m;
     }
   }
 }
@@ -518,7 +519,7 @@ hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V,
 
 hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n, const uint32_t *order,
                          const uint32_t *dkeys, const uint16_t *rect, const Grid &g, uint32_t *vals, uint32_t *ranges,
-                         uint16_t *masks, uint64_t *keys, hipStream_t st) {
+                         void *masks, uint64_t *keys, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_ranges, dim3(grid_for(n, (uint64_t)kBlock * kRangeItems)), dim3(kBlock), 0, st, bin_keys,
                      ranks, n, order, dkeys,

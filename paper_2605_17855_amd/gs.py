@@ -198,13 +198,13 @@ class Projected:
 class Bins:
     """Device buffers of gs_bins: `capacity` entries and the bin ranges of one camera/group."""
 
-    def __init__(self, capacity: int, nbins: int, device="cuda"):
+    def __init__(self, capacity: int, nbins: int, device="cuda", group: int = 1):
         import torch
         self.capacity = int(capacity)
         c = max(self.capacity, 1)
         self.keys = torch.empty((c,), dtype=torch.int64, device=device)
         self.vals = torch.empty((c,), dtype=torch.int32, device=device)
-        self.masks = torch.empty((c,), dtype=torch.int16, device=device)
+        self.masks = torch.empty((c,), dtype=torch.int64 if group == 8 else torch.int16, device=device)
         self.ranges = torch.empty((max(nbins, 1), 2), dtype=torch.int32, device=device)
         b = gs_bins()
         b.keys, b.vals, b.masks = _ptr(self.keys), _ptr(self.vals), _ptr(self.masks)
@@ -307,7 +307,7 @@ class Renderer:
 
     def _alloc_bins(self, capacity: int):
         import torch
-        self.bins = Bins(capacity, self.nbins, self.device)
+        self.bins = Bins(capacity, self.nbins, self.device, self.group)
         c = camera_stub(self.width, self.height)
         o = options(self.group)
         need = int(lib().gs_workspace_bytes(self.n, capacity, C.byref(c), C.byref(o)))

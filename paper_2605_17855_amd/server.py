@@ -205,14 +205,21 @@ class Server:
 FIXED_BYTES = 1 << 18
 
 
-def job_bytes(n_gaussians: int, n_entries: int, pixels: int) -> int:
-    return BYTES_PER_ENTRY * int(n_entries) + BYTES_PER_GAUSSIAN * int(n_gaussians) + int(pixels) // 32 + FIXED_BYTES
+def mask_bytes(group: int) -> int:
+    """Bytes of one entry's tile-membership mask (16 bits up to 4x4 groups, 64 for 8x8)."""
+    return 8 if group == 8 else 2
 
 
-def entry_capacity(reserve: int, n_gaussians: int, pixels: int) -> int:
+def job_bytes(n_gaussians: int, n_entries: int, pixels: int, group: int = 1) -> int:
+    per_entry = BYTES_PER_ENTRY - 2 + mask_bytes(group)
+    return per_entry * int(n_entries) + BYTES_PER_GAUSSIAN * int(n_gaussians) + int(pixels) // 32 + FIXED_BYTES
+
+
+def entry_capacity(reserve: int, n_gaussians: int, pixels: int, group: int = 1) -> int:
     """Entries a reservation of `reserve` bytes holds (inverse of job_bytes)."""
+    per_entry = BYTES_PER_ENTRY - 2 + mask_bytes(group)
     return max(0, (int(reserve) - BYTES_PER_GAUSSIAN * int(n_gaussians) - int(pixels) // 32 - FIXED_BYTES)
-               // BYTES_PER_ENTRY)
+               // per_entry)
 
 
 class FakeBackend:
@@ -443,10 +450,10 @@ class GpuBackend:
         # than its pixel area), so observations are kept per resolution
         px = job.width * job.height
         kpp = self.kpp_seen.get((job.scene, job.width, job.height), self.kpp[job.scene])
-        return job_bytes(self.scenes[job.scene].n, self.safety * kpp * px, px)
+        return job_bytes(self.scenes[job.scene].n, self.safety * kpp * px, px, self.opt.group)
 
     def exact_bytes(self, job, n_keys):
-        return job_bytes(self.scenes[job.scene].n, int(n_keys * 1.02) + 1024, job.width * job.height)
+        return job_bytes(self.scenes[job.scene].n, int(n_keys * 1.02) + 1024, job.width * job.height, self.opt.group)
 
     def try_reserve(self, job, need):
         with self.lock:
@@ -460,7 +467,7 @@ class GpuBackend:
         """gs_bins and workspace carved from the arena at `off` (raw device pointers)."""
         gs, C = self.gs, self.C
         n = self.scenes[job.scene].n
-        cap = entry_capacity(job.reserve, n, job.width * job.height)
+        cap = entry_capacity(job.reserve, n, job.width * job.height, self.opt.group)
         tx, ty = (job.width + 15) // 16, (job.height + 15) // 16
         g = self.opt.group
         nbins = ((tx + g - 1) // g) * ((ty + g - 1) // g)
@@ -477,7 +484,7 @@ class GpuBackend:
         b = gs.gs_bins()
         b.keys = take(8 * c)
         b.vals = take(4 * c)
-        b.masks = take(2 * c + 2)
+        b.masks = take(mask_bytes(self.opt.group) * c + 8)
         b.capacity = cap
         b.ranges = take(8 * nbins)
         ws = take(ws_bytes)

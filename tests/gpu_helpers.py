@@ -44,7 +44,7 @@ def projected_numpy(r: "gs.Renderer"):
 def bins_numpy(r: "gs.Renderer", n_keys: int):
     b = r.bins
     return dict(keys=b.keys.cpu().numpy().view(np.uint64)[:n_keys], vals=b.vals.cpu().numpy().view(np.uint32)[:n_keys],
-                masks=b.masks.cpu().numpy().view(np.uint16)[:n_keys],
+                masks=b.masks.cpu().numpy().view(np.uint64 if r.group == 8 else np.uint16)[:n_keys],
                 ranges=b.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2))
 
 
@@ -116,7 +116,7 @@ def check_bins(rec, cam, r, n_keys, group, tight=False):
     dbits = gdepth.view(np.uint32)[order]
     assert np.all((dbits[1:] > dbits[:-1]) | ((dbits[1:] == dbits[:-1]) & (order[1:] > order[:-1])))
     if group > 1:
-        gm = b["masks"][keep_g].astype(np.uint32)
+        gm = b["masks"][keep_g].astype(np.uint64)
         om = masks[keep_o]
         ok = og == gg
         assert np.array_equal(gm[ok], om[ok])

@@ -42,13 +42,14 @@ def test_num_bins():
     assert L.gs_num_bins(C.byref(c), 1) == 120 * 68
     assert L.gs_num_bins(C.byref(c), 2) == 60 * 34
     assert L.gs_num_bins(C.byref(c), 4) == 30 * 17
+    assert L.gs_num_bins(C.byref(c), 8) == 15 * 9
     assert L.gs_num_bins(None, 1) == 0
 
 
 @pytest.mark.parametrize("field,value,status", [
     ("group", 0, gs.GS_ERR_INVALID_ARG),
     ("group", 3, gs.GS_ERR_UNSUPPORTED),
-    ("group", 8, gs.GS_ERR_UNSUPPORTED),
+    ("group", 16, gs.GS_ERR_UNSUPPORTED),
     ("precision", 7, gs.GS_ERR_INVALID_ARG),
     ("splits", 0, gs.GS_ERR_INVALID_ARG),
     ("aux_flags", 16, gs.GS_ERR_INVALID_ARG),
@@ -71,10 +72,20 @@ def test_tight_culling_needs_group_one():
     L = gs.lib()
     p = gs.gs_projected(1, 1, 1, 1, 1, 1, 1, 1)
     b = gs.gs_bins(1, 1, 1, 16, 1)
-    for group, status in ((2, gs.GS_ERR_UNSUPPORTED), (4, gs.GS_ERR_UNSUPPORTED)):
+    for group, status in ((2, gs.GS_ERR_UNSUPPORTED), (4, gs.GS_ERR_UNSUPPORTED), (8, gs.GS_ERR_UNSUPPORTED)):
         o = gs.options(precision="fp16", group=group, tight=True)
         assert L.gs_rasterize(C.byref(p), C.byref(b), C.byref(_cam()), C.byref(o), C.c_void_p(1), None,
                               None) == status
+
+
+def test_group_eight_needs_mfma():
+    L = gs.lib()
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1, 1, 1)
+    b = gs.gs_bins(1, 1, 1, 16, 1)
+    o = gs.options(precision="fp32", group=8)
+    assert L.gs_rasterize(C.byref(p), C.byref(b), C.byref(_cam()), C.byref(o), C.c_void_p(1), None,
+                          None) == gs.GS_ERR_UNSUPPORTED
+    assert b"MFMA" in L.gs_last_error()
 
 
 def test_fp16_three_splits_unsupported():

@@ -100,7 +100,7 @@ def test_radix_sort_bit_ranges(lo, hi):
     assert np.array_equal(vd.cpu().numpy().view(np.uint32), vals[order])
 
 
-@pytest.mark.parametrize("group", [1, 2, 4])
+@pytest.mark.parametrize("group", [1, 2, 4, 8])
 def test_bin_sort_small(small, group):
     sc, cam, ref, ds = small
     note(f"bin sort 4096 / 128x128 group {group}")
@@ -108,7 +108,7 @@ def test_bin_sort_small(small, group):
     check_bins(ref["records"], cam, out["renderer"], out["n_keys"], group)
 
 
-@pytest.mark.parametrize("group", [1, 2])
+@pytest.mark.parametrize("group", [1, 2, 8])
 def test_bin_sort_1m(big, group):
     sc, cam, rec, ds = big
     note(f"bin sort 1M / 1080p group {group}")
@@ -152,7 +152,7 @@ def test_grouping_bit_identical(prec, splits, size):
     ds = gs.DeviceScene(sc)
     note(f"grouping identity {prec}/{splits} {size}")
     base = render(ds, cam, group=1, precision=prec, splits=splits, aux=AUX_ALL)
-    for g in (2, 4):
+    for g in (2, 4, 8):
         out = render(ds, cam, group=g, precision=prec, splits=splits, aux=AUX_ALL)
         for k in ("image", "tfinal", "wsum", "neval"):
             assert np.array_equal(out[k], base[k]), (g, k)
@@ -258,7 +258,7 @@ def test_1080psampled_tiles(big):
         assert np.abs(out["wsum"] + out["tfinal"] - 1.0).max() <= 1e-5
 
 
-@pytest.mark.parametrize("prec,group", [("fp16", 1), ("fp32", 1), ("bf16", 2)])
+@pytest.mark.parametrize("prec,group", [("fp16", 1), ("fp32", 1), ("bf16", 2), ("fp16", 8)])
 def test_batch_matches_single_renders(prec, group):
     """Persistent batched rasterization: every image equals rendering its job alone (bit-identical)."""
     import torch

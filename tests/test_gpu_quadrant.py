@@ -46,7 +46,7 @@ def scene(request):
 
 
 @pytest.mark.parametrize("prec,splits", [("fp16", 2), ("bf16", 3), ("bf16", 2)])
-@pytest.mark.parametrize("group", [1, 2, 4])
+@pytest.mark.parametrize("group", [1, 2, 4, 8])
 def test_quadrant_culling_bit_identical(scene, prec, splits, group):
     name, sc, cam, ds = scene
     note(f"quadrant culling {name} {prec}/{splits} group {group}")
@@ -67,7 +67,7 @@ def test_quadrant_culling_one_piece_reported(scene, prec):
 def test_quadrant_culling_1m_1080p():
     sc, cam = scenes.clustered_1m()
     ds = gs.DeviceScene(sc)
-    for group, tight in ((1, False), (4, False), (1, True)):
+    for group, tight in ((1, False), (4, False), (8, False), (1, True)):
         note(f"quadrant culling 1M 1080p fp16/2 group {group} tight {tight}")
         a, b = _pair(ds, cam, group=group, precision="fp16", splits=2, tight=tight)
         _assert_same(a, b, (group, tight))

@@ -323,7 +323,7 @@ def test_tile_lists_equal_full_lists_on_their_tiles():
             assert seg.size == 0
 
 
-@pytest.mark.parametrize("G", [2, 4])
+@pytest.mark.parametrize("G", [2, 4, 8])
 def test_group_lists_filter_to_tile_lists(G):
     # Filtering a depth-sorted group list by a member tile's mask bit gives that tile's list.
     sc, cam = scenes.small_camera_space()
