@@ -315,7 +315,7 @@ def sweep(gs, torch, args):
                              "raster_avg_ms": float(np.mean(rm)), "stage_ms": timed_frames.stages})
                 log(f"  G{group}{' tight' if tight else ''} {prec}: {rows[-1]['frames_per_s']:.1f} frames/s, "
                     f"raster {rows[-1]['raster_avg_ms']:.3f} ms")
-            keys["1t" if tight else group] = np.mean([rend.render(ds, c, gs.options(group=group, tight=tight))
+            keys["1t" if tight else group] = np.mean([rend.render(ds, c, gs.options(group=group, precision="fp16", tight=tight))
                                                       for c in cams[:5]])
             del rend
         lr.append({"workload": name, "entries": {str(g): float(k) for g, k in keys.items()},

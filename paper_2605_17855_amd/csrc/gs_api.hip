@@ -140,7 +140,16 @@ Workspace carve(void *ws, int64_t n, uint64_t capacity) {
   return w;
 }
 
-gsi::RasterJob make_job(const gs_projected &p, const gs_bins &b, const gsi::Grid &g, float *image, float *aux) {
+// Workgroups per bin.  With 4x4 and 8x8 groups each workgroup takes one row of the group's
+// member tiles: a 1080p frame has 510 (4x4) or 135 (8x8) groups, too few to fill 256 CUs
+// with one workgroup per group walking 16 or 64 tiles.  Every tile still sees its rows in
+// the same order with the same arithmetic, so the image does not depend on the split.
+int raster_parts(const gs_options &o) {
+  return (o.precision != GS_PREC_FP32 && o.group >= 4) ? o.group : 1;
+}
+
+gsi::RasterJob make_job(const gs_projected &p, const gs_bins &b, const gsi::Grid &g, float *image, float *aux,
+                        int parts) {
   gsi::RasterJob j;
   j.xy = reinterpret_cast<const double2 *>(p.xy);
   j.conic = reinterpret_cast<const float4 *>(p.conic);
@@ -152,6 +161,8 @@ gsi::RasterJob make_job(const gs_projected &p, const gs_bins &b, const gsi::Grid
   j.aux = aux;
   j.W = g.W; j.H = g.H; j.TX = g.TX; j.TY = g.TY; j.GX = g.GX; j.GY = g.GY;
   j.nbins = (int)g.nbins;
+  j.parts = parts;
+  j.items = (int)g.nbins * parts;
   j.bin0 = 0;
   return j;
 }
@@ -304,7 +315,7 @@ gs_status gs_rasterize(const gs_projected *proj, const gs_bins *bins, const gs_c
   if (!image) return fail(GS_ERR_INVALID_ARG, "image is NULL");
   if (opt->aux_flags && !aux) return fail(GS_ERR_INVALID_ARG, "aux is NULL with aux_flags set");
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
-  const gsi::RasterJob j = make_job(*proj, *bins, g, image, aux);
+  const gsi::RasterJob j = make_job(*proj, *bins, g, image, aux, raster_parts(*opt));
   const gsi::RasterParams p = make_params(*opt);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (opt->precision == GS_PREC_FP32)
@@ -331,7 +342,7 @@ gs_status gs_render(const gs_scene *scene, const gs_camera *cam, const gs_option
   GS_HIP(gsi::launch_preprocess(*scene, *cam, g, *proj, (opt->flags & GS_OPT_TIGHT) != 0, st));
   GS_HIP(gsi::launch_scan_compact(proj->count, proj->offset, scene->n, proj->order, proj->n_visible, ws, st));
   if ((s = do_bin_sort(proj, scene->n, cam, opt, bins, n_keys, ws, st))) return s;
-  const gsi::RasterJob j = make_job(*proj, *bins, g, image, aux);
+  const gsi::RasterJob j = make_job(*proj, *bins, g, image, aux, raster_parts(*opt));
   const gsi::RasterParams p = make_params(*opt);
   if (opt->precision == GS_PREC_FP32)
     GS_HIP(gsi::launch_raster_fp32(j, p, st));
@@ -388,10 +399,10 @@ gs_status gs_rasterize_batch(const gs_job *jobs, int32_t n_jobs, const gs_option
     if (!jb.image) return fail(GS_ERR_INVALID_ARG, "job %d: image is NULL", i);
     if (opt->aux_flags && !jb.aux) return fail(GS_ERR_INVALID_ARG, "job %d: aux is NULL with aux_flags set", i);
     const gsi::Grid g = gsi::make_grid(jb.cam.width, jb.cam.height, opt->group);
-    table.jobs[i] = make_job(*jb.proj, *jb.bins, g, jb.image, jb.aux);
+    table.jobs[i] = make_job(*jb.proj, *jb.bins, g, jb.image, jb.aux, raster_parts(*opt));
     table.jobs[i].bin0 = (int)total;
-    total += g.nbins;
-    if (total >= (1ll << 31)) return fail(GS_ERR_UNSUPPORTED, "batch has >= 2^31 bins");
+    total += table.jobs[i].items;
+    if (total >= (1ll << 31)) return fail(GS_ERR_UNSUPPORTED, "batch has >= 2^31 work items");
   }
   table.n_jobs = n_jobs;
   table.total = (int)total;

@@ -173,7 +173,9 @@ struct RasterJob {
   float *aux;
   int W, H, TX, TY, GX, GY;
   int nbins;
-  int bin0;  // first (job, bin) work item of this job in a batched launch
+  int parts;  // workgroups per bin: each takes G / parts rows of the group's member tiles
+  int items;  // nbins * parts work items (one workgroup each)
+  int bin0;   // first work item of this job in a batched launch
 };
 
 struct RasterParams {

@@ -29,7 +29,8 @@ struct Fp32Shared {
   float4 c[kBlock];  // (b, mask bits, -, -)
 };
 
-// Renders bin `bin` of job J (one workgroup).  Shared by the single-image and batched kernels.
+// Renders bin `bin` of job J (one workgroup; this rasterizer takes one work item per bin).
+// Shared by the single-image and batched kernels.
 template <int G, bool AUX>
 __device__ __forceinline__ void raster_bin_fp32(const RasterJob &J, const RasterParams &P, int bin, Fp32Shared &sm) {
   constexpr int NT = G * G;
@@ -136,7 +137,7 @@ __device__ __forceinline__ void raster_bin_fp32(const RasterJob &J, const Raster
 template <int G, bool AUX>
 __global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParams P) {
   __shared__ Fp32Shared sm;
-  raster_bin_fp32<G, AUX>(J, P, xcd_remap(blockIdx.x, J.nbins), sm);
+  raster_bin_fp32<G, AUX>(J, P, xcd_remap(blockIdx.x, J.items), sm);
 }
 
 // Persistent batched rasterizer (see the MFMA variant).
@@ -174,7 +175,7 @@ hipError_t launch_g(const RasterJob &j, const RasterParams &p, const BatchArgs *
     hipLaunchKernelGGL((k_raster_fp32_batch<G, AUX>), dim3((unsigned)b->grid), dim3(kBlock), 0, st, *b->table, p,
                        b->counter);
   } else {
-    hipLaunchKernelGGL((k_raster_fp32<G, AUX>), dim3((unsigned)j.nbins), dim3(kBlock), 0, st, j, p);
+    hipLaunchKernelGGL((k_raster_fp32<G, AUX>), dim3((unsigned)j.items), dim3(kBlock), 0, st, j, p);
   }
   return hipGetLastError();
 }
@@ -192,7 +193,7 @@ hipError_t dispatch(const RasterJob &j, const RasterParams &p, const BatchArgs *
 }  // namespace
 
 hipError_t launch_raster_fp32(const RasterJob &j, const RasterParams &p, hipStream_t st) {
-  if (j.nbins == 0) return hipSuccess;
+  if (j.items == 0) return hipSuccess;
   return dispatch(j, p, nullptr, st);
 }
 

@@ -328,15 +328,21 @@ __device__ __forceinline__ void make_pixel_operand(short8 &B0, short8 &B1, short
 
 }
 
-// Renders bin `bin` of job J (one workgroup).  Shared by the single-image and batched kernels.
+// Renders work item `item` of job J (one workgroup): the member tiles of rows
+// [part * G / parts, (part + 1) * G / parts) of bin item / parts, part = item % parts.  Shared
+// by the single-image and batched kernels.
 template <int G, int PREC, int S, bool AUX>
-__device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const RasterParams &P, int bin,
+__device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const RasterParams &P, int item,
                                                 MfmaShared<G, S> &sm, short8 B0, short8 B1, short8 B20,
                                                 short8 B21) {
   constexpr int NT = G * G;
   constexpr int RS = (S == 3) ? 32 : 16;
   constexpr int kTileUnroll = G >= 4 ? 1 : NT;
   using TileMask = typename std::conditional<(NT > 32), uint64_t, uint32_t>::type;
+  // G <= 2: one workgroup per bin (the tile loops below stay fully unrolled)
+  const int bin = G >= 4 ? item / J.parts : item;
+  const int k0 = G >= 4 ? (item % J.parts) * (G / J.parts) * G : 0;
+  const int k1 = G >= 4 ? k0 + (G / J.parts) * G : NT;
   const int gx = bin % J.GX, gy = bin / J.GX;
   const int ox = gx * G * kTile, oy = gy * G * kTile;
   const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
@@ -355,7 +361,7 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
     st[k].cut = inside ? kCutLog2 : INFINITY;
     st[k].nstop = 0; st[k].nblend = 0;
     rows_done[k] = 0;
-    if (tx0 < J.W && ty0 < J.H) alive_mask |= (TileMask)1 << k;
+    if (k >= k0 && k < k1 && tx0 < J.W && ty0 < J.H) alive_mask |= (TileMask)1 << k;
   }
 
   int it = 0;          // processing steps so far (LDS double-buffer parity)
@@ -411,7 +417,7 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
         sm.r2[t] = cl;
       }
 #pragma unroll kTileUnroll
-      for (int k = 0; k < NT; ++k) {
+      for (int k = k0; k < k1; ++k) {
         const uint64_t bk = __ballot((mk >> k) & 1u);
         if (lane == 0) sm.wcnt[cp][k][w] = (uint32_t)__popcll(bk);
       }
@@ -425,7 +431,7 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
       // G = 2: fully unrolled, all state in registers.  G = 4 and 8: one copy of the step; the
       // member tiles' state lives in private memory and the step works on a register copy
 #pragma unroll kTileUnroll
-      for (int k = 0; k < NT; ++k) {
+      for (int k = k0; k < k1; ++k) {
         const uint4 ck = *reinterpret_cast<const uint4 *>(sm.wcnt[cp][k]);
         const uint32_t nk = ck.x + ck.y + ck.z + ck.w;
         if (!((alive_mask >> k) & 1u) || nk == 0) continue;
@@ -470,7 +476,7 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
 
   const int64_t HW = (int64_t)J.W * J.H;
 #pragma unroll kTileUnroll
-  for (int k = 0; k < NT; ++k) {
+  for (int k = k0; k < k1; ++k) {
     const int xx = ox + (k % G) * kTile + px, yy = oy + (k / G) * kTile + py;
     if (xx >= J.W || yy >= J.H) continue;
     const int64_t pix = (int64_t)yy * J.W + xx;
@@ -495,11 +501,11 @@ __global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParam
   __shared__ MfmaShared<G, S> sm;
   short8 B0, B1, B20, B21;
   make_pixel_operand<PREC>(B0, B1, B20, B21);
-  raster_bin_mfma<G, PREC, S, AUX>(J, P, xcd_remap(blockIdx.x, J.nbins), sm, B0, B1, B20, B21);
+  raster_bin_mfma<G, PREC, S, AUX>(J, P, xcd_remap(blockIdx.x, J.items), sm, B0, B1, B20, B21);
 }
 
-// Persistent batched rasterizer: workgroups take (job, bin) items from *counter until all
-// `total` items are done; job j owns items [jobs[j].bin0, jobs[j].bin0 + jobs[j].nbins).
+// Persistent batched rasterizer: workgroups take (job, item) work items from *counter until
+// all `total` are done; job j owns items [jobs[j].bin0, jobs[j].bin0 + jobs[j].items).
 template <int G, int PREC, int S, bool AUX>
 __global__ __launch_bounds__(kBlock) void k_raster_mfma_batch(const BatchTable tb,
                                                               RasterParams P, uint32_t *counter) {
@@ -536,7 +542,7 @@ hipError_t launch_t(const RasterJob &j, const RasterParams &p, const BatchArgs *
     hipLaunchKernelGGL((k_raster_mfma_batch<G, PREC, S, AUX>), dim3((unsigned)b->grid), dim3(kBlock), 0, st, *b->table, p,
                        b->counter);
   } else {
-    hipLaunchKernelGGL((k_raster_mfma<G, PREC, S, AUX>), dim3((unsigned)j.nbins), dim3(kBlock), 0, st, j, p);
+    hipLaunchKernelGGL((k_raster_mfma<G, PREC, S, AUX>), dim3((unsigned)j.items), dim3(kBlock), 0, st, j, p);
   }
   return hipGetLastError();
 }
@@ -574,7 +580,7 @@ hipError_t dispatch(const RasterJob &j, const RasterParams &p, const BatchArgs *
 }  // namespace
 
 hipError_t launch_raster_mfma(const RasterJob &j, const RasterParams &p, hipStream_t st) {
-  if (j.nbins == 0) return hipSuccess;
+  if (j.items == 0) return hipSuccess;
   return dispatch(j, p, nullptr, st);
 }
 
