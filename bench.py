@@ -304,9 +304,12 @@ def sweep(gs, torch, args):
         ds = gs.DeviceScene(sc)
         cams = scenes.orbit(max(args.sweep_steps, 1), w, h, seed=seed)
         keys = {}
-        for group, tight in ((1, False), (1, True), (2, False), (4, False), (8, False)):
+        variants = ((1, False, ("fp32", "fp16", "bf16")), (1, True, ("fp32", "fp16", "bf16")),
+                    (2, False, ("fp32", "fp16", "bf16")), (4, False, ("fp32", "fp16", "bf16")),
+                    (8, False, ("fp16", "bf16")), (2, True, ("fp16",)), (4, True, ("fp16",)), (8, True, ("fp16",)))
+        for group, tight, precs in variants:
             rend = gs.Renderer(sc.n, w, h, group=group)
-            for prec in ("fp32", "fp16", "bf16") if group != 8 else ("fp16", "bf16"):
+            for prec in precs:
                 splits = 3 if prec == "bf16" else 2
                 opt = gs.options(group=group, precision=prec, splits=splits, tight=tight)
                 el, fm, rm = timed_frames(gs, torch, ds, cams, rend, opt, args.sweep_steps, 3)
@@ -315,11 +318,11 @@ def sweep(gs, torch, args):
                              "raster_avg_ms": float(np.mean(rm)), "stage_ms": timed_frames.stages})
                 log(f"  G{group}{' tight' if tight else ''} {prec}: {rows[-1]['frames_per_s']:.1f} frames/s, "
                     f"raster {rows[-1]['raster_avg_ms']:.3f} ms")
-            keys["1t" if tight else group] = np.mean([rend.render(ds, c, gs.options(group=group, precision="fp16", tight=tight))
+            keys[f"{group}t" if tight else group] = np.mean([rend.render(ds, c, gs.options(group=group, precision="fp16", tight=tight))
                                                       for c in cams[:5]])
             del rend
         lr.append({"workload": name, "entries": {str(g): float(k) for g, k in keys.items()},
-                   "load_reduction": {str(g): 1.0 - keys[g] / keys[1] for g in (2, 4, 8, "1t")}})
+                   "load_reduction": {str(g): 1.0 - keys[g] / keys[1] for g in (2, 4, 8, "1t", "2t", "4t", "8t")}})
         del ds
         torch.cuda.empty_cache()
     return {"rows": rows, "load_reduction": lr, "steps": args.sweep_steps}

@@ -68,12 +68,14 @@ enum {
 /* gs_options.flags */
 enum {
   /* Opacity-aware tile culling (the tighter ellipse-tile intersection the paper's method is
-   * combined with; group 1 only): a Gaussian is listed in a tile of its footprint square only
-   * while some point of the rectangle spanned by the tile's pixel centres satisfies
+   * combined with): a Gaussian is listed in a tile of its footprint square only while some
+   * point of the rectangle spanned by the tile's pixel centres satisfies
    * q(p) = (p - mu')^T conic (p - mu') <= 2 ln(255 o) + 0.01, i.e. while its alpha can reach
-   * the 1/255 cut there (the 0.01 margin covers FP32/FP16 rounding).  Every dropped pair has
-   * alpha below the cut at every pixel of the tile, so the image, T_final and the weight sum
-   * are those of the full lists; entry counts and GS_AUX_NEVAL counts are smaller. */
+   * the 1/255 cut there (the 0.01 margin covers FP32/FP16 rounding).  With GxG groups the
+   * same test decides each member tile: a group entry holds the mask of the member tiles
+   * that pass and exists only when one does.  Every dropped pair has alpha below the cut at
+   * every pixel of the tile, so the image, T_final and the weight sum are those of the full
+   * lists; entry counts and GS_AUX_NEVAL counts are smaller. */
   GS_OPT_TIGHT = 1u,
   /* The MFMA rasterizers leave out of each 8x8 quadrant's MFMA blocks the rows whose alpha
    * cannot reach the 1/255 cut at any pixel centre of that quadrant (the test is taken with a

@@ -198,6 +198,41 @@ def tight_lists(rec: dict, cam, start, ids):
     return st, ids[keep], amb, keep
 
 
+def tight_group_keep(rec: dict, cam, group: int, start, ids, masks):
+    """Opacity-aware culling of the GxG group lists (start, ids, masks) of `lists`: each member
+    tile of an entry's mask is tested with tight_keep; returns, per entry of those lists, the
+    mask of the member tiles that pass, whether any passes (the entry is kept), and whether
+    any member decision lies in the guard band."""
+    tx, _, gx, _ = grid(cam, group)
+    G = group
+    nb = len(start) - 1
+    bins = np.repeat(np.arange(nb), np.diff(start))
+    bit = np.arange(G * G, dtype=np.uint64)
+    has = ((np.asarray(masks, np.uint64)[:, None] >> bit[None, :]) & np.uint64(1)) != 0
+    e, k = np.nonzero(has)
+    ly, lx = k // G, k % G
+    tiles = ((bins[e] // gx) * G + ly) * tx + (bins[e] % gx) * G + lx
+    keep, amb = tight_keep(rec, ids[e], tiles, cam)
+    newm = np.zeros(len(ids), np.uint64)
+    np.bitwise_or.at(newm, e[keep], np.left_shift(np.uint64(1), k[keep].astype(np.uint64)))
+    eamb = np.zeros(len(ids), bool)
+    eamb[e[amb]] = True
+    return newm, newm != 0, eamb
+
+
+def tight_group_lists(rec: dict, cam, group: int):
+    """The group lists of `lists(rec, cam, group)` under opacity-aware culling (start, ids,
+    masks), and the per-entry ambiguity of the decision."""
+    st, ids, masks = lists(rec, cam, group)
+    newm, kept, eamb = tight_group_keep(rec, cam, group, st, ids, masks)
+    nb = len(st) - 1
+    bins = np.repeat(np.arange(nb), np.diff(st))
+    counts = np.bincount(bins[kept], minlength=nb)
+    out = np.zeros(nb + 1, np.int64)
+    out[1:] = np.cumsum(counts)
+    return out, ids[kept], newm[kept], eamb[kept]
+
+
 def ambiguous_membership(rec: dict, cam):
     """Per tile, the Gaussians whose membership flips inside the footprint-edge (1e-3 px) or
     near-plane (1e-6) guard band.  Returns CSR (start, ids)."""

@@ -65,8 +65,6 @@ gs_status check_options(const gs_options *o) {
   if (o->aux_flags & ~(uint32_t)(GS_AUX_TFINAL | GS_AUX_WSUM | GS_AUX_NEVAL | GS_AUX_NBLEND))
     return fail(GS_ERR_INVALID_ARG, "aux_flags 0x%x", o->aux_flags);
   if (o->flags & ~(uint32_t)(GS_OPT_TIGHT | GS_OPT_ALL_ROWS)) return fail(GS_ERR_INVALID_ARG, "flags 0x%x", o->flags);
-  if ((o->flags & GS_OPT_TIGHT) && o->group != 1)
-    return fail(GS_ERR_UNSUPPORTED, "opacity-aware tile culling needs group 1");
   for (int i = 0; i < 3; ++i)
     if (!std::isfinite(o->bg[i])) return fail(GS_ERR_INVALID_ARG, "background non-finite");
   return GS_OK;
@@ -244,7 +242,8 @@ gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
                            bins->ranges, w.sort, st, &in_alt));
   const uint32_t *kf = in_alt ? w.bkey_alt : w.bkey;
   const uint32_t *ranks = in_alt ? w.bval_alt : bins->vals;
-  GS_HIP(gsi::launch_ranges(kf, ranks, K, proj->order, dkeys, proj->rect, g, bins->vals, bins->ranges,
+  GS_HIP(gsi::launch_ranges(kf, ranks, K, proj->order, dkeys, proj->rect, proj->xy, proj->conic,
+                            (opt->flags & GS_OPT_TIGHT) != 0, g, bins->vals, bins->ranges,
                             opt->group > 1 ? bins->masks : nullptr, bins->keys, st));
   return GS_OK;
 }

@@ -111,6 +111,93 @@ __device__ __forceinline__ void tight_row_span(const TightEllipse &e, int ty, in
   }
 }
 
+// Opacity-aware culling with GxG groups (G <= 8).  Group row gy holds tile rows
+// [gy G, gy G + G) of the footprint; a group is kept while the span of one of those rows
+// reaches one of its G tile columns, i.e. lies partly in [gx G, gx G + G).  A row's span
+// [lo, hi] does so for the group columns [lo / G, hi / G]; the kept columns of a group row are
+// the union of those ranges over its rows (not always one interval: a thin, slanted ellipse
+// can pass the one-pixel gap between two rows' pixel-centre bands far to the side).
+struct TightGroupRow {
+  int lo[8], hi[8];   // group columns reached from each tile row (lo > hi: none)
+  int cmin, cmax;     // their hull (cmin > cmax: none)
+  bool chain;         // the reached rows are consecutive and each range meets or touches the
+                      // previous one, so the union is the hull (the usual case)
+};
+
+__device__ __forceinline__ TightGroupRow tight_group_row(const TightEllipse &e, int G, int gy, int y1) {
+  TightGroupRow r;
+  r.cmin = 1 << 30;
+  r.cmax = -1;
+  r.chain = true;
+  int plo = 0, phi = -1;     // the previous tile row's range
+  bool seen = false, ended = false;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    r.lo[i] = 0;
+    r.hi[i] = -1;
+    const int ty = gy * G + i;
+    if (i < G && ty >= e.y0 && ty <= y1) {
+      int lo, hi;
+      tight_row_span(e, ty, &lo, &hi);
+      if (lo <= hi) {
+        r.lo[i] = lo / G;
+        r.hi[i] = hi / G;
+        r.cmin = min(r.cmin, r.lo[i]);
+        r.cmax = max(r.cmax, r.hi[i]);
+        if (ended || (seen && (r.lo[i] > phi + 1 || r.hi[i] < plo - 1))) r.chain = false;
+        seen = true;
+        plo = r.lo[i];
+        phi = r.hi[i];
+      } else if (seen) {
+        ended = true;
+      }
+    }
+  }
+  return r;
+}
+
+__device__ __forceinline__ bool tight_group_has(const TightGroupRow &r, int c) {
+  bool any = false;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) any |= (r.lo[i] <= c) & (c <= r.hi[i]);
+  return any;
+}
+
+__device__ __forceinline__ uint32_t tight_group_count(const TightGroupRow &r) {
+  if (r.cmin > r.cmax) return 0u;
+  if (r.chain) return (uint32_t)(r.cmax - r.cmin + 1);
+  uint32_t n = 0;
+  for (int c = r.cmin; c <= r.cmax; ++c) n += tight_group_has(r, c) ? 1u : 0u;
+  return n;
+}
+
+// Group column of the row's kept group number `nth` (nth < tight_group_count(r)).
+__device__ __forceinline__ int tight_group_nth(const TightGroupRow &r, uint32_t nth) {
+  if (r.chain) return r.cmin + (int)nth;
+  for (int c = r.cmin; c <= r.cmax; ++c) {
+    if (!tight_group_has(r, c)) continue;
+    if (nth == 0) return c;
+    --nth;
+  }
+  return r.cmax;   // (not reached)
+}
+
+// Membership mask of group (gx, gy) under the culling: bit (ty % G) G + (tx % G) for each
+// member tile the ellipse meets.
+__device__ __forceinline__ uint64_t tight_group_mask(const TightEllipse &e, int G, int gx, int gy, int y1) {
+  uint64_t m = 0;
+  for (int ly = 0; ly < G; ++ly) {
+    const int ty = gy * G + ly;
+    if (ty < e.y0 || ty > y1) continue;
+    int lo, hi;
+    tight_row_span(e, ty, &lo, &hi);
+    lo = max(lo, gx * G);
+    hi = min(hi, gx * G + G - 1);
+    if (lo <= hi) m |= (((1ull << (hi - lo + 1)) - 1ull) << (lo - gx * G)) << (ly * G);
+  }
+  return m;
+}
+
 // ---- preprocess + scans ------------------------------------------------------
 hipError_t launch_preprocess(const gs_scene &s, const gs_camera &c, const Grid &g, const gs_projected &o,
                              bool tight, hipStream_t st);
@@ -157,8 +244,8 @@ hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V,
 // (vals[i] = order[ranks[i]]; ranks may alias vals) of the sorted entries; dkeys[r] are the
 // depth bits of the r-th Gaussian in depth order.
 hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n, const uint32_t *order,
-                         const uint32_t *dkeys, const uint16_t *rect, const Grid &g, uint32_t *vals, uint32_t *ranges,
-                         void *masks, uint64_t *keys, hipStream_t st);
+                         const uint32_t *dkeys, const uint16_t *rect, const double *xy, const float *conic, bool tight,
+                         const Grid &g, uint32_t *vals, uint32_t *ranges, void *masks, uint64_t *keys, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
 
 // ---- rasterizers -------------------------------------------------------------

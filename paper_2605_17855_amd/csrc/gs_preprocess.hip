@@ -145,13 +145,18 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
         const int G = a.G;
         cnt = (uint32_t)((x1 / G - x0 / G + 1) * (y1 / G - y0 / G + 1));
         if (a.tight) {
-          // entries of the tiles the alpha-cut ellipse meets (the binning walks the same spans)
+          // entries of the tiles (groups) the alpha-cut ellipse meets; the binning walks the
+          // same spans
           const TightEllipse el = tight_ellipse(mx, my, ca, cb, cc, opac, x0, x1, y0);
           cnt = 0;
-          for (int ty = y0; ty <= y1; ++ty) {
-            int lo, hi;
-            tight_row_span(el, ty, &lo, &hi);
-            cnt += (uint32_t)(hi - lo + 1);
+          if (G == 1) {
+            for (int ty = y0; ty <= y1; ++ty) {
+              int lo, hi;
+              tight_row_span(el, ty, &lo, &hi);
+              cnt += (uint32_t)(hi - lo + 1);
+            }
+          } else {
+            for (int gy = y0 / G; gy <= y1 / G; ++gy) cnt += tight_group_count(tight_group_row(el, G, gy, y1));
           }
         }
         rc = make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)(x1 + 1),

@@ -313,14 +313,16 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
   }
 }
 
-// Binning under opacity-aware culling (group 1): a Gaussian's entries follow its tile rows,
-// each row a span from tight_row_span; entry j walks the rows until its own.  (Measured on
-// the 1M-Gaussian 1080p frame, this beat an LDS table of row spans built per workgroup: the
-// span of a row is a few instructions, the table's dependent loads and prefix pass are not.)
+// Binning under opacity-aware culling: a Gaussian's entries follow its tile rows (group
+// rows), each a span from tight_row_span (a union of group-column ranges); entry j walks the
+// rows until its own.  (Measured on the 1M-Gaussian 1080p frame, this beat an LDS table of
+// row spans built per workgroup: the span of a row is a few instructions, the table's
+// dependent loads and prefix pass are not.)
 __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order, const uint64_t *dpos, uint32_t nvis,
                                                           uint64_t K, const ushort4 *rect, const double2 *xy,
-                                                          const float4 *conic, int TX, uint32_t *bin_keys,
-                                                          uint32_t *vals, uint32_t *ranges, uint64_t nranges) {
+                                                          const float4 *conic, int TX, int G, int GX,
+                                                          uint32_t *bin_keys, uint32_t *vals, uint32_t *ranges,
+                                                          uint64_t nranges) {
   __shared__ uint64_t s_pos[kBinItems + 1];
   __shared__ uint32_t s_first;
   const uint64_t e0 = (uint64_t)blockIdx.x * kBinItems;
@@ -338,18 +340,30 @@ __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order,
       const double2 m = xy[g];
       const float4 co = conic[g];
       const TightEllipse el = tight_ellipse(m.x, m.y, co.x, co.y, co.z, co.w, r.x, r.z - 1, r.y);
-      uint32_t tile = (uint32_t)((r.w - 1) * TX + r.x);   // (not reached for consistent counts)
-      for (int ty = r.y; ty < r.w; ++ty) {
-        int lo, hi;
-        tight_row_span(el, ty, &lo, &hi);
-        const uint32_t cnt = (uint32_t)(hi - lo + 1);
-        if (left < cnt) {
-          tile = (uint32_t)(ty * TX + lo) + left;
-          break;
+      uint32_t bin = 0;   // (the walk always ends early for counts from the preprocess)
+      if (G == 1) {
+        for (int ty = r.y; ty < r.w; ++ty) {
+          int lo, hi;
+          tight_row_span(el, ty, &lo, &hi);
+          const uint32_t cnt = (uint32_t)(hi - lo + 1);
+          if (left < cnt) {
+            bin = (uint32_t)(ty * TX + lo) + left;
+            break;
+          }
+          left -= cnt;
         }
-        left -= cnt;
+      } else {
+        for (int gy = r.y / G; gy <= (r.w - 1) / G; ++gy) {
+          const TightGroupRow row = tight_group_row(el, G, gy, r.w - 1);
+          const uint32_t cnt = tight_group_count(row);
+          if (left < cnt) {
+            bin = (uint32_t)(gy * GX + tight_group_nth(row, left));
+            break;
+          }
+          left -= cnt;
+        }
       }
-      bin_keys[e] = tile;
+      bin_keys[e] = bin;
       vals[e] = rank;   // the Gaussian's rank in depth order; k_ranges turns it into its index
     }
   }
@@ -365,8 +379,8 @@ constexpr int kRangeItems = 4;
 
 __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n,
                                                    const uint32_t *order, const uint32_t *dkeys, const ushort4 *rect,
-                                                   int G, int GX, uint32_t *vals, uint32_t *ranges, void *masks,
-                                                   uint64_t *keys) {
+                                                   const double2 *xy, const float4 *conic, int tight, int G, int GX,
+                                                   uint32_t *vals, uint32_t *ranges, void *masks, uint64_t *keys) {
   const uint64_t base = (uint64_t)blockIdx.x * kBlock * kRangeItems + threadIdx.x;
   uint32_t bin[kRangeItems], prev[kRangeItems], next[kRangeItems], r[kRangeItems];
 #pragma unroll
@@ -397,12 +411,20 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, con
     if (G > 1 && masks) {
       const ushort4 rc = rect[g[j]];
       const int gx = (int)(b % (uint32_t)GX), gy = (int)(b / (uint32_t)GX);
-      // member tiles inside the footprint: a rectangle of rows [y0, y1) and columns [x0, x1)
-      const int x0 = max((int)rc.x - gx * G, 0), x1 = min((int)rc.z - gx * G, G);
-      const int y0 = max((int)rc.y - gy * G, 0), y1 = min((int)rc.w - gy * G, G);
-      const uint64_t row = ((1ull << (x1 - x0)) - 1ull) << x0;   // x1 - x0 <= G <= 8
       uint64_t m = 0;
-      for (int ly = y0; ly < y1; ++ly) m |= row << (ly * G);
+      if (tight) {
+        // member tiles the alpha-cut ellipse meets
+        const double2 mu = xy[g[j]];
+        const float4 co = conic[g[j]];
+        const TightEllipse el = tight_ellipse(mu.x, mu.y, co.x, co.y, co.z, co.w, rc.x, rc.z - 1, rc.y);
+        m = tight_group_mask(el, G, gx, gy, rc.w - 1);
+      } else {
+        // member tiles inside the footprint: a rectangle of rows [y0, y1) and columns [x0, x1)
+        const int x0 = max((int)rc.x - gx * G, 0), x1 = min((int)rc.z - gx * G, G);
+        const int y0 = max((int)rc.y - gy * G, 0), y1 = min((int)rc.w - gy * G, G);
+        const uint64_t row = ((1ull << (x1 - x0)) - 1ull) << x0;   // x1 - x0 <= G <= 8
+        for (int ly = y0; ly < y1; ++ly) m |= row << (ly * G);
+      }
       if (G == 8) static_cast<uint64_t *>(masks)[i] = m;
       else static_cast<uint16_t *>(masks)[i] = (uint16_t)m;
     }
@@ -508,7 +530,7 @@ hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V,
   const float4 *c4 = reinterpret_cast<const float4 *>(conic);
   if (tight)
     hipLaunchKernelGGL(k_binning_tight, dim3(grid_for(K, kBinItems)), dim3(kBlock), 0, st, order, dpos, V, K, r4, m2,
-                       c4, g.TX, bkey, bval, ranges, nranges);
+                       c4, g.TX, g.G, g.GX, bkey, bval, ranges, nranges);
   else
     hipLaunchKernelGGL(k_binning, dim3(grid_for(K, kBinItems)), dim3(kBlock), 0, st, order, dpos, V, K, r4, g.G,
                        g.GX, bkey, bval, ranges, nranges);
@@ -518,12 +540,13 @@ hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V,
 }
 
 hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n, const uint32_t *order,
-                         const uint32_t *dkeys, const uint16_t *rect, const Grid &g, uint32_t *vals, uint32_t *ranges,
-                         void *masks, uint64_t *keys, hipStream_t st) {
+                         const uint32_t *dkeys, const uint16_t *rect, const double *xy, const float *conic, bool tight,
+                         const Grid &g, uint32_t *vals, uint32_t *ranges, void *masks, uint64_t *keys, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_ranges, dim3(grid_for(n, (uint64_t)kBlock * kRangeItems)), dim3(kBlock), 0, st, bin_keys,
-                     ranks, n, order, dkeys,
-                     reinterpret_cast<const ushort4 *>(rect), g.G, g.GX, vals, ranges, masks, keys);
+                     ranks, n, order, dkeys, reinterpret_cast<const ushort4 *>(rect),
+                     reinterpret_cast<const double2 *>(xy), reinterpret_cast<const float4 *>(conic), tight ? 1 : 0,
+                     g.G, g.GX, vals, ranges, masks, keys);
   return hipGetLastError();
 }
 

@@ -95,9 +95,9 @@ def check_bins(rec, cam, r, n_keys, group, tight=False):
     keep_o = ~amb[ids]
     keep_g = ~amb[vals]
     if tight:
-        # the culled lists; (Gaussian, tile) pairs whose culling decision lies in the guard band
-        # are left out on both sides
-        keep_t, amb_t = oracle.tight_keep(rec, ids, ob, cam)
+        # the culled lists; entries with a member-tile decision in the guard band are left out
+        # on both sides
+        masks, keep_t, amb_t = oracle.tight_group_keep(rec, cam, group, st, ids, masks)
         bad = set(zip(ids[amb_t].tolist(), ob[amb_t].tolist()))
         keep_o &= keep_t & ~amb_t
         keep_g &= np.array([(int(g), int(b)) not in bad for g, b in zip(vals, bins_of)], bool) if bad else True

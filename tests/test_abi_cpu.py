@@ -68,16 +68,6 @@ def test_rasterize_rejects_bad_options(field, value, status):
     assert L.gs_last_error()
 
 
-def test_tight_culling_needs_group_one():
-    L = gs.lib()
-    p = gs.gs_projected(1, 1, 1, 1, 1, 1, 1, 1)
-    b = gs.gs_bins(1, 1, 1, 16, 1)
-    for group, status in ((2, gs.GS_ERR_UNSUPPORTED), (4, gs.GS_ERR_UNSUPPORTED), (8, gs.GS_ERR_UNSUPPORTED)):
-        o = gs.options(precision="fp16", group=group, tight=True)
-        assert L.gs_rasterize(C.byref(p), C.byref(b), C.byref(_cam()), C.byref(o), C.c_void_p(1), None,
-                              None) == status
-
-
 def test_group_eight_needs_mfma():
     L = gs.lib()
     p = gs.gs_projected(1, 1, 1, 1, 1, 1, 1, 1)

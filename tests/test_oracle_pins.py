@@ -581,3 +581,32 @@ def test_tight_isotropic_closed_form():
     ddy = np.maximum(np.maximum(y0 - 57.9, 57.9 - (y0 + 15)), 0)
     assert np.array_equal(keep, np.hypot(ddx, ddy) <= rho)
     assert 4 < keep.sum() < 40
+
+
+@pytest.mark.parametrize("G", [1, 2, 4, 8])
+def test_tight_group_lists_filter_to_tight_tile_lists(G):
+    """Opacity-aware culling decides each member tile of a group on its own: filtering the
+    culled group lists by a member tile's mask bit gives that tile's culled list, in order,
+    and no kept entry has an empty mask."""
+    sc = scenes.camera_box_scene(3000, seed=41, log_scale_mu=math.log(0.03), log_scale_sigma=0.9)
+    cam = scenes.pinhole(200, 136, 60.0)
+    rec = oracle.preprocess(sc, cam)
+    st1, ids1, _ = oracle.lists(rec, cam, 1)
+    tst1, tids1, _, _ = oracle.tight_lists(rec, cam, st1, ids1)
+    stg, idsg, masks, _ = oracle.tight_group_lists(rec, cam, G)
+    tx, ty, gx, gy = oracle.grid(cam, G)
+    assert (masks != 0).all()
+    assert idsg.size < oracle.lists(rec, cam, G)[0][-1]
+    seen = 0
+    for u in range(gx * gy):
+        seg, mseg = idsg[stg[u]:stg[u + 1]], masks[stg[u]:stg[u + 1]]
+        for ly in range(G):
+            for lx in range(G):
+                txx, tyy = (u % gx) * G + lx, (u // gx) * G + ly
+                if txx >= tx or tyy >= ty:
+                    continue
+                t = tyy * tx + txx
+                filt = seg[(mseg & np.uint64(1 << (ly * G + lx))) != 0]
+                assert np.array_equal(filt, tids1[tst1[t]:tst1[t + 1]]), (G, u, lx, ly)
+                seen += filt.size
+    assert seen == tids1.size
