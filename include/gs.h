@@ -114,7 +114,9 @@ typedef struct {
   const float *log_scale;   /* 3 x n: log of the per-axis standard deviation */
   const float *quat;        /* 4 x n: (w, x, y, z) rows, normalised by the library */
   const float *opacity;     /* n, in (0, 1) */
-  const float *sh;          /* (deg+1)^2 x 3 x n: basis index l*l + l + m, then channel, then Gaussian */
+  const float *sh;          /* n x (deg+1)^2 x 3: Gaussian, then basis index l*l + l + m, then channel.  Each
+                               Gaussian's coefficients are contiguous, so culled ones cost no SH traffic;
+                               16-byte aligned */
 } gs_scene;
 
 /* Per-Gaussian screen-space records written by gs_preprocess (n entries each;

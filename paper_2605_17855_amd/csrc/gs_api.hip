@@ -78,6 +78,7 @@ gs_status check_scene(const gs_scene *s) {
   if (s->sh_degree > 3) return fail(GS_ERR_UNSUPPORTED, "sh_degree %d > 3", s->sh_degree);
   if (s->n > 0 && (!s->mean || !s->log_scale || !s->quat || !s->opacity || !s->sh))
     return fail(GS_ERR_INVALID_ARG, "scene array is NULL");
+  if (reinterpret_cast<uintptr_t>(s->sh) & 15u) return fail(GS_ERR_INVALID_ARG, "scene sh is not 16-byte aligned");
   return GS_OK;
 }
 

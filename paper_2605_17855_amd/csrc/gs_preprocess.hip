@@ -165,9 +165,19 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
         float dx = (float)px - a.campos[0], dy = (float)py - a.campos[1], dz = (float)pz - a.campos[2];
         const float di = rsqrtf(dx * dx + dy * dy + dz * dz);
         dx *= di; dy *= di; dz *= di;
+        // the Gaussian's coefficients are contiguous: only visible Gaussians fetch their lines
         float coef[NB * 3];
+        const float *shg = a.sh + (int64_t)g * (NB * 3);
+        if constexpr ((NB * 3) % 4 == 0) {
 #pragma unroll
-        for (int k = 0; k < NB * 3; ++k) coef[k] = a.sh[(int64_t)k * n + g];
+          for (int k = 0; k < NB * 3; k += 4) {
+            const float4 v = *reinterpret_cast<const float4 *>(shg + k);
+            coef[k] = v.x; coef[k + 1] = v.y; coef[k + 2] = v.z; coef[k + 3] = v.w;
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < NB * 3; ++k) coef[k] = shg[k];
+        }
         float b[16];
         sh_basis<DEG>(dx, dy, dz, b);
         float col[3];

@@ -162,7 +162,9 @@ class DeviceScene:
         self.log_scale = torch.from_numpy(np.ascontiguousarray(scene.log_scale)).to(device)
         self.quat = torch.from_numpy(np.ascontiguousarray(scene.quat)).to(device)
         self.opacity = torch.from_numpy(np.ascontiguousarray(scene.opacity)).to(device)
-        self.sh = torch.from_numpy(np.ascontiguousarray(scene.sh)).to(device)
+        # per-Gaussian contiguous coefficients (n, (deg+1)^2 * 3), the library's layout
+        sh = np.asarray(scene.sh).reshape((self.sh_degree + 1) ** 2 * 3, self.n)
+        self.sh = torch.from_numpy(np.ascontiguousarray(sh.T)).to(device)
         s = gs_scene()
         s.n, s.sh_degree, s.reserved = self.n, self.sh_degree, 0
         s.mean, s.log_scale, s.quat = _ptr(self.mean), _ptr(self.log_scale), _ptr(self.quat)

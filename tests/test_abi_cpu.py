@@ -143,9 +143,15 @@ def test_scene_checks():
     s = gs.gs_scene(10, 0, 0, 1, 1, None, 1, 1)
     assert L.gs_preprocess(C.byref(s), C.byref(c), C.byref(o), C.byref(p), ws, 1 << 20,
                            None) == gs.GS_ERR_INVALID_ARG
+    # the SH coefficients are read as 16-byte vectors
+    s = gs.gs_scene(10, 3, 0, 1, 1, 1, 1, 20)
+    assert L.gs_preprocess(C.byref(s), C.byref(c), C.byref(o), C.byref(p), ws, 1 << 20,
+                           None) == gs.GS_ERR_INVALID_ARG
+    assert b"aligned" in L.gs_last_error()
     # workspace too small
-    s = gs.gs_scene(100000, 0, 0, 1, 1, 1, 1, 1)
+    s = gs.gs_scene(100000, 0, 0, 1, 1, 1, 1, 16)
     assert L.gs_preprocess(C.byref(s), C.byref(c), C.byref(o), C.byref(p), ws, 8, None) == gs.GS_ERR_INVALID_ARG
+    assert b"workspace" in L.gs_last_error()
 
 
 def test_sort_argument_checks():
