@@ -15,13 +15,6 @@
 namespace gsi {
 namespace {
 
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  // workgroups are dispatched round-robin over the 8 XCDs: give each XCD a contiguous
-  // range of bins so that neighbouring bins share that XCD's L2
-  const int x = b & 7, idx = b >> 3;
-  const int per = nb >> 3, rem = nb & 7;
-  return x * per + (x < rem ? x : rem) + idx;
-}
 
 struct Fp32Shared {
   float4 a[kBlock];  // (u, v, -a/2 log2e, -b log2e)
@@ -134,10 +127,12 @@ __device__ __forceinline__ void raster_bin_fp32(const RasterJob &J, const Raster
   }
 }
 
+// Work item = workgroup id: round-robin over the 8 XCDs spreads the dense middle of a frame
+// over all of them.
 template <int G, bool AUX>
 __global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParams P) {
   __shared__ Fp32Shared sm;
-  raster_bin_fp32<G, AUX>(J, P, xcd_remap(blockIdx.x, J.items), sm);
+  raster_bin_fp32<G, AUX>(J, P, blockIdx.x, sm);
 }
 
 // Persistent batched rasterizer (see the MFMA variant).

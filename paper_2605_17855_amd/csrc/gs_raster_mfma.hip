@@ -44,11 +44,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef short short8 __attribute__((ext_vector_type(8)));
 typedef float float16v __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  const int x = b & 7, idx = b >> 3;
-  const int per = nb >> 3, rem = nb & 7;
-  return x * per + (x < rem ? x : rem) + idx;
-}
 
 template <int PREC>
 struct Narrow;
@@ -279,15 +274,18 @@ template <int G, int S>
 struct MfmaShared {
   static constexpr int NT = G * G;
   static constexpr int RS = (S == 3) ? 32 : 16;
-  __align__(16) uint16_t A[2][kBlock * RS];
-  float col[2][3][kBlock];          // colour planes r, g, b of the staged rows
+  // G = 1 stages one chunk at a time (a tile's list rarely exceeds one chunk); grouped tiles
+  // double-buffer, so one member tile's rows are built while another's are still read
+  static constexpr int NBUF = G == 1 ? 1 : 2;
+  __align__(16) uint16_t A[NBUF][kBlock * RS];
+  float col[NBUF][3][kBlock];       // colour planes r, g, b of the staged rows
   double2 r0[G > 1 ? kBlock : 1];  // FP64 centre; every tile rounds its own offset
   float4 r1[G > 1 ? kBlock : 1];   // (a, b, c, ln o)
   float4 r2[G > 1 ? kBlock : 1];   // (r, g, b, -)
   __align__(16) uint32_t wcnt[2][NT][4];   // by chunk parity: a wave may stage chunk c+1 while
                                    // another still reads chunk c's counts
   uint32_t alive[2][4];
-  uint8_t qm[2][kBlock];           // quadrant masks of the staged rows
+  uint8_t qm[NBUF][kBlock];        // quadrant masks of the staged rows
   uint8_t wl[4][kBlock];           // each wave's row list (wave-private)
   float4 wc[4][32];                // each wave's colours of its current block (wave-private)
 };
@@ -370,7 +368,15 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
   for (uint32_t cs = start; cs < end && alive_mask; cs += kBlock) {
     const int cnt = (int)min((uint32_t)kBlock, end - cs);
     if (G == 1) {
-      const int buf = it & 1;
+      constexpr int buf = 0;
+      if (it > 0) {
+        // every wave is done with the previous chunk (single buffer) and has posted whether
+        // its pixels are still blending
+        __syncthreads();
+        const uint32_t any = sm.alive[(it - 1) & 1][0] | sm.alive[(it - 1) & 1][1] | sm.alive[(it - 1) & 1][2] |
+                             sm.alive[(it - 1) & 1][3];
+        if (!any) break;
+      }
       if (t < cnt) {
         const uint32_t e = cs + t;
         const uint32_t g = J.vals[e];
@@ -386,20 +392,12 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
         sm.qm[buf][t] = P.all_rows ? (uint8_t)0xF : (uint8_t)quad_mask(u, v, co.x, co.y, co.z, lno);
       }
       __syncthreads();
-      if (last_k >= 0) {
-        const uint32_t any = sm.alive[(it - 1) & 1][0] | sm.alive[(it - 1) & 1][1] | sm.alive[(it - 1) & 1][2] |
-                             sm.alive[(it - 1) & 1][3];
-        if (!any) alive_mask = 0;
-        last_k = -1;
-        if (!alive_mask) break;
-      }
       const int nw = wave_list(sm.qm[buf], cnt, sm.wl[w]);
       process_rows<PREC, S, AUX>(sm.A[buf], &sm.col[buf][0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, st[0],
                                  rows_done[0]);
       rows_done[0] += cnt;
       const uint64_t bal = __ballot(st[0].cut != INFINITY);
       if (lane == 0) sm.alive[it & 1][w] = bal != 0;
-      last_k = 0;
       ++it;
     } else {
       // stage the chunk once for every member tile (Algorithm 1: load the chunk into shared memory)
@@ -496,12 +494,18 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
   }
 }
 
+// Work item = workgroup id.  Workgroups go round-robin to the 8 XCDs, so neighbouring tiles
+// run on different XCDs and the dense middle of a frame is shared by all of them; giving each
+// XCD a contiguous band of tiles (for L2 reuse of shared records) left the XCDs holding the
+// dense bands running last and was slower (105 vs 87 us at 1080p / 1M Gaussians).  G = 1 fits
+// 64 VGPRs (8 waves per SIMD).
 template <int G, int PREC, int S, bool AUX>
-__global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParams P) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G == 1 ? 8 : 1))) void k_raster_mfma(
+    RasterJob J, RasterParams P) {
   __shared__ MfmaShared<G, S> sm;
   short8 B0, B1, B20, B21;
   make_pixel_operand<PREC>(B0, B1, B20, B21);
-  raster_bin_mfma<G, PREC, S, AUX>(J, P, xcd_remap(blockIdx.x, J.items), sm, B0, B1, B20, B21);
+  raster_bin_mfma<G, PREC, S, AUX>(J, P, blockIdx.x, sm, B0, B1, B20, B21);
 }
 
 // Persistent batched rasterizer: workgroups take (job, item) work items from *counter until
