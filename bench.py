@@ -40,8 +40,8 @@ PEAK_FP32_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (packed) x 2 (FMA) x
 # FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by what the same counters read for a plain
 # device copy of known size (x2 and x1).  They describe the kernel built from the source and
 # compiler flags hashed in `sha256`; after any change to either the traffic is reported as null.
-RASTER_COUNTERS = dict(sha256="ae9e1b4bbf2a360f681c162b06f98ed9a79e82ad385b05d1962e9c7c553640ea",
-                       fetch_kib=55166, write_kib=25219, fetch_scale=2.0, write_scale=1.0,
+RASTER_COUNTERS = dict(sha256="4779f7f4c6157e2aff9fbf81fa2861815eb80d306cd7937af50161ef0e0d6ea5",
+                       fetch_kib=87555, write_kib=24706, fetch_scale=2.0, write_scale=1.0,
                        precision="fp16", splits=2, group=1)
 
 
@@ -49,8 +49,10 @@ def raster_source_hash():
     import hashlib
     from paper_2605_17855_amd import build
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2605_17855_amd", "csrc", "gs_raster_mfma.hip"), "rb") as f:
-        h.update(f.read())
+    for part in (("paper_2605_17855_amd", "csrc", "gs_raster_mfma.hip"),
+                 ("paper_2605_17855_amd", "csrc", "gs_internal.hpp"), ("include", "gs.h")):
+        with open(os.path.join(ROOT, *part), "rb") as f:
+            h.update(f.read())
     h.update(" ".join(f for f in build.FLAGS if not os.path.isabs(f)).encode())
     return h.hexdigest()
 

@@ -497,11 +497,10 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
 // Work item = workgroup id.  Workgroups go round-robin to the 8 XCDs, so neighbouring tiles
 // run on different XCDs and the dense middle of a frame is shared by all of them; giving each
 // XCD a contiguous band of tiles (for L2 reuse of shared records) left the XCDs holding the
-// dense bands running last and was slower (105 vs 87 us at 1080p / 1M Gaussians).  G = 1 fits
-// 64 VGPRs (8 waves per SIMD).
+// dense bands running last and was slower (105 vs 87 us at 1080p / 1M Gaussians).  (Forcing
+// 64 VGPRs for 8 waves per SIMD spilled to scratch and was slower than the 72 VGPRs here.)
 template <int G, int PREC, int S, bool AUX>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G == 1 ? 8 : 1))) void k_raster_mfma(
-    RasterJob J, RasterParams P) {
+__global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParams P) {
   __shared__ MfmaShared<G, S> sm;
   short8 B0, B1, B20, B21;
   make_pixel_operand<PREC>(B0, B1, B20, B21);
