@@ -7,7 +7,8 @@ same arrays without sharing any of the method's code.
 
 The paper evaluates trained scenes (its Table of evaluated workloads) that are
 not available here; these generators stand in for them with the shapes and
-value distributions listed below.  Scene arrays follow the library layout:
+value distributions listed below (`ply.load_ply` reads trained scenes into the
+same arrays).  Scene arrays (host, numpy):
 
     mean       float32 (3, n)            world-space centre
     log_scale  float32 (3, n)            per-axis log standard deviation
@@ -15,6 +16,8 @@ value distributions listed below.  Scene arrays follow the library layout:
     opacity    float32 (n,)              in (0, 1)
     sh         float32 ((deg+1)^2, 3, n) spherical-harmonics coefficients,
                                          basis index l*l + l + m, channel-major
+                                         (the device copy holds each Gaussian's
+                                         coefficients contiguously)
 
 Cameras map world to camera coordinates with x right, y down, z forward.
 """

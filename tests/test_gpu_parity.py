@@ -295,3 +295,17 @@ def test_batch_matches_single_renders(prec, group):
     torch.cuda.synchronize()
     for k, o in zip(order, outs):
         assert torch.equal(o[0], singles[k][0]) and torch.equal(o[1], singles[k][1])
+
+
+def test_ply_scene_renders_like_its_source(tmp_path):
+    """A scene written and read back in the trained-scene PLY layout renders as the original
+    (opacity and quaternion pass through logit/normalisation, so equal up to rounding)."""
+    from paper_2605_17855_amd import ply
+    sc = scenes.clustered_scene(20000, seed=23, clusters=8)
+    cam = scenes.look_at([3.0, 1.0, 1.5], 160, 90)
+    ply.save_ply(sc, str(tmp_path / "s.ply"))
+    back = ply.load_ply(str(tmp_path / "s.ply"))
+    note("ply round trip render")
+    a = render(gs.DeviceScene(sc), cam, precision="fp16")
+    b = render(gs.DeviceScene(back), cam, precision="fp16")
+    assert psnr(a["image"], b["image"]) >= 90.0
