@@ -179,35 +179,45 @@ gsi::RasterParams make_params(const gs_options &o) {
 
 // One event per host thread for the count readback (created on first use, destroyed when
 // the thread ends); calls on different threads may run concurrently on different streams.
+// The counts land in pinned, coherent host memory that k_depth_keys writes directly, so no copy
+// command sits between the depth-key kernel and the depth sort and the call returns to the
+// host at once (a copy into pageable memory is staged and waits for the GPU).
 struct CountsEvent {
   hipEvent_t ev = nullptr;
+  uint64_t *host = nullptr;   // {K, V}
   ~CountsEvent() {
     if (ev) (void)hipEventDestroy(ev);
+    if (host) (void)hipHostFree(host);
   }
 };
 
-hipEvent_t counts_event() {
+CountsEvent *counts_event() {
   thread_local CountsEvent holder;
   if (!holder.ev && hipEventCreateWithFlags(&holder.ev, hipEventDisableTiming) != hipSuccess) holder.ev = nullptr;
-  return holder.ev;
+  if (!holder.host &&
+      hipHostMalloc(reinterpret_cast<void **>(&holder.host), 64, hipHostMallocCoherent | hipHostMallocPortable) !=
+          hipSuccess)
+    holder.host = nullptr;
+  return (holder.ev && holder.host) ? &holder : nullptr;
 }
 
 gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam, const gs_options *opt,
                       const gs_bins *bins, uint64_t *n_keys, void *ws, hipStream_t st) {
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
   const Workspace w = carve(ws, n, bins->capacity);
-  // The one host synchronization reads the entry count K and the visible count V.  The copy is
-  // followed by an event, and the depth sort and depth-order offset scan (which read V on the
-  // device) are enqueued before the host waits on that event, so the GPU keeps working while
-  // the counts travel to the host.
-  uint64_t kv[2] = {0, 0};
-  hipEvent_t ev = counts_event();
-  if (!ev) return fail(GS_ERR_HIP, "hipEventCreateWithFlags failed");
+  // The one host synchronization reads the entry count K and the visible count V, which
+  // k_depth_keys writes to pinned host memory (and to the workspace).  An event follows, and the
+  // depth sort and depth-order offset scan (which read V on the device) are enqueued before the
+  // host waits on it, so the GPU keeps working while the host waits.
+  CountsEvent *ce = counts_event();
+  if (!ce) return fail(GS_ERR_HIP, "event or pinned count buffer could not be created");
+  hipEvent_t ev = ce->ev;
+  volatile uint64_t *hkv = ce->host;
+  hkv[0] = hkv[1] = ~0ull;   // overwritten by the kernel
   const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
   GS_HIP(gsi::launch_depth_keys(proj->order, reinterpret_cast<const float4 *>(proj->rgb), proj->n_visible, nn, w.dkey,
-                                proj->offset + n, w.counts, st));
-  GS_HIP(hipMemcpyAsync(kv, w.counts, sizeof(kv), hipMemcpyDeviceToHost, st));
-  // from here on the copy into kv may be in flight: every exit waits for it first
+                                proj->offset + n, w.counts, ce->host, st));
+  // from here on the kernel may be writing the counts: every exit waits for it first
   hipError_t e = hipEventRecord(ev, st);
   if (e != hipSuccess) {
     (void)hipStreamSynchronize(st);
@@ -229,6 +239,11 @@ gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
     return hip_fail(es, "hipEventSynchronize");
   }
   if (e != hipSuccess) return hip_fail(e, "depth sort");
+  uint64_t kv[2] = {hkv[0], hkv[1]};
+  if (kv[0] == ~0ull || kv[1] == ~0ull) {
+    // not visible through the pinned buffer: read the workspace copy (the kernel has finished)
+    GS_HIP(hipMemcpy(kv, w.counts, sizeof(kv), hipMemcpyDeviceToHost));
+  }
   const uint64_t K = kv[0];
   const uint32_t V = (uint32_t)kv[1];
   *n_keys = K;

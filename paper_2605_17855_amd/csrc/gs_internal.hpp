@@ -224,7 +224,8 @@ hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32
 // keys[i] = depth bits of order[i] for i < *nvis (n_max >= *nvis), and counts = {*K, *nvis}
 // (the entry and visible counts side by side, for one copy to the host).
 hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max,
-                             uint32_t *keys, const uint64_t *K, uint64_t *counts, hipStream_t st);
+                             uint32_t *keys, const uint64_t *K, uint64_t *counts, uint64_t *host_counts,
+                             hipStream_t st);
 // Sorts the visible list order[0..*nvis) by the depth keys (4 passes, stable), using keys_alt/
 // vals_alt (n_max each) as scratch, and writes count_sorted[i] = count[order[i]] for the
 // sorted list (n_max > 1).  Reads the visible count on the device, so it can be enqueued

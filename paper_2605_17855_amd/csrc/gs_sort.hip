@@ -225,12 +225,16 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
 // Depth keys of the visible Gaussians (key[i] = bits(depth of order[i]), i < *nvis), and the
 // zeroing of the bin ranges.
 __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis,
-                                                       uint32_t *keys, const uint64_t *K, uint64_t *counts) {
+                                                       uint32_t *keys, const uint64_t *K, uint64_t *counts,
+                                                       uint64_t *host_counts) {
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   const uint32_t V = *nvis;
   if (blockIdx.x == 0 && threadIdx.x == 0) {   // the entry and visible counts, side by side
-    counts[0] = *K;
+    const uint64_t k = *K;
+    counts[0] = k;
     counts[1] = V;
+    host_counts[0] = k;    // pinned host memory, read by the host after the kernel's event
+    host_counts[1] = V;
   }
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < V; i += stride)
     keys[i] = __float_as_uint(rgb[order[i]].w);
@@ -505,9 +509,11 @@ hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32
 }
 
 hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max,
-                             uint32_t *keys, const uint64_t *K, uint64_t *counts, hipStream_t st) {
+                             uint32_t *keys, const uint64_t *K, uint64_t *counts, uint64_t *host_counts,
+                             hipStream_t st) {
   const unsigned blocks = grid_for(n_max) < 2048u ? grid_for(n_max) : 2048u;   // grid-stride beyond
-  hipLaunchKernelGGL(k_depth_keys, dim3(blocks), dim3(kBlock), 0, st, order, rgb, nvis, keys, K, counts);
+  hipLaunchKernelGGL(k_depth_keys, dim3(blocks), dim3(kBlock), 0, st, order, rgb, nvis, keys, K, counts,
+                     host_counts);
   return hipGetLastError();
 }
 
