@@ -199,9 +199,12 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
 }
 
 // ---- exclusive scan: u32 counts -> u64 offsets (n + 1 entries) ------------------
-// Reduce-then-scan in three launches with no inter-workgroup waits: per-tile sums, one
-// workgroup scanning the tile sums, and a down-sweep that rescans each tile from its
-// offset.  Block scans use wave shuffles (one LDS exchange of the four wave totals).
+// Reduce-then-scan with no inter-workgroup waits: per-tile sums, then a down-sweep in which
+// each workgroup adds up the sums of the tiles before its own (read from L2) and rescans its
+// tile from that offset; the last tile also writes the grand totals.  Above kDirectTiles
+// tiles that adding up would grow quadratically, so one workgroup first scans the tile sums
+// in place (three launches).  Block scans use wave shuffles (one LDS exchange of the four
+// wave totals).
 // Optionally the values are gathered through an index list (v[i] = in[idx[i]]), the indices
 // with v[i] > 0 are compacted in index order (the visible list), and n is read from device
 // memory (the grid covers an upper bound).
@@ -284,10 +287,11 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *in, cons
   }
 }
 
-// one workgroup: exclusive scan of the tile sums in place; grand totals to out[n] and *nvis
+constexpr int64_t kDirectTiles = 4096;
+
+// one workgroup: exclusive scan of the tile sums in place
 template <bool COMPACT>
-__global__ __launch_bounds__(kBlock) void k_scan_top(uint64_t *bsum, uint32_t *bvis, int64_t nb, int64_t n_host,
-                                                     const uint32_t *n_dev, uint64_t *out, uint32_t *nvis) {
+__global__ __launch_bounds__(kBlock) void k_scan_top(uint64_t *bsum, uint32_t *bvis, int64_t nb) {
   __shared__ uint64_t sh[4];
   __shared__ uint32_t shv[4];
   uint64_t carry = 0;
@@ -305,22 +309,41 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(uint64_t *bsum, uint32_t *b
       carryv += totv;
     }
   }
-  if (threadIdx.x == 0) {
-    const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
-    out[n] = carry;
-    if (COMPACT) *nvis = carryv;
-  }
 }
 
-template <bool GATHER, bool COMPACT, int kScanItems>
+// PREFIXED: bsum/bvis already hold each tile's exclusive offset (k_scan_top ran)
+template <bool GATHER, bool COMPACT, int kScanItems, bool PREFIXED>
 __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, const uint32_t *idx, int64_t n_host,
                                                       const uint32_t *n_dev, const uint64_t *bsum,
-                                                      const uint32_t *bvis, uint64_t *out, uint32_t *order) {
+                                                      const uint32_t *bvis, uint64_t *out, uint32_t *order,
+                                                      uint32_t *nvis) {
   constexpr int64_t kScanTile = scan_tile<kScanItems>();
   __shared__ uint64_t sh[4];
   __shared__ uint32_t shv[4];
   const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
-  if ((int64_t)blockIdx.x * kScanTile >= n) return;
+  if ((int64_t)blockIdx.x * kScanTile >= n) {
+    if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) {   // empty scan: the totals are zero
+      out[0] = 0;
+      if (COMPACT) *nvis = 0;
+    }
+    return;
+  }
+  // offset of this tile: the sums of the tiles before it
+  uint64_t pre_all = 0;
+  uint32_t prev_all = 0;
+  if (PREFIXED) {
+    pre_all = bsum[blockIdx.x];
+    if (COMPACT) prev_all = bvis[blockIdx.x];
+  } else {
+    uint64_t pre = 0;
+    uint32_t prev = 0;
+    for (int64_t j = threadIdx.x; j < (int64_t)blockIdx.x; j += kBlock) {
+      pre += bsum[j];
+      if (COMPACT) prev += bvis[j];
+    }
+    block_exclusive_scan<uint64_t>(pre, sh, &pre_all);
+    if (COMPACT) block_exclusive_scan<uint32_t>(prev, shv, &prev_all);
+  }
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
   load_items<GATHER, kScanItems>(in, idx, base, n, v);
@@ -332,11 +355,12 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, const 
     c += v[i] > 0;
   }
   uint64_t tot;
-  uint64_t run = bsum[blockIdx.x] + block_exclusive_scan<uint64_t>(s, sh, &tot);
-  uint32_t runv = 0;
-  if (COMPACT) {
-    uint32_t totv;
-    runv = bvis[blockIdx.x] + block_exclusive_scan<uint32_t>(c, shv, &totv);
+  uint64_t run = pre_all + block_exclusive_scan<uint64_t>(s, sh, &tot);
+  uint32_t runv = 0, totv = 0;
+  if (COMPACT) runv = prev_all + block_exclusive_scan<uint32_t>(c, shv, &totv);
+  if (threadIdx.x == 0 && (int64_t)(blockIdx.x + 1) * kScanTile >= n) {   // the last tile: grand totals
+    out[n] = pre_all + tot;
+    if (COMPACT) *nvis = prev_all + totv;
   }
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
@@ -357,10 +381,14 @@ hipError_t scan_impl_t(const uint32_t *in, const uint32_t *idx, uint64_t *out, i
   if (nb > 0)
     hipLaunchKernelGGL((k_scan_reduce<GATHER, COMPACT, ITEMS>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx, n,
                        n_dev, bsum, bvis);
-  hipLaunchKernelGGL((k_scan_top<COMPACT>), dim3(1), dim3(kBlock), 0, st, bsum, bvis, nb, n, n_dev, out, nvis);
-  if (nb > 0)
-    hipLaunchKernelGGL((k_scan_down<GATHER, COMPACT, ITEMS>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx, n,
-                       n_dev, bsum, bvis, out, order);
+  if (nb > kDirectTiles) {
+    hipLaunchKernelGGL((k_scan_top<COMPACT>), dim3(1), dim3(kBlock), 0, st, bsum, bvis, nb);
+    hipLaunchKernelGGL((k_scan_down<GATHER, COMPACT, ITEMS, true>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx,
+                       n, n_dev, bsum, bvis, out, order, nvis);
+  } else {
+    hipLaunchKernelGGL((k_scan_down<GATHER, COMPACT, ITEMS, false>), dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kBlock),
+                       0, st, in, idx, n, n_dev, bsum, bvis, out, order, nvis);
+  }
   return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 """GPU parity tests: the HIP library against the FP64 oracle (and, for the sort, against a
 library stable sort of the same seeded keys).  All calls go through the C ABI binding."""
+import ctypes as C
 import math
 
 import numpy as np
@@ -309,3 +310,40 @@ def test_ply_scene_renders_like_its_source(tmp_path):
     a = render(gs.DeviceScene(sc), cam, precision="fp16")
     b = render(gs.DeviceScene(back), cam, precision="fp16")
     assert psnr(a["image"], b["image"]) >= 90.0
+
+
+@pytest.mark.parametrize("n", [5000, 1 << 20, (1 << 20) + 1, 17_000_000])
+def test_count_scan_and_compaction(n):
+    """The preprocess's count scan and visible-list compaction, bit-exact against a host
+    cumulative sum of the same counts: one-tile, 2^20 (1,024-value tiles), just above (4,096-
+    value tiles), and 17M values (more than 4,096 tiles: the tile sums are scanned by one
+    workgroup first).  Degree-0 splats in front of a small camera, most of them visible."""
+    import torch
+    rng = np.random.default_rng(3)
+    sc = scenes.camera_box_scene(n, seed=4) if n <= 5000 else None
+    if sc is None:
+        sc = scenes.Scene(np.stack([rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(2, 6, n)]).astype(np.float32),
+                          np.full((3, n), np.log(0.01), np.float32), np.tile(np.array([[1], [0], [0], [0]], np.float32), (1, n)),
+                          np.full(n, 0.5, np.float32), np.zeros((1, 3, n), np.float32), 0)
+        sc.mean[2, ::7] = -1.0      # some behind the camera
+    cam = scenes.pinhole(64, 48, 60.0)
+    note(f"count scan n={n}")
+    ds = gs.DeviceScene(sc)
+    proj = gs.Projected(n)
+    opt = gs.options()
+    c = gs.camera_stub(cam.width, cam.height)
+    ws = torch.empty((int(gs.lib().gs_workspace_bytes(n, 1024, C.byref(c), C.byref(opt))),), dtype=torch.uint8,
+                     device="cuda")
+    gs.gs_preprocess(ds, cam, opt, proj, ws)
+    torch.cuda.synchronize()
+    count = proj.count.cpu().numpy().view(np.uint32)[:n].astype(np.uint64)
+    offset = proj.offset.cpu().numpy().view(np.uint64)[: n + 1]
+    want = np.zeros(n + 1, np.uint64)
+    want[1:] = np.cumsum(count)
+    assert np.array_equal(offset, want)
+    vis = np.nonzero(count)[0]
+    V = int(proj.n_visible.cpu().numpy().view(np.uint32)[0])
+    assert V == vis.size and 0 < V < n
+    assert np.array_equal(proj.order.cpu().numpy().view(np.uint32)[:V].astype(np.int64), vis)
+    del ds, proj, ws
+    torch.cuda.empty_cache()
