@@ -303,8 +303,8 @@ gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_op
   if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID_ARG, "workspace %zu bytes, need %zu", ws_bytes, need);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
-  GS_HIP(gsi::launch_preprocess(*scene, *cam, g, *out, (opt->flags & GS_OPT_TIGHT) != 0, st));
-  GS_HIP(gsi::launch_scan_compact(out->count, out->offset, scene->n, out->order, out->n_visible, ws, st));
+  GS_HIP(gsi::launch_preprocess(*scene, *cam, g, *out, (opt->flags & GS_OPT_TIGHT) != 0, ws, st));
+  GS_HIP(gsi::launch_scan_compact(out->count, out->offset, scene->n, out->order, out->n_visible, ws, true, st));
   return GS_OK;
 }
 
@@ -354,8 +354,8 @@ gs_status gs_render(const gs_scene *scene, const gs_camera *cam, const gs_option
   if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID_ARG, "workspace %zu bytes, need %zu", ws_bytes, need);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
-  GS_HIP(gsi::launch_preprocess(*scene, *cam, g, *proj, (opt->flags & GS_OPT_TIGHT) != 0, st));
-  GS_HIP(gsi::launch_scan_compact(proj->count, proj->offset, scene->n, proj->order, proj->n_visible, ws, st));
+  GS_HIP(gsi::launch_preprocess(*scene, *cam, g, *proj, (opt->flags & GS_OPT_TIGHT) != 0, ws, st));
+  GS_HIP(gsi::launch_scan_compact(proj->count, proj->offset, scene->n, proj->order, proj->n_visible, ws, true, st));
   if ((s = do_bin_sort(proj, scene->n, cam, opt, bins, n_keys, ws, st))) return s;
   const gsi::RasterJob j = make_job(*proj, *bins, g, image, aux, raster_parts(*opt));
   const gsi::RasterParams p = make_params(*opt);

@@ -199,14 +199,18 @@ __device__ __forceinline__ uint64_t tight_group_mask(const TightEllipse &e, int 
 }
 
 // ---- preprocess + scans ------------------------------------------------------
+// scan_tmp (scan_tmp_bytes(n) bytes, may be null): when scan_presummed(n), the preprocess also
+// leaves there the tile sums of the count scan, and launch_scan_compact(.., presummed = true)
+// then skips its reduce pass
+bool scan_presummed(int64_t n);
 hipError_t launch_preprocess(const gs_scene &s, const gs_camera &c, const Grid &g, const gs_projected &o,
-                             bool tight, hipStream_t st);
+                             bool tight, void *scan_tmp, hipStream_t st);
 // Scans (reduce-then-scan); tmp holds scan_tmp_bytes(n) bytes.
 size_t scan_tmp_bytes(int64_t n);
 // out[0..n] = exclusive prefix sum of in[0..n) (out[n] = total); order[0..*nvis) = indices i
 // with in[i] > 0, in index order
 hipError_t launch_scan_compact(const uint32_t *in, uint64_t *out, int64_t n, uint32_t *order, uint32_t *nvis,
-                               void *tmp, hipStream_t st);
+                               void *tmp, bool presummed, hipStream_t st);
 // out[0..m] = exclusive prefix sum of in[idx[i]] for i < m = *n_dev (m <= n_max)
 hipError_t launch_scan_gather(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n_max,
                               const uint32_t *n_dev, void *tmp, hipStream_t st);

@@ -34,7 +34,39 @@ struct PreArgs {
   float4 *rgb;
   ushort4 *rect;
   uint32_t *count;
+  uint64_t *bsum;   // if set: per-workgroup sums of the counts and of the visible flags, the
+  uint32_t *bvis;   // tile sums of the count scan (256-value tiles)
 };
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
+  }
+  return v;
+}
+
+// exclusive scan over the workgroup; *total = sum over the workgroup
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *sh4, T *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const T incl = wave_inclusive_scan<T>(v);
+  if (lane == 63) sh4[w] = incl;
+  __syncthreads();
+  T before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    const T x = sh4[k];
+    before += k < w ? x : (T)0;
+    all += x;
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - v;
+}
 
 // Real orthonormal spherical harmonics with the Condon-Shortley phase, index l*l + l + m,
 // for a unit direction (x, y, z).  Constants are sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!)
@@ -74,10 +106,8 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float *b) {
 // turn).  The per-Gaussian parameters are loaded before the near-plane test for the same
 // reason: one round trip to memory instead of two.
 template <int DEG>
-__global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
+__device__ __forceinline__ uint32_t preprocess_one(const PreArgs &a, int64_t g) {
   constexpr int NB = (DEG + 1) * (DEG + 1);
-  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (g >= a.n) return;
   const int64_t n = a.n;
   uint32_t cnt = 0;
   ushort4 rc = make_ushort4(0, 0, 0, 0);
@@ -196,6 +226,25 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
   }
   a.count[g] = cnt;
   a.rect[g] = rc;
+  return cnt;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
+  __shared__ uint64_t sh[4];
+  __shared__ uint32_t shv[4];
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t cnt = g < a.n ? preprocess_one<DEG>(a, g) : 0u;
+  if (a.bsum) {   // the count scan's tile sums, so that it needs no reduce pass
+    uint64_t tot;
+    uint32_t totv;
+    block_exclusive_scan<uint64_t>(cnt, sh, &tot);
+    block_exclusive_scan<uint32_t>(cnt > 0 ? 1u : 0u, shv, &totv);
+    if (threadIdx.x == 0) {
+      a.bsum[blockIdx.x] = tot;
+      a.bvis[blockIdx.x] = totv;
+    }
+  }
 }
 
 // ---- exclusive scan: u32 counts -> u64 offsets (n + 1 entries) ------------------
@@ -213,36 +262,6 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(PreArgs a) {
 constexpr int64_t kSmallScan = 1ll << 20;
 template <int ITEMS>
 constexpr int64_t scan_tile() { return (int64_t)kBlock * ITEMS; }
-
-template <typename T>
-__device__ __forceinline__ T wave_inclusive_scan(T v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const T u = __shfl_up(v, off, 64);
-    if (lane >= off) v += u;
-  }
-  return v;
-}
-
-// exclusive scan over the workgroup; *total = sum over the workgroup
-template <typename T>
-__device__ __forceinline__ T block_exclusive_scan(T v, T *sh4, T *total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const T incl = wave_inclusive_scan<T>(v);
-  if (lane == 63) sh4[w] = incl;
-  __syncthreads();
-  T before = 0, all = 0;
-#pragma unroll
-  for (int k = 0; k < kBlock / 64; ++k) {
-    const T x = sh4[k];
-    before += k < w ? x : (T)0;
-    all += x;
-  }
-  __syncthreads();
-  *total = all;
-  return before + incl - v;
-}
 
 template <bool GATHER, int kScanItems>
 __device__ __forceinline__ void load_items(const uint32_t *in, const uint32_t *idx, int64_t base, int64_t n,
@@ -311,12 +330,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(uint64_t *bsum, uint32_t *b
   }
 }
 
-// PREFIXED: bsum/bvis already hold each tile's exclusive offset (k_scan_top ran)
+// PREFIXED: bsum/bvis already hold each tile's exclusive offset (k_scan_top ran); otherwise
+// they hold sums of `spt` consecutive groups per tile (spt = 1: the reduce pass's tile sums;
+// more: the preprocess's 256-value sums)
 template <bool GATHER, bool COMPACT, int kScanItems, bool PREFIXED>
 __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, const uint32_t *idx, int64_t n_host,
                                                       const uint32_t *n_dev, const uint64_t *bsum,
                                                       const uint32_t *bvis, uint64_t *out, uint32_t *order,
-                                                      uint32_t *nvis) {
+                                                      uint32_t *nvis, int spt) {
   constexpr int64_t kScanTile = scan_tile<kScanItems>();
   __shared__ uint64_t sh[4];
   __shared__ uint32_t shv[4];
@@ -337,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, const 
   } else {
     uint64_t pre = 0;
     uint32_t prev = 0;
-    for (int64_t j = threadIdx.x; j < (int64_t)blockIdx.x; j += kBlock) {
+    for (int64_t j = threadIdx.x; j < (int64_t)blockIdx.x * spt; j += kBlock) {
       pre += bsum[j];
       if (COMPACT) prev += bvis[j];
     }
@@ -374,9 +395,17 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, const 
 
 template <bool GATHER, bool COMPACT, int ITEMS>
 hipError_t scan_impl_t(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n, const uint32_t *n_dev,
-                       uint32_t *order, uint32_t *nvis, void *tmp, hipStream_t st) {
+                       uint32_t *order, uint32_t *nvis, void *tmp, bool presummed, hipStream_t st) {
   const int64_t nb = (n + scan_tile<ITEMS>() - 1) / scan_tile<ITEMS>();
   uint64_t *bsum = static_cast<uint64_t *>(tmp);
+  if (presummed) {
+    // the preprocess left one sum per 256 values (scan_presummed(n) holds)
+    const int64_t n256 = (n + kBlock - 1) / kBlock;
+    uint32_t *bv = reinterpret_cast<uint32_t *>(bsum + (n256 > 0 ? n256 : 1));
+    hipLaunchKernelGGL((k_scan_down<GATHER, COMPACT, ITEMS, false>), dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kBlock),
+                       0, st, in, idx, n, n_dev, bsum, bv, out, order, nvis, (int)(scan_tile<ITEMS>() / kBlock));
+    return hipGetLastError();
+  }
   uint32_t *bvis = reinterpret_cast<uint32_t *>(bsum + (nb > 0 ? nb : 1));
   if (nb > 0)
     hipLaunchKernelGGL((k_scan_reduce<GATHER, COMPACT, ITEMS>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx, n,
@@ -384,25 +413,27 @@ hipError_t scan_impl_t(const uint32_t *in, const uint32_t *idx, uint64_t *out, i
   if (nb > kDirectTiles) {
     hipLaunchKernelGGL((k_scan_top<COMPACT>), dim3(1), dim3(kBlock), 0, st, bsum, bvis, nb);
     hipLaunchKernelGGL((k_scan_down<GATHER, COMPACT, ITEMS, true>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx,
-                       n, n_dev, bsum, bvis, out, order, nvis);
+                       n, n_dev, bsum, bvis, out, order, nvis, 1);
   } else {
     hipLaunchKernelGGL((k_scan_down<GATHER, COMPACT, ITEMS, false>), dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kBlock),
-                       0, st, in, idx, n, n_dev, bsum, bvis, out, order, nvis);
+                       0, st, in, idx, n, n_dev, bsum, bvis, out, order, nvis, 1);
   }
   return hipGetLastError();
 }
 
 template <bool GATHER, bool COMPACT>
 hipError_t scan_impl(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n, const uint32_t *n_dev,
-                     uint32_t *order, uint32_t *nvis, void *tmp, hipStream_t st) {
-  if (n <= kSmallScan) return scan_impl_t<GATHER, COMPACT, 4>(in, idx, out, n, n_dev, order, nvis, tmp, st);
-  return scan_impl_t<GATHER, COMPACT, 16>(in, idx, out, n, n_dev, order, nvis, tmp, st);
+                     uint32_t *order, uint32_t *nvis, void *tmp, hipStream_t st, bool presummed = false) {
+  if (n <= kSmallScan) return scan_impl_t<GATHER, COMPACT, 4>(in, idx, out, n, n_dev, order, nvis, tmp, presummed, st);
+  return scan_impl_t<GATHER, COMPACT, 16>(in, idx, out, n, n_dev, order, nvis, tmp, presummed, st);
 }
 
 }  // namespace
 
+bool scan_presummed(int64_t n) { return n > 0 && n <= kSmallScan; }
+
 hipError_t launch_preprocess(const gs_scene &s, const gs_camera &c, const Grid &g, const gs_projected &o,
-                             bool tight, hipStream_t st) {
+                             bool tight, void *scan_tmp, hipStream_t st) {
   if (s.n == 0) return hipSuccess;
   PreArgs a;
   a.n = s.n;
@@ -431,6 +462,12 @@ hipError_t launch_preprocess(const gs_scene &s, const gs_camera &c, const Grid &
   a.rect = reinterpret_cast<ushort4 *>(o.rect);
   a.count = o.count;
   const unsigned blocks = (unsigned)((s.n + kBlock - 1) / kBlock);
+  a.bsum = nullptr;
+  a.bvis = nullptr;
+  if (scan_tmp && scan_presummed(s.n)) {   // layout read by scan_impl_t (presummed)
+    a.bsum = static_cast<uint64_t *>(scan_tmp);
+    a.bvis = reinterpret_cast<uint32_t *>(a.bsum + blocks);
+  }
   switch (s.sh_degree) {
     case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3(blocks), dim3(kBlock), 0, st, a); break;
     case 1: hipLaunchKernelGGL(k_preprocess<1>, dim3(blocks), dim3(kBlock), 0, st, a); break;
@@ -447,12 +484,14 @@ size_t scan_tmp_bytes(int64_t n) {
   int64_t nb = (small + scan_tile<4>() - 1) / scan_tile<4>();
   const int64_t nb_large = (n + scan_tile<16>() - 1) / scan_tile<16>();
   if (nb_large > nb) nb = nb_large;
+  const int64_t n256 = (small + kBlock - 1) / kBlock;   // the preprocess's sums (scan_presummed)
+  if (n256 > nb) nb = n256;
   return (size_t)((nb > 0 ? nb : 1) * (sizeof(uint64_t) + sizeof(uint32_t)) + 16);
 }
 
 hipError_t launch_scan_compact(const uint32_t *in, uint64_t *out, int64_t n, uint32_t *order, uint32_t *nvis,
-                               void *tmp, hipStream_t st) {
-  return scan_impl<false, true>(in, nullptr, out, n, nullptr, order, nvis, tmp, st);
+                               void *tmp, bool presummed, hipStream_t st) {
+  return scan_impl<false, true>(in, nullptr, out, n, nullptr, order, nvis, tmp, st, presummed && scan_presummed(n));
 }
 
 hipError_t launch_scan_dev(const uint32_t *in, uint64_t *out, int64_t n_max, const uint32_t *n_dev, void *tmp,
