@@ -265,7 +265,7 @@ struct RasterJob {
   float *aux;
   int W, H, TX, TY, GX, GY;
   int nbins;
-  int parts;  // workgroups per bin: each takes G / parts rows of the group's member tiles
+  int parts;  // workgroups per bin: each takes G^2 / parts of the group's member tiles (row-major)
   int items;  // nbins * parts work items (one workgroup each)
   int bin0;   // first work item of this job in a batched launch
 };

@@ -326,9 +326,9 @@ __device__ __forceinline__ void make_pixel_operand(short8 &B0, short8 &B1, short
 
 }
 
-// Renders work item `item` of job J (one workgroup): the member tiles of rows
-// [part * G / parts, (part + 1) * G / parts) of bin item / parts, part = item % parts.  Shared
-// by the single-image and batched kernels.
+// Renders work item `item` of job J (one workgroup): member tiles
+// [part * G^2 / parts, (part + 1) * G^2 / parts) (row-major) of bin item / parts, part =
+// item % parts.  Shared by the single-image and batched kernels.
 template <int G, int PREC, int S, bool AUX>
 __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const RasterParams &P, int item,
                                                 MfmaShared<G, S> &sm, short8 B0, short8 B1, short8 B20,
@@ -339,8 +339,8 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
   using TileMask = typename std::conditional<(NT > 32), uint64_t, uint32_t>::type;
   // G <= 2: one workgroup per bin (the tile loops below stay fully unrolled)
   const int bin = G >= 4 ? item / J.parts : item;
-  const int k0 = G >= 4 ? (item % J.parts) * (G / J.parts) * G : 0;
-  const int k1 = G >= 4 ? k0 + (G / J.parts) * G : NT;
+  const int k0 = G >= 4 ? (item % J.parts) * (NT / J.parts) : 0;
+  const int k1 = G >= 4 ? k0 + NT / J.parts : NT;
   const int gx = bin % J.GX, gy = bin / J.GX;
   const int ox = gx * G * kTile, oy = gy * G * kTile;
   const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
