@@ -299,7 +299,7 @@ def sweep(gs, torch, args):
             ("3M Gaussians, 256 clusters, 3840x2160", lambda: scenes.clustered_3m(width=3840, height=2160), 3840, 2160, 3),
             ("dense 6M Gaussians, log-scale N(ln 0.05, 0.5), opacity sigmoid(N(-1,1)), 1920x1080",
              lambda: scenes.dense_6m(), 1920, 1080, 5)]
-    rows, lr = [], []
+    rows, lr, adaptive = [], [], []
     for name, make, w, h, seed in work:
         log(f"sweep: {name}")
         sc, _ = make()
@@ -323,11 +323,26 @@ def sweep(gs, torch, args):
             keys[f"{group}t" if tight else group] = np.mean([rend.render(ds, c, gs.options(group=group, precision="fp16", tight=tight))
                                                       for c in cams[:5]])
             del rend
+        # per-scene adaptive group side (opacity-aware culling on, FP16): probe, then time
+        from paper_2605_17855_amd.adaptive import AdaptiveRenderer
+        ar = AdaptiveRenderer(sc.n, w, h, precision="fp16", splits=2, tight=True, probes=2)
+        for i in range(2 * len(ar.renderers)):
+            ar.render(ds, cams[i % len(cams)])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.sweep_steps):
+            ar.render(ds, cams[i % len(cams)])
+        torch.cuda.synchronize()
+        adaptive.append({"workload": name, "chosen_group": ar.chooser.chosen,
+                         "probe_best_ms": {str(g): min(t) for g, t in ar.chooser.times.items()},
+                         "frames_per_s": args.sweep_steps / (time.perf_counter() - t0)})
+        log(f"  adaptive (culling on): G{ar.chooser.chosen}, {adaptive[-1]['frames_per_s']:.1f} frames/s")
+        del ar
         lr.append({"workload": name, "entries": {str(g): float(k) for g, k in keys.items()},
                    "load_reduction": {str(g): 1.0 - keys[g] / keys[1] for g in (2, 4, 8, "1t", "2t", "4t", "8t")}})
         del ds
         torch.cuda.empty_cache()
-    return {"rows": rows, "load_reduction": lr, "steps": args.sweep_steps}
+    return {"rows": rows, "load_reduction": lr, "adaptive": adaptive, "steps": args.sweep_steps}
 
 
 def main():

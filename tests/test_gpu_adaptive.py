@@ -1,0 +1,35 @@
+"""Per-scene group-side choice on the GPU: every frame equals the G = 1 render bit for bit
+(the MFMA rasterizers give the same image for every group side), the probes visit every
+side, and the committed side is the fastest probed one."""
+import numpy as np
+import pytest
+
+from paper_2605_17855_amd import gs, scenes
+from paper_2605_17855_amd.adaptive import AdaptiveRenderer
+from gpu_helpers import note, render
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec,sides", [("fp16", {1, 2, 4, 8}), ("fp32", {1, 2, 4})])
+def test_adaptive_group_choice_keeps_images(prec, sides):
+    import torch
+    sc = scenes.clustered_scene(20000, seed=23, clusters=8)
+    cam = scenes.look_at([3.0, 1.0, 1.5], 320, 180)
+    ds = gs.DeviceScene(sc)
+    note(f"adaptive groups {prec}")
+    ref = render(ds, cam, group=1, precision=prec)["image"]
+    ar = AdaptiveRenderer(sc.n, cam.width, cam.height, precision=prec, probes=2)
+    used = []
+    for _ in range(2 * len(sides) + 4):
+        img, g = ar.render(ds, cam)
+        torch.cuda.synchronize()
+        used.append(g)
+        if prec == "fp16" or g == 1:
+            assert np.array_equal(img.cpu().numpy().astype(np.float64), ref), g
+        else:   # FP32 grouped tiles sum in the same order but are compiled separately
+            assert np.abs(img.cpu().numpy() - ref).max() <= 1e-5
+    assert set(used[:2 * len(sides)]) == sides
+    t = ar.chooser.times
+    assert ar.chooser.chosen == min(t, key=lambda s: (min(t[s]), s))
+    assert all(u == ar.chooser.chosen for u in used[2 * len(sides):])
