@@ -323,20 +323,21 @@ def sweep(gs, torch, args):
             keys[f"{group}t" if tight else group] = np.mean([rend.render(ds, c, gs.options(group=group, precision="fp16", tight=tight))
                                                       for c in cams[:5]])
             del rend
-        # per-scene adaptive group side (opacity-aware culling on, FP16): probe, then time
+        # per-scene adaptive (group side, culling) variant, FP16: probe, then time
         from paper_2605_17855_amd.adaptive import AdaptiveRenderer
-        ar = AdaptiveRenderer(sc.n, w, h, precision="fp16", splits=2, tight=True, probes=2)
-        for i in range(2 * len(ar.renderers)):
+        ar = AdaptiveRenderer(sc.n, w, h, precision="fp16", splits=2, probes=2)
+        for i in range(2 * len(ar.variants)):
             ar.render(ds, cams[i % len(cams)])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(args.sweep_steps):
             ar.render(ds, cams[i % len(cams)])
         torch.cuda.synchronize()
-        adaptive.append({"workload": name, "chosen_group": ar.chooser.chosen,
-                         "probe_best_ms": {str(g): min(t) for g, t in ar.chooser.times.items()},
+        adaptive.append({"workload": name, "chosen_group": ar.chooser.chosen[0], "chosen_tight": ar.chooser.chosen[1],
+                         "probe_best_ms": {f"{g}{'t' if t else ''}": min(v) for (g, t), v in ar.chooser.times.items()},
                          "frames_per_s": args.sweep_steps / (time.perf_counter() - t0)})
-        log(f"  adaptive (culling on): G{ar.chooser.chosen}, {adaptive[-1]['frames_per_s']:.1f} frames/s")
+        log(f"  adaptive: G{ar.chooser.chosen[0]}{' culling' if ar.chooser.chosen[1] else ''}, "
+            f"{adaptive[-1]['frames_per_s']:.1f} frames/s")
         del ar
         lr.append({"workload": name, "entries": {str(g): float(k) for g, k in keys.items()},
                    "load_reduction": {str(g): 1.0 - keys[g] / keys[1] for g in (2, 4, 8, "1t", "2t", "4t", "8t")}})

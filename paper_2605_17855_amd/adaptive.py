@@ -5,10 +5,11 @@ Which group side renders a scene fastest depends on the scene and the resolution
 shrinks the sort by the load reduction but adds staging work per member tile, and where the
 balance falls differs from the paper's hardware (on the sensitivity workloads here 1x1 tiles
 with opacity-aware culling win at 3M Gaussians, 8x8 groups in the dense 6M scene).  With the
-MFMA precisions every group side gives bit-identical images, so the choice changes only the
-speed: `AdaptiveRenderer` renders the first frames of a scene once with each candidate side,
-timed on the stream with HIP events, and then keeps the fastest (re-probing after
-`reprobe_every` frames, or after `chooser.reset()`).
+MFMA precisions every group side, with or without opacity-aware culling, gives bit-identical
+images, so the choice changes only the speed: `AdaptiveRenderer` renders the first frames of
+a scene once with each candidate (group side, culling) variant, timed on the stream with HIP
+events, and then keeps the fastest (re-probing after `reprobe_every` frames, or after
+`chooser.reset()`).
 """
 from __future__ import annotations
 
@@ -61,38 +62,40 @@ class GroupChooser:
 
 
 class AdaptiveRenderer:
-    """Renders frames of one scene with the group side a GroupChooser picks; one gs.Renderer
-    (and its buffers) per candidate side."""
+    """Renders frames of one scene with the (group side, culling) variant a GroupChooser picks;
+    one gs.Renderer (and its buffers) per group side."""
 
     def __init__(self, n: int, width: int, height: int, precision="fp16", splits: int = 2,
-                 groups=(1, 2, 4, 8), tight: bool = False, probes: int = 2, reprobe_every: int = 0,
+                 groups=(1, 2, 4, 8), tight=(False, True), probes: int = 2, reprobe_every: int = 0,
                  bg=(0.0, 0.0, 0.0), device="cuda"):
         prec = gs.PRECISIONS[precision] if isinstance(precision, str) else precision
         if prec == gs.GS_PREC_FP32:
             groups = [g for g in groups if g != 8]      # the FP32 rasterizer has no 8x8 groups
+        tights = (tight,) if isinstance(tight, bool) else tuple(tight)
         self.n, self.width, self.height = n, width, height
-        self.opts = {g: gs.options(group=g, precision=prec, splits=splits, bg=bg, tight=tight) for g in groups}
+        self.variants = [(g, t) for g in groups for t in tights]
+        self.opts = {v: gs.options(group=v[0], precision=prec, splits=splits, bg=bg, tight=v[1]) for v in self.variants}
         self.renderers = {g: gs.Renderer(n, width, height, group=g, device=device) for g in groups}
-        self.chooser = GroupChooser(groups, probes, reprobe_every)
-        self.last_group = None
+        self.chooser = GroupChooser(self.variants, probes, reprobe_every)
+        self.last_variant = None
 
     def render(self, scene: "gs.DeviceScene", cam, stream=None):
-        """Renders one frame; returns (image tensor, group side used)."""
+        """Renders one frame; returns (image tensor, (group side, culling) used)."""
         import torch
         if (cam.width, cam.height) != (self.width, self.height):
             raise ValueError("camera size differs from the renderer's")
-        g = self.chooser.next()
-        ren = self.renderers[g]
+        v = self.chooser.next()
+        ren = self.renderers[v[0]]
         st = stream if stream is not None else torch.cuda.current_stream()
         if self.chooser.chosen is None:
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(st)
-            ren.render(scene, cam, self.opts[g], stream=st)
+            ren.render(scene, cam, self.opts[v], stream=st)
             b.record(st)
             b.synchronize()
-            self.chooser.observe(g, a.elapsed_time(b))
+            self.chooser.observe(v, a.elapsed_time(b))
         else:
-            ren.render(scene, cam, self.opts[g], stream=st)
-            self.chooser.observe(g, 0.0)
-        self.last_group = g
-        return ren.image, g
+            ren.render(scene, cam, self.opts[v], stream=st)
+            self.chooser.observe(v, 0.0)
+        self.last_variant = v
+        return ren.image, v

@@ -1,6 +1,6 @@
-"""Per-scene group-side choice on the GPU: every frame equals the G = 1 render bit for bit
-(the MFMA rasterizers give the same image for every group side), the probes visit every
-side, and the committed side is the fastest probed one."""
+"""Per-scene (group side, culling) choice on the GPU: every frame equals the G = 1 render bit
+for bit (the MFMA rasterizers give the same image for every variant), the probes visit every
+variant, and the committed one is the fastest probed."""
 import numpy as np
 import pytest
 
@@ -21,15 +21,16 @@ def test_adaptive_group_choice_keeps_images(prec, sides):
     ref = render(ds, cam, group=1, precision=prec)["image"]
     ar = AdaptiveRenderer(sc.n, cam.width, cam.height, precision=prec, probes=2)
     used = []
-    for _ in range(2 * len(sides) + 4):
-        img, g = ar.render(ds, cam)
+    variants = {(g, t) for g in sides for t in (False, True)}
+    for _ in range(2 * len(variants) + 4):
+        img, (g, _t) = ar.render(ds, cam)
         torch.cuda.synchronize()
-        used.append(g)
+        used.append(ar.last_variant)
         if prec == "fp16" or g == 1:
             assert np.array_equal(img.cpu().numpy().astype(np.float64), ref), g
         else:   # FP32 grouped tiles sum in the same order but are compiled separately
             assert np.abs(img.cpu().numpy() - ref).max() <= 1e-5
-    assert set(used[:2 * len(sides)]) == sides
+    assert set(used[:2 * len(variants)]) == variants
     t = ar.chooser.times
     assert ar.chooser.chosen == min(t, key=lambda s: (min(t[s]), s))
-    assert all(u == ar.chooser.chosen for u in used[2 * len(sides):])
+    assert all(u == ar.chooser.chosen for u in used[2 * len(variants):])
