@@ -40,8 +40,8 @@ PEAK_FP32_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (packed) x 2 (FMA) x
 # FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by what the same counters read for a plain
 # device copy of known size (x2 and x1).  They describe the kernel built from the source and
 # compiler flags hashed in `sha256`; after any change to either the traffic is reported as null.
-RASTER_COUNTERS = dict(sha256="4ba30cff4b1c3f1f738c397b19af925b6a958a5dca0f485b3d07da7a124084c1",
-                       fetch_kib=87573, write_kib=24705, fetch_scale=2.0, write_scale=1.0,
+RASTER_COUNTERS = dict(sha256="4fda3804d0a698289663c3962536792a147611b728a90f25b97d499df70d9e7d",
+                       fetch_kib=87559, write_kib=24703, fetch_scale=2.0, write_scale=1.0,
                        precision="fp16", splits=2, group=1)
 
 
