@@ -330,21 +330,63 @@ __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order,
   __shared__ uint64_t s_pos[kBinItems + 1];
   __shared__ uint32_t s_first;
   const uint64_t e0 = (uint64_t)blockIdx.x * kBinItems;
+  const int lane = threadIdx.x & 63;
   uint32_t first, span;
   stage_block_gaussians(dpos, nvis, e0, s_pos, &s_first, &first, &span, ranges, nranges);
 #pragma unroll
   for (int it = 0; it < kBinItems / kBlock; ++it) {
     const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
-    if (e < K) {
+    const bool valid = e < K;
+    if (__ballot(valid) == 0) continue;
+    uint32_t rank = 0, g = 0, left = 0;
+    if (valid) {
       const uint32_t l = local_gaussian(s_pos, span, e);
-      const uint32_t rank = first + l;
-      const uint32_t g = order[rank];
-      uint32_t left = (uint32_t)(e - s_pos[l]);
+      rank = first + l;
+      g = order[rank];
+      left = (uint32_t)(e - s_pos[l]);
+    }
+    uint32_t bin = 0;   // (the walks always end early for counts from the preprocess)
+    bool placed = false;
+    if (G == 1) {
+      // A wave whose entries all belong to one Gaussian (the large ones, where walking the
+      // rows per entry costs most) shares the walk: lane k takes tile row k, a wave prefix
+      // sum of the row counts gives each row's first entry, and each lane finds its row by
+      // bisection over those sums.  Same spans as the preprocess counted.
+      const uint32_t g0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)g);
+      if (__ballot(valid && g != g0) == 0) {
+        const ushort4 r = rect[g0];
+        const int R = r.w - r.y;
+        if (R <= 64) {
+          const double2 m = xy[g0];
+          const float4 co = conic[g0];
+          const TightEllipse el = tight_ellipse(m.x, m.y, co.x, co.y, co.z, co.w, r.x, r.z - 1, r.y);
+          int lo = 0, hi = -1;
+          if (lane < R) tight_row_span(el, r.y + lane, &lo, &hi);
+          const uint32_t cnt = (uint32_t)(hi - lo + 1);
+          uint32_t incl = cnt;
+#pragma unroll
+          for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t u = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += u;
+          }
+          int pos = 0;   // rows whose entries all precede this lane's entry
+#pragma unroll
+          for (int step = 32; step > 0; step >>= 1) {
+            const uint32_t v = __shfl(incl, pos + step - 1, 64);
+            if (v <= left) pos += step;
+          }
+          const uint32_t ip = __shfl(incl, pos, 64), cp = __shfl(cnt, pos, 64);
+          const int lop = __shfl(lo, pos, 64);
+          bin = (uint32_t)((r.y + pos) * TX + lop) + (left - (ip - cp));
+          placed = true;
+        }
+      }
+    }
+    if (valid && !placed) {
       const ushort4 r = rect[g];
       const double2 m = xy[g];
       const float4 co = conic[g];
       const TightEllipse el = tight_ellipse(m.x, m.y, co.x, co.y, co.z, co.w, r.x, r.z - 1, r.y);
-      uint32_t bin = 0;   // (the walk always ends early for counts from the preprocess)
       if (G == 1) {
         for (int ty = r.y; ty < r.w; ++ty) {
           int lo, hi;
@@ -367,6 +409,8 @@ __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order,
           left -= cnt;
         }
       }
+    }
+    if (valid) {
       bin_keys[e] = bin;
       vals[e] = rank;   // the Gaussian's rank in depth order; k_ranges turns it into its index
     }
