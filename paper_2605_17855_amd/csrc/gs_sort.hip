@@ -347,39 +347,51 @@ __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order,
     }
     uint32_t bin = 0;   // (the walks always end early for counts from the preprocess)
     bool placed = false;
-    if (G == 1) {
-      // A wave whose entries all belong to one Gaussian (the large ones, where walking the
-      // rows per entry costs most) shares the walk: lane k takes tile row k, a wave prefix
-      // sum of the row counts gives each row's first entry, and each lane finds its row by
-      // bisection over those sums.  Same spans as the preprocess counted.
-      const uint32_t g0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)g);
-      if (__ballot(valid && g != g0) == 0) {
-        const ushort4 r = rect[g0];
-        const int R = r.w - r.y;
-        if (R <= 64) {
-          const double2 m = xy[g0];
-          const float4 co = conic[g0];
-          const TightEllipse el = tight_ellipse(m.x, m.y, co.x, co.y, co.z, co.w, r.x, r.z - 1, r.y);
-          int lo = 0, hi = -1;
-          if (lane < R) tight_row_span(el, r.y + lane, &lo, &hi);
-          const uint32_t cnt = (uint32_t)(hi - lo + 1);
-          uint32_t incl = cnt;
-#pragma unroll
-          for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t u = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += u;
+    // A wave whose entries all belong to one Gaussian (the large ones, where walking the rows
+    // per entry costs most) shares the walk: lane k takes tile (group) row k, a wave prefix
+    // sum of the row counts gives each row's first entry, and each lane finds its row by
+    // bisection over those sums.  Same spans as the preprocess counted.
+    const uint32_t g0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)g);
+    if (__ballot(valid && g != g0) == 0) {
+      const ushort4 r = rect[g0];
+      const int row0 = r.y / G;
+      const int R = (r.w - 1) / G - row0 + 1;   // tile rows (G = 1) or group rows
+      if (R <= 64) {
+        const double2 m = xy[g0];
+        const float4 co = conic[g0];
+        const TightEllipse el = tight_ellipse(m.x, m.y, co.x, co.y, co.z, co.w, r.x, r.z - 1, r.y);
+        int lo = 0, hi = -1;
+        uint32_t cnt = 0;
+        if (lane < R) {
+          if (G == 1) {
+            tight_row_span(el, r.y + lane, &lo, &hi);
+            cnt = (uint32_t)(hi - lo + 1);
+          } else {
+            cnt = tight_group_count(tight_group_row(el, G, row0 + lane, r.w - 1));
           }
-          int pos = 0;   // rows whose entries all precede this lane's entry
-#pragma unroll
-          for (int step = 32; step > 0; step >>= 1) {
-            const uint32_t v = __shfl(incl, pos + step - 1, 64);
-            if (v <= left) pos += step;
-          }
-          const uint32_t ip = __shfl(incl, pos, 64), cp = __shfl(cnt, pos, 64);
-          const int lop = __shfl(lo, pos, 64);
-          bin = (uint32_t)((r.y + pos) * TX + lop) + (left - (ip - cp));
-          placed = true;
         }
+        uint32_t incl = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const uint32_t u = __shfl_up(incl, off, 64);
+          if (lane >= off) incl += u;
+        }
+        int pos = 0;   // rows whose entries all precede this lane's entry
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+          const uint32_t v = __shfl(incl, pos + step - 1, 64);
+          if (v <= left) pos += step;
+        }
+        const uint32_t ip = __shfl(incl, pos, 64), cp = __shfl(cnt, pos, 64);
+        const uint32_t within = left - (ip - cp);
+        if (G == 1) {
+          const int lop = __shfl(lo, pos, 64);
+          bin = (uint32_t)((r.y + pos) * TX + lop) + within;
+        } else if (valid) {
+          const TightGroupRow row = tight_group_row(el, G, row0 + pos, r.w - 1);
+          bin = (uint32_t)((row0 + pos) * GX + tight_group_nth(row, within));
+        }
+        placed = true;
       }
     }
     if (valid && !placed) {
