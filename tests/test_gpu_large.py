@@ -2,7 +2,7 @@
 3M Gaussians (256-cluster mixture) at 1920x1080 and 3840x2160 with 1x1, 2x2 and 4x4 tile
 groups in FP32, FP16 and BF16 and 8x8 groups in FP16 and BF16; and the dense 6M-Gaussian
 stress scene (log-scale N(ln 0.05, 0.5), opacity sigmoid(N(-1, 1))) in FP32 and in FP16
-with 4x4 groups.
+with 1x1, 4x4 and 8x8 groups.
 
 Bars (same as the 1080p workload): FP32 max abs <= 1e-4 per channel on pixels outside the
 guard bands; FP16/BF16 PSNR >= 45 dB and mean abs error <= 2e-3 over the sampled tiles;
@@ -81,10 +81,11 @@ def test_dense_6m_stress():
     ds = gs.DeviceScene(sc)
     ref, m, ok = _sampled_reference(rec, cam, 200, 13)
     images = {}
-    for prec, group in (("fp32", 1), ("fp16", 4), ("fp16", 1)):
+    for prec, group in (("fp32", 1), ("fp16", 4), ("fp16", 8), ("fp16", 1)):
         note(f"dense 6M {prec} group {group}")
         out = render(ds, cam, group=group, precision=prec, splits=SPLITS[prec], aux=AUX)
         _check(f"dense 6M G{group} K={out['n_keys']}", out, ref, m, ok, prec)
         images[(prec, group)] = out["image"]
         del out
     assert np.array_equal(images[("fp16", 1)], images[("fp16", 4)])
+    assert np.array_equal(images[("fp16", 1)], images[("fp16", 8)])

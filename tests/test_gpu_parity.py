@@ -347,3 +347,18 @@ def test_count_scan_and_compaction(n):
     assert np.array_equal(proj.order.cpu().numpy().view(np.uint32)[:V].astype(np.int64), vis)
     del ds, proj, ws
     torch.cuda.empty_cache()
+
+
+def test_maximum_width():
+    """The widest image the library accepts (16,384 pixels: 1,024 tile columns), one tile row
+    and a ragged second one, against the oracle."""
+    sc = scenes.camera_box_scene(3000, seed=12)
+    cam = scenes.pinhole(16384, 24, 120.0)
+    ref = oracle.render(sc, cam, bg=(0.1, 0.2, 0.3))
+    ok = ref["ambiguous"] == 0
+    ds = gs.DeviceScene(sc)
+    for prec, tol, group in (("fp32", 1e-4, 1), ("fp16", 2e-3, 1), ("fp16", 2e-3, 8)):
+        note(f"maximum width {prec} group {group}")
+        out = render(ds, cam, precision=prec, bg=(0.1, 0.2, 0.3), group=group)
+        assert out["image"].shape == (3, 24, 16384)
+        assert np.abs(out["image"] - ref["image"])[:, ok].max() <= tol
