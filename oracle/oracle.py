@@ -303,3 +303,83 @@ def load_reduction(rec: dict, cam, group: int) -> tuple:
     n_total = int(s1[-1])
     n_group = int(sg[-1])
     return n_total, n_group, (1.0 - n_group / n_total) if n_total else 0.0
+
+
+def composite_backward(rec: dict, cam, start, ids, dimage, bg=(0.0, 0.0, 0.0)) -> dict:
+    """Gradients of L = sum over channels and pixels of dimage * image, where image is the
+    front-to-back composite of `composite` (Background: alpha = min(0.99, o exp(power)),
+    power = -1/2 d^T conic d with d = pixel centre - centre, pairs with alpha < 1/255 skipped,
+    C = sum alpha_i T_i c_i + T bg, stop before the Gaussian that would take T below 1e-4),
+    with respect to each Gaussian's colour (n, 3), opacity (n), conic (a, b, c) (n, 3) and
+    image-plane centre (n, 2).
+
+    Written from the derivative of that recurrence (the method has no backward pass of its
+    own; this is the exact gradient of its forward on the branch the forward takes: clamped
+    alphas, skipped pairs and the stop are held fixed).  Per pixel and blended Gaussian i:
+        dC/dc_i = alpha_i T_i
+        dC/dalpha_i = c_i T_i - (S_i + T_end bg) / (1 - alpha_i),  S_i = sum_{j > i} c_j alpha_j T_j
+    and, unless clamped, dalpha/do = alpha / o, dalpha/dpower = alpha, dpower/d(a, b, c) =
+    -(dx^2 / 2, dx dy, dy^2 / 2), dpower/d(x, y) = (a dx + b dy, b dx + c dy).  FP64, numpy over
+    the pixels of one tile at a time; for small workloads only."""
+    W, H = cam.width, cam.height
+    tx_n = (W + TILE - 1) // TILE
+    ty_n = (H + TILE - 1) // TILE
+    n = rec["depth"].shape[0]
+    xy, conic, rgb, op = rec["xy"], rec["conic"], rec["rgb"], rec["opacity"]
+    bg = np.asarray(bg, np.float64)
+    dimage = np.asarray(dimage, np.float64).reshape(3, H, W)
+    g_rgb = np.zeros((n, 3))
+    g_op = np.zeros(n)
+    g_conic = np.zeros((n, 3))
+    g_xy = np.zeros((n, 2))
+    for tile in range(tx_n * ty_n):
+        s, e = int(start[tile]), int(start[tile + 1])
+        if s == e:
+            continue
+        tx, ty = tile % tx_n, tile // tx_n
+        yy, xx = np.meshgrid(np.arange(ty * TILE, min(ty * TILE + TILE, H)),
+                             np.arange(tx * TILE, min(tx * TILE + TILE, W)), indexing="ij")
+        xx, yy = xx.ravel(), yy.ravel()
+        px, py = xx + 0.5, yy + 0.5
+        gp = dimage[:, yy, xx]                       # (3, P)
+        lst = np.asarray(ids[s:e], np.int64)
+        L, P = lst.size, px.size
+        A = np.zeros((L, P))
+        TT = np.zeros((L, P))
+        ACT = np.zeros((L, P), bool)
+        FREE = np.zeros((L, P), bool)                # alpha not clamped at 0.99
+        T = np.ones(P)
+        alive = np.ones(P, bool)
+        for k, g in enumerate(lst):
+            dx, dy = px - xy[g, 0], py - xy[g, 1]
+            a, b, c = conic[g]
+            raw = op[g] * np.exp(-0.5 * (a * dx * dx + 2.0 * b * dx * dy + c * dy * dy))
+            al = np.minimum(0.99, raw)
+            ok = alive & (al >= 1.0 / 255.0)
+            Tn = T * (1.0 - al)
+            stop = ok & (Tn < 1e-4)
+            act = ok & ~stop
+            alive &= ~stop
+            A[k], TT[k], ACT[k], FREE[k] = al, T, act, raw < 0.99
+            T = np.where(act, Tn, T)
+        Tend = T
+        S = np.zeros((3, P))
+        for k in range(L - 1, -1, -1):
+            act = ACT[k]
+            if not act.any():
+                continue
+            g = lst[k]
+            al, Tk = A[k], TT[k]
+            c3 = rgb[g][:, None]
+            w = al * Tk * act
+            g_rgb[g] += (gp * w).sum(axis=1)
+            dC_da = c3 * Tk - (S + bg[:, None] * Tend) / (1.0 - al)
+            dL_da = (gp * dC_da).sum(axis=0) * act
+            dL_dp = dL_da * al * FREE[k]
+            g_op[g] += (dL_da * FREE[k] * al / op[g]).sum()
+            dx, dy = px - xy[g, 0], py - xy[g, 1]
+            a, b, c = conic[g]
+            g_conic[g] += [(-0.5 * dx * dx * dL_dp).sum(), (-dx * dy * dL_dp).sum(), (-0.5 * dy * dy * dL_dp).sum()]
+            g_xy[g] += [((a * dx + b * dy) * dL_dp).sum(), ((b * dx + c * dy) * dL_dp).sum()]
+            S += c3 * w
+    return dict(rgb=g_rgb, opacity=g_op, conic=g_conic, xy=g_xy)
