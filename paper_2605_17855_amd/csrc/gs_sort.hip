@@ -55,7 +55,7 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nbit
 }
 
 // Per-tile digit counts: counts[d * tiles + tile].  Keys are loaded up front (8 in flight
-// per lane) and each wave adds one LDS atomic per distinct digit.
+// per lane) and counted with one LDS atomic each.
 // n is *n_dev when n_dev is given (the grid then covers an upper bound and the surplus
 // workgroups return at once), else n_host.
 __device__ __forceinline__ uint64_t count_of(uint64_t n_host, const uint32_t *n_dev) {
@@ -72,7 +72,6 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(const KT *keys, uint64_t
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   h[t] = 0;
   const uint32_t dmask = (1u << nbits) - 1u;
-  const uint64_t lt = (1ull << lane) - 1ull;
   const uint64_t base = (uint64_t)blockIdx.x * kSortTile + (uint64_t)w * kWaveTile;
   KT key[kRounds];
 #pragma unroll
@@ -85,8 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(const KT *keys, uint64_t
   for (int r = 0; r < kRounds; ++r) {
     const bool valid = base + (uint64_t)r * 64 + lane < n;
     const uint32_t d = (uint32_t)(key[r] >> shift) & dmask;
-    const uint64_t peers = match_digit(d, valid, nbits);
-    if (valid && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    if (valid) atomicAdd(&h[d], 1u);   // (cheaper than grouping equal digits per wave first)
   }
   __syncthreads();
   counts[(uint64_t)t * tiles_max + blockIdx.x] = h[t];
