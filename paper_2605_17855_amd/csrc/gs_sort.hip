@@ -58,6 +58,30 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nbit
   return peers;
 }
 
+// Exclusive scan of v over the 256 threads of the workgroup (wave shuffles, one LDS
+// exchange of the four wave totals); *total = the sum.  sh4 holds 4 values.
+__device__ __forceinline__ uint32_t block_exclusive_scan_u32(uint32_t v, uint32_t *sh4, uint32_t *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t u = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += u;
+  }
+  if (lane == 63) sh4[w] = incl;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    const uint32_t x = sh4[k];
+    before += k < w ? x : 0u;
+    all += x;
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - v;
+}
+
 // Per-tile digit counts: counts[d * tiles + tile].  Keys are loaded up front (8 in flight
 // per lane) and counted with one LDS atomic each.
 // n is *n_dev when n_dev is given (the grid then covers an upper bound and the surplus
@@ -99,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(const KT *keys, uint64_t
 __global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t *counts, uint32_t tiles_max,
                                                              uint32_t *totals, uint64_t n_host, const uint32_t *n_dev,
                                                              uint32_t tile_size) {
-  __shared__ uint32_t sh[kBlock];
+  __shared__ uint32_t sh[4];
   const int d = blockIdx.x, t = threadIdx.x;
   uint32_t *row = counts + (uint64_t)d * tiles_max;
   // tiles holding keys (the count kernel wrote no counts for the others)
@@ -110,16 +134,9 @@ __global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t *counts, u
   uint32_t s = 0;
   for (uint32_t i = 0; i < per; ++i)
     if (b0 + i < tiles) s += row[b0 + i];
-  sh[t] = s;
-  __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    const uint32_t add = t >= off ? sh[t - off] : 0u;
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
-  }
-  uint32_t run = sh[t] - s;
-  if (t == kBlock - 1) totals[d] = sh[t];
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan_u32(s, sh, &tot);
+  if (t == 0) totals[d] = tot;
   for (uint32_t i = 0; i < per; ++i)
     if (b0 + i < tiles) {
       const uint32_t c = row[b0 + i];
@@ -141,6 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
   __shared__ uint32_t wcnt[4][kDigits];
   __shared__ uint32_t bstart[kDigits];
   __shared__ uint32_t gbase[kDigits];
+  __shared__ uint32_t sh4[4];
   __shared__ KT s_key[kSortTile];
   __shared__ uint32_t s_val[kSortTile];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -182,20 +200,9 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
   // start (scan over digits of the totals, plus this tile's offset within the digit)
   const uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
   const uint32_t tot = c0 + c1 + c2 + c3;
-  bstart[t] = tot;
-  gbase[t] = tot_d;
-  __syncthreads();
-  for (int off = 1; off < kDigits; off <<= 1) {
-    const uint32_t a1 = t >= off ? bstart[t - off] : 0u;
-    const uint32_t a2 = t >= off ? gbase[t - off] : 0u;
-    __syncthreads();
-    bstart[t] += a1;
-    gbase[t] += a2;
-    __syncthreads();
-  }
-  const uint32_t bs = bstart[t] - tot;
-  const uint32_t gb = gbase[t] - tot_d + off_d;
-  __syncthreads();
+  uint32_t all;
+  const uint32_t bs = block_exclusive_scan_u32(tot, sh4, &all);
+  const uint32_t gb = block_exclusive_scan_u32(tot_d, sh4, &all) + off_d;
   bstart[t] = bs;
   gbase[t] = gb;
   wcnt[0][t] = bs;
