@@ -87,6 +87,7 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 plain comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle compositing time")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-backward", action="store_true", help="skip the backward-pass timing")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving workload")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered rate / saturated throughput")
@@ -236,6 +237,33 @@ def _cpu_model():
     except OSError:
         pass
     return None
+
+
+def backward_leg(gs, torch, ds, cams, n, steps, warmup):
+    """Times gs_rasterize_backward (FP32, tile bins) on each pose after its forward render,
+    with a fixed N(0, 1) upstream gradient; HIP events around the backward launch only."""
+    st = torch.cuda.current_stream()
+    rend = gs.Renderer(n, 1920, 1080, group=1)
+    opt = gs.options(group=1, precision="fp32")
+    grads = gs.Grads(n)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    dimg = torch.randn((3, 1080, 1920), generator=gen, device="cuda")
+    evs = []
+    for i in range(warmup + steps):
+        cam = cams[i % len(cams)]
+        rend.render(ds, cam, opt)
+        grads.zero_()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        gs.gs_rasterize_backward(rend.proj, rend.bins, cam, opt, dimg, grads)
+        b.record(st)
+        if i >= warmup:
+            evs.append((a, b))
+    torch.cuda.synchronize()
+    ms = [a.elapsed_time(b) for a, b in evs]
+    return {"kernel": "k_raster_backward", "precision": "fp32", "frames": steps, "avg_ms": float(np.mean(ms)),
+            "p50_ms": float(np.percentile(ms, 50)), "p99_ms": float(np.percentile(ms, 99))}
 
 
 def serve(gs, torch, args):
@@ -428,6 +456,11 @@ def main():
                  "entries_per_frame": ent, "evals_per_frame": ek / args.steps,
                  "roofline_frac": (FLOPS_PER_EVAL * ek + FLOPS_PER_BLEND * eb) / t_raster_s / 1e12 / PEAK_FP32_TFLOPS}
 
+    backward = None
+    if not args.no_backward:
+        log("timing the backward pass (FP32, tile bins)")
+        backward = backward_leg(gs, torch, ds, cams, sc.n, args.steps, args.warmup)
+
     cpu = None
     quality = {}
     if not args.no_cpu_baseline:
@@ -461,6 +494,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "tight_culling": tight,
+        "backward": backward,
         "serving": serving,
     }
     print(json.dumps(line), flush=True)

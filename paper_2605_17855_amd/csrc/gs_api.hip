@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 
+#include "gs_backward.hpp"
 #include "gs_internal.hpp"
 
 namespace {
@@ -337,6 +338,37 @@ gs_status gs_rasterize(const gs_projected *proj, const gs_bins *bins, const gs_c
     GS_HIP(gsi::launch_raster_fp32(j, p, st));
   else
     GS_HIP(gsi::launch_raster_mfma(j, p, st));
+  return GS_OK;
+}
+
+gs_status gs_rasterize_backward(const gs_projected *proj, const gs_bins *bins, const gs_camera *cam,
+                                const gs_options *opt, const float *dimage, const gs_grads *grads, void *stream) {
+  gs_status s;
+  if ((s = check_camera(cam)) || (s = check_options(opt))) return s;
+  if (opt->group != 1) return fail(GS_ERR_UNSUPPORTED, "backward pass over group %d bins (tile bins only)", opt->group);
+  if ((s = check_bins(bins, 1, false))) return s;
+  if (!proj || !proj->xy || !proj->conic || !proj->rgb) return fail(GS_ERR_INVALID_ARG, "projected record is NULL");
+  if (!dimage) return fail(GS_ERR_INVALID_ARG, "dimage is NULL");
+  if (!grads || !grads->rgb || !grads->opacity || !grads->conic || !grads->xy)
+    return fail(GS_ERR_INVALID_ARG, "gradient buffer is NULL");
+  const gsi::Grid g = gsi::make_grid(cam->width, cam->height, 1);
+  gsi::BackwardJob j;
+  j.xy = reinterpret_cast<const double2 *>(proj->xy);
+  j.conic = reinterpret_cast<const float4 *>(proj->conic);
+  j.rgb = reinterpret_cast<const float4 *>(proj->rgb);
+  j.vals = bins->vals;
+  j.ranges = bins->ranges;
+  j.dimage = dimage;
+  j.g_rgb = grads->rgb;
+  j.g_op = grads->opacity;
+  j.g_conic = grads->conic;
+  j.g_xy = grads->xy;
+  j.W = g.W;
+  j.H = g.H;
+  j.TX = g.TX;
+  j.TY = g.TY;
+  for (int c = 0; c < 3; ++c) j.bg[c] = opt->bg[c];
+  GS_HIP(gsi::launch_raster_backward(j, static_cast<hipStream_t>(stream)));
   return GS_OK;
 }
 

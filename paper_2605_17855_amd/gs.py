@@ -58,6 +58,10 @@ class gs_bins(C.Structure):
                 ("capacity", C.c_uint64), ("ranges", C.c_void_p)]
 
 
+class gs_grads(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("opacity", C.c_void_p), ("conic", C.c_void_p), ("xy", C.c_void_p)]
+
+
 class gs_job(C.Structure):
     _fields_ = [("proj", C.POINTER(gs_projected)), ("bins", C.POINTER(gs_bins)), ("cam", gs_camera),
                 ("image", C.c_void_p), ("aux", C.c_void_p)]
@@ -65,7 +69,7 @@ class gs_job(C.Structure):
 
 EXPORTS = ["gs_num_bins", "gs_workspace_bytes", "gs_preprocess", "gs_bin_sort", "gs_rasterize", "gs_render",
            "gs_sort_workspace_bytes", "gs_radix_sort_u64", "gs_max_batch", "gs_rasterize_batch",
-           "gs_status_string", "gs_last_error"]
+           "gs_rasterize_backward", "gs_status_string", "gs_last_error"]
 
 _lib = None
 
@@ -99,8 +103,10 @@ def lib():
     L.gs_max_batch.argtypes = []
     L.gs_max_batch.restype = C.c_int32
     L.gs_rasterize_batch.argtypes = [P(gs_job), C.c_int32, P(gs_options), C.c_void_p, C.c_void_p]
+    L.gs_rasterize_backward.argtypes = [P(gs_projected), P(gs_bins), P(gs_camera), P(gs_options), C.c_void_p,
+                                        P(gs_grads), C.c_void_p]
     for f in ("gs_preprocess", "gs_bin_sort", "gs_rasterize", "gs_render", "gs_radix_sort_u64",
-              "gs_rasterize_batch"):
+              "gs_rasterize_batch", "gs_rasterize_backward"):
         getattr(L, f).restype = C.c_int
     L.gs_status_string.argtypes = [C.c_int]
     L.gs_status_string.restype = C.c_char_p
@@ -248,6 +254,32 @@ def gs_bin_sort(proj: Projected, cam, opt: gs_options, bins: Bins, ws, stream=No
 def gs_rasterize(proj: Projected, bins: Bins, cam, opt: gs_options, image, aux=None, stream=None):
     _check(lib().gs_rasterize(C.byref(proj.struct), C.byref(bins.struct), C.byref(camera(cam)), C.byref(opt),
                               _ptr(image), _ptr(aux), _stream(stream)))
+
+
+class Grads:
+    """Device buffers of gs_grads for n Gaussians (FP32, zeroed; gs_rasterize_backward adds to them)."""
+
+    def __init__(self, n: int, device="cuda"):
+        import torch
+        m = max(n, 1)
+        self.rgb = torch.zeros((m, 3), dtype=torch.float32, device=device)
+        self.opacity = torch.zeros((m,), dtype=torch.float32, device=device)
+        self.conic = torch.zeros((m, 3), dtype=torch.float32, device=device)
+        self.xy = torch.zeros((m, 2), dtype=torch.float32, device=device)
+        g = gs_grads()
+        g.rgb, g.opacity, g.conic, g.xy = _ptr(self.rgb), _ptr(self.opacity), _ptr(self.conic), _ptr(self.xy)
+        self.struct = g
+
+    def zero_(self):
+        for t in (self.rgb, self.opacity, self.conic, self.xy):
+            t.zero_()
+
+
+def gs_rasterize_backward(proj: Projected, bins: Bins, cam, opt: gs_options, dimage, grads: Grads, stream=None):
+    """Adds to `grads` the gradients of sum(dimage * image) for the image gs_rasterize writes
+    (FP32 arithmetic, tile bins)."""
+    _check(lib().gs_rasterize_backward(C.byref(proj.struct), C.byref(bins.struct), C.byref(camera(cam)),
+                                       C.byref(opt), _ptr(dimage), C.byref(grads.struct), _stream(stream)))
 
 
 def gs_render(scene: DeviceScene, cam, opt: gs_options, proj: Projected, bins: Bins, image, aux, ws,

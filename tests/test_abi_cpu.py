@@ -12,7 +12,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "gs.h")).read()
+    inc = os.path.join(ROOT, "include")
+    text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", text)))
 
@@ -215,3 +216,29 @@ def test_rasterizer_operands_rounded_from_fp32(tmp_path):
     asm = out.read_text()
     assert "v_mfma_f32_32x32x16_f16" in asm
     assert not re.search(r"v_(fma|mad)_mix(lo|hi)_(f16|bf16)", asm)
+
+
+def test_backward_rejects_invalid_calls():
+    """gs_rasterize_backward validates on the host: group bins, NULL buffers, bad camera."""
+    L = gs.lib()
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1, 1, 1)
+    b = gs.gs_bins(1, 1, 1, 16, 1)
+    g = gs.gs_grads(1, 1, 1, 1)
+    d = C.c_void_p(1)
+    call = L.gs_rasterize_backward
+    assert call(C.byref(p), C.byref(b), C.byref(_cam()), C.byref(gs.options(group=2)), d, C.byref(g),
+                None) == gs.GS_ERR_UNSUPPORTED
+    assert b"tile bins" in L.gs_last_error()
+    assert call(C.byref(p), C.byref(b), C.byref(_cam()), C.byref(gs.options()), None, C.byref(g),
+                None) == gs.GS_ERR_INVALID_ARG
+    assert call(C.byref(p), C.byref(b), C.byref(_cam()), C.byref(gs.options()), d, None, None) == gs.GS_ERR_INVALID_ARG
+    g0 = gs.gs_grads(1, None, 1, 1)
+    assert call(C.byref(p), C.byref(b), C.byref(_cam()), C.byref(gs.options()), d, C.byref(g0),
+                None) == gs.GS_ERR_INVALID_ARG
+    assert b"gradient" in L.gs_last_error()
+    p0 = gs.gs_projected(1, None, 1, 1, 1, 1, 1, 1)
+    assert call(C.byref(p0), C.byref(b), C.byref(_cam()), C.byref(gs.options()), d, C.byref(g),
+                None) == gs.GS_ERR_INVALID_ARG
+    c = _cam()
+    c.width = 0
+    assert call(C.byref(p), C.byref(b), C.byref(c), C.byref(gs.options()), d, C.byref(g), None) == gs.GS_ERR_INVALID_ARG

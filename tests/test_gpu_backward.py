@@ -1,0 +1,197 @@
+"""Parity of the GPU backward pass of the compositing (gs_rasterize_backward) with the FP64
+oracle's (oracle.composite_backward, pinned by finite differences, a conservation law and a
+closed form).
+
+Both sides get the same inputs, made by the oracle: its per-Gaussian records (conic, colour
+and opacity rounded to FP32, the precision the device records hold, so the FP64 reference
+differentiates exactly the values the kernel reads) and its depth-sorted tile lists.  The
+upstream gradient is seeded N(0, 1) per channel and pixel, set to zero on the pixels where
+the oracle's forward flags a decision (the 1/255 cut, the 0.99 clamp, the 1e-4 stop) inside
+the band that FP32 arithmetic may take either way: every gradient term of a pixel is linear
+in its upstream gradient, so those pixels then contribute nothing on either side.
+
+Bar, per gradient field: max |gpu - ref| <= 2e-5 max|ref| + 2e-5 |ref| and relative L2 error
+<= 1e-5 (measured: below 1e-6 relative to the field's largest value, L2 below 1e-6).  The
+kernel evaluates the power as the FP32 rasterizer does (alpha to ~1e-6
+relative, from the FP32 offset to the centre and the exp2 of the scaled quadratic), recovers
+T_i = T_{i+1} / (1 - alpha_i) with ~1.5 ulp per step, and sums over pixels in FP32 with
+atomics in no fixed order; the terms (1 - alpha)^-1 reach 100 for clamped alphas."""
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2605_17855_amd import gs, scenes
+from gpu_helpers import note, sampled_tiles
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("rgb", "opacity", "conic", "xy")
+
+
+def _fp32_records(rec):
+    r = dict(rec)
+    for k in ("conic", "rgb", "opacity"):
+        r[k] = rec[k].astype(np.float32).astype(np.float64)
+    return r
+
+
+def _upload(rec, start, ids):
+    import torch
+    n = rec["depth"].shape[0]
+    proj = gs.Projected(n)
+    if n:
+        proj.xy.copy_(torch.from_numpy(np.ascontiguousarray(rec["xy"])))
+        conic = np.concatenate([rec["conic"], rec["opacity"][:, None]], axis=1).astype(np.float32)
+        rgb = np.concatenate([rec["rgb"], rec["depth"][:, None]], axis=1).astype(np.float32)
+        proj.conic.copy_(torch.from_numpy(conic))
+        proj.rgb.copy_(torch.from_numpy(rgb))
+    total = int(start[-1])
+    bins = gs.Bins(max(total, 1), start.size - 1)
+    if total:
+        bins.vals[:total].copy_(torch.from_numpy(np.asarray(ids[:total], np.int32)))
+    ranges = np.stack([start[:-1], start[1:]], axis=1).astype(np.int32)
+    bins.ranges.copy_(torch.from_numpy(ranges))
+    return proj, bins
+
+
+def _upstream(rec, cam, start, ids, bg, seed):
+    rng = np.random.default_rng(seed)
+    dimg = rng.normal(size=(3, cam.height, cam.width))
+    fwd = oracle.composite(rec, cam, start, ids, bg=bg)
+    dimg[:, fwd["ambiguous"] != 0] = 0.0
+    return dimg, fwd
+
+
+def _gpu_backward(proj, bins, cam, dimg, bg, n, calls=1):
+    import torch
+    grads = gs.Grads(n)
+    d = torch.from_numpy(np.ascontiguousarray(dimg, np.float32)).cuda()
+    for _ in range(calls):
+        gs.gs_rasterize_backward(proj, bins, cam, gs.options(bg=bg), d, grads)
+    torch.cuda.synchronize()
+    return {f: getattr(grads, f).cpu().numpy().astype(np.float64)[:n] for f in FIELDS}
+
+
+def _compare(tag, got, ref):
+    for f in FIELDS:
+        a, b = got[f].reshape(-1), ref[f].reshape(-1)
+        scale = float(np.abs(b).max()) if b.size else 0.0
+        err = np.abs(a - b)
+        mx = float(err.max()) if b.size else 0.0
+        l2 = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+        print(f"{tag} {f}: max|ref| {scale:.3e}, max err {mx:.3e}, rel L2 {l2:.3e}")
+        assert np.all(err <= 2e-5 * scale + 2e-5 * np.abs(b)), (tag, f)
+        assert l2 <= 1e-5 or scale == 0.0, (tag, f, l2)
+
+
+def _case(sc, cam, bg, seed):
+    rec = _fp32_records(oracle.preprocess(sc, cam))
+    start, ids, _ = oracle.lists(rec, cam, 1)
+    dimg, fwd = _upstream(rec, cam, start, ids, bg, seed)
+    ref = oracle.composite_backward(rec, cam, start, ids, dimg, bg)
+    proj, bins = _upload(rec, start, ids)
+    return rec, start, ids, dimg, fwd, ref, proj, bins
+
+
+@pytest.mark.parametrize("bg", [(0.0, 0.0, 0.0), (0.3, 0.6, 0.1)])
+def test_backward_matches_oracle_ragged(bg):
+    """1,500 Gaussians at 200x120: 13x8 tiles with a ragged last column and row."""
+    note(f"backward ragged bg={bg}")
+    sc = scenes.camera_box_scene(1500, seed=61, log_scale_mu=np.log(0.04))
+    cam = scenes.pinhole(200, 120, 60.0)
+    rec, start, ids, dimg, fwd, ref, proj, bins = _case(sc, cam, bg, 62)
+    got = _gpu_backward(proj, bins, cam, dimg, bg, sc.n)
+    _compare("ragged", got, ref)
+    assert np.count_nonzero(ref["opacity"]) > 500
+
+
+def test_backward_dense_stops_and_clamps():
+    """Large, partly opaque splats: most pixels stop (T < 1e-4) and a tenth of the splats
+    have opacity 0.999, so their centres are clamped at 0.99."""
+    note("backward dense")
+    sc = scenes.camera_box_scene(2500, seed=63, log_scale_mu=np.log(0.12), log_scale_sigma=0.3)
+    sc.opacity[::10] = 0.999
+    cam = scenes.pinhole(96, 80, 60.0)
+    bg = (0.2, 0.2, 0.2)
+    rec, start, ids, dimg, fwd, ref, proj, bins = _case(sc, cam, bg, 64)
+    assert (fwd["tfinal"] < 1e-3).mean() > 0.25
+    got = _gpu_backward(proj, bins, cam, dimg, bg, sc.n)
+    _compare("dense", got, ref)
+
+
+def test_backward_accumulates():
+    """Two calls add their gradients: the result is twice one call's (to rounding)."""
+    note("backward accumulate")
+    sc = scenes.camera_box_scene(800, seed=65)
+    cam = scenes.pinhole(64, 48, 60.0)
+    rec, start, ids, dimg, fwd, ref, proj, bins = _case(sc, cam, (0.0, 0.0, 0.0), 66)
+    got = _gpu_backward(proj, bins, cam, dimg, (0.0, 0.0, 0.0), sc.n, calls=2)
+    _compare("twice", {f: got[f] / 2.0 for f in FIELDS}, ref)
+
+
+def test_backward_empty():
+    """No visible Gaussian (every tile list empty), and no Gaussian at all: nothing is added."""
+    import torch
+    cam = scenes.pinhole(80, 48, 60.0)
+    for n in (0, 300):
+        note(f"backward empty n={n}")
+        sc = scenes.camera_box_scene(n, seed=67)
+        if n:
+            sc.mean[2, :] = -1.0          # all behind the camera
+        rec = _fp32_records(oracle.preprocess(sc, cam))
+        start, ids, _ = oracle.lists(rec, cam, 1)
+        assert int(start[-1]) == 0
+        proj, bins = _upload(rec, start, ids)
+        grads = gs.Grads(n)
+        d = torch.ones((3, cam.height, cam.width), dtype=torch.float32, device="cuda")
+        gs.gs_rasterize_backward(proj, bins, cam, gs.options(), d, grads)
+        torch.cuda.synchronize()
+        for f in FIELDS:
+            assert not getattr(grads, f).any()
+
+
+def test_backward_over_library_bins():
+    """On the library's own projection and bins (gs_preprocess, gs_bin_sort), with and
+    without opacity-aware culling: the culled entries blend nothing, so both give the same
+    gradients (to the rounding of the atomics' order)."""
+    import torch
+    note("backward over library bins")
+    sc = scenes.camera_box_scene(3000, seed=68, log_scale_mu=np.log(0.03))
+    cam = scenes.pinhole(160, 112, 60.0)
+    n = sc.n
+    ds = gs.DeviceScene(sc)
+    rng = np.random.default_rng(69)
+    d = torch.from_numpy(rng.normal(size=(3, cam.height, cam.width)).astype(np.float32)).cuda()
+    out = {}
+    for tight in (False, True):
+        r = gs.Renderer(n, cam.width, cam.height)
+        opt = gs.options(bg=(0.1, 0.1, 0.1), tight=tight)
+        r.render(ds, cam, opt)
+        grads = gs.Grads(n)
+        gs.gs_rasterize_backward(r.proj, r.bins, cam, opt, d, grads)
+        torch.cuda.synchronize()
+        out[tight] = {f: getattr(grads, f).cpu().numpy().astype(np.float64) for f in FIELDS}
+    for f in FIELDS:
+        a, b = out[True][f], out[False][f]
+        assert np.abs(a - b).max() <= 1e-4 * np.abs(b).max(), f
+    assert np.count_nonzero(out[False]["opacity"]) > 100
+
+
+def test_backward_headline_sampled_tiles():
+    """The 1M-Gaussian, 1920x1080 workload on 48 sampled tiles: both sides get the same tile
+    lists, with every other tile's list empty."""
+    note("backward 1M 1080p sampled tiles")
+    sc, cam = scenes.clustered_1m()
+    rec = _fp32_records(oracle.preprocess(sc, cam))
+    tiles = sampled_tiles(cam, 48, 70)
+    start, ids = oracle.tile_lists(rec, cam, tiles)
+    bg = (0.0, 0.0, 0.0)
+    rng = np.random.default_rng(71)
+    dimg = rng.normal(size=(3, cam.height, cam.width))
+    fwd = oracle.composite(rec, cam, start, ids, bg=bg, tiles=tiles, nthreads=8)
+    dimg[:, fwd["ambiguous"] != 0] = 0.0
+    ref = oracle.composite_backward(rec, cam, start, ids, dimg, bg)
+    proj, bins = _upload(rec, start, ids)
+    got = _gpu_backward(proj, bins, cam, dimg, bg, sc.n)
+    _compare("1M sampled", got, ref)
+    assert int(start[-1]) > 5000
