@@ -41,7 +41,8 @@ typedef struct {
  * power is evaluated in FP32 exactly as that rasterizer does, so both take the same
  * branch at every pair.  dimage: 3 x H x W FP32 planes (the image's layout).
  * The gradients are ADDED to *grads (zero them before the first call; several views or
- * frames can be summed into one set of buffers).
+ * frames can be summed into one set of buffers) with hardware FP32 atomic adds, so the
+ * four buffers must be ordinary (coarse-grained) device memory, as hipMalloc returns.
  * proj and bins are what gs_preprocess and gs_bin_sort wrote (opacity-aware bins, from
  * GS_OPT_TIGHT, give the same gradients).  Reads opt->group, which must be 1 (tile bins;
  * GS_ERR_UNSUPPORTED otherwise), and opt->bg; ignores the precision and the aux flags.

@@ -11,7 +11,8 @@
 //  2. the list back to front.  T_i = T_{i+1} / (1 - alpha_i) recovers the transmittance in
 //     front of each blended Gaussian and S, the colour the later Gaussians add, grows by
 //     c_i alpha_i T_i.  A pair's nine gradient terms are summed over the wave with
-//     shuffles and one lane adds them to the Gaussian's gradients with atomics.
+//     DPP and lane swaps, and nine lanes add them to the Gaussian's gradients, one hardware FP32
+//     atomic add each (the buffers are ordinary device memory).
 #include "gs_backward.hpp"
 
 namespace gsi {
@@ -25,10 +26,24 @@ struct BwdShared {
   uint32_t last;      // end of the longest blended prefix of the tile's pixels
 };
 
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 64 lanes, the same bits in every lane (each step adds a lane's value to its
+// partner's, symmetric in the two).  Within 16-lane rows by DPP: quad_perm [1,0,3,2] and
+// [2,3,0,1], then the half-row and row mirrors; across rows by the lane-swap instructions:
+// rows 0 <-> 1 and 2 <-> 3, then the two halves of the wave.
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dpp<0xB1>(v);
+  v += dpp<0x4E>(v);
+  v += dpp<0x141>(v);
+  v += dpp<0x140>(v);
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(h[0]) + __uint_as_float(h[1]);
 }
 
 __device__ __forceinline__ void stage(const BackwardJob &J, BwdShared &sm, uint32_t cs, int cnt, int ox, int oy) {
@@ -136,17 +151,17 @@ __global__ __launch_bounds__(kBlock) void k_raster_backward(BackwardJob J) {
       }
 #pragma unroll
       for (int k = 0; k < 9; ++k) v[k] = wave_sum(v[k]);
-      if (lane == 0) {
-        const uint32_t g = __float_as_uint(sm.d[j].y);
-        atomicAdd(&J.g_rgb[3 * (size_t)g], v[0]);
-        atomicAdd(&J.g_rgb[3 * (size_t)g + 1], v[1]);
-        atomicAdd(&J.g_rgb[3 * (size_t)g + 2], v[2]);
-        atomicAdd(&J.g_op[g], v[3]);
-        atomicAdd(&J.g_conic[3 * (size_t)g], v[4]);
-        atomicAdd(&J.g_conic[3 * (size_t)g + 1], v[5]);
-        atomicAdd(&J.g_conic[3 * (size_t)g + 2], v[6]);
-        atomicAdd(&J.g_xy[2 * (size_t)g], v[7]);
-        atomicAdd(&J.g_xy[2 * (size_t)g + 1], v[8]);
+      // every lane holds the nine sums: lanes 0..8 add one each, in one vector atomic
+      if (lane < 9) {
+        const size_t g = __float_as_uint(sm.d[j].y);
+        float val = v[0];
+#pragma unroll
+        for (int k = 1; k < 9; ++k) val = (lane == k) ? v[k] : val;
+        float *dst = lane < 3 ? J.g_rgb + 3 * g + lane
+                   : lane == 3 ? J.g_op + g
+                   : lane < 7 ? J.g_conic + 3 * g + (lane - 4)
+                   : J.g_xy + 2 * g + (lane - 7);
+        unsafeAtomicAdd(dst, val);
       }
     }
     ce = cs;
