@@ -10,9 +10,10 @@
 //     for the pixel's final transmittance T_end and the end of its blended prefix;
 //  2. the list back to front.  T_i = T_{i+1} / (1 - alpha_i) recovers the transmittance in
 //     front of each blended Gaussian and S, the colour the later Gaussians add, grows by
-//     c_i alpha_i T_i.  A pair's nine gradient terms are summed over the wave with
-//     DPP and lane swaps, and nine lanes add them to the Gaussian's gradients, one hardware FP32
-//     atomic add each (the buffers are ordinary device memory).
+//     c_i alpha_i T_i.  A pair's nine gradient terms are summed over the wave (a
+//     reduce-scatter with lane swaps, then DPP row sums) and nine lanes add them to the
+//     Gaussian's gradients, one hardware FP32 atomic add each (the buffers are ordinary
+//     device memory).
 #include "gs_backward.hpp"
 
 namespace gsi {
@@ -31,19 +32,50 @@ __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
-// Sum over the 64 lanes, the same bits in every lane (each step adds a lane's value to its
-// partner's, symmetric in the two).  Within 16-lane rows by DPP: quad_perm [1,0,3,2] and
-// [2,3,0,1], then the half-row and row mirrors; across rows by the lane-swap instructions:
-// rows 0 <-> 1 and 2 <-> 3, then the two halves of the wave.
-__device__ __forceinline__ float wave_sum(float v) {
+// Sum over the 16 lanes of each row (every lane of the row gets it): quad_perm [1,0,3,2] and
+// [2,3,0,1], then the half-row and row mirrors.
+__device__ __forceinline__ float row_sum(float v) {
   v += dpp<0xB1>(v);
   v += dpp<0x4E>(v);
   v += dpp<0x141>(v);
   v += dpp<0x140>(v);
-  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-  v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-  return __uint_as_float(h[0]) + __uint_as_float(h[1]);
+  return v;
+}
+
+// Reduce-scatter steps of two registers at once.  swap32_add: lanes 0..31 get a[i] + a[i+32],
+// lanes 32..63 get b[i-32] + b[i].  swap16_add (rows of 16 lanes): row 0 gets a's rows 0 + 1,
+// row 1 b's rows 0 + 1, row 2 a's rows 2 + 3, row 3 b's rows 2 + 3.
+__device__ __forceinline__ float swap32_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Wave sums of the nine gradient terms v[0..8], added to the Gaussian's gradients by nine lanes
+// in one hardware FP32 atomic.  After the two swap steps the rows of x0 hold the partial sums
+// of terms (0, 2, 1, 3), those of x1 terms (4, 6, 5, 7) and every row of x2 term 8; a row sum
+// completes each.  Term f goes to rgb[3g + f] (f < 3), opacity[g] (3), conic[3g + f - 4]
+// (4..6), xy[2g + f - 7] (7, 8).
+__device__ __forceinline__ void add_terms(const BackwardJob &J, const float (&v)[9], uint32_t g, int lane) {
+  const float x0 = row_sum(swap16_add(swap32_add(v[0], v[1]), swap32_add(v[2], v[3])));
+  const float x1 = row_sum(swap16_add(swap32_add(v[4], v[5]), swap32_add(v[6], v[7])));
+  const float w8 = swap32_add(v[8], v[8]);
+  const float x2 = row_sum(swap16_add(w8, w8));
+  const int row = lane >> 4, c = lane & 15;
+  if (c < 2 || (c == 2 && row == 0)) {
+    const int rf = row == 1 ? 2 : row == 2 ? 1 : row;
+    const int f = c == 0 ? rf : c == 1 ? 4 + rf : 8;
+    const float val = c == 0 ? x0 : c == 1 ? x1 : x2;
+    const size_t G = g;
+    float *dst = f < 3 ? J.g_rgb + 3 * G + f
+               : f == 3 ? J.g_op + G
+               : f < 7 ? J.g_conic + 3 * G + (f - 4)
+               : J.g_xy + 2 * G + (f - 7);
+    unsafeAtomicAdd(dst, val);
+  }
 }
 
 __device__ __forceinline__ void stage(const BackwardJob &J, BwdShared &sm, uint32_t cs, int cnt, int ox, int oy) {
@@ -149,20 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_backward(BackwardJob J) {
         S2 = fmaf(Cc.x, wgt, S2);
         T = Ti;
       }
-#pragma unroll
-      for (int k = 0; k < 9; ++k) v[k] = wave_sum(v[k]);
-      // every lane holds the nine sums: lanes 0..8 add one each, in one vector atomic
-      if (lane < 9) {
-        const size_t g = __float_as_uint(sm.d[j].y);
-        float val = v[0];
-#pragma unroll
-        for (int k = 1; k < 9; ++k) val = (lane == k) ? v[k] : val;
-        float *dst = lane < 3 ? J.g_rgb + 3 * g + lane
-                   : lane == 3 ? J.g_op + g
-                   : lane < 7 ? J.g_conic + 3 * g + (lane - 4)
-                   : J.g_xy + 2 * g + (lane - 7);
-        unsafeAtomicAdd(dst, val);
-      }
+      add_terms(J, v, __float_as_uint(sm.d[j].y), lane);
     }
     ce = cs;
   }
