@@ -8,12 +8,12 @@
 //  1. the forward recurrence again, in the forward rasterizer's FP32 arithmetic (the same
 //     operations in the same order, so every cut, clamp and stop is decided the same way),
 //     for the pixel's final transmittance T_end and the end of its blended prefix;
-//  2. the list back to front.  T_i = T_{i+1} / (1 - alpha_i) recovers the transmittance in
-//     front of each blended Gaussian and S, the colour the later Gaussians add, grows by
-//     c_i alpha_i T_i.  A pair's nine gradient terms are summed over the wave (a
-//     reduce-scatter with lane swaps, then DPP row sums) and nine lanes add them to the
-//     Gaussian's gradients, one hardware FP32 atomic add each (the buffers are ordinary
-//     device memory).
+//  2. the list back to front.  T_i = T_{i+1} / (1 - alpha_i) (a 1-ulp hardware reciprocal)
+//     recovers the transmittance in front of each blended Gaussian and S, the colour the
+//     later Gaussians add, grows by c_i alpha_i T_i.  A pair's nine gradient terms are
+//     summed over the wave (a reduce-scatter with lane swaps, then DPP row sums) and nine
+//     lanes add them to the Gaussian's gradients, one hardware FP32 atomic add each (the
+//     buffers are ordinary device memory).
 #include "gs_backward.hpp"
 
 namespace gsi {
@@ -23,7 +23,7 @@ struct BwdShared {
   float4 a[kBlock];   // (u, v, -a/2 log2e, -b log2e): centre relative to the tile, power rows
   float4 b[kBlock];   // (-c/2 log2e, log2 o, r, g)
   float4 c[kBlock];   // (b colour, conic a, conic b, conic c)
-  float2 d[kBlock];   // (opacity, Gaussian index bits)
+  float2 d[kBlock];   // (1 / opacity, Gaussian index bits)
   uint32_t last;      // end of the longest blended prefix of the tile's pixels
 };
 
@@ -88,7 +88,7 @@ __device__ __forceinline__ void stage(const BackwardJob &J, BwdShared &sm, uint3
     sm.a[t] = make_float4((float)(m.x - ox), (float)(m.y - oy), -0.5f * kLog2e * co.x, -kLog2e * co.y);
     sm.b[t] = make_float4(-0.5f * kLog2e * co.z, __log2f(co.w), cl.x, cl.y);
     sm.c[t] = make_float4(cl.z, co.x, co.y, co.z);
-    sm.d[t] = make_float2(co.w, __uint_as_float(g));
+    sm.d[t] = make_float2(1.0f / co.w, __uint_as_float(g));
   }
 }
 
@@ -158,10 +158,10 @@ __global__ __launch_bounds__(kBlock) void k_raster_backward(BackwardJob J) {
       float v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
       if (act) {
         const float4 Cc = sm.c[j];
-        const float op = sm.d[j].x;
+        const float rop = sm.d[j].x;
         const float raw = __builtin_amdgcn_exp2f(D);
         const float al = fminf(kAlphaMax, raw);
-        const float inv = 1.0f / (1.0f - al);
+        const float inv = __builtin_amdgcn_rcpf(1.0f - al);   // 1 - alpha >= 0.01
         const float Ti = T * inv;
         const float wgt = al * Ti;
         v[0] = gp0 * wgt;
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_backward(BackwardJob J) {
         const float dLda = gp0 * (B.z * Ti - (S0 + bT0) * inv) + gp1 * (B.w * Ti - (S1 + bT1) * inv) +
                            gp2 * (Cc.x * Ti - (S2 + bT2) * inv);
         const float dLdp = raw < kAlphaMax ? dLda * al : 0.0f;
-        v[3] = dLdp / op;
+        v[3] = dLdp * rop;
         v[4] = -0.5f * dx * dx * dLdp;
         v[5] = -dx * dy * dLdp;
         v[6] = -0.5f * dy * dy * dLdp;

@@ -14,8 +14,8 @@ Bar, per gradient field: max |gpu - ref| <= 2e-5 max|ref| + 2e-5 |ref| and relat
 <= 1e-5 (measured: below 1e-6 relative to the field's largest value, L2 below 1e-6).  The
 kernel evaluates the power as the FP32 rasterizer does (alpha to ~1e-6
 relative, from the FP32 offset to the centre and the exp2 of the scaled quadratic), recovers
-T_i = T_{i+1} / (1 - alpha_i) with ~1.5 ulp per step, and sums over pixels in FP32 with
-atomics in no fixed order; the terms (1 - alpha)^-1 reach 100 for clamped alphas."""
+T_i = T_{i+1} / (1 - alpha_i) with ~2.5 ulp per step (hardware reciprocal), and sums over
+pixels in FP32 with atomics in no fixed order; the terms (1 - alpha)^-1 reach 100 for clamped alphas."""
 import numpy as np
 import pytest
 
