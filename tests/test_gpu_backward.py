@@ -195,3 +195,33 @@ def test_backward_headline_sampled_tiles():
     got = _gpu_backward(proj, bins, cam, dimg, bg, sc.n)
     _compare("1M sampled", got, ref)
     assert int(start[-1]) > 5000
+
+
+def test_backward_conservation_full_size():
+    """1M Gaussians at 1920x1080 on the library's own bins: with every colour and the
+    background equal to 1 the image is 1 at every pixel whatever the opacities and shapes
+    (sum alpha_i T_i + T_end = 1), so the opacity, conic and centre gradients vanish, to FP32
+    rounding, while with the scene's own colours they do not.  Fails if the later Gaussians'
+    term, the background term or the transmittance recovery is wrong anywhere on the path."""
+    import torch
+    note("backward conservation 1M 1080p")
+    sc, cam = scenes.clustered_1m()
+    ds = gs.DeviceScene(sc)
+    r = gs.Renderer(sc.n, cam.width, cam.height)
+    opt = gs.options(precision="fp32", bg=(1.0, 1.0, 1.0))
+    r.render(ds, cam, opt)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(72)
+    d = torch.randn((3, cam.height, cam.width), generator=gen, device="cuda")
+    own = gs.Grads(sc.n)
+    gs.gs_rasterize_backward(r.proj, r.bins, cam, opt, d, own)
+    r.proj.rgb[:, :3] = 1.0
+    ones = gs.Grads(sc.n)
+    gs.gs_rasterize_backward(r.proj, r.bins, cam, opt, d, ones)
+    torch.cuda.synchronize()
+    assert torch.allclose(ones.rgb, own.rgb, rtol=1e-4, atol=1e-4 * float(own.rgb.abs().max()))
+    for f in ("opacity", "conic", "xy"):
+        scale = float(getattr(own, f).abs().max())
+        resid = float(getattr(ones, f).abs().max())
+        print(f"conservation {f}: max |grad| with scene colours {scale:.3e}, with colours 1 {resid:.3e}")
+        assert scale > 0 and resid <= 1e-4 * scale, (f, scale, resid)

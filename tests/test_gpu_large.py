@@ -71,7 +71,15 @@ def test_3m_groups_and_precisions(three_m, prec):
         del out
     if prec != "fp32":
         for group in (2, 4, 8):
-            assert np.array_equal(images[1], images[group]), group
+            diff = np.any(images[1] != images[group], axis=0)
+            if diff.any():
+                ys, xs = np.nonzero(diff)
+                tx = (cam.width + 15) // 16
+                print(f"G1 vs G{group}: {int(diff.sum())} differing pixels, first (y, x) "
+                      f"{list(zip(ys[:8].tolist(), xs[:8].tolist()))}, tiles "
+                      f"{sorted(set((ys // 16 * tx + xs // 16).tolist()))[:8]}, max abs "
+                      f"{float(np.abs(images[1] - images[group]).max()):.3e}", flush=True)
+            assert not diff.any(), group
 
 
 def test_dense_6m_stress():
