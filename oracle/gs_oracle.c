@@ -435,3 +435,144 @@ void oracle_composite(int W, int H, const double *xy, const double *depth, const
   for (int i = 0; i < nthreads; ++i) pthread_join(th[i], NULL);
   free(th); free(jobs);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Admissible results of a pixel whose decisions fall in a guard band.       */
+/* ------------------------------------------------------------------------ */
+/* A decision inside a guard band is one that exact arithmetic takes one way and FP32
+ * arithmetic may take the other, so several images are correct there (each is the plain
+ * definition applied to inputs within rounding of the true ones).  For one pixel this
+ * enumerates them: every combination of
+ *   - tile membership of a Gaussian whose footprint edge or near-plane distance lies in its
+ *     guard band (the tile's ambiguous-membership set): listed or not;
+ *   - the 1/255 cut when |ln alpha - ln(1/255)| is inside its band: skipped or blended;
+ *   - the 1e-4 stop when |ln T' - ln 1e-4| is inside its band: stop or blend;
+ *   - two consecutive contributing Gaussians whose depths differ by less than the depth band:
+ *     either order;
+ * each composited front to back exactly as composite_tile does.  Only Gaussians whose
+ * ln alpha reaches the cut's band at this pixel take part: the others contribute nothing
+ * under any reading. */
+typedef struct {
+  int64_t id;
+  double z, lnal, alpha;
+  int optional;
+} or_cand;
+
+typedef struct {
+  double px, py;
+  const double *rgb, *bg;
+  double *out;       /* max_alt x 4: colour with background, T_final */
+  int max_alt, n_out, overflow;
+} or_alt_ctx;
+
+static int cmp_cand(const void *pa, const void *pb) {
+  const or_cand *a = (const or_cand *)pa, *b = (const or_cand *)pb;
+  if (a->z < b->z) return -1;
+  if (a->z > b->z) return 1;
+  return (a->id > b->id) - (a->id < b->id);
+}
+
+static void alt_emit(or_alt_ctx *X, double T, const double *C) {
+  if (X->n_out >= X->max_alt) { X->overflow = 1; return; }
+  double *o = X->out + 4 * (size_t)X->n_out++;
+  for (int ch = 0; ch < 3; ++ch) o[ch] = C[ch] + T * X->bg[ch];
+  o[3] = T;
+}
+
+/* walks seq[i..m) from (T, C); `noswap` = first position whose swap with its successor was
+ * already taken by the caller (so it is not offered again) */
+static void alt_walk(or_alt_ctx *X, or_cand *seq, int m, int i, double T, const double *Cin, int noswap) {
+  const double lnamin = log(OR_ALPHA_MIN), lntmin = log(OR_T_MIN);
+  double C[3] = {Cin[0], Cin[1], Cin[2]};
+  for (; i < m; ++i) {
+    if (X->overflow) return;
+    or_cand *a = &seq[i];
+    /* order of two near-equal depths */
+    if (i != noswap && i + 1 < m && seq[i + 1].z - a->z < OR_GUARD_Z * a->z) {
+      or_cand *sw = (or_cand *)malloc(sizeof(or_cand) * (size_t)(m - i));
+      memcpy(sw, seq + i, sizeof(or_cand) * (size_t)(m - i));
+      or_cand t = sw[0]; sw[0] = sw[1]; sw[1] = t;
+      alt_walk(X, sw, m - i, 0, T, C, 0);
+      free(sw);
+      if (X->overflow) return;
+    }
+    /* membership */
+    if (a->optional) {
+      alt_walk(X, seq, m, i + 1, T, C, noswap > i + 1 ? noswap : -1);   /* not listed */
+      if (X->overflow) return;
+    }
+    /* the 1/255 cut */
+    int blend;
+    if (fabs(a->lnal - lnamin) < OR_GUARD_LNA) {
+      alt_walk(X, seq, m, i + 1, T, C, -1);   /* skipped */
+      if (X->overflow) return;
+      blend = 1;
+    } else {
+      blend = a->alpha >= OR_ALPHA_MIN;
+    }
+    if (!blend) continue;
+    double Tn = T * (1.0 - a->alpha);
+    int stop;
+    if (fabs(log(Tn) - lntmin) < OR_GUARD_LNT) {
+      alt_emit(X, T, C);                      /* stopped here */
+      if (X->overflow) return;
+      stop = 0;
+    } else {
+      stop = Tn < OR_T_MIN;
+    }
+    if (stop) { alt_emit(X, T, C); return; }
+    for (int ch = 0; ch < 3; ++ch) C[ch] += a->alpha * T * X->rgb[3 * a->id + ch];
+    T = Tn;
+  }
+  alt_emit(X, T, C);
+}
+
+/* For each pixel pix[q] (row-major index), writes up to max_alt results to
+ * out[(q * max_alt + k) * 4 + (0..2: colour with background, 3: T_final)] and their number to
+ * nout[q], or -1 when there are more than max_alt. */
+void oracle_alternatives(int W, int H, const double *xy, const double *depth, const double *conic,
+                         const double *rgb, const double *opacity, const int64_t *start, const int64_t *ids,
+                         const int64_t *astart, const int64_t *aids, const double *bg, int64_t npix,
+                         const int64_t *pix, int max_alt, double *out, int32_t *nout) {
+  const double lnamin = log(OR_ALPHA_MIN);
+  int TX = (W + OR_TILE - 1) / OR_TILE;
+  for (int64_t q = 0; q < npix; ++q) {
+    int px_i = (int)(pix[q] % W), py_i = (int)(pix[q] / W);
+    int64_t tile = (int64_t)(py_i / OR_TILE) * TX + px_i / OR_TILE;
+    int64_t s = start[tile], e = start[tile + 1], as = astart[tile], ae = astart[tile + 1];
+    or_cand *seq = (or_cand *)malloc(sizeof(or_cand) * (size_t)(e - s + ae - as + 1));
+    int m = 0;
+    double px = px_i + 0.5, py = py_i + 0.5;
+    for (int64_t k = s; k < e + (ae - as); ++k) {
+      int64_t g;
+      int optional = 0;
+      if (k < e) {
+        g = ids[k];
+        for (int64_t u = as; u < ae; ++u) if (aids[u] == g) optional = 1;
+      } else {
+        g = aids[as + (k - e)];
+        int listed = 0;
+        for (int64_t u = s; u < e; ++u) if (ids[u] == g) { listed = 1; break; }
+        if (listed) continue;
+        optional = 1;
+      }
+      double dx = px - xy[2 * g], dy = py - xy[2 * g + 1];
+      double a = conic[3 * g], b = conic[3 * g + 1], c = conic[3 * g + 2];
+      double power = -0.5 * (a * dx * dx + 2.0 * b * dx * dy + c * dy * dy);
+      double lnal = log(opacity[g]) + power;
+      if (lnal < lnamin - OR_GUARD_LNA) continue;   /* never contributes here */
+      or_cand *cd = &seq[m++];
+      cd->id = g; cd->z = depth[g]; cd->lnal = lnal; cd->optional = optional;
+      cd->alpha = fmin(OR_ALPHA_MAX, opacity[g] * exp(power));
+    }
+    qsort(seq, (size_t)m, sizeof(or_cand), cmp_cand);
+    or_alt_ctx X;
+    X.px = px; X.py = py; X.rgb = rgb; X.bg = bg;
+    X.out = out + (size_t)q * (size_t)max_alt * 4;
+    X.max_alt = max_alt; X.n_out = 0; X.overflow = 0;
+    const double C0[3] = {0.0, 0.0, 0.0};
+    alt_walk(&X, seq, m, 0, 1.0, C0, -1);
+    nout[q] = X.overflow ? -1 : X.n_out;
+    free(seq);
+  }
+}

@@ -75,6 +75,9 @@ def lib():
                                            _i64p, _i64p, _dp, C.c_int, C.c_void_p, C.c_int64,
                                            _dp, _dp, _dp, _i64p, _u8p]
             L.oracle_composite.restype = None
+            L.oracle_alternatives.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _i64p, _i64p,
+                                              _i64p, _i64p, _dp, C.c_int64, _i64p, C.c_int, _dp, _i32p]
+            L.oracle_alternatives.restype = None
             _lib = L
     return _lib
 
@@ -284,6 +287,54 @@ def composite(rec: dict, cam, start, ids, bg=(0.0, 0.0, 0.0), nthreads: int = 1,
                            None if sel is None else sel.ctypes.data, 0 if sel is None else sel.size,
                            image, tfinal, wsum, neval, ambig)
     return dict(image=image, tfinal=tfinal, wsum=wsum, neval=neval, ambiguous=ambig)
+
+
+def alternatives(rec: dict, cam, start, ids, pixels, bg=(0.0, 0.0, 0.0), amb=None, max_alt: int = 64):
+    """Every admissible result of the given pixels (row-major indices) under the readings of
+    the decisions that fall inside a guard band (1/255 cut, 1e-4 stop, order of near-equal
+    depths, tile membership at a footprint edge or the near plane): each combination of the
+    two ways of taking them, composited from the definition as `composite` does.
+    Returns (results (npix, max_alt, 4): colour with background and T_final; counts (npix,):
+    the number of results, or -1 when there are more than max_alt)."""
+    W, H = cam.width, cam.height
+    if amb is None:
+        amb = ambiguous_membership(rec, cam)
+    astart, aids = amb
+    pix = np.ascontiguousarray(pixels, np.int64).ravel()
+    out = np.zeros((max(pix.size, 1), max_alt, 4))
+    cnt = np.zeros(max(pix.size, 1), np.int32)
+    if pix.size:
+        lib().oracle_alternatives(W, H, np.ascontiguousarray(rec["xy"]), rec["depth"],
+                                  np.ascontiguousarray(rec["conic"]), np.ascontiguousarray(rec["rgb"]),
+                                  rec["opacity"], start,
+                                  np.ascontiguousarray(ids if ids.size else np.zeros(1, np.int64)), astart, aids,
+                                  np.ascontiguousarray(bg, np.float64), pix.size, pix, int(max_alt), out, cnt)
+    return out[: pix.size], cnt[: pix.size]
+
+
+def check_flagged(image, tfinal, rec: dict, cam, start, ids, ambiguous, bg=(0.0, 0.0, 0.0), tol_img: float = 1e-4,
+                  tol_t: float = 1e-5, amb=None, max_alt: int = 64) -> dict:
+    """Checks a renderer's pixels that the oracle flagged (a decision inside a guard band):
+    each must be within tol_img per channel (and tol_t in T_final, if given) of one of that
+    pixel's admissible results.  image (3, H, W), tfinal (H, W) or None, ambiguous (H, W) from
+    `composite`.  Returns counts: checked, matched, failed, unresolved (more than max_alt
+    readings: left unchecked) and the flagged pixels' indices by outcome."""
+    W = cam.width
+    pix = np.flatnonzero(np.asarray(ambiguous) != 0)
+    alts, cnt = alternatives(rec, cam, start, ids, pix, bg, amb, max_alt)
+    img = np.asarray(image).reshape(3, -1)[:, pix].T          # (P, 3)
+    d = np.abs(alts[:, :, :3] - img[:, None, :]).max(axis=2)  # (P, A)
+    ok = d <= tol_img
+    if tfinal is not None:
+        t = np.asarray(tfinal).ravel()[pix]
+        ok &= np.abs(alts[:, :, 3] - t[:, None]) <= tol_t
+    valid = np.arange(max_alt)[None, :] < np.maximum(cnt, 0)[:, None]
+    matched = (ok & valid).any(axis=1) & (cnt > 0)
+    unresolved = cnt < 0
+    failed = ~matched & ~unresolved
+    return dict(checked=int(pix.size), matched=int(matched.sum()), failed=int(failed.sum()),
+                unresolved=int(unresolved.sum()), failed_pixels=pix[failed], unresolved_pixels=pix[unresolved],
+                width=W)
 
 
 def render(scene, cam, bg=(0.0, 0.0, 0.0), nthreads: int = 1) -> dict:

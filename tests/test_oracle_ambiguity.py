@@ -1,0 +1,251 @@
+"""Pins of the oracle's guard bands and of the admissible results it enumerates for the pixels
+whose decisions fall inside them (oracle.alternatives, oracle.check_flagged).
+
+A decision inside a band is one that FP32 inputs may take the other way (the 1/255 cut on
+alpha, the 1e-4 stop on T, the order of near-equal depths, a footprint edge at a tile boundary
+or a depth at the near plane; Background: alpha = min(0.99, o exp(power)), the cut and the stop;
+"Gaussian sorting" by depth), so the image there has several correct values.  Each case below
+is built so that one decision sits inside (or well outside) its band, and the admissible results
+are checked against the closed form of the front-to-back blend (Porter-Duff "over")."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2605_17855_amd import scenes
+
+
+def _scene(means, log_scales, opac, rgb):
+    """Camera-space Gaussians (identity rotation), SH degree 0 from the colours."""
+    means = np.asarray(means, np.float64).reshape(-1, 3).T
+    n = means.shape[1]
+    y00 = 0.28209479177387814
+    sh = ((np.asarray(rgb, np.float64).reshape(n, 3).T - 0.5) / y00)[None]
+    return scenes.Scene(means.astype(np.float32), np.asarray(log_scales, np.float32).reshape(n, 3).T.copy(),
+                        np.tile(np.array([[1.0], [0.0], [0.0], [0.0]], np.float32), (1, n)),
+                        np.asarray(opac, np.float32), sh.astype(np.float32), 0)
+
+
+def _centred(cam, z, px=8, py=8):
+    """Camera-space centre that projects onto the centre of pixel (px, py)."""
+    return [(px + 0.5 - cam.cx) * z / cam.fx, (py + 0.5 - cam.cy) * z / cam.fy, z]
+
+
+def _edge_at(cam, z, log_scale, edge_x, my, side=1.0):
+    """Camera-space centre whose footprint edge mu'_x + side * r lands on edge_x (the radius
+    depends on the lateral position through the Jacobian, so the placement is iterated)."""
+    mx = edge_x
+    for _ in range(30):
+        mean = [(mx - cam.cx) * z / cam.fx, (my - cam.cy) * z / cam.fy, z]
+        rec = oracle.preprocess(_scene([mean], [[log_scale] * 3], [0.9], [[0.5, 0.5, 0.5]]), cam)
+        err = rec["xy"][0, 0] + side * rec["radius"][0] - edge_x
+        if abs(err) < 1e-7:
+            break
+        mx -= err
+    return mean
+
+
+def _render(sc, cam, bg=(0.0, 0.0, 0.0)):
+    out = oracle.render(sc, cam, bg=bg)
+    return out, out["records"]
+
+
+def _alts(out, rec, cam, y, x, bg=(0.0, 0.0, 0.0)):
+    alts, cnt = oracle.alternatives(rec, cam, out["start"], out["ids"], [y * cam.width + x], bg)
+    assert cnt[0] > 0
+    return alts[0, :cnt[0]]
+
+
+def _has(alts, colour, T, tol=1e-12):
+    return bool(np.any((np.abs(alts[:, :3] - colour).max(axis=1) <= tol) & (np.abs(alts[:, 3] - T) <= tol)))
+
+
+def _op(x):
+    return float(np.float32(x))
+
+
+def _colours(rec, idx):
+    return [np.asarray(rec["rgb"][i]) for i in idx]
+
+
+@pytest.mark.parametrize("factor,flagged", [(1.0005, True), (0.9995, True), (1.05, False), (0.95, False)])
+def test_stop_band(factor, flagged):
+    """Three co-centred Gaussians, alphas 0.98, 0.98 and a3 with (1 - 0.98)^2 (1 - a3) =
+    1e-4 * factor: inside the band |ln T' - ln 1e-4| < 2e-3 the pixel is flagged and both the
+    stopped and the blended result are admissible; outside it only the rule's result is."""
+    cam = scenes.pinhole(16, 16, 60.0)
+    a3 = _op(1.0 - 1e-4 * factor / (0.02 * 0.02))
+    ops = [0.98, 0.98, a3]
+    rgbs = [[0.9, 0.1, 0.2], [0.2, 0.8, 0.1], [0.1, 0.3, 0.95]]
+    sc = _scene([_centred(cam, z) for z in (2.0, 3.0, 4.0)], [[math.log(0.02)] * 3] * 3, ops, rgbs)
+    out, rec = _render(sc, cam)
+    assert bool(out["ambiguous"][8, 8] & oracle.PIX_T) == flagged
+    al = [float(np.float32(o)) for o in ops]
+    c = _colours(rec, range(3))
+    T1, T2 = 1 - al[0], (1 - al[0]) * (1 - al[1])
+    stopped = al[0] * c[0] + T1 * al[1] * c[1]
+    blended = stopped + T2 * al[2] * c[2]
+    T3 = T2 * (1 - al[2])
+    A = _alts(out, rec, cam, 8, 8)
+    rule_stops = T3 < 1e-4
+    assert _has(A, stopped if rule_stops else blended, T2 if rule_stops else T3, 1e-9)
+    assert _has(A, blended if rule_stops else stopped, T3 if rule_stops else T2, 1e-9) == flagged
+    assert len(A) == (2 if flagged else 1)
+
+
+@pytest.mark.parametrize("rel,flagged", [(1.2e-7, True), (5e-7, True), (1e-2, False)])
+def test_depth_tie_band(rel, flagged):
+    """Two co-centred Gaussians whose depths differ by `rel` (relative): inside the 1e-6 band
+    either order is admissible (the GPU orders by the FP32 bits of depth, ties by index);
+    both "over" results then appear, with the rule's own order among them."""
+    cam = scenes.pinhole(16, 16, 60.0)
+    z1 = 2.0
+    z2 = float(np.float32(z1 * (1 + rel)))
+    if z2 == z1:
+        z2 = float(np.nextafter(np.float32(z1), np.float32(3.0)))
+    sc = _scene([_centred(cam, z1), _centred(cam, z2)], [[math.log(0.02)] * 3] * 2, [0.6, 0.7],
+                [[0.9, 0.1, 0.2], [0.1, 0.2, 0.9]])
+    out, rec = _render(sc, cam)
+    assert bool(out["ambiguous"][8, 8] & oracle.PIX_TIE) == flagged
+    a1, a2 = _op(0.6), _op(0.7)
+    c1, c2 = _colours(rec, (0, 1))
+    front_first = a1 * c1 + (1 - a1) * a2 * c2      # Gaussian 0 nearer
+    back_first = a2 * c2 + (1 - a2) * a1 * c1
+    T = (1 - a1) * (1 - a2)
+    A = _alts(out, rec, cam, 8, 8)
+    assert _has(A, front_first, T, 1e-12)
+    assert _has(A, back_first, T, 1e-12) == flagged
+    assert np.allclose(out["image"][:, 8, 8], front_first, atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("offset,flagged", [(5e-4, True), (-5e-4, True), (0.05, False)])
+def test_membership_band(offset, flagged):
+    """A wide Gaussian whose footprint's right edge mu'_x + r lies `offset` px from the tile
+    boundary x = 16: inside the 1e-3 px band it may or may not be listed in tile 1, so it is in
+    that tile's ambiguous-membership set, the pixel (8, 16) where its alpha passes the cut is
+    flagged, and both the listed and the unlisted result are admissible."""
+    cam = scenes.pinhole(32, 16, 60.0)
+    z = 2.0
+    ls = math.log(0.2)
+    mean = _edge_at(cam, z, ls, 16.0 + offset, 8.5)
+    sc = _scene([mean], [[ls] * 3], [0.99], [[0.8, 0.6, 0.4]])
+    out, rec = _render(sc, cam)
+    edge = rec["xy"][0, 0] + rec["radius"][0]
+    assert abs(edge - (16.0 + offset)) < 1e-5
+    assert bool(rec["flags"][0] & oracle.AMB_EDGES) == flagged
+    astart, aids = oracle.ambiguous_membership(rec, cam)
+    assert (0 in aids[astart[1]:astart[2]].tolist()) == flagged      # tile 1 = (tx 1, ty 0)
+    assert 0 not in aids[astart[0]:astart[1]].tolist()               # tile 0 holds it either way
+    listed = 0 in out["ids"][out["start"][1]:out["start"][2]].tolist()
+    assert listed == (offset > 0)
+    # alpha at pixel (8, 16) reaches the cut, so membership decides the pixel
+    dx, dy = 16.5 - rec["xy"][0, 0], 8.5 - rec["xy"][0, 1]
+    a, b, c = rec["conic"][0]
+    al = min(0.99, _op(0.99) * math.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy)))
+    assert al > 1 / 255
+    assert bool(out["ambiguous"][8, 16] & oracle.PIX_MEMBER) == flagged
+    A = _alts(out, rec, cam, 8, 16)
+    col = np.asarray(rec["rgb"][0])
+    assert _has(A, al * col, 1 - al, 1e-12) == (flagged or listed)
+    assert _has(A, np.zeros(3), 1.0, 0.0) == (flagged or not listed)
+
+
+def test_alpha_cut_band_alternatives():
+    """The 1/255 cut inside its band: both the skipped (background) and the blended result."""
+    cam = scenes.pinhole(16, 16, 60.0)
+    o = _op(1 / 255 * (1 + 3e-5))
+    sc = _scene([_centred(cam, 2.0)], [[math.log(0.02)] * 3], [o], [[0.7, 0.5, 0.3]])
+    out, rec = _render(sc, cam, bg=(0.1, 0.2, 0.3))
+    assert out["ambiguous"][8, 8] & oracle.PIX_ALPHA
+    A = _alts(out, rec, cam, 8, 8, bg=(0.1, 0.2, 0.3))
+    col, bg = np.asarray(rec["rgb"][0]), np.array([0.1, 0.2, 0.3])
+    assert _has(A, bg, 1.0, 0.0)
+    assert _has(A, o * col + (1 - o) * bg, 1 - o, 1e-12)
+
+
+def test_near_plane_membership():
+    """A Gaussian at depth znear + 5e-7 (inside the 1e-6 band): listed by the rule, but its
+    membership is ambiguous in every tile of its footprint."""
+    cam = scenes.pinhole(32, 32, 60.0)
+    z = float(np.float32(cam.znear + 5e-7))
+    sc = _scene([[0.0, 0.0, z]], [[math.log(0.001)] * 3], [0.9], [[0.5, 0.5, 0.5]])
+    out, rec = _render(sc, cam)
+    assert rec["flags"][0] & oracle.AMB_ZNEAR
+    astart, aids = oracle.ambiguous_membership(rec, cam)
+    x0, y0, x1, y1 = rec["rect"][0]
+    tx = (cam.width + 15) // 16
+    for ty in range(y0, y1):
+        for txx in range(x0, x1):
+            t = ty * tx + txx
+            assert 0 in aids[astart[t]:astart[t + 1]].tolist()
+
+
+def test_ambiguous_membership_by_brute_force():
+    """Every (Gaussian, tile) pair whose membership changes when the footprint edges move by
+    +-1e-3 px is in ambiguous_membership, and no other pair is (Gaussians clear of the near
+    plane).  Footprints are placed with edges on, near and away from tile boundaries."""
+    cam = scenes.pinhole(96, 64, 60.0)
+    rng = np.random.default_rng(8)
+    z = 2.0
+    ls = math.log(0.1)
+    means = []
+    for k in range(60):
+        ex = 16.0 * rng.integers(1, 6) + rng.choice([0.0, 4e-4, -4e-4, 0.3, -2e-3])
+        my = 16.0 * rng.integers(1, 4) + rng.choice([0.0, 6e-4, -6e-4, 0.7, 5.0])
+        means.append(_edge_at(cam, z, ls, ex, my, side=1.0 if rng.random() < 0.5 else -1.0))
+    n = len(means)
+    sc = _scene(means, [[ls] * 3] * n, [0.9] * n, [[0.5, 0.5, 0.5]] * n)
+    rec = oracle.preprocess(sc, cam)
+    astart, aids = oracle.ambiguous_membership(rec, cam)
+    tx_n, ty_n = 6, 4
+    eps = 1e-3
+    for g in range(n):
+        mx, my = rec["xy"][g]
+        rr = rec["radius"][g]
+        for ty in range(ty_n):
+            for tx in range(tx_n):
+                def member(e):
+                    return (mx - rr - e < 16 * tx + 16 and mx + rr + e >= 16 * tx and
+                            my - rr - e < 16 * ty + 16 and my + rr + e >= 16 * ty)
+                flips = member(eps) != member(-eps)
+                t = ty * tx_n + tx
+                listed = g in aids[astart[t]:astart[t + 1]].tolist()
+                assert listed == flips, (g, tx, ty)
+
+
+@pytest.mark.parametrize("workload", ["small", "world"])
+def test_alternatives_reduce_to_composite(workload):
+    """Unflagged pixels have exactly one admissible result, bit-identical to `composite`;
+    at flagged pixels the rule's own result is one of the admissible ones (bitwise)."""
+    if workload == "small":
+        sc, cam = scenes.small_camera_space()
+    else:
+        sc = scenes.clustered_scene(60000, seed=19, clusters=8, half_box=2.0)
+        cam = scenes.look_at([3.0, -2.0, 1.0], 200, 120)
+    out = oracle.render(sc, cam, nthreads=4)
+    rec = out["records"]
+    amb = out["ambiguous"].ravel()
+    unf = np.flatnonzero(amb == 0)
+    alts, cnt = oracle.alternatives(rec, cam, out["start"], out["ids"], unf)
+    assert np.all(cnt == 1)
+    assert np.array_equal(alts[:, 0, :3], out["image"].reshape(3, -1)[:, unf].T)
+    assert np.array_equal(alts[:, 0, 3], out["tfinal"].ravel()[unf])
+    r = oracle.check_flagged(out["image"], out["tfinal"], rec, cam, out["start"], out["ids"], out["ambiguous"],
+                             tol_img=0.0, tol_t=0.0)
+    assert r["failed"] == 0 and r["matched"] + r["unresolved"] == r["checked"]
+    assert r["unresolved"] <= 1e-3 * amb.size
+
+
+def test_check_flagged_rejects_a_wrong_pixel():
+    """A flagged pixel whose value matches none of its admissible results is reported."""
+    cam = scenes.pinhole(16, 16, 60.0)
+    o = _op(1 / 255 * (1 + 3e-5))
+    sc = _scene([_centred(cam, 2.0)], [[math.log(0.02)] * 3], [o], [[0.7, 0.5, 0.3]])
+    out, rec = _render(sc, cam)
+    img = out["image"].copy()
+    img[1, 8, 8] += 5e-3
+    r = oracle.check_flagged(img, None, rec, cam, out["start"], out["ids"], out["ambiguous"])
+    assert r["failed"] == 1 and r["failed_pixels"].tolist() == [8 * 16 + 8]
+    r = oracle.check_flagged(out["image"], None, rec, cam, out["start"], out["ids"], out["ambiguous"])
+    assert r["failed"] == 0 and r["matched"] == r["checked"] >= 1
