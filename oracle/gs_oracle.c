@@ -447,14 +447,17 @@ void oracle_composite(int W, int H, const double *xy, const double *depth, const
  *     guard band (the tile's ambiguous-membership set): listed or not;
  *   - the 1/255 cut when |ln alpha - ln(1/255)| is inside its band: skipped or blended;
  *   - the 1e-4 stop when |ln T' - ln 1e-4| is inside its band: stop or blend;
- *   - two consecutive contributing Gaussians whose depths differ by less than the depth band:
- *     either order;
+ *   - the depth order: by (depth, index), the definition, or by (depth rounded to FP32, index),
+ *     the order of 32-bit depth keys (FP32 rounding is monotone, so the two differ only where
+ *     Gaussians whose depths round to the same FP32 value are not in index order; the pixel is
+ *     flagged by the wider OR_GUARD_Z band);
  * each composited front to back exactly as composite_tile does.  Only Gaussians whose
  * ln alpha reaches the cut's band at this pixel take part: the others contribute nothing
  * under any reading. */
 typedef struct {
   int64_t id;
   double z, lnal, alpha;
+  float z32;
   int optional;
 } or_cand;
 
@@ -472,6 +475,13 @@ static int cmp_cand(const void *pa, const void *pb) {
   return (a->id > b->id) - (a->id < b->id);
 }
 
+static int cmp_cand32(const void *pa, const void *pb) {
+  const or_cand *a = (const or_cand *)pa, *b = (const or_cand *)pb;
+  if (a->z32 < b->z32) return -1;
+  if (a->z32 > b->z32) return 1;
+  return (a->id > b->id) - (a->id < b->id);
+}
+
 static void alt_emit(or_alt_ctx *X, double T, const double *C) {
   if (X->n_out >= X->max_alt) { X->overflow = 1; return; }
   double *o = X->out + 4 * (size_t)X->n_out++;
@@ -479,32 +489,22 @@ static void alt_emit(or_alt_ctx *X, double T, const double *C) {
   o[3] = T;
 }
 
-/* walks seq[i..m) from (T, C); `noswap` = first position whose swap with its successor was
- * already taken by the caller (so it is not offered again) */
-static void alt_walk(or_alt_ctx *X, or_cand *seq, int m, int i, double T, const double *Cin, int noswap) {
+/* walks seq[i..m) from (T, C) */
+static void alt_walk(or_alt_ctx *X, const or_cand *seq, int m, int i, double T, const double *Cin) {
   const double lnamin = log(OR_ALPHA_MIN), lntmin = log(OR_T_MIN);
   double C[3] = {Cin[0], Cin[1], Cin[2]};
   for (; i < m; ++i) {
     if (X->overflow) return;
-    or_cand *a = &seq[i];
-    /* order of two near-equal depths */
-    if (i != noswap && i + 1 < m && seq[i + 1].z - a->z < OR_GUARD_Z * a->z) {
-      or_cand *sw = (or_cand *)malloc(sizeof(or_cand) * (size_t)(m - i));
-      memcpy(sw, seq + i, sizeof(or_cand) * (size_t)(m - i));
-      or_cand t = sw[0]; sw[0] = sw[1]; sw[1] = t;
-      alt_walk(X, sw, m - i, 0, T, C, 0);
-      free(sw);
-      if (X->overflow) return;
-    }
+    const or_cand *a = &seq[i];
     /* membership */
     if (a->optional) {
-      alt_walk(X, seq, m, i + 1, T, C, noswap > i + 1 ? noswap : -1);   /* not listed */
+      alt_walk(X, seq, m, i + 1, T, C);   /* not listed */
       if (X->overflow) return;
     }
     /* the 1/255 cut */
     int blend;
     if (fabs(a->lnal - lnamin) < OR_GUARD_LNA) {
-      alt_walk(X, seq, m, i + 1, T, C, -1);   /* skipped */
+      alt_walk(X, seq, m, i + 1, T, C);   /* skipped */
       if (X->overflow) return;
       blend = 1;
     } else {
@@ -562,7 +562,7 @@ void oracle_alternatives(int W, int H, const double *xy, const double *depth, co
       double lnal = log(opacity[g]) + power;
       if (lnal < lnamin - OR_GUARD_LNA) continue;   /* never contributes here */
       or_cand *cd = &seq[m++];
-      cd->id = g; cd->z = depth[g]; cd->lnal = lnal; cd->optional = optional;
+      cd->id = g; cd->z = depth[g]; cd->z32 = (float)depth[g]; cd->lnal = lnal; cd->optional = optional;
       cd->alpha = fmin(OR_ALPHA_MAX, opacity[g] * exp(power));
     }
     qsort(seq, (size_t)m, sizeof(or_cand), cmp_cand);
@@ -571,7 +571,15 @@ void oracle_alternatives(int W, int H, const double *xy, const double *depth, co
     X.out = out + (size_t)q * (size_t)max_alt * 4;
     X.max_alt = max_alt; X.n_out = 0; X.overflow = 0;
     const double C0[3] = {0.0, 0.0, 0.0};
-    alt_walk(&X, seq, m, 0, 1.0, C0, -1);
+    alt_walk(&X, seq, m, 0, 1.0, C0);
+    /* the order of 32-bit depth keys, where it differs */
+    or_cand *seq32 = (or_cand *)malloc(sizeof(or_cand) * (size_t)(m ? m : 1));
+    memcpy(seq32, seq, sizeof(or_cand) * (size_t)m);
+    qsort(seq32, (size_t)m, sizeof(or_cand), cmp_cand32);
+    int same = 1;
+    for (int k = 0; k < m && same; ++k) same = seq32[k].id == seq[k].id;
+    if (!same) alt_walk(&X, seq32, m, 0, 1.0, C0);
+    free(seq32);
     nout[q] = X.overflow ? -1 : X.n_out;
     free(seq);
   }

@@ -94,29 +94,64 @@ def test_stop_band(factor, flagged):
     assert len(A) == (2 if flagged else 1)
 
 
-@pytest.mark.parametrize("rel,flagged", [(1.2e-7, True), (5e-7, True), (1e-2, False)])
-def test_depth_tie_band(rel, flagged):
-    """Two co-centred Gaussians whose depths differ by `rel` (relative): inside the 1e-6 band
-    either order is admissible (the GPU orders by the FP32 bits of depth, ties by index);
-    both "over" results then appear, with the rule's own order among them."""
+def _posed_pair(cam, d, nudge_ulps):
+    """Two Gaussians centred on pixel (8, 8) under a camera turned about y (so depths are FP64
+    values, not FP32 inputs): index 0 at depth ~d, index 1 moved by `nudge_ulps` FP32 ulps in
+    world x, which moves its depth by a fraction of an FP32 ulp."""
+    th = 0.3
+    R = np.array([[math.cos(th), 0.0, math.sin(th)], [0.0, 1.0, 0.0], [-math.sin(th), 0.0, math.cos(th)]])
+    cam.R = R.astype(np.float32)
+    cam.t = np.zeros(3, np.float32)
+    tc = np.array([(8.5 - cam.cx) * d / cam.fx, (8.5 - cam.cy) * d / cam.fy, d])
+    m0 = (cam.R.astype(np.float64).T @ tc).astype(np.float32)
+    m1 = m0.copy()
+    for _ in range(abs(nudge_ulps)):
+        m1[0] = np.nextafter(m1[0], np.float32(np.sign(nudge_ulps) * 10.0))
+    return [m0.tolist(), m1.tolist()]
+
+
+@pytest.mark.parametrize("case", ["fp32_tie_reversed", "fp32_tie_in_order", "band_distinct_fp32", "apart"])
+def test_depth_order_alternatives(case):
+    """Depth order: the definition orders by (depth, index); 32-bit depth keys order by (depth
+    rounded to FP32, index).  Both are admissible, and differ only for Gaussians whose depths
+    round to the same FP32 value out of index order: then the pixel has both "over" results;
+    otherwise (same FP32 value in index order, distinct FP32 values inside the 1e-6 flag band,
+    or depths far apart) only the definition's."""
     cam = scenes.pinhole(16, 16, 60.0)
-    z1 = 2.0
-    z2 = float(np.float32(z1 * (1 + rel)))
-    if z2 == z1:
-        z2 = float(np.nextafter(np.float32(z1), np.float32(3.0)))
-    sc = _scene([_centred(cam, z1), _centred(cam, z2)], [[math.log(0.02)] * 3] * 2, [0.6, 0.7],
-                [[0.9, 0.1, 0.2], [0.1, 0.2, 0.9]])
+    d = 2.0
+    for nudge in range(1, 200):
+        means = _posed_pair(cam, d, nudge if case != "fp32_tie_in_order" else -nudge)
+        if case == "apart":
+            means[1] = _posed_pair(cam, d * 1.01, 0)[0]
+        sc = _scene(means, [[math.log(0.02)] * 3] * 2, [0.6, 0.7], [[0.9, 0.1, 0.2], [0.1, 0.2, 0.9]])
+        rec = oracle.preprocess(sc, cam)
+        z0, z1 = rec["depth"]
+        same32 = np.float32(z0) == np.float32(z1)
+        if case == "fp32_tie_reversed" and same32 and z1 < z0:
+            break
+        if case == "fp32_tie_in_order" and same32 and z0 < z1:
+            break
+        if case == "band_distinct_fp32" and not same32 and 0 < abs(z1 - z0) < 1e-6 * z0:
+            break
+        if case == "apart":
+            break
+    else:
+        pytest.fail(f"no configuration for {case}")
     out, rec = _render(sc, cam)
-    assert bool(out["ambiguous"][8, 8] & oracle.PIX_TIE) == flagged
-    a1, a2 = _op(0.6), _op(0.7)
-    c1, c2 = _colours(rec, (0, 1))
-    front_first = a1 * c1 + (1 - a1) * a2 * c2      # Gaussian 0 nearer
-    back_first = a2 * c2 + (1 - a2) * a1 * c1
-    T = (1 - a1) * (1 - a2)
+    near, far = (1, 0) if rec["depth"][1] < rec["depth"][0] else (0, 1)
+    an, af = _op([0.6, 0.7][near]), _op([0.6, 0.7][far])
+    cn, cf = _colours(rec, (near, far))
+    by_depth = an * cn + (1 - an) * af * cf
+    by_index = (_op(0.6) * cn + (1 - _op(0.6)) * _op(0.7) * cf) if near == 0 else \
+        (_op(0.6) * cf + (1 - _op(0.6)) * _op(0.7) * cn)
+    T = (1 - an) * (1 - af)
+    assert bool(out["ambiguous"][8, 8] & oracle.PIX_TIE) == (case != "apart")
     A = _alts(out, rec, cam, 8, 8)
-    assert _has(A, front_first, T, 1e-12)
-    assert _has(A, back_first, T, 1e-12) == flagged
-    assert np.allclose(out["image"][:, 8, 8], front_first, atol=1e-12, rtol=0)
+    assert _has(A, by_depth, T, 1e-12)
+    assert np.allclose(out["image"][:, 8, 8], by_depth, atol=1e-12, rtol=0)
+    assert len(A) == (2 if case == "fp32_tie_reversed" else 1)
+    if case == "fp32_tie_reversed":
+        assert _has(A, by_index, T, 1e-12)
 
 
 @pytest.mark.parametrize("offset,flagged", [(5e-4, True), (-5e-4, True), (0.05, False)])
