@@ -35,6 +35,9 @@ METRIC = "frames/s @1080p 1M Gaussians: MFMA-FP16 vs FP32 plain at PSNR≥45dB; 
 FLOPS_PER_EVAL = 14
 FLOPS_PER_BLEND = 9
 PEAK_FP32_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (packed) x 2 (FMA) x 2.4 GHz
+PEAK_FP32_NONPACKED_TFLOPS = 78.6   # the same without packed FP32 (which this build does not emit)
+PEAK_FP16_MFMA_TFLOPS = 2500.0      # dense FP16 / BF16 matrix peak
+POWER_FLOPS = 12                    # the power's 6 multiply-adds, moved onto the matrix cores
 
 # HBM bytes per launch of the rasterizer on this workload (FP16, splits 2, 1x1 groups): rocprofv3
 # FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by what the same counters read for a plain
@@ -49,7 +52,7 @@ def raster_source_hash():
     import hashlib
     from paper_2605_17855_amd import build
     h = hashlib.sha256()
-    for part in (("paper_2605_17855_amd", "csrc", "gs_raster_mfma.hip"),
+    for part in (("paper_2605_17855_amd", "csrc", "gs_raster_mfma.hip"), ("paper_2605_17855_amd", "csrc", "gs_mfma.hpp"),
                  ("paper_2605_17855_amd", "csrc", "gs_internal.hpp"), ("include", "gs.h")):
         with open(os.path.join(ROOT, *part), "rb") as f:
             h.update(f.read())
@@ -88,6 +91,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle compositing time")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-backward", action="store_true", help="skip the backward-pass timing")
+    ap.add_argument("--no-pipelined", action="store_true", help="skip the two-frames-in-flight rate")
+    ap.add_argument("--no-all-rows", action="store_true",
+                    help="skip the MFMA run without quadrant culling (its launches share the kernel's name)")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving workload")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered rate / saturated throughput")
@@ -146,6 +152,37 @@ def timed_frames(gs, torch, ds, cams, rend, opt, steps, warmup):
                            "bin_sort_ms": float(np.mean([e[3].elapsed_time(e[1]) for e in evs])),
                            "rasterize_ms": float(np.mean(raster_ms))}
     return elapsed, frame_ms, raster_ms
+
+
+def pipelined_frames(gs, torch, ds, cams, n, opt, steps, warmup, inflight=2):
+    """Frames/s with `inflight` frames of the orbit in flight at once: frame i runs on stream
+    i % inflight with its own buffers, so one frame's latency-bound sort overlaps another's
+    rasterization (each frame is still the whole path, and the host still waits once per frame
+    for its entry count)."""
+    streams = [torch.cuda.Stream() for _ in range(inflight)]
+    rends = [gs.Renderer(n, 1920, 1080, group=opt.group) for _ in range(inflight)]
+    for k in range(inflight):
+        with torch.cuda.stream(streams[k]):
+            for cam in cams[:max(steps, warmup, 1)]:
+                rends[k].render(ds, cam, opt, stream=streams[k])
+    torch.cuda.synchronize()
+
+    def frame(i):
+        k = i % inflight
+        st = streams[k]
+        cam = cams[i % len(cams)]
+        gs.gs_preprocess(ds, cam, opt, rends[k].proj, rends[k].ws, stream=st)
+        gs.gs_bin_sort(rends[k].proj, cam, opt, rends[k].bins, rends[k].ws, stream=st)
+        gs.gs_rasterize(rends[k].proj, rends[k].bins, cam, opt, rends[k].image, stream=st)
+
+    for i in range(warmup):
+        frame(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        frame(i)
+    torch.cuda.synchronize()
+    return steps / (time.perf_counter() - t0)
 
 
 def work_units(gs, torch, ds, cams, rend, opt_kwargs, steps):
@@ -228,6 +265,56 @@ def cpu_baseline_and_psnr(gs, torch, sc, cam, image_gpu, target_s):
     return base, quality
 
 
+def quality_over_poses(gs, torch, sc, cams, rend, opt, steps, tiles_per_pose=96, max_poses=50):
+    """Image quality of the chosen form against the FP64 oracle on every timed pose (at most
+    max_poses, evenly spaced when there are more): per pose, a seeded sample of tiles is
+    composited by the oracle and compared with the GPU image of that pose.  PSNR and MAE over
+    all sampled pixels; max abs over those whose decisions lie outside the guard bands; the
+    flagged ones are checked against the oracle's admissible results (oracle.check_flagged)."""
+    from oracle import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    n_timed = min(steps, len(cams))
+    poses = np.unique(np.linspace(0, n_timed - 1, min(n_timed, max_poses)).round().astype(int))
+    sq = ab = npx = 0.0
+    mx = 0.0
+    flagged = matched = failed = unresolved = 0
+    tx, ty = (cams[0].width + 15) // 16, (cams[0].height + 15) // 16
+    for k in poses:
+        cam = cams[k]
+        rend.render(sc["device"], cam, opt)
+        torch.cuda.synchronize()
+        img = rend.image.double().cpu().numpy()
+        rec = oracle.preprocess(sc["scene"], cam)
+        tiles = np.sort(np.random.default_rng(1000 + int(k)).choice(tx * ty, size=min(tiles_per_pose, tx * ty),
+                                                                      replace=False))
+        st, ids = oracle.tile_lists(rec, cam, tiles)
+        amb = oracle.ambiguous_membership(rec, cam)
+        ref = oracle.composite(rec, cam, st, ids, nthreads=threads, tiles=tiles, amb=amb)
+        mask = np.zeros((cam.height, cam.width), bool)
+        for t in tiles:
+            mask[(t // tx) * 16:(t // tx) * 16 + 16, (t % tx) * 16:(t % tx) * 16 + 16] = True
+        a, b = np.clip(img[:, mask], 0, 1), np.clip(ref["image"][:, mask], 0, 1)
+        sq += float(((a - b) ** 2).sum())
+        ab += float(np.abs(img[:, mask] - ref["image"][:, mask]).sum())
+        npx += a.size
+        ok = mask & (ref["ambiguous"] == 0)
+        mx = max(mx, float(np.abs(img[:, ok] - ref["image"][:, ok]).max()))
+        fl = ref["ambiguous"].copy()
+        fl[~mask] = 0
+        r = oracle.check_flagged(img, None, rec, cam, st, ids, fl, tol_img=1e-3, amb=amb)
+        flagged += r["checked"]
+        matched += r["matched"]
+        failed += r["failed"]
+        unresolved += r["unresolved"]
+    mse = sq / max(npx, 1)
+    sampled = npx / 3
+    return {"psnr_db": float("inf") if mse == 0 else float(10 * np.log10(1 / mse)), "mae": ab / max(npx, 1),
+            "max_abs": mx, "poses": int(len(poses)), "tiles_per_pose": int(tiles_per_pose),
+            "flagged_pixel_frac": flagged / max(sampled, 1),
+            "flagged_matched": matched, "flagged_failed": failed, "flagged_unresolved": unresolved,
+            "unresolved_pixel_frac": unresolved / max(sampled, 1)}
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -237,6 +324,39 @@ def _cpu_model():
     except OSError:
         pass
     return None
+
+
+def backward_mfma_leg(gs, torch, ds, cams, n, steps, warmup, precision, splits):
+    """Times gs_rasterize_backward_mfma on each pose after that pose's MFMA forward (which also
+    writes the T_final and blended-prefix-end planes the backward starts from), with a fixed
+    N(0, 1) upstream gradient; HIP events around the backward launch only."""
+    st = torch.cuda.current_stream()
+    rend = gs.Renderer(n, 1920, 1080, group=1)
+    opt = gs.options(group=1, precision=precision, splits=splits, aux_flags=gs.GS_AUX_TFINAL | gs.GS_AUX_LAST)
+    grads = gs.Grads(n)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    dimg = torch.randn((3, 1080, 1920), generator=gen, device="cuda")
+    evs = []
+    fwd_evs = []
+    for i in range(warmup + steps):
+        cam = cams[i % len(cams)]
+        f0 = torch.cuda.Event(enable_timing=True)
+        f0.record(st)
+        rend.render(ds, cam, opt)
+        grads.zero_()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        gs.gs_rasterize_backward_mfma(rend.proj, rend.bins, cam, opt, dimg, rend.aux[0], rend.aux[1], grads)
+        b.record(st)
+        if i >= warmup:
+            evs.append((a, b))
+    torch.cuda.synchronize()
+    ms = [a.elapsed_time(b) for a, b in evs]
+    return {"kernel": f"k_raster_backward_mfma ({precision}, splits {splits})", "precision": precision,
+            "frames": steps, "avg_ms": float(np.mean(ms)), "p50_ms": float(np.percentile(ms, 50)),
+            "p99_ms": float(np.percentile(ms, 99)),
+            "forward_state": "GS_AUX_TFINAL | GS_AUX_LAST planes of the MFMA forward (no replay)"}
 
 
 def backward_leg(gs, torch, ds, cams, n, steps, warmup):
@@ -288,11 +408,11 @@ def serve(gs, torch, args):
     pool = int(args.serve_pool_gib * (1 << 30))
     slots = 16
 
-    def run(reqs):
+    def run(reqs, max_batch=32):
         be = server.GpuBackend(dss, slots=slots, pool_bytes=pool, opt=opt, max_pixels=max_px,
                                keys_per_pixel=kpp)
         try:
-            st = server.Server(be, pool, slots=slots, max_batch=32, max_inflight_batches=3).run(reqs)
+            st = server.Server(be, pool, slots=slots, max_batch=max_batch, max_inflight_batches=3).run(reqs)
         finally:
             be.close()
         torch.cuda.synchronize()
@@ -302,6 +422,8 @@ def serve(gs, torch, args):
     run(scenes.serving_requests(64, rate_hz=1e7, seed=48))
     log("serving: saturated burst of 1000 requests")
     sat = run(scenes.serving_requests(1000, rate_hz=1e7, seed=47))
+    log("serving: the same burst with one job per raster launch")
+    sat1 = run(scenes.serving_requests(1000, rate_hz=1e7, seed=47), max_batch=1)
     rate = args.serve_load * sat.frames_per_s
     log(f"serving: saturated {sat.frames_per_s:.0f} frames/s; open loop at {rate:.0f} req/s, "
         f"{args.serve_requests} requests")
@@ -311,7 +433,10 @@ def serve(gs, torch, args):
             "requests": args.serve_requests, "offered_rate_hz": rate, "load": args.serve_load,
             "frames_per_s": st.frames_per_s, "p50_ms": st.latency_p50_ms, "p99_ms": st.latency_p99_ms,
             "mean_ms": st.latency_mean_ms, "saturated_frames_per_s": sat.frames_per_s,
-            "saturated_p99_ms": sat.latency_p99_ms, "completed": st.completed, "failed": st.failed,
+            "saturated_p99_ms": sat.latency_p99_ms, "saturated_mean_batch": sat.mean_batch,
+            "saturated_frames_per_s_one_job_per_launch": sat1.frames_per_s,
+            "saturated_p99_ms_one_job_per_launch": sat1.latency_p99_ms,
+            "completed": st.completed, "failed": st.failed,
             "retries": st.retries, "batches": st.batches, "mean_batch": st.mean_batch,
             "max_inflight_jobs": st.max_inflight_jobs, "pool_bytes": pool,
             "max_reserved_bytes": st.max_reserved_bytes, "slots": slots,
@@ -420,9 +545,32 @@ def main():
                 "frac": achieved / PEAK_FP32_TFLOPS, "traffic": raster_traffic(args),
                 "kernel": f"k_raster_mfma (precision {args.precision}, splits {args.splits}, group {args.group})"
                           if args.precision != "fp32" else "k_raster_fp32",
+                "frac_vs_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+                "mfma_frac": (POWER_FLOPS * e_pix / raster_total_s / 1e12 / PEAK_FP16_MFMA_TFLOPS)
+                if args.precision != "fp32" else None,
+                "traffic_source": "profiles/hbm_counters_1m_1080p_fp16.md (rocprofv3 FETCH_SIZE, WRITE_SIZE of the "
+                                  "kernel built from the hashed sources; not measured in this run)",
                 "avg_launch_ms": float(np.mean(raster_ms)),
                 "evals_per_frame": e_pix / args.steps, "blends_per_frame": blend / args.steps,
                 "entries_per_frame": entries_pf, "visible_per_frame": visible_pf}
+
+    pipelined = None
+    if not args.no_pipelined:
+        log("timing two frames in flight (two streams, separate buffers)")
+        pipelined = {"frames_in_flight": 2, "frames_per_s": pipelined_frames(gs, torch, ds, cams, sc.n, opt,
+                                                                              args.steps, args.warmup)}
+
+    all_rows = None
+    if args.precision != "fp32" and not args.no_all_rows:
+        # the same frames with quadrant culling off (every row in every quadrant, as the FP32
+        # rasterizer runs them): separates the contraction's share of the speedup from the culling's
+        log("timing the MFMA rasterizer with every row in every quadrant")
+        rend_a = gs.Renderer(sc.n, 1920, 1080, group=args.group)
+        _, fma, rma = timed_frames(gs, torch, ds, cams, rend_a, gs.options(all_rows=True, **okw), args.steps,
+                                   args.warmup)
+        all_rows = {"option": "GS_OPT_ALL_ROWS", "raster_avg_ms": float(np.mean(rma)),
+                    "p50_ms": float(np.percentile(fma, 50)), "p99_ms": float(np.percentile(fma, 99))}
+        del rend_a
 
     compare = None
     if not args.no_compare and args.precision != "fp32":
@@ -460,12 +608,19 @@ def main():
     if not args.no_backward:
         log("timing the backward pass (FP32, tile bins)")
         backward = backward_leg(gs, torch, ds, cams, sc.n, args.steps, args.warmup)
+        if args.precision != "fp32":
+            log(f"timing the backward pass of the MFMA forward ({args.precision})")
+            backward["mfma"] = backward_mfma_leg(gs, torch, ds, cams, sc.n, args.steps, args.warmup, args.precision,
+                                                 args.splits)
+            backward["mfma"]["vs_mfma_forward_raster"] = backward["mfma"]["avg_ms"] / float(np.mean(raster_ms))
 
     cpu = None
     quality = {}
     if not args.no_cpu_baseline:
-        log("FP64 oracle: CPU baseline and PSNR on sampled tiles")
-        cpu, quality = cpu_baseline_and_psnr(gs, torch, sc, cams[0], first_img, args.cpu_seconds)
+        log("FP64 oracle: CPU baseline on the first pose")
+        cpu, _ = cpu_baseline_and_psnr(gs, torch, sc, cams[0], first_img, args.cpu_seconds)
+        log("FP64 oracle: quality of the chosen form over the timed poses")
+        quality = quality_over_poses(gs, torch, {"scene": sc, "device": ds}, cams, rend, opt, args.steps)
 
     serving = None
     if not args.no_serve:
@@ -476,7 +631,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.precision if args.precision != "fp32" else "fp32",
         "data": "synthetic",
-        "config": {"workload": "1M Gaussians, 64-cluster mixture, SH degree 3, 1920x1080, 200-pose orbit, "
+        "config": {"workload": f"1M Gaussians, 64-cluster mixture, SH degree 3, 1920x1080, {min(args.steps, len(cams))} "
+                               f"poses of a {len(cams)}-pose orbit (one frame per pose), "
                                f"{args.group}x{args.group} tile groups, {args.precision} splits {args.splits}",
                    "gaussians": sc.n, "width": 1920, "height": 1080, "group": args.group,
                    "precision": args.precision, "splits": args.splits},
@@ -484,13 +640,17 @@ def main():
         "raster_avg_ms": float(np.mean(raster_ms)),
         "mpix_gauss_evals_per_s": e_pix / raster_total_s / 1e6,
         "psnr_db_vs_oracle": quality.get("psnr_db"), "mae_vs_oracle": quality.get("mae"),
-        "max_abs_vs_oracle": quality.get("max_abs"), "ambiguous_pixel_frac": quality.get("ambiguous_pixel_frac"),
+        "max_abs_vs_oracle": quality.get("max_abs"), "quality_vs_oracle": quality or None,
         "stage_ms": stages,
         "executed_work_efficiency": {"e_pix_over_e_tile": e_pix / max(exe["e_tile"], 1),
                                      "e_pix_over_e_wave": e_pix / max(exe["e_wave"], 1)},
         "fp32_plain": compare,
         "speedup_vs_fp32": (fps / compare["frames_per_s"]) if compare else None,
         "raster_speedup_vs_fp32": (compare["raster_avg_ms"] / float(np.mean(raster_ms))) if compare else None,
+        "mfma_all_rows": all_rows,
+        "pipelined": pipelined,
+        "raster_speedup_vs_fp32_all_rows": (compare["raster_avg_ms"] / all_rows["raster_avg_ms"])
+        if (compare and all_rows) else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "tight_culling": tight,

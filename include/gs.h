@@ -21,8 +21,11 @@
  *     pointer are host memory.  The caller allocates and owns every buffer; the
  *     library never allocates, frees or retains a pointer after a call returns.
  *   - All device work is enqueued on `stream` (a hipStream_t passed as void*,
- *     NULL = the null stream).  gs_bin_sort and gs_render wait on the stream
- *     once, to read the entry count.  Every other call is asynchronous.
+ *     NULL = the null stream).  gs_bin_sort and gs_render wait once on the host for
+ *     the entry and visible counts (a bounded poll of gs_projected.host_counts, which
+ *     the device writes, or a stream synchronization).  Every other call is asynchronous.
+ *     An error return of gs_bin_sort or gs_render after work was enqueued first waits
+ *     for that work, so the caller may reuse every buffer at once.
  *   - Errors are return codes.  Arguments are validated on the host before any
  *     HIP call; an invalid call returns GS_ERR_INVALID_ARG or GS_ERR_UNSUPPORTED
  *     and touches no memory.  A failing HIP call returns GS_ERR_HIP.  A message
@@ -62,7 +65,10 @@ enum {
   GS_AUX_TFINAL = 1u,       /* transmittance left after the last blended Gaussian */
   GS_AUX_WSUM = 2u,         /* sum over blended Gaussians of alpha*T (so WSUM + TFINAL = 1) */
   GS_AUX_NEVAL = 4u,        /* Gaussians evaluated before the stop, as a float count */
-  GS_AUX_NBLEND = 8u        /* Gaussians blended (alpha >= 1/255, before the stop), as a float count */
+  GS_AUX_NBLEND = 8u,       /* Gaussians blended (alpha >= 1/255, before the stop), as a float count */
+  GS_AUX_LAST = 16u         /* end of the blended prefix: 1 + the position, in the pixel's tile list, of the last
+                               Gaussian blended (0 if none), as a float; with GS_AUX_TFINAL it is the forward
+                               state the MFMA backward pass starts from */
 };
 
 /* gs_options.flags */
@@ -82,7 +88,14 @@ enum {
    * margin of 1 in q, far above its own and the split operands' rounding, so the image and
    * every aux plane are those of the full rows).  This flag makes every quadrant run every row
    * of its tile, the plain tile loop; it exists to check that equality and changes no result. */
-  GS_OPT_ALL_ROWS = 2u
+  GS_OPT_ALL_ROWS = 2u,
+  /* Grouped MFMA rasterization (group > 1) stages a chunk of the group's list once and, by default,
+   * also builds each entry's Gaussian-side row once, in the frame of the whole group, for all its
+   * member tiles (the tiles then differ only in the pixel-side operand; 2x2 groups, larger ones
+   * always use per-tile rows).  The image equals the 1x1 one in exact arithmetic
+   * and to the split operands' rounding in FP16/BF16.  This flag makes every member tile build its
+   * rows in its own frame instead, which gives images bit-identical to group 1. */
+  GS_OPT_TILE_ROWS = 4u
 };
 
 typedef struct {
@@ -131,6 +144,11 @@ typedef struct {
   uint32_t *order;          /* n: the visible Gaussians (count > 0), first *n_visible entries valid;
                                index order after gs_preprocess, (depth, index) order after gs_bin_sort */
   uint32_t *n_visible;      /* 1: number of visible Gaussians */
+  uint64_t *host_counts;    /* HOST memory, 2 values, or NULL: pinned memory the caller allocated with
+                               hipHostMalloc (e.g. a pinned tensor), through which gs_bin_sort receives the
+                               entry and visible counts from the device without a copy command; with NULL
+                               they are copied from the workspace after a wait for the whole stream, which
+                               also waits for the depth sort the pinned path overlaps with the host's wait */
 } gs_projected;
 
 /* Duplicated and sorted entries (capacity entries each) and per-bin ranges. */

@@ -51,6 +51,21 @@ gs_status gs_rasterize_backward(const gs_projected *proj, const gs_bins *bins, c
                                 const gs_options *opt, const float *dimage, const gs_grads *grads,
                                 void *stream);
 
+/* The same gradients for the image of the tensorized forward (opt->precision GS_PREC_FP16_MFMA or
+ * GS_PREC_BF16_MFMA with opt->splits as in gs_rasterize; Background: eq. power as the MFMA
+ * contraction of the design section).  The power of each pair is the forward's own MFMA result
+ * (same Gaussian-side rows, same pixel-side operand), so the backward takes the forward's branch
+ * at every pair; instead of replaying the forward it starts from the forward's state:
+ *   t_final  H x W FP32: the forward's GS_AUX_TFINAL plane (final transmittance);
+ *   last     H x W FP32: the forward's GS_AUX_LAST plane (end of the blended prefix),
+ * both from gs_rasterize of the same (proj, bins, cam, opt) with aux_flags holding
+ * GS_AUX_TFINAL | GS_AUX_LAST.  Tile bins only (opt->group 1, else GS_ERR_UNSUPPORTED);
+ * GS_OPT_ALL_ROWS turns quadrant culling off (same gradients up to the order of the atomic sums).
+ * Gradients are ADDED to *grads with FP32 atomics, as in gs_rasterize_backward.  Asynchronous. */
+gs_status gs_rasterize_backward_mfma(const gs_projected *proj, const gs_bins *bins, const gs_camera *cam,
+                                     const gs_options *opt, const float *dimage, const float *t_final,
+                                     const float *last, const gs_grads *grads, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,14 +67,18 @@ class AdaptiveRenderer:
 
     def __init__(self, n: int, width: int, height: int, precision="fp16", splits: int = 2,
                  groups=(1, 2, 4, 8), tight=(False, True), probes: int = 2, reprobe_every: int = 0,
-                 bg=(0.0, 0.0, 0.0), device="cuda"):
+                 bg=(0.0, 0.0, 0.0), device="cuda", tile_rows: bool = False):
         prec = gs.PRECISIONS[precision] if isinstance(precision, str) else precision
         if prec == gs.GS_PREC_FP32:
             groups = [g for g in groups if g != 8]      # the FP32 rasterizer has no 8x8 groups
         tights = (tight,) if isinstance(tight, bool) else tuple(tight)
         self.n, self.width, self.height = n, width, height
         self.variants = [(g, t) for g in groups for t in tights]
-        self.opts = {v: gs.options(group=v[0], precision=prec, splits=splits, bg=bg, tight=v[1]) for v in self.variants}
+        # tile_rows: grouped MFMA variants build rows per member tile, so every variant's image is
+        # bit-identical to the 1x1 one; by default they build them once per group (same image to
+        # the 16-bit operands' rounding)
+        self.opts = {v: gs.options(group=v[0], precision=prec, splits=splits, bg=bg, tight=v[1], tile_rows=tile_rows)
+                     for v in self.variants}
         self.renderers = {g: gs.Renderer(n, width, height, group=g, device=device) for g in groups}
         self.chooser = GroupChooser(self.variants, probes, reprobe_every)
         self.last_variant = None

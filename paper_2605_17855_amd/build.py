@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libgs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["gs_api.hip", "gs_preprocess.hip", "gs_sort.hip", "gs_raster_fp32.hip", "gs_raster_mfma.hip", "gs_backward.hip"]
-HEADERS = ["gs_internal.hpp", "gs_backward.hpp"]
+HEADERS = ["gs_internal.hpp", "gs_backward.hpp", "gs_mfma.hpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC,

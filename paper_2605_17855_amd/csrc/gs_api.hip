@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <chrono>
 
 #include "gs_backward.hpp"
 #include "gs_internal.hpp"
@@ -63,9 +64,10 @@ gs_status check_options(const gs_options *o) {
   } else if (o->group == 8) {
     return fail(GS_ERR_UNSUPPORTED, "group 8 needs an MFMA precision (the FP32 rasterizer keeps every member tile in registers)");
   }
-  if (o->aux_flags & ~(uint32_t)(GS_AUX_TFINAL | GS_AUX_WSUM | GS_AUX_NEVAL | GS_AUX_NBLEND))
+  if (o->aux_flags & ~(uint32_t)(GS_AUX_TFINAL | GS_AUX_WSUM | GS_AUX_NEVAL | GS_AUX_NBLEND | GS_AUX_LAST))
     return fail(GS_ERR_INVALID_ARG, "aux_flags 0x%x", o->aux_flags);
-  if (o->flags & ~(uint32_t)(GS_OPT_TIGHT | GS_OPT_ALL_ROWS)) return fail(GS_ERR_INVALID_ARG, "flags 0x%x", o->flags);
+  if (o->flags & ~(uint32_t)(GS_OPT_TIGHT | GS_OPT_ALL_ROWS | GS_OPT_TILE_ROWS))
+    return fail(GS_ERR_INVALID_ARG, "flags 0x%x", o->flags);
   for (int i = 0; i < 3; ++i)
     if (!std::isfinite(o->bg[i])) return fail(GS_ERR_INVALID_ARG, "background non-finite");
   return GS_OK;
@@ -109,8 +111,11 @@ struct Workspace {
   uint64_t *dpos;        // first entry of each visible Gaussian in depth order (n + 1)
   uint32_t *csort;       // entry count of each visible Gaussian in depth order (n)
   uint32_t *bkey;        // bin key of each entry (capacity)
+  uint32_t *bval;        // depth rank of each entry's Gaussian (capacity)
   uint32_t *bkey_alt;    // bin sort double buffer (capacity)
   uint32_t *bval_alt;    // (capacity)
+  uint32_t *bfirst;      // first Gaussian (depth rank) of each 1,024-entry block (capacity / 1,024 + 1)
+  uint64_t nbfirst;
   uint64_t *counts;      // {K, V}: packed for the one device-to-host copy
   size_t total;
 };
@@ -133,8 +138,11 @@ Workspace carve(void *ws, int64_t n, uint64_t capacity) {
   w.dpos = reinterpret_cast<uint64_t *>(take((nn + 1) * 8));
   w.csort = reinterpret_cast<uint32_t *>(take(nn * 4));
   w.bkey = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
+  w.bval = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
   w.bkey_alt = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
   w.bval_alt = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
+  w.nbfirst = capacity / gsi::kFirstsBlock + 1;
+  w.bfirst = reinterpret_cast<uint32_t *>(take(w.nbfirst * 4));
   w.counts = reinterpret_cast<uint64_t *>(take(2 * sizeof(uint64_t)));
   w.total = off;
   return w;
@@ -175,93 +183,162 @@ gsi::RasterParams make_params(const gs_options &o) {
   for (int i = 0; i < 3; ++i) p.bg[i] = o.bg[i];
   p.aux_flags = o.aux_flags;
   p.all_rows = (o.flags & GS_OPT_ALL_ROWS) != 0;
+  p.tile_rows = (o.flags & GS_OPT_TILE_ROWS) != 0;
   return p;
 }
 
-// One event per host thread for the count readback (created on first use, destroyed when
-// the thread ends); calls on different threads may run concurrently on different streams.
-// The counts land in pinned, coherent host memory that k_depth_keys writes directly, so no copy
-// command sits between the depth-key kernel and the depth sort and the call returns to the
-// host at once (a copy into pageable memory is staged and waits for the GPU).
-struct CountsEvent {
-  hipEvent_t ev = nullptr;
-  uint64_t *host = nullptr;   // {K, V}
-  ~CountsEvent() {
-    if (ev) (void)hipEventDestroy(ev);
-    if (host) (void)hipHostFree(host);
+// Waits for the entry and visible counts that k_depth_keys writes into the caller's pinned host
+// memory (set to a sentinel before the launch): a poll of that memory, bounded in time; should
+// the values not arrive, the stream is synchronized and the workspace copy is read instead.
+bool poll_counts(volatile uint64_t *h, uint64_t *kv) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t spin = 0;; ++spin) {
+    const uint64_t a = h[0], b = h[1];
+    if (a != ~0ull && b != ~0ull) {
+      kv[0] = a;
+      kv[1] = b;
+      return true;
+    }
+    if ((spin & 1023u) == 1023u && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) return false;
   }
-};
-
-CountsEvent *counts_event() {
-  thread_local CountsEvent holder;
-  if (!holder.ev && hipEventCreateWithFlags(&holder.ev, hipEventDisableTiming) != hipSuccess) holder.ev = nullptr;
-  if (!holder.host &&
-      hipHostMalloc(reinterpret_cast<void **>(&holder.host), 64, hipHostMallocCoherent | hipHostMallocPortable) !=
-          hipSuccess)
-    holder.host = nullptr;
-  return (holder.ev && holder.host) ? &holder : nullptr;
 }
 
 gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam, const gs_options *opt,
                       const gs_bins *bins, uint64_t *n_keys, void *ws, hipStream_t st) {
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
   const Workspace w = carve(ws, n, bins->capacity);
-  // The one host synchronization reads the entry count K and the visible count V, which
-  // k_depth_keys writes to pinned host memory (and to the workspace).  An event follows, and the
-  // depth sort and depth-order offset scan (which read V on the device) are enqueued before the
-  // host waits on it, so the GPU keeps working while the host waits.
-  CountsEvent *ce = counts_event();
-  if (!ce) return fail(GS_ERR_HIP, "event or pinned count buffer could not be created");
-  hipEvent_t ev = ce->ev;
-  volatile uint64_t *hkv = ce->host;
-  hkv[0] = hkv[1] = ~0ull;   // overwritten by the kernel
+  // The one host wait reads the entry count K and the visible count V, which k_depth_keys writes
+  // to the caller's pinned host memory (and to the workspace).  The depth sort and depth-order
+  // offset scan (which read V on the device) are enqueued before the host polls for them, so
+  // the GPU keeps working while the host waits.
+  volatile uint64_t *hkv = proj->host_counts;
+  if (hkv) hkv[0] = hkv[1] = ~0ull;   // overwritten by the kernel
   const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
   GS_HIP(gsi::launch_depth_keys(proj->order, reinterpret_cast<const float4 *>(proj->rgb), proj->n_visible, nn, w.dkey,
-                                proj->offset + n, w.counts, ce->host, st));
-  // from here on the kernel may be writing the counts: every exit waits for it first
-  hipError_t e = hipEventRecord(ev, st);
-  if (e != hipSuccess) {
-    (void)hipStreamSynchronize(st);
-    return hip_fail(e, "hipEventRecord");
-  }
+                                proj->offset + n, w.counts, proj->host_counts, w.sort, st));
+  // from here on the kernel may be writing the counts: every exit waits for the stream first
   bool in_alt = false;
-  e = gsi::sort_depth(proj->order, proj->n_visible, nn, w.dkey, w.dkey_alt, w.dval_alt, w.sort, st, &in_alt,
+  hipError_t e = gsi::sort_depth(proj->order, proj->n_visible, nn, w.dkey, w.dkey_alt, w.dval_alt, w.sort, st, &in_alt,
                       proj->count, w.csort);
   const uint32_t *dkeys = in_alt ? w.dkey_alt : w.dkey;   // depth bits in depth order
   if (e == hipSuccess && in_alt) e = hipMemcpyAsync(proj->order, w.dval_alt, nn * 4, hipMemcpyDeviceToDevice, st);
   // first entry of each Gaussian in depth order (the sort placed the counts in that order when
   // it ran; a single Gaussian needs no sort)
   if (e == hipSuccess)
-    e = nn > 1 ? gsi::launch_scan_dev(w.csort, w.dpos, (int64_t)nn, proj->n_visible, w.scan, st)
+    e = nn > 1 ? gsi::launch_scan_dev(w.csort, w.dpos, (int64_t)nn, proj->n_visible, w.scan, st, w.bfirst, w.nbfirst)
                : gsi::launch_scan_gather(proj->count, proj->order, w.dpos, (int64_t)nn, proj->n_visible, w.scan, st);
-  const hipError_t es = hipEventSynchronize(ev);
-  if (es != hipSuccess) {
+  if (e != hipSuccess) {
     (void)hipStreamSynchronize(st);
-    return hip_fail(es, "hipEventSynchronize");
+    return hip_fail(e, "depth sort");
   }
-  if (e != hipSuccess) return hip_fail(e, "depth sort");
-  uint64_t kv[2] = {hkv[0], hkv[1]};
-  if (kv[0] == ~0ull || kv[1] == ~0ull) {
-    // not visible through the pinned buffer: read the workspace copy (the kernel has finished)
+  uint64_t kv[2] = {0, 0};
+  if (!hkv || !poll_counts(hkv, kv)) {
+    // no pinned buffer, or the values did not arrive through it: the workspace copy, after the
+    // stream has drained
+    const hipError_t es = hipStreamSynchronize(st);
+    if (es != hipSuccess) return hip_fail(es, "hipStreamSynchronize");
     GS_HIP(hipMemcpy(kv, w.counts, sizeof(kv), hipMemcpyDeviceToHost));
   }
   const uint64_t K = kv[0];
   const uint32_t V = (uint32_t)kv[1];
   *n_keys = K;
-  if (K > bins->capacity)
-    return fail(GS_ERR_CAPACITY, "%llu entries exceed capacity %llu", (unsigned long long)K,
-                (unsigned long long)bins->capacity);
-  if (K >= (1ull << 32)) return fail(GS_ERR_UNSUPPORTED, "%llu entries >= 2^32", (unsigned long long)K);
-  if ((int64_t)V > n) return fail(GS_ERR_INVALID_ARG, "visible count %u exceeds n", V);
-  // one thread per entry and the bin digits (also clears the bin ranges)
-  GS_HIP(gsi::bin_and_sort(proj->order, w.dpos, V, K, proj->rect, proj->xy, proj->conic,
-                           (opt->flags & GS_OPT_TIGHT) != 0, g, w.bkey, bins->vals, w.bkey_alt, w.bval_alt,
-                           bins->ranges, w.sort, st, &in_alt));
-  const uint32_t *kf = in_alt ? w.bkey_alt : w.bkey;
-  const uint32_t *ranks = in_alt ? w.bval_alt : bins->vals;
-  GS_HIP(gsi::launch_ranges(kf, ranks, K, proj->order, dkeys, proj->rect, proj->xy, proj->conic,
-                            (opt->flags & GS_OPT_TIGHT) != 0, g, bins->vals, bins->ranges,
-                            opt->group > 1 ? bins->masks : nullptr, bins->keys, st));
+  // The depth sort and the depth-order scan enqueued above may still be writing the workspace
+  // and proj->order: an error return first waits for them, so that the caller may release or
+  // reuse the workspace (on any stream) as soon as the call returns.
+  const char *why = nullptr;
+  gs_status bad = GS_OK;
+  if (K > bins->capacity) bad = GS_ERR_CAPACITY, why = "entries exceed capacity";
+  else if (K >= (1ull << 32)) bad = GS_ERR_UNSUPPORTED, why = "entries >= 2^32";
+  else if ((int64_t)V > n) bad = GS_ERR_INVALID_ARG, why = "visible count exceeds n";
+  if (bad != GS_OK) {
+    const hipError_t ew = hipStreamSynchronize(st);
+    if (ew != hipSuccess) return hip_fail(ew, "hipStreamSynchronize");
+    return fail(bad, "%s (%llu entries, capacity %llu, %u visible of %lld)", why, (unsigned long long)K,
+                (unsigned long long)bins->capacity, V, (long long)n);
+  }
+  // one thread per entry (also clears the bin ranges), the bin passes (the last one places the
+  // Gaussian indices and 64-bit keys), the ranges and masks
+  GS_HIP(gsi::bin_and_sort(proj->order, dkeys, w.dpos, nn > 1 ? w.bfirst : nullptr, V, K, proj->rect, proj->xy, proj->conic,
+                           (opt->flags & GS_OPT_TIGHT) != 0, g, w.bkey, w.bval, w.bkey_alt, w.bval_alt, bins->ranges,
+                           opt->group > 1 ? bins->masks : nullptr, bins->vals, bins->keys, w.sort, st));
+  return GS_OK;
+}
+
+// Validated job table of a batched launch (host only, no HIP call).
+gs_status batch_table(const gs_job *jobs, int32_t n_jobs, const gs_options *opt, gsi::BatchTable *table) {
+  gs_status s;
+  if ((s = check_options(opt))) return s;
+  if (n_jobs < 0) return fail(GS_ERR_INVALID_ARG, "n_jobs = %d", n_jobs);
+  if (n_jobs > gsi::kMaxBatch) return fail(GS_ERR_UNSUPPORTED, "n_jobs = %d above %d", n_jobs, gsi::kMaxBatch);
+  if (n_jobs == 0) return GS_OK;
+  if (!jobs) return fail(GS_ERR_INVALID_ARG, "jobs is NULL");
+  int64_t total = 0;
+  for (int32_t i = 0; i < n_jobs; ++i) {
+    const gs_job &jb = jobs[i];
+    if ((s = check_camera(&jb.cam))) return fail(s, "job %d: camera", i);
+    if ((s = check_bins(jb.bins, opt->group, false))) return fail(s, "job %d: bins", i);
+    if (!jb.proj || !jb.proj->xy || !jb.proj->conic || !jb.proj->rgb)
+      return fail(GS_ERR_INVALID_ARG, "job %d: projected record is NULL", i);
+    if (!jb.image) return fail(GS_ERR_INVALID_ARG, "job %d: image is NULL", i);
+    if (opt->aux_flags && !jb.aux) return fail(GS_ERR_INVALID_ARG, "job %d: aux is NULL with aux_flags set", i);
+    const gsi::Grid g = gsi::make_grid(jb.cam.width, jb.cam.height, opt->group);
+    table->jobs[i] = make_job(*jb.proj, *jb.bins, g, jb.image, jb.aux, raster_parts(*opt));
+    table->jobs[i].bin0 = (int)total;
+    total += table->jobs[i].items;
+    if (total >= (1ll << 31)) return fail(GS_ERR_UNSUPPORTED, "batch has >= 2^31 work items");
+  }
+  table->n_jobs = n_jobs;
+  table->total = (int)total;
+  return GS_OK;
+}
+
+// One persistent launch over the table; `counter` (one uint32 of device memory) is cleared by a
+// fill kernel on the stream first (no memset node, so the launch can be captured in a graph).
+gs_status batch_launch(const gsi::BatchTable &table, const gs_options &opt, uint32_t *counter, hipStream_t st) {
+  int dev = 0, cus = 0;
+  GS_HIP(hipGetDevice(&dev));
+  GS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const gsi::RasterParams p = make_params(opt);
+  // persistent grid: enough workgroups to fill every CU several times, never more than items
+  int64_t grid = (int64_t)cus * 8;
+  if (grid > table.total) grid = table.total;
+  GS_HIP(gsi::launch_fill_u32(counter, 1, 0u, st));
+  if (opt.precision == GS_PREC_FP32)
+    GS_HIP(gsi::launch_raster_fp32_batch(table, (int)grid, p, counter, st));
+  else
+    GS_HIP(gsi::launch_raster_mfma_batch(table, (int)grid, p, counter, st));
+  return GS_OK;
+}
+
+gs_status backward_job(const gs_projected *proj, const gs_bins *bins, const gs_camera *cam, const gs_options *opt,
+                       const float *dimage, const gs_grads *grads, gsi::BackwardJob *out) {
+  gs_status s;
+  if ((s = check_camera(cam)) || (s = check_options(opt))) return s;
+  if (opt->group != 1) return fail(GS_ERR_UNSUPPORTED, "backward pass over group %d bins (tile bins only)", opt->group);
+  if ((s = check_bins(bins, 1, false))) return s;
+  if (!proj || !proj->xy || !proj->conic || !proj->rgb) return fail(GS_ERR_INVALID_ARG, "projected record is NULL");
+  if (!dimage) return fail(GS_ERR_INVALID_ARG, "dimage is NULL");
+  if (!grads || !grads->rgb || !grads->opacity || !grads->conic || !grads->xy)
+    return fail(GS_ERR_INVALID_ARG, "gradient buffer is NULL");
+  const gsi::Grid g = gsi::make_grid(cam->width, cam->height, 1);
+  gsi::BackwardJob &j = *out;
+  j.xy = reinterpret_cast<const double2 *>(proj->xy);
+  j.conic = reinterpret_cast<const float4 *>(proj->conic);
+  j.rgb = reinterpret_cast<const float4 *>(proj->rgb);
+  j.vals = bins->vals;
+  j.ranges = bins->ranges;
+  j.dimage = dimage;
+  j.g_rgb = grads->rgb;
+  j.g_op = grads->opacity;
+  j.g_conic = grads->conic;
+  j.g_xy = grads->xy;
+  j.W = g.W;
+  j.H = g.H;
+  j.TX = g.TX;
+  j.TY = g.TY;
+  for (int c = 0; c < 3; ++c) j.bg[c] = opt->bg[c];
+  j.t_final = nullptr;
+  j.last = nullptr;
   return GS_OK;
 }
 
@@ -341,34 +418,29 @@ gs_status gs_rasterize(const gs_projected *proj, const gs_bins *bins, const gs_c
   return GS_OK;
 }
 
+
 gs_status gs_rasterize_backward(const gs_projected *proj, const gs_bins *bins, const gs_camera *cam,
                                 const gs_options *opt, const float *dimage, const gs_grads *grads, void *stream) {
-  gs_status s;
-  if ((s = check_camera(cam)) || (s = check_options(opt))) return s;
-  if (opt->group != 1) return fail(GS_ERR_UNSUPPORTED, "backward pass over group %d bins (tile bins only)", opt->group);
-  if ((s = check_bins(bins, 1, false))) return s;
-  if (!proj || !proj->xy || !proj->conic || !proj->rgb) return fail(GS_ERR_INVALID_ARG, "projected record is NULL");
-  if (!dimage) return fail(GS_ERR_INVALID_ARG, "dimage is NULL");
-  if (!grads || !grads->rgb || !grads->opacity || !grads->conic || !grads->xy)
-    return fail(GS_ERR_INVALID_ARG, "gradient buffer is NULL");
-  const gsi::Grid g = gsi::make_grid(cam->width, cam->height, 1);
   gsi::BackwardJob j;
-  j.xy = reinterpret_cast<const double2 *>(proj->xy);
-  j.conic = reinterpret_cast<const float4 *>(proj->conic);
-  j.rgb = reinterpret_cast<const float4 *>(proj->rgb);
-  j.vals = bins->vals;
-  j.ranges = bins->ranges;
-  j.dimage = dimage;
-  j.g_rgb = grads->rgb;
-  j.g_op = grads->opacity;
-  j.g_conic = grads->conic;
-  j.g_xy = grads->xy;
-  j.W = g.W;
-  j.H = g.H;
-  j.TX = g.TX;
-  j.TY = g.TY;
-  for (int c = 0; c < 3; ++c) j.bg[c] = opt->bg[c];
+  const gs_status s = backward_job(proj, bins, cam, opt, dimage, grads, &j);
+  if (s) return s;
   GS_HIP(gsi::launch_raster_backward(j, static_cast<hipStream_t>(stream)));
+  return GS_OK;
+}
+
+gs_status gs_rasterize_backward_mfma(const gs_projected *proj, const gs_bins *bins, const gs_camera *cam,
+                                     const gs_options *opt, const float *dimage, const float *t_final,
+                                     const float *last, const gs_grads *grads, void *stream) {
+  gsi::BackwardJob j;
+  gs_status s = backward_job(proj, bins, cam, opt, dimage, grads, &j);
+  if (s) return s;
+  if (opt->precision != GS_PREC_FP16_MFMA && opt->precision != GS_PREC_BF16_MFMA)
+    return fail(GS_ERR_INVALID_ARG, "precision %d is not an MFMA precision", opt->precision);
+  if (!t_final || !last) return fail(GS_ERR_INVALID_ARG, "t_final or last is NULL");
+  j.t_final = t_final;
+  j.last = last;
+  GS_HIP(gsi::launch_raster_backward_mfma(j, opt->precision, opt->splits, (opt->flags & GS_OPT_ALL_ROWS) != 0,
+                                          static_cast<hipStream_t>(stream)));
   return GS_OK;
 }
 
@@ -429,44 +501,11 @@ int32_t gs_max_batch(void) { return gsi::kMaxBatch; }
 
 gs_status gs_rasterize_batch(const gs_job *jobs, int32_t n_jobs, const gs_options *opt, uint32_t *work_counter,
                              void *stream) {
-  gs_status s;
-  if ((s = check_options(opt))) return s;
-  if (n_jobs < 0) return fail(GS_ERR_INVALID_ARG, "n_jobs = %d", n_jobs);
-  if (n_jobs > gsi::kMaxBatch) return fail(GS_ERR_UNSUPPORTED, "n_jobs = %d above %d", n_jobs, gsi::kMaxBatch);
-  if (n_jobs == 0) return GS_OK;
-  if (!jobs || !work_counter) return fail(GS_ERR_INVALID_ARG, "jobs or work_counter is NULL");
   gsi::BatchTable table{};
-  int64_t total = 0;
-  for (int32_t i = 0; i < n_jobs; ++i) {
-    const gs_job &jb = jobs[i];
-    if ((s = check_camera(&jb.cam))) return fail(s, "job %d: camera", i);
-    if ((s = check_bins(jb.bins, opt->group, false))) return fail(s, "job %d: bins", i);
-    if (!jb.proj || !jb.proj->xy || !jb.proj->conic || !jb.proj->rgb)
-      return fail(GS_ERR_INVALID_ARG, "job %d: projected record is NULL", i);
-    if (!jb.image) return fail(GS_ERR_INVALID_ARG, "job %d: image is NULL", i);
-    if (opt->aux_flags && !jb.aux) return fail(GS_ERR_INVALID_ARG, "job %d: aux is NULL with aux_flags set", i);
-    const gsi::Grid g = gsi::make_grid(jb.cam.width, jb.cam.height, opt->group);
-    table.jobs[i] = make_job(*jb.proj, *jb.bins, g, jb.image, jb.aux, raster_parts(*opt));
-    table.jobs[i].bin0 = (int)total;
-    total += table.jobs[i].items;
-    if (total >= (1ll << 31)) return fail(GS_ERR_UNSUPPORTED, "batch has >= 2^31 work items");
-  }
-  table.n_jobs = n_jobs;
-  table.total = (int)total;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  int dev = 0, cus = 0;
-  GS_HIP(hipGetDevice(&dev));
-  GS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const gsi::RasterParams p = make_params(*opt);
-  // persistent grid: enough workgroups to fill every CU several times, never more than items
-  int64_t grid = (int64_t)cus * 8;
-  if (grid > total) grid = total;
-  GS_HIP(gsi::launch_fill_u32(work_counter, 1, 0u, st));
-  if (opt->precision == GS_PREC_FP32)
-    GS_HIP(gsi::launch_raster_fp32_batch(table, (int)grid, p, work_counter, st));
-  else
-    GS_HIP(gsi::launch_raster_mfma_batch(table, (int)grid, p, work_counter, st));
-  return GS_OK;
+  gs_status s = batch_table(jobs, n_jobs, opt, &table);
+  if (s || n_jobs == 0) return s;
+  if (!work_counter) return fail(GS_ERR_INVALID_ARG, "work_counter is NULL");
+  return batch_launch(table, *opt, work_counter, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -214,9 +214,12 @@ hipError_t launch_scan_compact(const uint32_t *in, uint64_t *out, int64_t n, uin
 // out[0..m] = exclusive prefix sum of in[idx[i]] for i < m = *n_dev (m <= n_max)
 hipError_t launch_scan_gather(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n_max,
                               const uint32_t *n_dev, void *tmp, hipStream_t st);
-// out[0..m] = exclusive prefix sum of in[i] for i < m = *n_dev (m <= n_max)
+// out[0..m] = exclusive prefix sum of in[i] for i < m = *n_dev (m <= n_max); with block_first,
+// also block_first[b] = the i whose run [out[i], out[i] + in[i]) holds entry b * kFirstsBlock,
+// for b < n_blocks (the binning's first Gaussian of each block of entries)
+constexpr uint64_t kFirstsBlock = 1024;
 hipError_t launch_scan_dev(const uint32_t *in, uint64_t *out, int64_t n_max, const uint32_t *n_dev, void *tmp,
-                           hipStream_t st);
+                           hipStream_t st, uint32_t *block_first = nullptr, uint64_t n_blocks = 0);
 
 // ---- binning, sort, ranges -------------------------------------------------
 // scratch of a radix sort over at most n keys (per-tile digit counts and digit totals)
@@ -225,10 +228,11 @@ size_t radix_tmp_bytes(uint64_t n);
 // reports in *in_alt whether the result ended in the alternate buffers.
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
                       int hi, void *tmp, hipStream_t st, bool *in_alt);
-// keys[i] = depth bits of order[i] for i < *nvis (n_max >= *nvis), and counts = {*K, *nvis}
-// (the entry and visible counts side by side, for one copy to the host).
+// keys[i] = depth bits of order[i] for i < *nvis (n_max >= *nvis), counts = {*K, *nvis} (the
+// entry and visible counts side by side, for one copy to the host), and in tmp the first depth
+// pass's per-tile digit counts for the sort_depth call that follows (same n_max and tmp).
 hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max,
-                             uint32_t *keys, const uint64_t *K, uint64_t *counts, uint64_t *host_counts,
+                             uint32_t *keys, const uint64_t *K, uint64_t *counts, uint64_t *host_counts, void *tmp,
                              hipStream_t st);
 // Sorts the visible list order[0..*nvis) by the depth keys (4 passes, stable), using keys_alt/
 // vals_alt (n_max each) as scratch, and writes count_sorted[i] = count[order[i]] for the
@@ -237,20 +241,18 @@ hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, const uin
 hipError_t sort_depth(uint32_t *order, const uint32_t *nvis, uint64_t n_max, uint32_t *keys, uint32_t *keys_alt,
                       uint32_t *vals_alt, void *tmp, hipStream_t st, bool *in_alt, const uint32_t *count,
                       uint32_t *count_sorted);
-// Entries of the V depth-ordered visible Gaussians (the i-th one's first entry at dpos[i])
-// into (bkey, bval = the Gaussian's rank i in depth order), then a stable sort on the bin bits.
-// Also clears the bin ranges ranges[0 .. 2 nbins) before k_ranges fills the non-empty ones.
-// With tight (group 1), entries follow the culled spans of tight_row_span.
-hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V, uint64_t K, const uint16_t *rect,
-                        const double *xy, const float *conic, bool tight, const Grid &g, uint32_t *bkey,
-                        uint32_t *bval, uint32_t *bkey_alt, uint32_t *bval_alt, uint32_t *ranges, void *tmp,
-                        hipStream_t st, bool *in_alt);
-// Bin ranges (zeroed before), masks (group > 1), the 64-bit keys and the Gaussian indices
-// (vals[i] = order[ranks[i]]; ranks may alias vals) of the sorted entries; dkeys[r] are the
-// depth bits of the r-th Gaussian in depth order.
-hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n, const uint32_t *order,
-                         const uint32_t *dkeys, const uint16_t *rect, const double *xy, const float *conic, bool tight,
-                         const Grid &g, uint32_t *vals, uint32_t *ranges, void *masks, uint64_t *keys, hipStream_t st);
+// Entries of the V depth-ordered visible Gaussians (the i-th one's first entry at dpos[i];
+// dkeys[i] its depth bits) as (bin key, rank in depth order) pairs in (bkey, bval), a stable
+// sort on the bin bits ping-ponging with (bkey_alt, bval_alt) whose last pass writes the final
+// Gaussian indices to vals and the 64-bit keys to keys, then the bin ranges (cleared first) and,
+// for group > 1, the membership masks.  With tight (opacity-aware culling) entries follow the
+// culled spans of tight_row_span.  vals and keys must not alias the four work arrays.
+// block_first (or nullptr): the first Gaussian of every 1,024-entry block (launch_scan_dev).
+hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint64_t *dpos, const uint32_t *block_first,
+                        uint32_t V, uint64_t K,
+                        const uint16_t *rect, const double *xy, const float *conic, bool tight, const Grid &g,
+                        uint32_t *bkey, uint32_t *bval, uint32_t *bkey_alt, uint32_t *bval_alt, uint32_t *ranges,
+                        void *masks, uint32_t *vals, uint64_t *keys, void *tmp, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
 
 // ---- rasterizers -------------------------------------------------------------
@@ -275,6 +277,7 @@ struct RasterParams {
   float bg[3];
   uint32_t aux_flags;
   bool all_rows;               // every quadrant runs every row (no quadrant culling)
+  bool tile_rows;              // grouped MFMA rasterizers: each member tile builds its own rows
 };
 
 hipError_t launch_raster_fp32(const RasterJob &j, const RasterParams &p, hipStream_t st);

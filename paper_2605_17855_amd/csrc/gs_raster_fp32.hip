@@ -34,7 +34,7 @@ __device__ __forceinline__ void raster_bin_fp32(const RasterJob &J, const Raster
   const int px = (w & 1) * 8 + (lane & 7), py = (w >> 1) * 8 + (lane >> 3);
 
   float T[NT], C0[NT], C1[NT], C2[NT], Ws[NT], cut[NT];
-  uint32_t nstop[NT], nseen[NT], nblend[NT];
+  uint32_t nstop[NT], nseen[NT], nblend[NT], nlast[NT];
   float X[NT], Y[NT];
 #pragma unroll
   for (int k = 0; k < NT; ++k) {
@@ -44,7 +44,7 @@ __device__ __forceinline__ void raster_bin_fp32(const RasterJob &J, const Raster
     const bool inside = (ox + lx < J.W) && (oy + ly < J.H);
     T[k] = 1.0f; C0[k] = C1[k] = C2[k] = 0.0f; Ws[k] = 0.0f;
     cut[k] = inside ? kCutLog2 : INFINITY;
-    nstop[k] = 0; nseen[k] = 0; nblend[k] = 0;
+    nstop[k] = 0; nseen[k] = 0; nblend[k] = 0; nlast[k] = 0;
   }
 
   for (uint32_t cs = start; cs < end; cs += kBlock) {
@@ -99,6 +99,7 @@ __device__ __forceinline__ void raster_bin_fp32(const RasterJob &J, const Raster
             Ws[k] += wgt;
             nblend[k] += ok ? 1u : 0u;
             nstop[k] = ok ? nstop[k] : nseen[k];
+            nlast[k] = ok ? nseen[k] : nlast[k];
           }
         }
       }
@@ -123,6 +124,7 @@ __device__ __forceinline__ void raster_bin_fp32(const RasterJob &J, const Raster
         J.aux[(plane++) * HW + pix] = (float)(stopped ? nstop[k] : nseen[k]);
       }
       if (P.aux_flags & GS_AUX_NBLEND) J.aux[(plane++) * HW + pix] = (float)nblend[k];
+      if (P.aux_flags & GS_AUX_LAST) J.aux[(plane++) * HW + pix] = (float)nlast[k];
     }
   }
 }

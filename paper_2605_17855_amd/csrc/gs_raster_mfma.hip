@@ -34,177 +34,27 @@
 // grouped and ungrouped images are bit-identical.
 #include <type_traits>
 
-#include "gs_internal.hpp"
+#include "gs_mfma.hpp"
 
 namespace gsi {
 namespace {
 
-typedef _Float16 half8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef short short8 __attribute__((ext_vector_type(8)));
-typedef float float16v __attribute__((ext_vector_type(16)));
-
-
-template <int PREC>
-struct Narrow;
-
-// The encoders take their argument as a materialised FP32 value (the empty asm pins it to a
-// register): otherwise the compiler may fuse the FP32 multiply that produced it with the
-// conversion into one mixed-precision FMA, which rounds once instead of twice, and may do so
-// in one kernel and not in another, so the same Gaussian's row would differ between the
-// ungrouped, grouped and batched rasterizers.
-__device__ __forceinline__ float as_fp32(float x) {
-  asm volatile("" : "+v"(x));
-  return x;
-}
-
-template <>
-struct Narrow<GS_PREC_FP16_MFMA> {
-  static constexpr float kScale = 2048.0f;            // 2^11
-  __device__ static __forceinline__ uint16_t enc(float x) {
-    return __builtin_bit_cast(uint16_t, (_Float16)as_fp32(x));
-  }
-  __device__ static __forceinline__ float dec(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
-  __device__ static __forceinline__ float16v mma(short8 a, short8 b, float16v c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a), __builtin_bit_cast(half8, b), c, 0,
-                                                  0, 0);
-  }
-};
-
-template <>
-struct Narrow<GS_PREC_BF16_MFMA> {
-  static constexpr float kScale = 256.0f;             // 2^8
-  __device__ static __forceinline__ uint16_t enc(float x) { return __builtin_bit_cast(uint16_t, (__bf16)as_fp32(x)); }
-  __device__ static __forceinline__ float dec(uint16_t h) { return (float)__builtin_bit_cast(__bf16, h); }
-  __device__ static __forceinline__ float16v mma(short8 a, short8 b, float16v c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
-                                                   0, 0, 0);
-  }
-};
-
-// LDS row of one Gaussian: RS 16-bit slots.  Slot (h, i) of MFMA 0 is row[8h + i]; MFMA 1
-// (splits == 3) uses row[16 + 8h + i].
-//   splits 1: [k0..k5, 0, 0 | 0 x 8]
-//   splits 2: [k0..k5, l0, l1 | l2..l5, 0 x 4]
-//   splits 3: the splits-2 row, then [m0..m5, 0, 0 | 0 x 8]
-template <int PREC, int S>
-__device__ __forceinline__ void build_row(uint16_t *row, float u, float v, float a, float b, float c, float lno) {
-  using N = Narrow<PREC>;
-  const float p3 = fmaf(a, u, b * v), p4 = fmaf(b, u, c * v);
-  const float q = fmaf(u, p3, v * p4);
-  float k[6] = {-0.5f * kLog2e * a, -kLog2e * b, -0.5f * kLog2e * c, kLog2e * p3, kLog2e * p4,
-                kLog2e * fmaf(-0.5f, q, lno)};
-  uint16_t hi[6], lo[6], lo2[6];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    hi[i] = N::enc(k[i]);
-    float r = (k[i] - N::dec(hi[i])) * N::kScale;
-    lo[i] = N::enc(r);
-    r = (r - N::dec(lo[i])) * N::kScale;
-    lo2[i] = N::enc(r);
-  }
-  short8 v0, v1;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) v0[i] = (short)hi[i];
-  v0[6] = S >= 2 ? (short)lo[0] : 0;
-  v0[7] = S >= 2 ? (short)lo[1] : 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) v1[i] = S >= 2 ? (short)lo[2 + i] : 0;
-#pragma unroll
-  for (int i = 4; i < 8; ++i) v1[i] = 0;
-  *reinterpret_cast<short8 *>(row) = v0;
-  *reinterpret_cast<short8 *>(row + 8) = v1;
-  if (S == 3) {
-    short8 v2, v3;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) v2[i] = (short)lo2[i];
-    v2[6] = v2[7] = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v3[i] = 0;
-    *reinterpret_cast<short8 *>(row + 16) = v2;
-    *reinterpret_cast<short8 *>(row + 24) = v3;
-  }
-}
-
-// Quadrant culling.  Wave w blends the pixels of quadrant (w & 1, w >> 1) only, so a row that
-// cannot pass the 1/255 alpha cut at any pixel centre of that quadrant is left out of the
-// wave's MFMA blocks.  Bit qx + 2 qy of the mask is set unless the minimum of the conic's
-// quadratic form q(d) = a dx^2 + 2 b dx dy + c dy^2 over the quadrant's pixel centres exceeds
-// 2 ln(255 o) + kQuadMargin (alpha >= 1/255 reads q <= 2 ln(255 o)).  The margin in q, 0.72
-// in log2(alpha), is far above the rounding of this test and of the split 16-bit power, so a
-// left-out row is one whose D stays below the cut at every pixel of the quadrant: the blended
-// result is the one every row would give.
-//
-// A rectangle that does not hold the centre has its minimum on an edge that faces the
-// centre.  Along the facing horizontal edge y = ey the minimum is at dx = -b dy / a clamped
-// into the edge, and q = a (dx + b dy / a)^2 + (det / a) dy^2 holds only non-negative terms;
-// likewise along the facing vertical edge.  Clamping the centre into the rectangle picks the
-// facing edges; a centre inside gives q = 0.
-constexpr float kQuadMargin = 1.0f;
-constexpr float kQuadQ0 = 11.0825270f + kQuadMargin;   // 2 ln 255 + margin
-
-__device__ __forceinline__ uint32_t quad_mask(float u, float v, float a, float b, float c, float lno) {
-  const float Q = fmaf(2.0f, lno, kQuadQ0);
-  if (!(Q > 0.0f)) return 0u;               // o < 1/255 e^{-margin/2}: never reaches the cut
-  const float det = (float)((double)a * c - (double)b * b);
-  if (!(a > 0.0f && c > 0.0f && det > 0.0f)) return 0xFu;
-  const float ia = __builtin_amdgcn_rcpf(a), ic = __builtin_amdgcn_rcpf(c);
-  const float ba = b * ia, bc = b * ic, ga = det * ia, gc = det * ic;
-  uint32_t mask = 0;
-#pragma unroll
-  for (int qy = 0; qy < 2; ++qy) {
-#pragma unroll
-    for (int qx = 0; qx < 2; ++qx) {
-      const float xl = (float)(8 * qx - 8), xh = (float)(8 * qx - 1);
-      const float yl = (float)(8 * qy - 8), yh = (float)(8 * qy - 1);
-      // facing horizontal edge
-      const float dy = fminf(fmaxf(v, yl), yh) - v;
-      const float th = -ba * dy;
-      const float sh = fminf(fmaxf(th, xl - u), xh - u) - th;
-      const float qh = fmaf(a * sh, sh, ga * dy * dy);
-      // facing vertical edge
-      const float dx = fminf(fmaxf(u, xl), xh) - u;
-      const float tv = -bc * dx;
-      const float sv = fminf(fmaxf(tv, yl - v), yh - v) - tv;
-      const float qv = fmaf(c * sv, sv, gc * dx * dx);
-      if (fminf(qh, qv) <= Q) mask |= 1u << (qx + 2 * qy);
-    }
-  }
-  return mask;
-}
-
-// Compacts, in order, the rows [0, nrows) whose quadrant mask holds this wave's bit into the
-// wave's own list; returns its length (uniform).
-__device__ __forceinline__ int wave_list(const uint8_t *qm, int nrows, uint8_t *wl) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int n = 0;
-  for (int r0 = 0; r0 < nrows; r0 += 64) {
-    const int r = r0 + lane;
-    const bool in = r < nrows && ((qm[r] >> w) & 1u);
-    const uint64_t b = __ballot(in);
-    if (in) wl[n + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u))] = (uint8_t)r;
-    n += __popcll(b);
-  }
-  // the list is written and read by lanes of this wave only
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  return n;
-}
-
+using namespace mfma;
 struct TileState {
   float T, C0, C1, C2, W, cut;
-  uint32_t nstop, nblend;
+  uint32_t nstop, nblend, last;   // last: 1 + list position of the last blended Gaussian
 };
 
 // Runs the rows wl[0, n) of buffer A/col (ascending indices) for one member tile.  Rows are
 // gathered from LDS by index; the slots past n in the last block take a row whose D is -1000
 // at every pixel, so they never pass the cut.  The block's 32 colours (and row indices) are
 // copied to the wave's own buffer wc, so the blend reads them at fixed offsets.
+// tpos (auxiliary outputs of the grouped kernel only): position of each staged row in the
+// member tile's own list, within the chunk; without it the row index is that position.
 template <int PREC, int S, bool AUX>
 __device__ __forceinline__ void process_rows(const uint16_t *sA, const float *scol, const uint8_t *wl, int n,
                                              float4 *wc, short8 B0, short8 B1, short8 B20, short8 B21,
-                                             TileState &st, uint32_t row_base) {
+                                             TileState &st, uint32_t row_base, const uint8_t *tpos = nullptr) {
   using N = Narrow<PREC>;
   constexpr int RS = (S == 3) ? 32 : 16;
   const int lane = threadIdx.x & 63;
@@ -219,7 +69,8 @@ __device__ __forceinline__ void process_rows(const uint16_t *sA, const float *sc
     const int ri = real ? (int)wl[slot] : 0;
     const uint16_t *rp = sA + (size_t)ri * RS + 8 * (lane >> 5);
     const short8 a = real ? *reinterpret_cast<const short8 *>(rp) : pad;
-    const float4 gc = make_float4(scol[ri], scol[kBlock + ri], scol[2 * kBlock + ri], __int_as_float(ri));
+    const int rpos = (AUX && tpos) ? (int)tpos[ri] : ri;
+    const float4 gc = make_float4(scol[ri], scol[kBlock + ri], scol[2 * kBlock + ri], __int_as_float(rpos));
     float16v z = {};
     float16v d0 = N::mma(a, B0, z);
     float16v d1 = N::mma(a, B1, z);
@@ -264,6 +115,7 @@ __device__ __forceinline__ void process_rows(const uint16_t *sA, const float *sc
         if (AUX) {
           st.W += wgt;
           st.nblend += 1u;
+          st.last = wgt > 0.0f ? row_base + (uint32_t)__float_as_int(cl.w) + 1 : st.last;
         }
       }
     }
@@ -290,40 +142,169 @@ struct MfmaShared {
   float4 wc[4][32];                // each wave's colours of its current block (wave-private)
 };
 
-// Pixel-side operand: phi of this lane's panel pixel (n = lane % 32) in both panels.
-template <int PREC>
-__device__ __forceinline__ void make_pixel_operand(short8 &B0, short8 &B1, short8 &B20, short8 &B21) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+// ---- grouped tiles with the Gaussian-side rows built once per group -----------------------
+// Grouped rasterization with a shared Gaussian (Algorithm 1): a chunk of the group's list is
+// staged once, and each entry's Gaussian-side row is built once, in the frame of the whole
+// group (origin at the group's centre), for every member tile.  The member tiles differ only in
+// the pixel-side operand: phi of the tile's pixels in the group frame.  This is done for 2x2
+// groups (|x|, |y| <= 16: phi exact in FP16 and BF16); larger frames keep the per-tile rows
+// below, because the terms of the power grow with the frame's size squared while the FP32
+// accumulation and the split operands keep a fixed relative precision (a 4x4 frame measured
+// ~1e-3 of image error against 1x1 tiles' ~5e-6).  Each wave then walks, per member tile, the rows
+// whose quadrant mask has its bit (the entry's membership bit folded in), with no workgroup
+// barrier between member tiles.  In exact arithmetic this is the per-tile power; in FP16/BF16
+// the split operands now multiply larger phi entries, so the grouped image matches the
+// ungrouped one to the operands' rounding (held to the oracle's tolerance) instead of bit for bit.
+template <int G, int PREC>
+struct GroupFrame {
+  static constexpr bool value = G == 2;
+};
+
+template <int S>
+struct MfmaGroupShared {
+  static constexpr int RS = (S == 3) ? 32 : 16;
+  static constexpr int NTP = 4;    // member tiles per workgroup: a 2x2 group
+  __align__(16) uint16_t A[kBlock * RS];
+  float col[3][kBlock];
+  uint16_t qm[kBlock];             // bit 4 j + q: quadrant q of the workgroup's member tile j
+  uint8_t tpos[NTP][kBlock];       // auxiliary outputs: row position in member tile j's list
+  uint32_t wcnt[NTP][4];
+  uint32_t alive[2][4];
+  uint8_t wl[4][kBlock];
+  float4 wc[4][32];
+};
+
+template <int G, int PREC, int S, bool AUX>
+__device__ __forceinline__ void raster_bin_mfma_group(const RasterJob &J, const RasterParams &P, int item,
+                                                      MfmaGroupShared<S> &sm) {
+  constexpr int NTP = MfmaGroupShared<S>::NTP;
+  constexpr int RS = MfmaGroupShared<S>::RS;
+  const int bin = G >= 4 ? item / J.parts : item;
+  const int k0 = G >= 4 ? (item % J.parts) * (G * G / J.parts) : 0;   // first member tile of the workgroup
+  const int gx = bin % J.GX, gy = bin / J.GX;
+  const int ox = gx * G * kTile, oy = gy * G * kTile;
+  const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int qx0 = (w & 1) * 8, qy0 = (w >> 1) * 8;
-  {
-    using N = Narrow<PREC>;
-    const int n = lane & 31, h = lane >> 5;
-    const float inv = 1.0f / N::kScale, inv2 = inv * inv;
+  const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
+  const double fx0 = (double)ox + 8.0 * G + 0.5, fy0 = (double)oy + 8.0 * G + 0.5;   // group frame origin
+
+  TileState st[NTP];
+  uint32_t rows_done[NTP];
+  uint32_t alive_w = 0;            // uniform per wave: member tiles where this wave's pixels still blend
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      const float x = (float)(qx0 + (n & 7) - 8), y = (float)(qy0 + (n >> 3) + 4 * p - 8);
-      const float phi[6] = {x * x, x * y, y * y, x, y, 1.0f};
-      short8 b, b2;
-      if (h == 0) {
-#pragma unroll
-        for (int i = 0; i < 6; ++i) b[i] = (short)N::enc(phi[i]);
-        b[6] = (short)N::enc(phi[0] * inv);
-        b[7] = (short)N::enc(phi[1] * inv);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) b2[i] = (short)N::enc(phi[i] * inv2);
-        b2[6] = b2[7] = 0;
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) b[i] = (short)N::enc(phi[2 + i] * inv);
-#pragma unroll
-        for (int i = 4; i < 8; ++i) b[i] = 0;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) b2[i] = 0;
-      }
-      if (p == 0) { B0 = b; B20 = b2; } else { B1 = b; B21 = b2; }
-    }
+  for (int j = 0; j < NTP; ++j) {
+    const int k = k0 + j;
+    const int tx0 = ox + (k % G) * kTile, ty0 = oy + (k / G) * kTile;
+    const bool inside = (tx0 + px < J.W) && (ty0 + py < J.H);
+    st[j].T = 1.0f; st[j].C0 = st[j].C1 = st[j].C2 = 0.0f; st[j].W = 0.0f;
+    st[j].cut = inside ? kCutLog2 : INFINITY;
+    st[j].nstop = 0; st[j].nblend = 0; st[j].last = 0;
+    rows_done[j] = 0;
+    if (__ballot(inside) != 0) alive_w |= 1u << j;
   }
 
+  int it = 0;
+  for (uint32_t cs = start; cs < end; cs += kBlock) {
+    const int cnt = (int)min((uint32_t)kBlock, end - cs);
+    if (it > 0) {
+      // every wave is done with the previous chunk and has posted whether it still blends
+      __syncthreads();
+      const uint32_t any = sm.alive[(it - 1) & 1][0] | sm.alive[(it - 1) & 1][1] | sm.alive[(it - 1) & 1][2] |
+                           sm.alive[(it - 1) & 1][3];
+      if (!any) break;
+    }
+    uint32_t mk = 0;
+    if (t < cnt) {
+      const uint32_t e = cs + t;
+      const uint32_t g = J.vals[e];
+      const double2 m = J.xy[g];
+      const float4 co = J.conic[g];
+      const float4 cl = J.rgb[g];
+      mk = (uint32_t) static_cast<const uint16_t *>(J.masks)[e];
+      const float u = (float)(m.x - fx0), v = (float)(m.y - fy0);
+      const float lno = __logf(co.w);
+      build_row<PREC, S>(&sm.A[t * RS], u, v, co.x, co.y, co.z, lno);
+      sm.col[0][t] = cl.x;
+      sm.col[1][t] = cl.y;
+      sm.col[2][t] = cl.z;
+      uint32_t q = 0;
+#pragma unroll
+      for (int j = 0; j < NTP; ++j) {
+        const int k = k0 + j;
+        if ((mk >> k) & 1u) {
+          // the quadrant test in member tile k's own frame
+          const float ut = u + (float)(8 * G - 8 - (k % G) * kTile), vt = v + (float)(8 * G - 8 - (k / G) * kTile);
+          q |= (P.all_rows ? 0xFu : quad_mask(ut, vt, co.x, co.y, co.z, lno)) << (4 * j);
+        }
+      }
+      sm.qm[t] = (uint16_t)q;
+    }
+    if (AUX) {
+#pragma unroll
+      for (int j = 0; j < NTP; ++j) {
+        const uint64_t bk = __ballot((mk >> (k0 + j)) & 1u);
+        if (lane == 0) sm.wcnt[j][w] = (uint32_t)__popcll(bk);
+      }
+    }
+    __syncthreads();
+    if (AUX) {
+      // each row's position in every member tile's list (entries of the chunk with its bit)
+#pragma unroll
+      for (int j = 0; j < NTP; ++j) {
+        const uint64_t bk = __ballot((mk >> (k0 + j)) & 1u);
+        const uint32_t woff = (w > 0 ? sm.wcnt[j][0] : 0u) + (w > 1 ? sm.wcnt[j][1] : 0u) +
+                              (w > 2 ? sm.wcnt[j][2] : 0u);
+        sm.tpos[j][t] = (uint8_t)(woff + __builtin_amdgcn_mbcnt_hi((uint32_t)(bk >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)bk, 0u)));
+      }
+      __syncthreads();
+    }
+    // one copy of the tile step: the member tile's state is moved into registers for it
+#pragma unroll 1
+    for (int j = 0; j < NTP; ++j) {
+      if (!((alive_w >> j) & 1u)) continue;
+      const int k = k0 + j;
+      short8 B0, B1, B20, B21;
+      make_pixel_operand<PREC>(B0, B1, B20, B21, (k % G) * kTile - 8 * G + 8, (k / G) * kTile - 8 * G + 8);
+      const int nw = wave_list_bit(sm.qm, cnt, 4 * j + w, sm.wl[w]);
+      TileState cur = st[j];
+      process_rows<PREC, S, AUX>(sm.A, &sm.col[0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, cur, rows_done[j],
+                                 AUX ? sm.tpos[j] : nullptr);
+      st[j] = cur;
+      if (__ballot(cur.cut != INFINITY) == 0) alive_w &= ~(1u << j);
+    }
+    if (AUX) {
+#pragma unroll
+      for (int j = 0; j < NTP; ++j)
+        rows_done[j] += sm.wcnt[j][0] + sm.wcnt[j][1] + sm.wcnt[j][2] + sm.wcnt[j][3];
+    }
+    if (lane == 0) sm.alive[it & 1][w] = alive_w != 0;
+    ++it;
+  }
+
+  const int64_t HW = (int64_t)J.W * J.H;
+#pragma unroll
+  for (int j = 0; j < NTP; ++j) {
+    const int k = k0 + j;
+    const int xx = ox + (k % G) * kTile + px, yy = oy + (k / G) * kTile + py;
+    if (xx >= J.W || yy >= J.H) continue;
+    const int64_t pix = (int64_t)yy * J.W + xx;
+    J.image[pix] = st[j].C0 + st[j].T * P.bg[0];
+    J.image[HW + pix] = st[j].C1 + st[j].T * P.bg[1];
+    J.image[2 * HW + pix] = st[j].C2 + st[j].T * P.bg[2];
+    if (AUX) {
+      int plane = 0;
+      if (P.aux_flags & GS_AUX_TFINAL) J.aux[(plane++) * HW + pix] = st[j].T;
+      if (P.aux_flags & GS_AUX_WSUM) J.aux[(plane++) * HW + pix] = st[j].W;
+      if (P.aux_flags & GS_AUX_NEVAL) {
+        const bool stopped = st[j].cut == INFINITY;
+        J.aux[(plane++) * HW + pix] = (float)(stopped ? st[j].nstop : rows_done[j]);
+      }
+      if (P.aux_flags & GS_AUX_NBLEND) J.aux[(plane++) * HW + pix] = (float)st[j].nblend;
+      if (P.aux_flags & GS_AUX_LAST) J.aux[(plane++) * HW + pix] = (float)st[j].last;
+    }
+  }
 }
 
 // Renders work item `item` of job J (one workgroup): member tiles
@@ -357,7 +338,7 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
     const bool inside = (tx0 + px < J.W) && (ty0 + py < J.H);
     st[k].T = 1.0f; st[k].C0 = st[k].C1 = st[k].C2 = 0.0f; st[k].W = 0.0f;
     st[k].cut = inside ? kCutLog2 : INFINITY;
-    st[k].nstop = 0; st[k].nblend = 0;
+    st[k].nstop = 0; st[k].nblend = 0; st[k].last = 0;
     rows_done[k] = 0;
     if (k >= k0 && k < k1 && tx0 < J.W && ty0 < J.H) alive_mask |= (TileMask)1 << k;
   }
@@ -490,6 +471,7 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
         J.aux[(plane++) * HW + pix] = (float)(stopped ? st[k].nstop : rows_done[k]);
       }
       if (P.aux_flags & GS_AUX_NBLEND) J.aux[(plane++) * HW + pix] = (float)st[k].nblend;
+      if (P.aux_flags & GS_AUX_LAST) J.aux[(plane++) * HW + pix] = (float)st[k].last;
     }
   }
 }
@@ -499,21 +481,39 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
 // XCD a contiguous band of tiles (for L2 reuse of shared records) left the XCDs holding the
 // dense bands running last and was slower (105 vs 87 us at 1080p / 1M Gaussians).  (Forcing
 // 64 VGPRs for 8 waves per SIMD spilled to scratch and was slower than the 72 VGPRs here.)
-template <int G, int PREC, int S, bool AUX>
+// The LDS layout and the renderer of one work item: rows in the group frame where its pixel
+// operand is exact, per-tile rows otherwise.
+// GF: the group-frame path (only where GroupFrame holds; GS_OPT_TILE_ROWS selects the per-tile
+// rows there as well, bit-identical to 1x1 tiles).
+template <int G, int PREC, int S, bool GF>
+struct SharedFor {
+  using type = typename std::conditional<GF, MfmaGroupShared<S>, MfmaShared<G, S>>::type;
+};
+
+template <int G, int PREC, int S, bool AUX, bool GF, typename SM>
+__device__ __forceinline__ void raster_item(const RasterJob &J, const RasterParams &P, int item, SM &sm, short8 B0,
+                                            short8 B1, short8 B20, short8 B21) {
+  if constexpr (GF)
+    raster_bin_mfma_group<G, PREC, S, AUX>(J, P, item, sm);
+  else
+    raster_bin_mfma<G, PREC, S, AUX>(J, P, item, sm, B0, B1, B20, B21);
+}
+
+template <int G, int PREC, int S, bool AUX, bool GF>
 __global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParams P) {
-  __shared__ MfmaShared<G, S> sm;
+  __shared__ typename SharedFor<G, PREC, S, GF>::type sm;
   short8 B0, B1, B20, B21;
   make_pixel_operand<PREC>(B0, B1, B20, B21);
-  raster_bin_mfma<G, PREC, S, AUX>(J, P, blockIdx.x, sm, B0, B1, B20, B21);
+  raster_item<G, PREC, S, AUX, GF>(J, P, blockIdx.x, sm, B0, B1, B20, B21);
 }
 
 // Persistent batched rasterizer: workgroups take (job, item) work items from *counter until
 // all `total` are done; job j owns items [jobs[j].bin0, jobs[j].bin0 + jobs[j].items).
-template <int G, int PREC, int S, bool AUX>
+template <int G, int PREC, int S, bool AUX, bool GF>
 __global__ __launch_bounds__(kBlock) void k_raster_mfma_batch(const BatchTable tb,
                                                               RasterParams P, uint32_t *counter) {
   const int total = tb.total;
-  __shared__ MfmaShared<G, S> sm;
+  __shared__ typename SharedFor<G, PREC, S, GF>::type sm;
   __shared__ int s_item;
   short8 B0, B1, B20, B21;
   make_pixel_operand<PREC>(B0, B1, B20, B21);
@@ -529,7 +529,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_mfma_batch(const BatchTable t
       if (tb.jobs[mid].bin0 <= item) lo = mid; else hi = mid;
     }
     const RasterJob J = tb.jobs[lo];
-    raster_bin_mfma<G, PREC, S, AUX>(J, P, item - J.bin0, sm, B0, B1, B20, B21);
+    raster_item<G, PREC, S, AUX, GF>(J, P, item - J.bin0, sm, B0, B1, B20, B21);
   }
 }
 
@@ -539,15 +539,23 @@ struct BatchArgs {
   uint32_t *counter;
 };
 
-template <int G, int PREC, int S, bool AUX>
-hipError_t launch_t(const RasterJob &j, const RasterParams &p, const BatchArgs *b, hipStream_t st) {
+template <int G, int PREC, int S, bool AUX, bool GF>
+hipError_t launch_gf(const RasterJob &j, const RasterParams &p, const BatchArgs *b, hipStream_t st) {
   if (b) {
-    hipLaunchKernelGGL((k_raster_mfma_batch<G, PREC, S, AUX>), dim3((unsigned)b->grid), dim3(kBlock), 0, st, *b->table, p,
-                       b->counter);
+    hipLaunchKernelGGL((k_raster_mfma_batch<G, PREC, S, AUX, GF>), dim3((unsigned)b->grid), dim3(kBlock), 0, st,
+                       *b->table, p, b->counter);
   } else {
-    hipLaunchKernelGGL((k_raster_mfma<G, PREC, S, AUX>), dim3((unsigned)j.items), dim3(kBlock), 0, st, j, p);
+    hipLaunchKernelGGL((k_raster_mfma<G, PREC, S, AUX, GF>), dim3((unsigned)j.items), dim3(kBlock), 0, st, j, p);
   }
   return hipGetLastError();
+}
+
+template <int G, int PREC, int S, bool AUX>
+hipError_t launch_t(const RasterJob &j, const RasterParams &p, const BatchArgs *b, hipStream_t st) {
+  if constexpr (GroupFrame<G, PREC>::value) {
+    if (!p.tile_rows) return launch_gf<G, PREC, S, AUX, true>(j, p, b, st);
+  }
+  return launch_gf<G, PREC, S, AUX, false>(j, p, b, st);
 }
 
 template <int G, int PREC>

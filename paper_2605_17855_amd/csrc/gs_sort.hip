@@ -148,12 +148,23 @@ __global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t *counts, u
 // Stable scatter of one tile: ranks from per-wave digit counters; the tile's start for digit
 // d is (keys with a smaller digit) + offsets[d][tile]; keys are placed in LDS in tile-local
 // digit order and then stored so that consecutive lanes write consecutive addresses.
+// Final placement of the bin sort's last pass (fin != nullptr): the value of each key is the
+// rank of its Gaussian in depth order; instead of the rank the pass writes the Gaussian index
+// order[rank] to vals and the 64-bit key (bin << 32) | dkeys[rank] to keys (the two V-sized
+// arrays stay in cache), next to the sorted bin keys.
+struct FinalOut {
+  const uint32_t *order;   // visible Gaussians in depth order
+  const uint32_t *dkeys;   // their depth bits
+  uint32_t *vals;          // Gaussian index of each sorted entry
+  uint64_t *keys;          // 64-bit key of each sorted entry
+};
+
 template <typename KT, int R>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const uint32_t *vin, KT *kout, uint32_t *vout,
                                                           uint64_t n_host, const uint32_t *n_dev, int shift, int nbits,
                                                           uint32_t tiles_max, const uint32_t *offsets,
                                                           const uint32_t *totals, const uint32_t *aux_in,
-                                                          uint32_t *aux_out) {
+                                                          uint32_t *aux_out, FinalOut fin) {
   constexpr int kRounds = SortTile<R>::kRounds, kWaveTile = SortTile<R>::kWaveTile, kSortTile = SortTile<R>::kTile;
   __shared__ uint32_t wcnt[4][kDigits];
   __shared__ uint32_t bstart[kDigits];
@@ -190,10 +201,17 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
     const uint32_t old = wcnt[w][d];
     pos[r] = old + rank;
-    // every lane of the wave has read the counter before the group's first lane updates it
+    // every lane of the wave has read the counter before the group's first lane updates it,
+    // and the update is visible to the whole wave before the next round reads (the counters
+    // are written and read by lanes of this wave only; the fences order the LDS accesses
+    // across the barrier for the compiler as well as the hardware)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (valid && rank == 0) wcnt[w][d] = old + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   __syncthreads();
   // thread t = digit: tile-local start (scan over digits of the tile's counts) and global
@@ -221,6 +239,29 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
   }
   __syncthreads();
   const uint32_t nvalid = (uint32_t)((n - tile0) < (uint64_t)kSortTile ? (n - tile0) : (uint64_t)kSortTile);
+  if (fin.vals) {
+    // all gathers of the thread first, then the stores (several round trips in flight)
+    uint32_t gi[kRounds], dk[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const uint32_t i = (uint32_t)t + (uint32_t)r * kBlock;
+      const uint32_t v = i < nvalid ? s_val[i] : 0u;
+      gi[r] = i < nvalid ? fin.order[v] : 0u;
+      dk[r] = i < nvalid ? fin.dkeys[v] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const uint32_t i = (uint32_t)t + (uint32_t)r * kBlock;
+      if (i >= nvalid) break;
+      const KT k = s_key[i];
+      const uint32_t d = (uint32_t)(k >> shift) & dmask;
+      const uint32_t p = gbase[d] + (i - bstart[d]);
+      kout[p] = k;
+      fin.vals[p] = gi[r];
+      fin.keys[p] = ((uint64_t)(uint32_t)k << 32) | dk[r];
+    }
+    return;
+  }
   for (uint32_t i = t; i < nvalid; i += kBlock) {
     const KT k = s_key[i];
     const uint32_t d = (uint32_t)(k >> shift) & dmask;
@@ -231,22 +272,47 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
   }
 }
 
-// Depth keys of the visible Gaussians (key[i] = bits(depth of order[i]), i < *nvis), and the
-// zeroing of the bin ranges.
+// Depth keys of the visible Gaussians (key[i] = bits(depth of order[i]), i < *nvis), the entry
+// and visible counts, and the first depth pass's per-tile digit counts (one workgroup per sort
+// tile of R x 256 keys; counts[d * gridDim.x + tile] for the digit bits [0, nbits0)).
+template <int R>
 __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis,
                                                        uint32_t *keys, const uint64_t *K, uint64_t *counts,
-                                                       uint64_t *host_counts) {
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+                                                       uint64_t *host_counts, int nbits0, uint32_t *dcounts) {
+  constexpr int kSortTile = SortTile<R>::kTile;
+  __shared__ uint32_t h[kDigits];
   const uint32_t V = *nvis;
   if (blockIdx.x == 0 && threadIdx.x == 0) {   // the entry and visible counts, side by side
     const uint64_t k = *K;
     counts[0] = k;
     counts[1] = V;
-    host_counts[0] = k;    // pinned host memory, read by the host after the kernel's event
-    host_counts[1] = V;
+    if (host_counts) {     // the caller's pinned host memory, polled by the host
+      host_counts[0] = k;
+      host_counts[1] = V;
+    }
   }
-  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < V; i += stride)
-    keys[i] = __float_as_uint(rgb[order[i]].w);
+  const uint64_t tile0 = (uint64_t)blockIdx.x * kSortTile;
+  if (tile0 >= V) return;
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t dmask = (1u << nbits0) - 1u;
+  uint32_t g[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t i = tile0 + (uint64_t)r * kBlock + threadIdx.x;
+    g[r] = i < V ? order[i] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t i = tile0 + (uint64_t)r * kBlock + threadIdx.x;
+    if (i < V) {
+      const uint32_t k = __float_as_uint(rgb[g[r]].w);
+      keys[i] = k;
+      atomicAdd(&h[k & dmask], 1u);
+    }
+  }
+  __syncthreads();
+  dcounts[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
 // ---- binning: one thread per entry -------------------------------------------
@@ -269,14 +335,19 @@ __device__ __forceinline__ uint32_t local_gaussian(const uint64_t *s_pos, uint32
 
 // Stages the first-entry offsets of the Gaussians that own entries [e0, e0 + kBinItems) into
 // s_pos[0..span] (s_pos[l] = dpos[first + l]) and clears the bin ranges (grid-stride).
-__device__ __forceinline__ void stage_block_gaussians(const uint64_t *dpos, uint32_t nvis, uint64_t e0,
-                                                      uint64_t *s_pos, uint32_t *s_first, uint32_t *first,
-                                                      uint32_t *span, uint32_t *ranges, uint64_t nranges) {
-  // the bin ranges start empty (k_ranges writes the non-empty ones, two kernels later)
+template <int ITEMS>
+__device__ __forceinline__ void stage_block_gaussians(const uint64_t *dpos, const uint32_t *block_first, uint32_t nvis,
+                                                      uint64_t e0, uint64_t *s_pos, uint32_t *s_first,
+                                                      uint32_t *first, uint32_t *span, uint32_t *ranges,
+                                                      uint64_t nranges) {
+  // the bin ranges start empty (the ranges kernel writes the non-empty ones after the sort)
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < nranges; i += (uint64_t)gridDim.x * kBlock)
     ranges[i] = 0u;
   const int t = threadIdx.x, lane = t & 63;
-  if (t < 64) {
+  if (block_first) {
+    // recorded by the offset scan (e0 is a multiple of its 1,024-entry blocks)
+    if (t == 0) *s_first = block_first[e0 / kFirstsBlock];
+  } else if (t < 64) {
     // 64-ary search for the last Gaussian i with dpos[i] <= e0, over [lo, hi)
     uint32_t lo = 0, hi = nvis;
     while (hi - lo > 1) {
@@ -294,22 +365,34 @@ __device__ __forceinline__ void stage_block_gaussians(const uint64_t *dpos, uint
   }
   __syncthreads();
   *first = *s_first;
-  *span = (nvis - *first) < (uint32_t)kBinItems ? (nvis - *first) : (uint32_t)kBinItems;
+  *span = (nvis - *first) < (uint32_t)ITEMS ? (nvis - *first) : (uint32_t)ITEMS;
   for (uint32_t i = t; i <= *span; i += kBlock) s_pos[i] = dpos[*first + i];
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const uint64_t *dpos, uint32_t nvis,
+// The first radix pass's per-tile digit counts, taken where the keys are written (the binning
+// workgroup covers exactly one sort tile): counts[d * tiles + tile] for the digit bits [0, nbits0).
+struct FirstCounts {
+  uint32_t *counts;   // nullptr: no sort follows
+  int nbits0;
+};
+
+template <int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const uint64_t *dpos,
+                                                    const uint32_t *block_first, uint32_t nvis,
                                                     uint64_t K, const ushort4 *rect, int G, int GX,
                                                     uint32_t *bin_keys, uint32_t *vals, uint32_t *ranges,
-                                                    uint64_t nranges) {
-  __shared__ uint64_t s_pos[kBinItems + 1];
+                                                    uint64_t nranges, FirstCounts fc) {
+  __shared__ uint64_t s_pos[ITEMS + 1];
   __shared__ uint32_t s_first;
-  const uint64_t e0 = (uint64_t)blockIdx.x * kBinItems;
+  __shared__ uint32_t h[kDigits];
+  const uint64_t e0 = (uint64_t)blockIdx.x * ITEMS;
+  h[threadIdx.x] = 0;
   uint32_t first, span;
-  stage_block_gaussians(dpos, nvis, e0, s_pos, &s_first, &first, &span, ranges, nranges);
+  stage_block_gaussians<ITEMS>(dpos, block_first, nvis, e0, s_pos, &s_first, &first, &span, ranges, nranges);
+  const uint32_t dmask = (1u << fc.nbits0) - 1u;
 #pragma unroll
-  for (int it = 0; it < kBinItems / kBlock; ++it) {
+  for (int it = 0; it < ITEMS / kBlock; ++it) {
     const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
     if (e < K) {
       const uint32_t l = local_gaussian(s_pos, span, e);
@@ -320,9 +403,15 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
       const int gx0 = r.x / G, gx1 = (r.z - 1) / G, gy0 = r.y / G;
       const int wdt = gx1 - gx0 + 1;
       const int gy = gy0 + (int)(j / (uint32_t)wdt), gx = gx0 + (int)(j % (uint32_t)wdt);
-      bin_keys[e] = (uint32_t)(gy * GX + gx);
-      vals[e] = rank;   // the Gaussian's rank in depth order; k_ranges turns it into its index
+      const uint32_t bin = (uint32_t)(gy * GX + gx);
+      bin_keys[e] = bin;
+      vals[e] = rank;   // the Gaussian's rank in depth order; the last sort pass turns it into its index
+      if (fc.counts) atomicAdd(&h[bin & dmask], 1u);
     }
+  }
+  if (fc.counts) {
+    __syncthreads();
+    fc.counts[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
   }
 }
 
@@ -331,19 +420,24 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
 // rows until its own.  (Measured on the 1M-Gaussian 1080p frame, this beat an LDS table of
 // row spans built per workgroup: the span of a row is a few instructions, the table's
 // dependent loads and prefix pass are not.)
-__global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order, const uint64_t *dpos, uint32_t nvis,
+template <int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order, const uint64_t *dpos,
+                                                          const uint32_t *block_first, uint32_t nvis,
                                                           uint64_t K, const ushort4 *rect, const double2 *xy,
                                                           const float4 *conic, int TX, int G, int GX,
                                                           uint32_t *bin_keys, uint32_t *vals, uint32_t *ranges,
-                                                          uint64_t nranges) {
-  __shared__ uint64_t s_pos[kBinItems + 1];
+                                                          uint64_t nranges, FirstCounts fc) {
+  __shared__ uint64_t s_pos[ITEMS + 1];
   __shared__ uint32_t s_first;
-  const uint64_t e0 = (uint64_t)blockIdx.x * kBinItems;
+  __shared__ uint32_t h[kDigits];
+  const uint64_t e0 = (uint64_t)blockIdx.x * ITEMS;
   const int lane = threadIdx.x & 63;
+  h[threadIdx.x] = 0;
   uint32_t first, span;
-  stage_block_gaussians(dpos, nvis, e0, s_pos, &s_first, &first, &span, ranges, nranges);
+  stage_block_gaussians<ITEMS>(dpos, block_first, nvis, e0, s_pos, &s_first, &first, &span, ranges, nranges);
+  const uint32_t dmask = (1u << fc.nbits0) - 1u;
 #pragma unroll
-  for (int it = 0; it < kBinItems / kBlock; ++it) {
+  for (int it = 0; it < ITEMS / kBlock; ++it) {
     const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
     const bool valid = e < K;
     if (__ballot(valid) == 0) continue;
@@ -433,8 +527,13 @@ __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order,
     }
     if (valid) {
       bin_keys[e] = bin;
-      vals[e] = rank;   // the Gaussian's rank in depth order; k_ranges turns it into its index
+      vals[e] = rank;   // the Gaussian's rank in depth order; the last sort pass turns it into its index
+      if (fc.counts) atomicAdd(&h[bin & dmask], 1u);
     }
+  }
+  if (fc.counts) {
+    __syncthreads();
+    fc.counts[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
   }
 }
 
@@ -500,6 +599,50 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, con
   }
 }
 
+// Bin ranges and (group > 1) membership masks once the last bin pass has placed the final
+// Gaussian indices and 64-bit keys: only the sorted bin keys are read for the ranges.
+__global__ __launch_bounds__(kBlock) void k_ranges_final(const uint32_t *bin_keys, uint64_t n, const uint32_t *vals,
+                                                         const ushort4 *rect, const double2 *xy, const float4 *conic,
+                                                         int tight, int G, int GX, uint32_t *ranges, void *masks) {
+  const uint64_t base = (uint64_t)blockIdx.x * kBlock * kRangeItems + threadIdx.x;
+  uint32_t bin[kRangeItems], prev[kRangeItems], next[kRangeItems];
+#pragma unroll
+  for (int j = 0; j < kRangeItems; ++j) {
+    const uint64_t i = base + (uint64_t)j * kBlock;
+    const bool in = i < n;
+    bin[j] = in ? bin_keys[i] : 0u;
+    prev[j] = (in && i > 0) ? bin_keys[i - 1] : 0xFFFFFFFFu;
+    next[j] = (in && i + 1 < n) ? bin_keys[i + 1] : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (int j = 0; j < kRangeItems; ++j) {
+    const uint64_t i = base + (uint64_t)j * kBlock;
+    if (i >= n) break;
+    const uint32_t b = bin[j];
+    if (prev[j] != b) ranges[2 * (uint64_t)b] = (uint32_t)i;
+    if (next[j] != b) ranges[2 * (uint64_t)b + 1] = (uint32_t)(i + 1);
+    if (G > 1 && masks) {
+      const uint32_t g = vals[i];
+      const ushort4 rc = rect[g];
+      const int gx = (int)(b % (uint32_t)GX), gy = (int)(b / (uint32_t)GX);
+      uint64_t m = 0;
+      if (tight) {
+        const double2 mu = xy[g];
+        const float4 co = conic[g];
+        const TightEllipse el = tight_ellipse(mu.x, mu.y, co.x, co.y, co.z, co.w, rc.x, rc.z - 1, rc.y);
+        m = tight_group_mask(el, G, gx, gy, rc.w - 1);
+      } else {
+        const int x0 = max((int)rc.x - gx * G, 0), x1 = min((int)rc.z - gx * G, G);
+        const int y0 = max((int)rc.y - gy * G, 0), y1 = min((int)rc.w - gy * G, G);
+        const uint64_t row = ((1ull << (x1 - x0)) - 1ull) << x0;
+        for (int ly = y0; ly < y1; ++ly) m |= row << (ly * G);
+      }
+      if (G == 8) static_cast<uint64_t *>(masks)[i] = m;
+      else static_cast<uint16_t *>(masks)[i] = (uint16_t)m;
+    }
+  }
+}
+
 inline unsigned grid_for(uint64_t n, uint64_t per = kBlock) {
   const uint64_t b = (n + per - 1) / per;
   return (unsigned)(b ? b : 1);
@@ -527,27 +670,37 @@ size_t radix_tmp_bytes(uint64_t n) {
   return ((size_t)kDigits * (tiles ? tiles : 1) + kDigits) * sizeof(uint32_t);
 }
 
+// Digit width of the passes over key bits [lo, hi): passes of (nearly) equal width, at most
+// 8 bits each (13 bits -> 7 + 6, 32 -> 4 x 8).
+inline int pass_width(int lo, int hi) {
+  const int passes = (hi - lo + 7) / 8;
+  return (hi - lo + passes - 1) / passes;
+}
+
+// first_counted: the per-tile digit counts of the first pass are already in tmp (written where
+// the keys were produced).  fin: the last pass places final Gaussian indices and 64-bit keys.
 template <typename KT, int R>
 hipError_t radix_passes_r(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n,
                           const uint32_t *n_dev, int lo, int hi, void *tmp, hipStream_t st, bool *in_alt,
-                          const uint32_t *aux_in, uint32_t *aux_out) {
+                          const uint32_t *aux_in, uint32_t *aux_out, const FinalOut *fin, bool first_counted) {
   const uint32_t tiles = (uint32_t)((n + SortTile<R>::kTile - 1) / SortTile<R>::kTile);
   uint32_t *counts = static_cast<uint32_t *>(tmp);
   uint32_t *totals = counts + (uint64_t)kDigits * tiles;
   KT *kin = keys, *kout = keys_alt;
   uint32_t *vin = vals, *vout = vals_alt;
-  // passes of (nearly) equal width, at most 8 bits each: 13 bits -> 7 + 6, 32 -> 4 x 8
-  const int passes = (hi - lo + 7) / 8;
-  const int width = (hi - lo + passes - 1) / passes;
+  const int width = pass_width(lo, hi);
+  const FinalOut none{nullptr, nullptr, nullptr, nullptr};
   for (int shift = lo; shift < hi; shift += width) {
     const int bits = (hi - shift) < width ? (hi - shift) : width;
     const bool last = shift + width >= hi;
-    hipLaunchKernelGGL((k_radix_count<KT, R>), dim3(tiles), dim3(kBlock), 0, st, kin, n, n_dev, shift, bits, tiles,
-                       counts);
+    if (!(first_counted && shift == lo))
+      hipLaunchKernelGGL((k_radix_count<KT, R>), dim3(tiles), dim3(kBlock), 0, st, kin, n, n_dev, shift, bits, tiles,
+                         counts);
     hipLaunchKernelGGL(k_radix_digit_scan, dim3(1u << bits), dim3(kBlock), 0, st, counts, tiles, totals, n, n_dev,
                        (uint32_t)SortTile<R>::kTile);
     hipLaunchKernelGGL((k_radix_scatter<KT, R>), dim3(tiles), dim3(kBlock), 0, st, kin, vin, kout, vout, n, n_dev,
-                       shift, bits, tiles, counts, totals, aux_in, last ? aux_out : nullptr);
+                       shift, bits, tiles, counts, totals, aux_in, last ? aux_out : nullptr,
+                       (last && fin) ? *fin : none);
     std::swap(kin, kout);
     std::swap(vin, vout);
     *in_alt = !*in_alt;
@@ -560,14 +713,15 @@ hipError_t radix_passes_r(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals
 template <typename KT>
 hipError_t radix_passes_t(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n,
                           const uint32_t *n_dev, int lo, int hi, void *tmp, hipStream_t st, bool *in_alt,
-                          const uint32_t *aux_in = nullptr, uint32_t *aux_out = nullptr) {
+                          const uint32_t *aux_in = nullptr, uint32_t *aux_out = nullptr,
+                          const FinalOut *fin = nullptr, bool first_counted = false) {
   *in_alt = false;
   if (hi <= lo || n <= 1) return hipSuccess;
   if (n <= kSmallSort)
     return radix_passes_r<KT, kSmallR>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt, aux_in,
-                                       aux_out);
+                                       aux_out, fin, first_counted);
   return radix_passes_r<KT, kLargeR>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt, aux_in,
-                                     aux_out);
+                                     aux_out, fin, first_counted);
 }
 
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
@@ -576,11 +730,18 @@ hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32
 }
 
 hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max,
-                             uint32_t *keys, const uint64_t *K, uint64_t *counts, uint64_t *host_counts,
+                             uint32_t *keys, const uint64_t *K, uint64_t *counts, uint64_t *host_counts, void *tmp,
                              hipStream_t st) {
-  const unsigned blocks = grid_for(n_max) < 2048u ? grid_for(n_max) : 2048u;   // grid-stride beyond
-  hipLaunchKernelGGL(k_depth_keys, dim3(blocks), dim3(kBlock), 0, st, order, rgb, nvis, keys, K, counts,
-                     host_counts);
+  // one workgroup per tile of the depth sort that follows (sort_depth, same n_max): its first
+  // pass's digit counts are taken here
+  const int nbits0 = pass_width(0, 32);
+  uint32_t *dcounts = static_cast<uint32_t *>(tmp);
+  if (n_max <= kSmallSort)
+    hipLaunchKernelGGL((k_depth_keys<kSmallR>), dim3((unsigned)sort_tiles(n_max ? n_max : 1)), dim3(kBlock), 0, st,
+                       order, rgb, nvis, keys, K, counts, host_counts, nbits0, dcounts);
+  else
+    hipLaunchKernelGGL((k_depth_keys<kLargeR>), dim3((unsigned)sort_tiles(n_max)), dim3(kBlock), 0, st, order, rgb,
+                       nvis, keys, K, counts, host_counts, nbits0, dcounts);
   return hipGetLastError();
 }
 
@@ -588,38 +749,55 @@ hipError_t sort_depth(uint32_t *order, const uint32_t *nvis, uint64_t n_max, uin
                       uint32_t *vals_alt, void *tmp, hipStream_t st, bool *in_alt, const uint32_t *count,
                       uint32_t *count_sorted) {
   return radix_passes_t<uint32_t>(keys, order, keys_alt, vals_alt, n_max, nvis, 0, 32, tmp, st, in_alt, count,
-                                  count_sorted);
+                                  count_sorted, nullptr, true);
 }
 
-hipError_t bin_and_sort(const uint32_t *order, const uint64_t *dpos, uint32_t V, uint64_t K, const uint16_t *rect,
-                        const double *xy, const float *conic, bool tight, const Grid &g, uint32_t *bkey,
-                        uint32_t *bval, uint32_t *bkey_alt, uint32_t *bval_alt, uint32_t *ranges, void *tmp,
-                        hipStream_t st, bool *in_alt) {
-  *in_alt = false;
+hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint64_t *dpos, const uint32_t *block_first,
+                        uint32_t V, uint64_t K,
+                        const uint16_t *rect, const double *xy, const float *conic, bool tight, const Grid &g,
+                        uint32_t *bkey, uint32_t *bval, uint32_t *bkey_alt, uint32_t *bval_alt, uint32_t *ranges,
+                        void *masks, uint32_t *vals, uint64_t *keys, void *tmp, hipStream_t st) {
   const uint64_t nranges = 2 * (uint64_t)g.nbins;
   if (K == 0) return launch_fill_u32(ranges, nranges, 0u, st);
   const ushort4 *r4 = reinterpret_cast<const ushort4 *>(rect);
   const double2 *m2 = reinterpret_cast<const double2 *>(xy);
   const float4 *c4 = reinterpret_cast<const float4 *>(conic);
-  if (tight)
-    hipLaunchKernelGGL(k_binning_tight, dim3(grid_for(K, kBinItems)), dim3(kBlock), 0, st, order, dpos, V, K, r4, m2,
-                       c4, g.TX, g.G, g.GX, bkey, bval, ranges, nranges);
-  else
-    hipLaunchKernelGGL(k_binning, dim3(grid_for(K, kBinItems)), dim3(kBlock), 0, st, order, dpos, V, K, r4, g.G,
-                       g.GX, bkey, bval, ranges, nranges);
-  if (K <= 1) return hipGetLastError();
-  return radix_passes_t<uint32_t>(bkey, bval, bkey_alt, bval_alt, K, nullptr, 0, bits_for((uint64_t)g.nbins), tmp,
-                                  st, in_alt);
-}
-
-hipError_t launch_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n, const uint32_t *order,
-                         const uint32_t *dkeys, const uint16_t *rect, const double *xy, const float *conic, bool tight,
-                         const Grid &g, uint32_t *vals, uint32_t *ranges, void *masks, uint64_t *keys, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ranges, dim3(grid_for(n, (uint64_t)kBlock * kRangeItems)), dim3(kBlock), 0, st, bin_keys,
-                     ranks, n, order, dkeys, reinterpret_cast<const ushort4 *>(rect),
-                     reinterpret_cast<const double2 *>(xy), reinterpret_cast<const float4 *>(conic), tight ? 1 : 0,
-                     g.G, g.GX, vals, ranges, masks, keys);
+  const int hi = bits_for((uint64_t)g.nbins);
+  // with a sort to follow (K > 1), the binning takes its first pass's digit counts
+  const FirstCounts fc{K > 1 ? static_cast<uint32_t *>(tmp) : nullptr, pass_width(0, hi)};
+  const bool large = K > kSmallSort;
+  const unsigned grid = grid_for(K, large ? SortTile<kLargeR>::kTile : SortTile<kSmallR>::kTile);
+  if (tight) {
+    if (large)
+      hipLaunchKernelGGL((k_binning_tight<SortTile<kLargeR>::kTile>), dim3(grid), dim3(kBlock), 0, st, order, dpos,
+                         block_first, V, K, r4, m2, c4, g.TX, g.G, g.GX, bkey, bval, ranges, nranges, fc);
+    else
+      hipLaunchKernelGGL((k_binning_tight<SortTile<kSmallR>::kTile>), dim3(grid), dim3(kBlock), 0, st, order, dpos,
+                         block_first, V, K, r4, m2, c4, g.TX, g.G, g.GX, bkey, bval, ranges, nranges, fc);
+  } else {
+    if (large)
+      hipLaunchKernelGGL((k_binning<SortTile<kLargeR>::kTile>), dim3(grid), dim3(kBlock), 0, st, order, dpos,
+                         block_first, V, K, r4, g.G, g.GX, bkey, bval, ranges, nranges, fc);
+    else
+      hipLaunchKernelGGL((k_binning<SortTile<kSmallR>::kTile>), dim3(grid), dim3(kBlock), 0, st, order, dpos,
+                         block_first, V, K, r4, g.G, g.GX, bkey, bval, ranges, nranges, fc);
+  }
+  if (K <= 1) {
+    // nothing to sort: the single entry's index, key and range directly
+    hipLaunchKernelGGL(k_ranges, dim3(1), dim3(kBlock), 0, st, bkey, bval, K, order, dkeys, r4, m2, c4,
+                       tight ? 1 : 0, g.G, g.GX, vals, ranges, masks, keys);
+    return hipGetLastError();
+  }
+  bool in_alt = false;
+  const FinalOut fin{order, dkeys, vals, keys};
+  // the bin passes ping-pong between (bkey, bval) and (bkey_alt, bval_alt); the last one writes
+  // the final indices and 64-bit keys, and its sorted bin keys land in kf
+  hipError_t e = radix_passes_t<uint32_t>(bkey, bval, bkey_alt, bval_alt, K, nullptr, 0, hi, tmp, st, &in_alt, nullptr,
+                                          nullptr, &fin, true);
+  if (e != hipSuccess) return e;
+  const uint32_t *kf = in_alt ? bkey_alt : bkey;
+  hipLaunchKernelGGL(k_ranges_final, dim3(grid_for(K, (uint64_t)kBlock * kRangeItems)), dim3(kBlock), 0, st, kf, K,
+                     vals, r4, m2, c4, tight ? 1 : 0, g.G, g.GX, ranges, masks);
   return hipGetLastError();
 }
 

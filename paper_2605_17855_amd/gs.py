@@ -18,9 +18,10 @@ LIB_PATH = os.path.join(_HERE, "libgs.so")
 
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_UNSUPPORTED, GS_ERR_CAPACITY, GS_ERR_HIP = range(5)
 GS_PREC_FP32, GS_PREC_FP16_MFMA, GS_PREC_BF16_MFMA = range(3)
-GS_AUX_TFINAL, GS_AUX_WSUM, GS_AUX_NEVAL, GS_AUX_NBLEND = 1, 2, 4, 8
+GS_AUX_TFINAL, GS_AUX_WSUM, GS_AUX_NEVAL, GS_AUX_NBLEND, GS_AUX_LAST = 1, 2, 4, 8, 16
 GS_OPT_TIGHT = 1
 GS_OPT_ALL_ROWS = 2
+GS_OPT_TILE_ROWS = 4
 PRECISIONS = {"fp32": GS_PREC_FP32, "fp16": GS_PREC_FP16_MFMA, "bf16": GS_PREC_BF16_MFMA}
 TILE = 16
 
@@ -50,7 +51,8 @@ class gs_scene(C.Structure):
 
 class gs_projected(C.Structure):
     _fields_ = [("xy", C.c_void_p), ("conic", C.c_void_p), ("rgb", C.c_void_p), ("rect", C.c_void_p),
-                ("count", C.c_void_p), ("offset", C.c_void_p), ("order", C.c_void_p), ("n_visible", C.c_void_p)]
+                ("count", C.c_void_p), ("offset", C.c_void_p), ("order", C.c_void_p), ("n_visible", C.c_void_p),
+                ("host_counts", C.c_void_p)]
 
 
 class gs_bins(C.Structure):
@@ -68,7 +70,7 @@ class gs_job(C.Structure):
 
 
 EXPORTS = ["gs_num_bins", "gs_workspace_bytes", "gs_preprocess", "gs_bin_sort", "gs_rasterize", "gs_render",
-           "gs_sort_workspace_bytes", "gs_radix_sort_u64", "gs_max_batch", "gs_rasterize_batch",
+           "gs_sort_workspace_bytes", "gs_radix_sort_u64", "gs_max_batch", "gs_rasterize_batch", "gs_rasterize_backward_mfma",
            "gs_rasterize_backward", "gs_status_string", "gs_last_error"]
 
 _lib = None
@@ -103,10 +105,13 @@ def lib():
     L.gs_max_batch.argtypes = []
     L.gs_max_batch.restype = C.c_int32
     L.gs_rasterize_batch.argtypes = [P(gs_job), C.c_int32, P(gs_options), C.c_void_p, C.c_void_p]
+    L.gs_rasterize_backward_mfma.argtypes = [P(gs_projected), P(gs_bins), P(gs_camera), P(gs_options), C.c_void_p,
+                                             C.c_void_p, C.c_void_p, P(gs_grads), C.c_void_p]
     L.gs_rasterize_backward.argtypes = [P(gs_projected), P(gs_bins), P(gs_camera), P(gs_options), C.c_void_p,
                                         P(gs_grads), C.c_void_p]
     for f in ("gs_preprocess", "gs_bin_sort", "gs_rasterize", "gs_render", "gs_radix_sort_u64",
-              "gs_rasterize_batch", "gs_rasterize_backward"):
+              "gs_rasterize_batch", "gs_rasterize_backward",
+              "gs_rasterize_backward_mfma"):
         getattr(L, f).restype = C.c_int
     L.gs_status_string.argtypes = [C.c_int]
     L.gs_status_string.restype = C.c_char_p
@@ -122,14 +127,15 @@ def _check(status: int):
 
 
 def options(group: int = 1, precision="fp32", splits: int = 2, bg=(0.0, 0.0, 0.0), aux_flags: int = 0,
-            tight: bool = False, all_rows: bool = False) -> gs_options:
+            tight: bool = False, all_rows: bool = False, tile_rows: bool = False) -> gs_options:
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     o = gs_options()
     o.group, o.precision, o.splits = group, precision, splits
     o.bg = (C.c_float * 3)(*bg)
     o.aux_flags = aux_flags
-    o.flags = (GS_OPT_TIGHT if tight else 0) | (GS_OPT_ALL_ROWS if all_rows else 0)
+    o.flags = (GS_OPT_TIGHT if tight else 0) | (GS_OPT_ALL_ROWS if all_rows else 0) | \
+        (GS_OPT_TILE_ROWS if tile_rows else 0)
     return o
 
 
@@ -196,10 +202,13 @@ class Projected:
         self.offset = torch.empty((n + 1,), dtype=torch.int64, device=device)
         self.order = torch.empty((m,), dtype=torch.int32, device=device)
         self.n_visible = torch.empty((1,), dtype=torch.int32, device=device)
+        # pinned host memory the library's count readback polls (entry and visible counts)
+        self.host_counts = torch.empty((2,), dtype=torch.int64, pin_memory=True)
         p = gs_projected()
         p.xy, p.conic, p.rgb = _ptr(self.xy), _ptr(self.conic), _ptr(self.rgb)
         p.rect, p.count, p.offset = _ptr(self.rect), _ptr(self.count), _ptr(self.offset)
         p.order, p.n_visible = _ptr(self.order), _ptr(self.n_visible)
+        p.host_counts = _ptr(self.host_counts)
         self.struct = p
 
 
@@ -282,6 +291,16 @@ def gs_rasterize_backward(proj: Projected, bins: Bins, cam, opt: gs_options, dim
                                        C.byref(opt), _ptr(dimage), C.byref(grads.struct), _stream(stream)))
 
 
+def gs_rasterize_backward_mfma(proj: Projected, bins: Bins, cam, opt: gs_options, dimage, t_final, last,
+                               grads: Grads, stream=None):
+    """Adds to `grads` the gradients of sum(dimage * image) for the image of the MFMA forward
+    (opt.precision fp16/bf16, opt.splits), starting from the forward's GS_AUX_TFINAL and
+    GS_AUX_LAST planes (t_final, last: (H, W) float32 device tensors)."""
+    _check(lib().gs_rasterize_backward_mfma(C.byref(proj.struct), C.byref(bins.struct), C.byref(camera(cam)),
+                                            C.byref(opt), _ptr(dimage), _ptr(t_final), _ptr(last),
+                                            C.byref(grads.struct), _stream(stream)))
+
+
 def gs_render(scene: DeviceScene, cam, opt: gs_options, proj: Projected, bins: Bins, image, aux, ws,
               stream=None) -> int:
     """Returns the entry count; raises GsError (status GS_ERR_CAPACITY with .n_keys) when bins is too small."""
@@ -319,8 +338,20 @@ def gs_rasterize_batch(items, opt: gs_options, counter, stream=None):
     _check(lib().gs_rasterize_batch(arr, n, C.byref(opt), _ptr(counter), _stream(stream)))
 
 
+def _job_array(items):
+    n = len(items)
+    arr = (gs_job * max(n, 1))()
+    for i, (proj, bins, cam, image, aux) in enumerate(items):
+        arr[i].proj = C.pointer(proj.struct)
+        arr[i].bins = C.pointer(bins.struct)
+        arr[i].cam = camera(cam)
+        arr[i].image = _ptr(image)
+        arr[i].aux = _ptr(aux)
+    return arr, n
+
+
 def aux_planes(flags: int) -> int:
-    return bin(flags & 15).count("1")
+    return bin(flags & 31).count("1")
 
 
 class Renderer:

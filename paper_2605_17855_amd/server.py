@@ -25,10 +25,10 @@ from typing import Dict, List, Optional
 
 import numpy as np
 
-# bytes per duplicated entry: key 8 + value 4 + mask 2, plus the workspace's bin key and
-# the two sort double buffers (4 + 4 + 4) and the sort's per-tile digit counts (up to 2 B
-# per key for sorts of at most 2^20 keys, whose tiles hold 512 keys)
-BYTES_PER_ENTRY = 28
+# bytes per duplicated entry: key 8 + value 4 + mask 2, plus the workspace's bin key and depth
+# rank and the sort's two double buffers (4 + 4 + 4 + 4) and its per-tile digit counts (1 B per
+# key: 256 four-byte counts per tile of at least 1,024 keys), rounded up
+BYTES_PER_ENTRY = 32
 # per-Gaussian workspace bytes: scan partials, depth keys and their double buffers, each
 # visible Gaussian's entry count and first-entry offset in depth order
 BYTES_PER_GAUSSIAN = 28

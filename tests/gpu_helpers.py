@@ -14,11 +14,11 @@ def note(msg: str):
 
 
 def render(dscene, cam, group=1, precision="fp32", splits=2, bg=(0.0, 0.0, 0.0), aux=0, capacity=0, tight=False,
-           all_rows=False):
+           all_rows=False, tile_rows=False):
     import torch
     r = gs.Renderer(dscene.n, cam.width, cam.height, group=group, capacity=capacity)
     opt = gs.options(group=group, precision=precision, splits=splits, bg=bg, aux_flags=aux, tight=tight,
-                     all_rows=all_rows)
+                     all_rows=all_rows, tile_rows=tile_rows)
     n_keys = r.render(dscene, cam, opt)
     torch.cuda.synchronize()
     out = dict(image=r.image.cpu().numpy().astype(np.float64), n_keys=n_keys, renderer=r)
@@ -26,7 +26,7 @@ def render(dscene, cam, group=1, precision="fp32", splits=2, bg=(0.0, 0.0, 0.0),
         planes = r.aux.cpu().numpy()
         k = 0
         for flag, name in ((gs.GS_AUX_TFINAL, "tfinal"), (gs.GS_AUX_WSUM, "wsum"), (gs.GS_AUX_NEVAL, "neval"),
-                           (gs.GS_AUX_NBLEND, "nblend")):
+                           (gs.GS_AUX_NBLEND, "nblend"), (gs.GS_AUX_LAST, "last")):
             if aux & flag:
                 out[name] = planes[k].astype(np.float64)
                 k += 1
@@ -120,3 +120,25 @@ def check_bins(rec, cam, r, n_keys, group, tight=False):
         om = masks[keep_o]
         ok = og == gg
         assert np.array_equal(gm[ok], om[ok])
+
+
+def check_flagged_pixels(tag, image, tfinal, ref, rec, cam, start, ids, mask=None, bg=(0.0, 0.0, 0.0),
+                         tol=1e-4, tol_t=1e-5):
+    """The pixels exempt from the element-wise bar (a decision in a guard band): each must match
+    one of the oracle's admissible results for that pixel (oracle.alternatives) within the same
+    bar.  Pixels with more readings than the enumeration holds stay unchecked; they must be
+    under 0.1 % of the compared pixels.  mask: the compared pixels (sampled tiles), or all."""
+    amb = np.asarray(ref["ambiguous"]).copy()
+    if mask is not None:
+        amb[~mask] = 0
+    r = oracle.check_flagged(image, tfinal, rec, cam, start, ids, amb, bg=bg, tol_img=tol, tol_t=tol_t)
+    total = int(mask.sum()) if mask is not None else amb.size
+    print(f"{tag}: flagged {r['checked']} of {total} pixels ({r['checked'] / max(total, 1):.4%}): "
+          f"{r['matched']} match an admissible result, {r['failed']} fail, {r['unresolved']} unresolved", flush=True)
+    if r["failed"]:
+        W = cam.width
+        bad = r["failed_pixels"][:8]
+        print(f"{tag}: failing pixels (y, x) {[(int(p // W), int(p % W)) for p in bad]}", flush=True)
+    assert r["failed"] == 0
+    assert r["unresolved"] <= 1e-3 * total
+    return r

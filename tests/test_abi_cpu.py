@@ -53,9 +53,9 @@ def test_num_bins():
     ("group", 16, gs.GS_ERR_UNSUPPORTED),
     ("precision", 7, gs.GS_ERR_INVALID_ARG),
     ("splits", 0, gs.GS_ERR_INVALID_ARG),
-    ("aux_flags", 16, gs.GS_ERR_INVALID_ARG),
     ("aux_flags", 32, gs.GS_ERR_INVALID_ARG),
-    ("flags", 4, gs.GS_ERR_INVALID_ARG),
+    ("aux_flags", 64, gs.GS_ERR_INVALID_ARG),
+    ("flags", 8, gs.GS_ERR_INVALID_ARG),
     ("flags", 0x80000000, gs.GS_ERR_INVALID_ARG),
 ])
 def test_rasterize_rejects_bad_options(field, value, status):

@@ -8,7 +8,7 @@ import pytest
 
 from oracle import oracle
 from paper_2605_17855_amd import gs, scenes
-from gpu_helpers import bins_numpy, check_bins, note, projected_numpy, psnr, render, sampled_tiles, tile_mask
+from gpu_helpers import check_flagged_pixels, bins_numpy, check_bins, note, projected_numpy, psnr, render, sampled_tiles, tile_mask
 
 pytestmark = pytest.mark.gpu
 
@@ -128,6 +128,8 @@ def test_fp32_image_small(small):
     assert np.abs(out["tfinal"] - ref["tfinal"])[ok].max() <= 1e-5
     assert np.abs(out["wsum"] + out["tfinal"] - 1.0).max() <= 1e-5
     assert np.array_equal(out["neval"][ok], ref["neval"][ok].astype(np.float64))
+    check_flagged_pixels("fp32 small", out["image"], out["tfinal"], ref, ref["records"], cam, ref["start"],
+                         ref["ids"])
 
 
 @pytest.mark.parametrize("prec,splits,required", [("fp16", 1, False), ("fp16", 2, True), ("bf16", 1, False),
@@ -148,15 +150,46 @@ def test_mfma_image_small(small, prec, splits, required):
 @pytest.mark.parametrize("prec,splits", [("fp16", 2), ("bf16", 3), ("fp16", 1)])
 @pytest.mark.parametrize("size", [(128, 128), (100, 70)])
 def test_grouping_bit_identical(prec, splits, size):
+    """Per-member-tile rows (GS_OPT_TILE_ROWS; always for the frames the group-frame operand
+    cannot hold exactly): every grouped image and aux plane equals the 1x1 one bit for bit."""
     sc, _ = scenes.small_camera_space()
     cam = scenes.pinhole(size[0], size[1], 60.0)
     ds = gs.DeviceScene(sc)
     note(f"grouping identity {prec}/{splits} {size}")
-    base = render(ds, cam, group=1, precision=prec, splits=splits, aux=AUX_ALL)
+    base = render(ds, cam, group=1, precision=prec, splits=splits, aux=AUX_ALL | gs.GS_AUX_LAST)
     for g in (2, 4, 8):
-        out = render(ds, cam, group=g, precision=prec, splits=splits, aux=AUX_ALL)
-        for k in ("image", "tfinal", "wsum", "neval"):
+        out = render(ds, cam, group=g, precision=prec, splits=splits, aux=AUX_ALL | gs.GS_AUX_LAST, tile_rows=True)
+        for k in ("image", "tfinal", "wsum", "neval", "last"):
             assert np.array_equal(out[k], base[k]), (g, k)
+
+
+@pytest.mark.parametrize("prec,splits,group", [("fp16", 2, 2), ("bf16", 3, 2)])
+@pytest.mark.parametrize("size", [(128, 128), (100, 70)])
+def test_group_frame_rows_match_oracle(small, prec, splits, group, size):
+    """Rows built once per group (the default for 2x2 groups): the image against
+    the FP64 oracle (PSNR >= 45 dB, MAE <= 2e-3, max abs <= 1e-3 outside the guard bands and an
+    admissible result within 1e-3 inside them), W + T_final = 1, and the evaluation and
+    blended-prefix counts equal to the 1x1 render's wherever no decision is in a guard band."""
+    sc, _, _, _ = small
+    cam = scenes.pinhole(size[0], size[1], 60.0)
+    ref = oracle.render(sc, cam)
+    ok = ref["ambiguous"] == 0
+    ds = gs.DeviceScene(sc)
+    note(f"group-frame rows {prec}/{splits} group {group} {size}")
+    aux = AUX_ALL | gs.GS_AUX_LAST
+    base = render(ds, cam, group=1, precision=prec, splits=splits, aux=aux)
+    out = render(ds, cam, group=group, precision=prec, splits=splits, aux=aux)
+    err = np.abs(out["image"] - ref["image"])
+    p = psnr(out["image"], ref["image"])
+    print(f"group frame {prec}/{splits} G{group} {size}: PSNR {p:.2f} dB, MAE {err.mean():.3e}, max abs "
+          f"{err[:, ok].max():.3e}, vs 1x1 max abs {np.abs(out['image'] - base['image']).max():.3e}")
+    assert p >= 45.0 and err.mean() <= 2e-3 and err[:, ok].max() <= 1e-3
+    assert np.abs(out["wsum"] + out["tfinal"] - 1.0).max() <= 1e-5
+    assert np.abs(out["tfinal"] - ref["tfinal"])[ok].max() <= 2e-3
+    check_flagged_pixels(f"group frame {prec} G{group} {size}", out["image"], out["tfinal"], ref, ref["records"], cam,
+                         ref["start"], ref["ids"], tol=1e-3, tol_t=2e-3)
+    for k in ("neval", "last"):
+        assert np.array_equal(out[k][ok], base[k][ok]), k
 
 
 def test_fp32_grouped_matches_oracle(small):
@@ -166,6 +199,8 @@ def test_fp32_grouped_matches_oracle(small):
         note(f"fp32 grouped {g}")
         out = render(ds, cam, group=g, precision="fp32")
         assert np.abs(out["image"] - ref["image"])[:, ok].max() <= 1e-4
+        check_flagged_pixels(f"fp32 group {g}", out["image"], None, ref, ref["records"], cam, ref["start"],
+                             ref["ids"])
 
 
 def test_determinism(small):
@@ -209,6 +244,8 @@ def test_ragged_sizes(size):
         out = render(ds, cam, precision=prec, bg=(0.1, 0.2, 0.3))
         assert out["image"].shape == (3, size[1], size[0])
         assert np.abs(out["image"] - ref["image"])[:, ok].max() <= tol
+        check_flagged_pixels(f"ragged {size} {prec}", out["image"], None, ref, ref["records"], cam, ref["start"],
+                             ref["ids"], bg=(0.1, 0.2, 0.3), tol=tol)
 
 
 def test_single_gaussian():
@@ -256,6 +293,8 @@ def test_1080psampled_tiles(big):
         assert p >= 45.0 and mae <= 2e-3
         if prec == "fp32":
             assert err[:, ok].max() <= 1e-4
+        check_flagged_pixels(f"1080p {prec}", out["image"], out["tfinal"], ref, rec, cam, st, ids, mask=m,
+                             tol=1e-4 if prec == "fp32" else 1e-3, tol_t=1e-5 if prec == "fp32" else 2e-3)
         assert np.abs(out["wsum"] + out["tfinal"] - 1.0).max() <= 1e-5
 
 
@@ -362,3 +401,5 @@ def test_maximum_width():
         out = render(ds, cam, precision=prec, bg=(0.1, 0.2, 0.3), group=group)
         assert out["image"].shape == (3, 24, 16384)
         assert np.abs(out["image"] - ref["image"])[:, ok].max() <= tol
+        check_flagged_pixels(f"maximum width {prec} group {group}", out["image"], None, ref, ref["records"], cam,
+                             ref["start"], ref["ids"], bg=(0.1, 0.2, 0.3), tol=tol)
