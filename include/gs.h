@@ -19,7 +19,9 @@
  * Conventions that hold for every call:
  *   - Pointers are DEVICE memory unless a comment says host.  Structs passed by
  *     pointer are host memory.  The caller allocates and owns every buffer; the
- *     library never allocates, frees or retains a pointer after a call returns.
+ *     library never allocates, frees or retains a pointer after a call returns (the one
+ *     exception is the device scratch array of gs_rasterize_batch_noalloc, which the
+ *     library's code object holds on each GPU).
  *   - All device work is enqueued on `stream` (a hipStream_t passed as void*,
  *     NULL = the null stream).  gs_bin_sort and gs_render wait once on the host for
  *     the entry and visible counts (a bounded poll of gs_projected.host_counts, which
@@ -219,6 +221,20 @@ typedef struct {
 int32_t gs_max_batch(void);
 gs_status gs_rasterize_batch(const gs_job *jobs, int32_t n_jobs, const gs_options *opt, uint32_t *work_counter,
                              void *stream);
+
+/* Allocation-free variant of gs_rasterize_batch, for callers that cannot allocate device memory
+ * or pass a workspace: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same jobs, options, validation and images as gs_rasterize_batch (the same kernels);
+ * the work counter that gs_rasterize_batch takes from the caller lives instead in a library-owned
+ * device array of GS_NOALLOC_SCRATCH_BYTES bytes, one per GPU, created with the library's code
+ * object on that GPU and held until the process ends.  Its device address is looked up on the
+ * first call on each device (with that device current); no call allocates or frees memory.
+ * The counter is cleared by a kernel on `stream` before each launch (no memset).  Every call on
+ * one GPU shares that GPU's array, so calls whose launches overlap on one GPU (different streams,
+ * or threads) race on the counter and must be serialized by the caller.  n_jobs above
+ * gs_max_batch() returns GS_ERR_UNSUPPORTED; the launch itself needs 4 of the scratch bytes. */
+#define GS_NOALLOC_SCRATCH_BYTES 256
+gs_status gs_rasterize_batch_noalloc(const gs_job *jobs, int32_t n_jobs, const gs_options *opt, void *stream);
 
 const char *gs_status_string(gs_status s);
 const char *gs_last_error(void);

@@ -5,9 +5,13 @@
 #include <cstdio>
 #include <cstring>
 #include <chrono>
+#include <mutex>
 
 #include "gs_backward.hpp"
 #include "gs_internal.hpp"
+
+// Device scratch of gs_rasterize_batch_noalloc (see scratch_on_current_device below).
+static __device__ __align__(256) uint32_t scratch[GS_NOALLOC_SCRATCH_BYTES / sizeof(uint32_t)];
 
 namespace {
 
@@ -310,6 +314,33 @@ gs_status batch_launch(const gsi::BatchTable &table, const gs_options &opt, uint
   return GS_OK;
 }
 
+// ---- scratch of the allocation-free entry point ------------------------------------------
+// A file-scope device array: every GPU the library runs on holds its own copy, at its own
+// address, until the process ends.  In host code `scratch` names a host-side stand-in, so its
+// device address is looked up once per device (with that device current) and only that
+// address is ever passed to a kernel.
+constexpr size_t kScratchBytes = GS_NOALLOC_SCRATCH_BYTES;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch_addr[kMaxDevices] = {};
+
+gs_status scratch_on_current_device(uint32_t **out) {
+  int dev = 0;
+  GS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(GS_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(GS_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_addr[dev] = static_cast<uint32_t *>(p);
+  }
+  *out = g_scratch_addr[dev];
+  return GS_OK;
+}
+
 gs_status backward_job(const gs_projected *proj, const gs_bins *bins, const gs_camera *cam, const gs_options *opt,
                        const float *dimage, const gs_grads *grads, gsi::BackwardJob *out) {
   gs_status s;
@@ -506,6 +537,17 @@ gs_status gs_rasterize_batch(const gs_job *jobs, int32_t n_jobs, const gs_option
   if (s || n_jobs == 0) return s;
   if (!work_counter) return fail(GS_ERR_INVALID_ARG, "work_counter is NULL");
   return batch_launch(table, *opt, work_counter, static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_rasterize_batch_noalloc(const gs_job *jobs, int32_t n_jobs, const gs_options *opt, void *stream) {
+  gsi::BatchTable table{};
+  gs_status s = batch_table(jobs, n_jobs, opt, &table);
+  if (s || n_jobs == 0) return s;
+  // the launch needs one work counter; the scratch array holds kScratchBytes
+  static_assert(sizeof(uint32_t) <= kScratchBytes, "scratch too small for the work counter");
+  uint32_t *counter = nullptr;
+  if ((s = scratch_on_current_device(&counter))) return s;
+  return batch_launch(table, *opt, counter, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

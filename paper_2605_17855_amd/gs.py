@@ -70,7 +70,8 @@ class gs_job(C.Structure):
 
 
 EXPORTS = ["gs_num_bins", "gs_workspace_bytes", "gs_preprocess", "gs_bin_sort", "gs_rasterize", "gs_render",
-           "gs_sort_workspace_bytes", "gs_radix_sort_u64", "gs_max_batch", "gs_rasterize_batch", "gs_rasterize_backward_mfma",
+           "gs_sort_workspace_bytes", "gs_radix_sort_u64", "gs_max_batch", "gs_rasterize_batch",
+           "gs_rasterize_batch_noalloc", "gs_rasterize_backward_mfma",
            "gs_rasterize_backward", "gs_status_string", "gs_last_error"]
 
 _lib = None
@@ -105,12 +106,13 @@ def lib():
     L.gs_max_batch.argtypes = []
     L.gs_max_batch.restype = C.c_int32
     L.gs_rasterize_batch.argtypes = [P(gs_job), C.c_int32, P(gs_options), C.c_void_p, C.c_void_p]
+    L.gs_rasterize_batch_noalloc.argtypes = [P(gs_job), C.c_int32, P(gs_options), C.c_void_p]
     L.gs_rasterize_backward_mfma.argtypes = [P(gs_projected), P(gs_bins), P(gs_camera), P(gs_options), C.c_void_p,
                                              C.c_void_p, C.c_void_p, P(gs_grads), C.c_void_p]
     L.gs_rasterize_backward.argtypes = [P(gs_projected), P(gs_bins), P(gs_camera), P(gs_options), C.c_void_p,
                                         P(gs_grads), C.c_void_p]
     for f in ("gs_preprocess", "gs_bin_sort", "gs_rasterize", "gs_render", "gs_radix_sort_u64",
-              "gs_rasterize_batch", "gs_rasterize_backward",
+              "gs_rasterize_batch", "gs_rasterize_batch_noalloc", "gs_rasterize_backward",
               "gs_rasterize_backward_mfma"):
         getattr(L, f).restype = C.c_int
     L.gs_status_string.argtypes = [C.c_int]
@@ -348,6 +350,13 @@ def _job_array(items):
         arr[i].image = _ptr(image)
         arr[i].aux = _ptr(aux)
     return arr, n
+
+
+def gs_rasterize_batch_noalloc(items, opt: gs_options, stream=None):
+    """gs_rasterize_batch with the work counter in the library's own device scratch (no buffer
+    from the caller, nothing allocated).  Calls that overlap on one GPU race on that counter."""
+    arr, n = _job_array(items)
+    _check(lib().gs_rasterize_batch_noalloc(arr, n, C.byref(opt), _stream(stream)))
 
 
 def aux_planes(flags: int) -> int:
