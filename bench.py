@@ -39,13 +39,19 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6   # the same without packed FP32 (which this b
 PEAK_FP16_MFMA_TFLOPS = 2500.0      # dense FP16 / BF16 matrix peak
 POWER_FLOPS = 12                    # the power's 6 multiply-adds, moved onto the matrix cores
 
-# HBM bytes per launch of the rasterizer on this workload (FP16, splits 2, 1x1 groups): rocprofv3
-# FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by what the same counters read for a plain
-# device copy of known size (x2 and x1).  They describe the kernel built from the source and
-# compiler flags hashed in `sha256`; after any change to either the traffic is reported as null.
-RASTER_COUNTERS = dict(sha256="4fda3804d0a698289663c3962536792a147611b728a90f25b97d499df70d9e7d",
-                       fetch_kib=87559, write_kib=24703, fetch_scale=2.0, write_scale=1.0,
+# Counters of one launch of the rasterizer on this workload (FP16, splits 2, 1x1 groups), from
+# rocprofv3: FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by what the same counters read
+# for a plain device copy of known size (x2 and x1); the wave-level VALU instruction count
+# (SQ_INSTS_VALU) and the SIMD cycles spent on VALU instructions (SQ_ACTIVE_INST_VALU, in units
+# of 4 cycles, summed over the SIMDs).  They describe the kernel built from the source and
+# compiler flags hashed in `sha256`; after any change to either they are reported as null.
+RASTER_COUNTERS = dict(sha256="abc45a1aade0d41e2a836f562bf997fda005fdff8edb94e4741715b67ae148c0",
+                       fetch_kib=87536, write_kib=24706, fetch_scale=2.0, write_scale=1.0,
+                       insts_valu=37.48e6, active_valu_quads=41.15e6,
                        precision="fp16", splits=2, group=1)
+SIMDS = 1024                # 256 CUs x 4 SIMDs
+CLOCK_HZ = 2.4e9
+VALU_CYCLES = 4             # a wave64 VALU instruction on a 16-lane SIMD
 
 
 def raster_source_hash():
@@ -60,8 +66,8 @@ def raster_source_hash():
     return h.hexdigest()
 
 
-def raster_traffic(args):
-    """Measured HBM bytes per launch, or None when they do not describe this kernel and workload."""
+def raster_counters(args):
+    """The stored counters when they describe this kernel and workload, else None."""
     c = RASTER_COUNTERS
     if (args.precision, args.splits, args.group) != (c["precision"], c["splits"], c["group"]):
         return None
@@ -70,7 +76,26 @@ def raster_traffic(args):
             return None
     except OSError:          # sources not shipped beside the library
         return None
+    return c
+
+
+def raster_traffic(args):
+    """Measured HBM bytes per launch, or None when they do not describe this kernel and workload."""
+    c = raster_counters(args)
+    if c is None:
+        return None
     return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
+
+
+def valu_fracs(args, launch_s):
+    """Shares of the chip's SIMD cycles over one launch: (issue, active).  issue counts every VALU
+    wave instruction as 4 cycles; active is the counted cycles the SIMDs spent on VALU
+    instructions (slower transcendentals included).  (None, None) without stored counters."""
+    c = raster_counters(args)
+    if c is None or launch_s <= 0:
+        return None, None
+    simd_cycles = SIMDS * launch_s * CLOCK_HZ
+    return VALU_CYCLES * c["insts_valu"] / simd_cycles, 4.0 * c["active_valu_quads"] / simd_cycles
 
 
 def log(msg):
@@ -541,6 +566,7 @@ def main():
     raster_total_s = sum(raster_ms) / 1e3
     flops = FLOPS_PER_EVAL * e_pix + FLOPS_PER_BLEND * blend
     achieved = flops / raster_total_s / 1e12
+    vfr = valu_fracs(args, float(np.mean(raster_ms)) / 1e3)
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_TFLOPS, "traffic": raster_traffic(args),
                 "kernel": f"k_raster_mfma (precision {args.precision}, splits {args.splits}, group {args.group})"
@@ -550,6 +576,9 @@ def main():
                 if args.precision != "fp32" else None,
                 "traffic_source": "profiles/hbm_counters_1m_1080p_fp16.md (rocprofv3 FETCH_SIZE, WRITE_SIZE of the "
                                   "kernel built from the hashed sources; not measured in this run)",
+                "valu_issue_frac": vfr[0], "valu_active_frac": vfr[1],
+                "valu_source": "profiles/sq_counters_raster_1m_1080p_fp16.md (SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU "
+                               "per launch) over this run's average launch",
                 "avg_launch_ms": float(np.mean(raster_ms)),
                 "evals_per_frame": e_pix / args.steps, "blends_per_frame": blend / args.steps,
                 "entries_per_frame": entries_pf, "visible_per_frame": visible_pf}
