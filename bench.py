@@ -484,22 +484,28 @@ def sweep(gs, torch, args):
         ds = gs.DeviceScene(sc)
         cams = scenes.orbit(max(args.sweep_steps, 1), w, h, seed=seed)
         keys = {}
-        variants = ((1, False, ("fp32", "fp16", "bf16")), (1, True, ("fp32", "fp16", "bf16")),
-                    (2, False, ("fp32", "fp16", "bf16")), (4, False, ("fp32", "fp16", "bf16")),
-                    (8, False, ("fp16", "bf16")), (2, True, ("fp16",)), (4, True, ("fp16",)), (8, True, ("fp16",)))
-        for group, tight, precs in variants:
+        # (group, tight, per-tile rows, precisions): 2x2 groups build rows in the group frame unless
+        # per-tile rows are asked for
+        variants = ((1, False, False, ("fp32", "fp16", "bf16")), (1, True, False, ("fp32", "fp16", "bf16")),
+                    (2, False, False, ("fp32", "fp16", "bf16")), (2, False, True, ("fp16", "bf16")),
+                    (4, False, False, ("fp32", "fp16", "bf16")),
+                    (8, False, False, ("fp16", "bf16")), (2, True, False, ("fp16",)), (4, True, False, ("fp16",)),
+                    (8, True, False, ("fp16",)))
+        for group, tight, tile_rows, precs in variants:
             rend = gs.Renderer(sc.n, w, h, group=group)
             for prec in precs:
                 splits = 3 if prec == "bf16" else 2
-                opt = gs.options(group=group, precision=prec, splits=splits, tight=tight)
+                opt = gs.options(group=group, precision=prec, splits=splits, tight=tight, tile_rows=tile_rows)
                 el, fm, rm = timed_frames(gs, torch, ds, cams, rend, opt, args.sweep_steps, 3)
                 rows.append({"workload": name, "precision": prec, "splits": splits, "group": group, "tight": tight,
+                             "tile_rows": tile_rows,
                              "frames_per_s": args.sweep_steps / el, "p99_ms": float(np.percentile(fm, 99)),
                              "raster_avg_ms": float(np.mean(rm)), "stage_ms": timed_frames.stages})
-                log(f"  G{group}{' tight' if tight else ''} {prec}: {rows[-1]['frames_per_s']:.1f} frames/s, "
-                    f"raster {rows[-1]['raster_avg_ms']:.3f} ms")
-            keys[f"{group}t" if tight else group] = np.mean([rend.render(ds, c, gs.options(group=group, precision="fp16", tight=tight))
-                                                      for c in cams[:5]])
+                log(f"  G{group}{' tight' if tight else ''}{' tile rows' if tile_rows else ''} {prec}: "
+                    f"{rows[-1]['frames_per_s']:.1f} frames/s, raster {rows[-1]['raster_avg_ms']:.3f} ms")
+            if not tile_rows:
+                keys[f"{group}t" if tight else group] = np.mean(
+                    [rend.render(ds, c, gs.options(group=group, precision="fp16", tight=tight)) for c in cams[:5]])
             del rend
         # per-scene adaptive (group side, culling) variant, FP16: probe, then time
         from paper_2605_17855_amd.adaptive import AdaptiveRenderer

@@ -255,6 +255,48 @@ hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint
                         void *masks, uint32_t *vals, uint64_t *keys, void *tmp, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
 
+// ---- XCD-aware work order ---------------------------------------------------------------
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b to XCD b % 8), and each XCD
+// has its own L2.  Work whose neighbours share data is therefore given to the XCDs in
+// contiguous pieces rather than one unit per XCD in turn.
+constexpr int kXcds = 8;
+
+// Sort tile of workgroup b when the ntiles tiles of a sort are split into 8 contiguous ranges
+// of per = ceil(ntiles / 8), XCD x walking [x per, (x + 1) per) in order: the runs that
+// neighbouring tiles scatter side by side into each digit's output then share one L2.  ntiles
+// may be known only on the device (a sort of a device-counted length); the grid is
+// xcd_sort_grid(t) workgroups for any t >= ntiles, and a workgroup with no tile gets ~0u.
+inline unsigned xcd_sort_grid(uint64_t tiles) {
+  const uint64_t per = (tiles + kXcds - 1) / kXcds;
+  return (unsigned)((per ? per : 1) * kXcds);
+}
+__device__ __forceinline__ uint32_t xcd_sort_tile(uint32_t b, uint64_t ntiles) {
+  const uint32_t per = (uint32_t)((ntiles + kXcds - 1) / kXcds), k = b / kXcds;
+  if (k >= per) return ~0u;
+  const uint32_t t = (b % kXcds) * per + k;
+  return t < ntiles ? t : ~0u;
+}
+
+// Bin of workgroup b of a single-image raster launch of xcd_raster_grid(GX, GY) workgroups:
+// blocks of kXcdBlock x kXcdBlock neighbouring bins, XCD x taking blocks x, x + 8, x + 16, ...
+// and each block's bins in turn, so that neighbouring bins (which share most of their
+// Gaussians) read them through one L2 while every XCD still draws blocks from the whole frame.
+// -1 for a workgroup past the frame's bins.
+constexpr int kXcdBlock = 4;
+inline unsigned xcd_raster_grid(int GX, int GY) {
+  const int nb = ((GX + kXcdBlock - 1) / kXcdBlock) * ((GY + kXcdBlock - 1) / kXcdBlock);
+  return (unsigned)(((nb + kXcds - 1) / kXcds) * kXcds * kXcdBlock * kXcdBlock);
+}
+__device__ __forceinline__ int xcd_raster_bin(int b, int GX, int GY) {
+  constexpr int kPer = kXcdBlock * kXcdBlock;
+  const int x = b % kXcds, k = b / kXcds;
+  const int block = x + kXcds * (k / kPer), within = k % kPer;
+  const int nbx = (GX + kXcdBlock - 1) / kXcdBlock;
+  const int gx = (block % nbx) * kXcdBlock + within % kXcdBlock;
+  const int gy = (block / nbx) * kXcdBlock + within / kXcdBlock;
+  return (gx < GX && gy < GY) ? gy * GX + gx : -1;
+}
+
 // ---- rasterizers -------------------------------------------------------------
 struct RasterJob {
   const double2 *xy;

@@ -129,12 +129,13 @@ __device__ __forceinline__ void raster_bin_fp32(const RasterJob &J, const Raster
   }
 }
 
-// Work item = workgroup id: round-robin over the 8 XCDs spreads the dense middle of a frame
-// over all of them.
+// One workgroup per bin, in the XCD-aware order of the MFMA rasterizer.
 template <int G, bool AUX>
 __global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParams P) {
   __shared__ Fp32Shared sm;
-  raster_bin_fp32<G, AUX>(J, P, blockIdx.x, sm);
+  const int item = xcd_raster_bin((int)blockIdx.x, J.GX, J.GY);
+  if (item < 0) return;
+  raster_bin_fp32<G, AUX>(J, P, item, sm);
 }
 
 // Persistent batched rasterizer (see the MFMA variant).
@@ -172,7 +173,7 @@ hipError_t launch_g(const RasterJob &j, const RasterParams &p, const BatchArgs *
     hipLaunchKernelGGL((k_raster_fp32_batch<G, AUX>), dim3((unsigned)b->grid), dim3(kBlock), 0, st, *b->table, p,
                        b->counter);
   } else {
-    hipLaunchKernelGGL((k_raster_fp32<G, AUX>), dim3((unsigned)j.items), dim3(kBlock), 0, st, j, p);
+    hipLaunchKernelGGL((k_raster_fp32<G, AUX>), dim3(xcd_raster_grid(j.GX, j.GY)), dim3(kBlock), 0, st, j, p);
   }
   return hipGetLastError();
 }

@@ -93,17 +93,21 @@ __device__ __forceinline__ void process_rows(const uint16_t *sA, const float *sc
 #pragma unroll
     for (int m = 0; m < 32; ++m) {
       if (D[m] >= st.cut) {
-        // T' = T (1 - alpha) as one FMA.  A stop (T' < 1e-4) blends nothing, keeps T and
-        // disables the pixel; it comes at most once per pixel, so the blend without the
-        // stop's selects runs whenever no active lane stops on this row
+#pragma clang fp contract(off)
+        // weight alpha T, then T' = T (1 - alpha) as one FMA written over T (no copy of T
+        // outlives the row).  A stop (T' < 1e-4) blends nothing, puts back T' + alpha T (T to
+        // within a unit in the last place, at T ~ 1e-4) and disables the pixel; it comes at most
+        // once per pixel, so the blend without the stop's selects runs whenever no active lane
+        // stops on this row.  Every operation rounds as written (no contraction), so all
+        // rasterizer variants blend bit for bit alike.
         const float4 cl = wc[m];
         const float al = fminf(kAlphaMax, __builtin_amdgcn_exp2f(D[m]));
-        float Tn = fmaf(-st.T, al, st.T);
         float wgt = al * st.T;
-        if (__builtin_expect(__ballot(!(Tn >= kTMin)) != 0, 0)) {
-          const bool ok = Tn >= kTMin;
+        st.T = fmaf(-st.T, al, st.T);
+        if (__builtin_expect(__ballot(!(st.T >= kTMin)) != 0, 0)) {
+          const bool ok = st.T >= kTMin;
+          st.T = ok ? st.T : st.T + wgt;
           wgt = ok ? wgt : 0.0f;
-          Tn = ok ? Tn : st.T;
           st.cut = ok ? st.cut : INFINITY;
           if (AUX) st.nstop = ok ? st.nstop : row_base + (uint32_t)__float_as_int(cl.w) + 1;
           if (AUX) st.nblend += ok ? 0u : ~0u;
@@ -111,7 +115,6 @@ __device__ __forceinline__ void process_rows(const uint16_t *sA, const float *sc
         st.C0 = fmaf(wgt, cl.x, st.C0);
         st.C1 = fmaf(wgt, cl.y, st.C1);
         st.C2 = fmaf(wgt, cl.z, st.C2);
-        st.T = Tn;
         if (AUX) {
           st.W += wgt;
           st.nblend += 1u;
@@ -504,7 +507,10 @@ __global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParam
   __shared__ typename SharedFor<G, PREC, S, GF>::type sm;
   short8 B0, B1, B20, B21;
   make_pixel_operand<PREC>(B0, B1, B20, B21);
-  raster_item<G, PREC, S, AUX, GF>(J, P, blockIdx.x, sm, B0, B1, B20, B21);
+  // one workgroup per bin (parts == 1) in the XCD-aware order, else one per work item
+  const int item = J.parts == 1 ? xcd_raster_bin((int)blockIdx.x, J.GX, J.GY) : (int)blockIdx.x;
+  if (item < 0) return;
+  raster_item<G, PREC, S, AUX, GF>(J, P, item, sm, B0, B1, B20, B21);
 }
 
 // Persistent batched rasterizer: workgroups take (job, item) work items from *counter until
@@ -545,7 +551,8 @@ hipError_t launch_gf(const RasterJob &j, const RasterParams &p, const BatchArgs 
     hipLaunchKernelGGL((k_raster_mfma_batch<G, PREC, S, AUX, GF>), dim3((unsigned)b->grid), dim3(kBlock), 0, st,
                        *b->table, p, b->counter);
   } else {
-    hipLaunchKernelGGL((k_raster_mfma<G, PREC, S, AUX, GF>), dim3((unsigned)j.items), dim3(kBlock), 0, st, j, p);
+    const unsigned grid = j.parts == 1 ? xcd_raster_grid(j.GX, j.GY) : (unsigned)j.items;
+    hipLaunchKernelGGL((k_raster_mfma<G, PREC, S, AUX, GF>), dim3(grid), dim3(kBlock), 0, st, j, p);
   }
   return hipGetLastError();
 }

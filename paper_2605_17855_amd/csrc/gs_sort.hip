@@ -96,11 +96,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(const KT *keys, uint64_t
   constexpr int kRounds = SortTile<R>::kRounds, kWaveTile = SortTile<R>::kWaveTile, kSortTile = SortTile<R>::kTile;
   __shared__ uint32_t h[kDigits];
   const uint64_t n = count_of(n_host, n_dev);
-  if ((uint64_t)blockIdx.x * kSortTile >= n) return;
+  const uint32_t tile = xcd_sort_tile(blockIdx.x, (n + kSortTile - 1) / kSortTile);
+  if (tile == ~0u) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   h[t] = 0;
   const uint32_t dmask = (1u << nbits) - 1u;
-  const uint64_t base = (uint64_t)blockIdx.x * kSortTile + (uint64_t)w * kWaveTile;
+  const uint64_t base = (uint64_t)tile * kSortTile + (uint64_t)w * kWaveTile;
   KT key[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(const KT *keys, uint64_t
     if (valid) atomicAdd(&h[d], 1u);   // (cheaper than grouping equal digits per wave first)
   }
   __syncthreads();
-  counts[(uint64_t)t * tiles_max + blockIdx.x] = h[t];
+  counts[(uint64_t)t * tiles_max + tile] = h[t];
 }
 
 // One workgroup per digit d: counts[d][*] becomes the exclusive prefix over tiles (within the
@@ -174,8 +175,9 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
   __shared__ uint32_t s_val[kSortTile];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint64_t n = count_of(n_host, n_dev);
-  const uint64_t tile0 = (uint64_t)blockIdx.x * kSortTile;
-  if (tile0 >= n) return;
+  const uint32_t tile = xcd_sort_tile(blockIdx.x, (n + kSortTile - 1) / kSortTile);
+  if (tile == ~0u) return;
+  const uint64_t tile0 = (uint64_t)tile * kSortTile;
   const uint32_t dmask = (1u << nbits) - 1u;
   const uint64_t lt = (1ull << lane) - 1ull;
   const uint64_t base = tile0 + (uint64_t)w * kWaveTile;
@@ -190,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
 #pragma unroll
   for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
   const uint32_t tot_d = t < (1 << nbits) ? totals[t] : 0u;   // the digit scan covers 2^nbits digits
-  const uint32_t off_d = offsets[(uint64_t)t * tiles_max + blockIdx.x];
+  const uint32_t off_d = offsets[(uint64_t)t * tiles_max + tile];
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
@@ -278,7 +280,8 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis,
                                                        uint32_t *keys, const uint64_t *K, uint64_t *counts,
-                                                       uint64_t *host_counts, int nbits0, uint32_t *dcounts) {
+                                                       uint64_t *host_counts, int nbits0, uint32_t *dcounts,
+                                                       uint32_t tiles) {
   constexpr int kSortTile = SortTile<R>::kTile;
   __shared__ uint32_t h[kDigits];
   const uint32_t V = *nvis;
@@ -291,8 +294,10 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, co
       host_counts[1] = V;
     }
   }
-  const uint64_t tile0 = (uint64_t)blockIdx.x * kSortTile;
-  if (tile0 >= V) return;
+  // the tile order of the sort's own passes over the V keys
+  const uint32_t tile = xcd_sort_tile(blockIdx.x, ((uint64_t)V + kSortTile - 1) / kSortTile);
+  if (tile == ~0u) return;
+  const uint64_t tile0 = (uint64_t)tile * kSortTile;
   h[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t dmask = (1u << nbits0) - 1u;
@@ -312,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, co
     }
   }
   __syncthreads();
-  dcounts[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+  dcounts[(uint64_t)threadIdx.x * tiles + tile] = h[threadIdx.x];
 }
 
 // ---- binning: one thread per entry -------------------------------------------
@@ -333,16 +338,19 @@ __device__ __forceinline__ uint32_t local_gaussian(const uint64_t *s_pos, uint32
   return lo;
 }
 
+// The bin ranges start empty (the ranges kernel writes the non-empty ones after the sort):
+// every workgroup of the binning grid clears its grid-stride share.
+__device__ __forceinline__ void clear_ranges(uint32_t *ranges, uint64_t nranges) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < nranges; i += (uint64_t)gridDim.x * kBlock)
+    ranges[i] = 0u;
+}
+
 // Stages the first-entry offsets of the Gaussians that own entries [e0, e0 + kBinItems) into
-// s_pos[0..span] (s_pos[l] = dpos[first + l]) and clears the bin ranges (grid-stride).
+// s_pos[0..span] (s_pos[l] = dpos[first + l]).
 template <int ITEMS>
 __device__ __forceinline__ void stage_block_gaussians(const uint64_t *dpos, const uint32_t *block_first, uint32_t nvis,
                                                       uint64_t e0, uint64_t *s_pos, uint32_t *s_first,
-                                                      uint32_t *first, uint32_t *span, uint32_t *ranges,
-                                                      uint64_t nranges) {
-  // the bin ranges start empty (the ranges kernel writes the non-empty ones after the sort)
-  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < nranges; i += (uint64_t)gridDim.x * kBlock)
-    ranges[i] = 0u;
+                                                      uint32_t *first, uint32_t *span) {
   const int t = threadIdx.x, lane = t & 63;
   if (block_first) {
     // recorded by the offset scan (e0 is a multiple of its 1,024-entry blocks)
@@ -371,10 +379,12 @@ __device__ __forceinline__ void stage_block_gaussians(const uint64_t *dpos, cons
 }
 
 // The first radix pass's per-tile digit counts, taken where the keys are written (the binning
-// workgroup covers exactly one sort tile): counts[d * tiles + tile] for the digit bits [0, nbits0).
+// workgroup covers exactly one sort tile, in the sort's XCD-aware tile order):
+// counts[d * tiles + tile] for the digit bits [0, nbits0).
 struct FirstCounts {
   uint32_t *counts;   // nullptr: no sort follows
   int nbits0;
+  uint32_t tiles;
 };
 
 template <int ITEMS>
@@ -386,10 +396,13 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
   __shared__ uint64_t s_pos[ITEMS + 1];
   __shared__ uint32_t s_first;
   __shared__ uint32_t h[kDigits];
-  const uint64_t e0 = (uint64_t)blockIdx.x * ITEMS;
+  const uint32_t tile = xcd_sort_tile(blockIdx.x, (K + ITEMS - 1) / ITEMS);
+  const uint64_t e0 = (uint64_t)tile * ITEMS;
+  clear_ranges(ranges, nranges);
+  if (tile == ~0u) return;
   h[threadIdx.x] = 0;
   uint32_t first, span;
-  stage_block_gaussians<ITEMS>(dpos, block_first, nvis, e0, s_pos, &s_first, &first, &span, ranges, nranges);
+  stage_block_gaussians<ITEMS>(dpos, block_first, nvis, e0, s_pos, &s_first, &first, &span);
   const uint32_t dmask = (1u << fc.nbits0) - 1u;
 #pragma unroll
   for (int it = 0; it < ITEMS / kBlock; ++it) {
@@ -411,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
   }
   if (fc.counts) {
     __syncthreads();
-    fc.counts[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+    fc.counts[(uint64_t)threadIdx.x * fc.tiles + tile] = h[threadIdx.x];
   }
 }
 
@@ -430,11 +443,14 @@ __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order,
   __shared__ uint64_t s_pos[ITEMS + 1];
   __shared__ uint32_t s_first;
   __shared__ uint32_t h[kDigits];
-  const uint64_t e0 = (uint64_t)blockIdx.x * ITEMS;
+  const uint32_t tile = xcd_sort_tile(blockIdx.x, (K + ITEMS - 1) / ITEMS);
+  const uint64_t e0 = (uint64_t)tile * ITEMS;
   const int lane = threadIdx.x & 63;
+  clear_ranges(ranges, nranges);
+  if (tile == ~0u) return;
   h[threadIdx.x] = 0;
   uint32_t first, span;
-  stage_block_gaussians<ITEMS>(dpos, block_first, nvis, e0, s_pos, &s_first, &first, &span, ranges, nranges);
+  stage_block_gaussians<ITEMS>(dpos, block_first, nvis, e0, s_pos, &s_first, &first, &span);
   const uint32_t dmask = (1u << fc.nbits0) - 1u;
 #pragma unroll
   for (int it = 0; it < ITEMS / kBlock; ++it) {
@@ -533,7 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order,
   }
   if (fc.counts) {
     __syncthreads();
-    fc.counts[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+    fc.counts[(uint64_t)threadIdx.x * fc.tiles + tile] = h[threadIdx.x];
   }
 }
 
@@ -694,11 +710,12 @@ hipError_t radix_passes_r(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals
     const int bits = (hi - shift) < width ? (hi - shift) : width;
     const bool last = shift + width >= hi;
     if (!(first_counted && shift == lo))
-      hipLaunchKernelGGL((k_radix_count<KT, R>), dim3(tiles), dim3(kBlock), 0, st, kin, n, n_dev, shift, bits, tiles,
-                         counts);
+      hipLaunchKernelGGL((k_radix_count<KT, R>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, kin, n, n_dev, shift,
+                         bits, tiles, counts);
     hipLaunchKernelGGL(k_radix_digit_scan, dim3(1u << bits), dim3(kBlock), 0, st, counts, tiles, totals, n, n_dev,
                        (uint32_t)SortTile<R>::kTile);
-    hipLaunchKernelGGL((k_radix_scatter<KT, R>), dim3(tiles), dim3(kBlock), 0, st, kin, vin, kout, vout, n, n_dev,
+    hipLaunchKernelGGL((k_radix_scatter<KT, R>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, kin, vin, kout, vout,
+                       n, n_dev,
                        shift, bits, tiles, counts, totals, aux_in, last ? aux_out : nullptr,
                        (last && fin) ? *fin : none);
     std::swap(kin, kout);
@@ -736,12 +753,13 @@ hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, const uin
   // pass's digit counts are taken here
   const int nbits0 = pass_width(0, 32);
   uint32_t *dcounts = static_cast<uint32_t *>(tmp);
+  const uint32_t tiles = (uint32_t)sort_tiles(n_max ? n_max : 1);
   if (n_max <= kSmallSort)
-    hipLaunchKernelGGL((k_depth_keys<kSmallR>), dim3((unsigned)sort_tiles(n_max ? n_max : 1)), dim3(kBlock), 0, st,
-                       order, rgb, nvis, keys, K, counts, host_counts, nbits0, dcounts);
+    hipLaunchKernelGGL((k_depth_keys<kSmallR>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, order, rgb, nvis, keys,
+                       K, counts, host_counts, nbits0, dcounts, tiles);
   else
-    hipLaunchKernelGGL((k_depth_keys<kLargeR>), dim3((unsigned)sort_tiles(n_max)), dim3(kBlock), 0, st, order, rgb,
-                       nvis, keys, K, counts, host_counts, nbits0, dcounts);
+    hipLaunchKernelGGL((k_depth_keys<kLargeR>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, order, rgb, nvis, keys,
+                       K, counts, host_counts, nbits0, dcounts, tiles);
   return hipGetLastError();
 }
 
@@ -764,9 +782,10 @@ hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint
   const float4 *c4 = reinterpret_cast<const float4 *>(conic);
   const int hi = bits_for((uint64_t)g.nbins);
   // with a sort to follow (K > 1), the binning takes its first pass's digit counts
-  const FirstCounts fc{K > 1 ? static_cast<uint32_t *>(tmp) : nullptr, pass_width(0, hi)};
   const bool large = K > kSmallSort;
-  const unsigned grid = grid_for(K, large ? SortTile<kLargeR>::kTile : SortTile<kSmallR>::kTile);
+  const unsigned tiles = grid_for(K, large ? SortTile<kLargeR>::kTile : SortTile<kSmallR>::kTile);
+  const FirstCounts fc{K > 1 ? static_cast<uint32_t *>(tmp) : nullptr, pass_width(0, hi), tiles};
+  const unsigned grid = xcd_sort_grid(tiles);   // the sort's tile order (k_radix_scatter)
   if (tight) {
     if (large)
       hipLaunchKernelGGL((k_binning_tight<SortTile<kLargeR>::kTile>), dim3(grid), dim3(kBlock), 0, st, order, dpos,
