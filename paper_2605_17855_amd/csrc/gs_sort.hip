@@ -322,11 +322,10 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, co
 
 // ---- binning: one thread per entry -------------------------------------------
 // dpos[i] = first entry of the i-th visible Gaussian in depth order (exclusive scan of its
-// bin count; dpos[V] = K).  Every visible Gaussian owns at least one entry, so a block's
-// kBinItems consecutive entries span at most kBinItems consecutive Gaussians: one
-// wave-wide search finds the first, the block stages their offsets in LDS, and each
-// entry finds its Gaussian by binary search there.
-constexpr int kBinItems = 1024;
+// bin count; dpos[V] = K).  Every visible Gaussian owns at least one entry, so a workgroup's
+// ITEMS consecutive entries span at most ITEMS consecutive Gaussians: the offset scan's block
+// firsts (or a wave-wide search) give the first, the workgroup stages their offsets in LDS,
+// and each entry finds its Gaussian by binary search there.
 
 // Last Gaussian (local index) of the staged offsets s_pos[0..span] whose first entry is <= e.
 __device__ __forceinline__ uint32_t local_gaussian(const uint64_t *s_pos, uint32_t span, uint64_t e) {
@@ -338,6 +337,20 @@ __device__ __forceinline__ uint32_t local_gaussian(const uint64_t *s_pos, uint32
   return lo;
 }
 
+// The same with a fixed number of steps (span <= ITEMS, s_pos[0] <= e < s_pos[span]): no
+// data-dependent loop, so the searches of a thread's several entries interleave.
+template <int ITEMS>
+__device__ __forceinline__ uint32_t local_gaussian_fixed(const uint64_t *s_pos, uint32_t span, uint64_t e) {
+  uint32_t lo = 0;
+#pragma unroll
+  for (uint32_t step = ITEMS / 2; step > 0; step >>= 1) {
+    const uint32_t c = lo + step;
+    const bool take = c <= span && s_pos[c <= span ? c : span] <= e;
+    lo = take ? c : lo;
+  }
+  return lo;
+}
+
 // The bin ranges start empty (the ranges kernel writes the non-empty ones after the sort):
 // every workgroup of the binning grid clears its grid-stride share.
 __device__ __forceinline__ void clear_ranges(uint32_t *ranges, uint64_t nranges) {
@@ -345,12 +358,13 @@ __device__ __forceinline__ void clear_ranges(uint32_t *ranges, uint64_t nranges)
     ranges[i] = 0u;
 }
 
-// Stages the first-entry offsets of the Gaussians that own entries [e0, e0 + kBinItems) into
-// s_pos[0..span] (s_pos[l] = dpos[first + l]).
+// Stages the first-entry offsets of the Gaussians that own entries [e0, e0 + ITEMS) into
+// s_pos[0..span] (s_pos[l] = dpos[first + l]) and, with s_g, their indices s_g[l] = order[first + l].
 template <int ITEMS>
 __device__ __forceinline__ void stage_block_gaussians(const uint64_t *dpos, const uint32_t *block_first, uint32_t nvis,
                                                       uint64_t e0, uint64_t *s_pos, uint32_t *s_first,
-                                                      uint32_t *first, uint32_t *span) {
+                                                      uint32_t *first, uint32_t *span,
+                                                      const uint32_t *order = nullptr, uint32_t *s_g = nullptr) {
   const int t = threadIdx.x, lane = t & 63;
   if (block_first) {
     // recorded by the offset scan (e0 is a multiple of its 1,024-entry blocks)
@@ -374,7 +388,10 @@ __device__ __forceinline__ void stage_block_gaussians(const uint64_t *dpos, cons
   __syncthreads();
   *first = *s_first;
   *span = (nvis - *first) < (uint32_t)ITEMS ? (nvis - *first) : (uint32_t)ITEMS;
-  for (uint32_t i = t; i <= *span; i += kBlock) s_pos[i] = dpos[*first + i];
+  for (uint32_t i = t; i <= *span; i += kBlock) {
+    s_pos[i] = dpos[*first + i];
+    if (s_g && i < *span) s_g[i] = order[*first + i];
+  }
   __syncthreads();
 }
 
@@ -387,13 +404,19 @@ struct FirstCounts {
   uint32_t tiles;
 };
 
+// One workgroup per sort tile of entries.  Each thread first finds the Gaussians of all its
+// entries (LDS searches, interleaved), then gathers their rects (one round trip for all of
+// them), then writes: the entry's Gaussian comes from the staged block, not from a gather per
+// entry.
 template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const uint64_t *dpos,
                                                     const uint32_t *block_first, uint32_t nvis,
                                                     uint64_t K, const ushort4 *rect, int G, int GX,
                                                     uint32_t *bin_keys, uint32_t *vals, uint32_t *ranges,
                                                     uint64_t nranges, FirstCounts fc) {
+  constexpr int NI = ITEMS / kBlock;
   __shared__ uint64_t s_pos[ITEMS + 1];
+  __shared__ uint32_t s_g[ITEMS];
   __shared__ uint32_t s_first;
   __shared__ uint32_t h[kDigits];
   const uint32_t tile = xcd_sort_tile(blockIdx.x, (K + ITEMS - 1) / ITEMS);
@@ -402,23 +425,28 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
   if (tile == ~0u) return;
   h[threadIdx.x] = 0;
   uint32_t first, span;
-  stage_block_gaussians<ITEMS>(dpos, block_first, nvis, e0, s_pos, &s_first, &first, &span);
+  stage_block_gaussians<ITEMS>(dpos, block_first, nvis, e0, s_pos, &s_first, &first, &span, order, s_g);
   const uint32_t dmask = (1u << fc.nbits0) - 1u;
+  uint32_t l[NI];
 #pragma unroll
-  for (int it = 0; it < ITEMS / kBlock; ++it) {
+  for (int it = 0; it < NI; ++it) {
+    const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
+    l[it] = e < K ? local_gaussian_fixed<ITEMS>(s_pos, span, e) : 0u;
+  }
+  ushort4 r[NI];
+#pragma unroll
+  for (int it = 0; it < NI; ++it) r[it] = rect[s_g[l[it]]];   // (l < span: a staged Gaussian)
+#pragma unroll
+  for (int it = 0; it < NI; ++it) {
     const uint64_t e = e0 + (uint64_t)it * kBlock + threadIdx.x;
     if (e < K) {
-      const uint32_t l = local_gaussian(s_pos, span, e);
-      const uint32_t rank = first + l;
-      const uint32_t g = order[rank];
-      const uint32_t j = (uint32_t)(e - s_pos[l]);
-      const ushort4 r = rect[g];
-      const int gx0 = r.x / G, gx1 = (r.z - 1) / G, gy0 = r.y / G;
+      const uint32_t j = (uint32_t)(e - s_pos[l[it]]);
+      const int gx0 = r[it].x / G, gx1 = (r[it].z - 1) / G, gy0 = r[it].y / G;
       const int wdt = gx1 - gx0 + 1;
       const int gy = gy0 + (int)(j / (uint32_t)wdt), gx = gx0 + (int)(j % (uint32_t)wdt);
       const uint32_t bin = (uint32_t)(gy * GX + gx);
       bin_keys[e] = bin;
-      vals[e] = rank;   // the Gaussian's rank in depth order; the last sort pass turns it into its index
+      vals[e] = first + l[it];   // the Gaussian's rank in depth order; the last sort pass turns it into its index
       if (fc.counts) atomicAdd(&h[bin & dmask], 1u);
     }
   }
