@@ -298,9 +298,21 @@ def test_1080psampled_tiles(big):
         assert np.abs(out["wsum"] + out["tfinal"] - 1.0).max() <= 1e-5
 
 
+_BATCH_REFS = {}
+
+
+def _batch_oracle(k, sc, cam, bg):
+    """The FP64 oracle's render of batch job k (computed once per module)."""
+    if k not in _BATCH_REFS:
+        _BATCH_REFS[k] = oracle.render(sc, cam, bg=bg)
+    return _BATCH_REFS[k]
+
+
 @pytest.mark.parametrize("prec,group", [("fp16", 1), ("fp32", 1), ("bf16", 2), ("fp16", 8)])
 def test_batch_matches_single_renders(prec, group):
-    """Persistent batched rasterization: every image equals rendering its job alone (bit-identical)."""
+    """Persistent batched rasterization: every image equals rendering its job alone (bit-identical),
+    and every batched image and its T_final plane meet the oracle's bars (flagged pixels: one of
+    their admissible results)."""
     import torch
     jobs = []
     specs = [(scenes.camera_box_scene(3000, seed=21), scenes.pinhole(128, 96, 60.0)),
@@ -327,6 +339,18 @@ def test_batch_matches_single_renders(prec, group):
     torch.cuda.synchronize()
     for (img, ax), j in zip(singles, jobs):
         assert torch.equal(img, j[3]) and torch.equal(ax, j[4])
+    bg = (0.2, 0.1, 0.0)
+    tol, tol_t = (1e-4, 1e-5) if prec == "fp32" else (1e-3, 2e-3)
+    for k, ((sc, cam), j) in enumerate(zip(specs, jobs)):
+        ref = _batch_oracle(k, sc, cam, bg)
+        img = j[3].double().cpu().numpy()
+        tf = j[4][0].double().cpu().numpy()
+        ok = ref["ambiguous"] == 0
+        err = np.abs(img - ref["image"])[:, ok]
+        assert (err.max() if err.size else 0.0) <= tol, (k, float(err.max()))
+        assert np.abs(tf - ref["tfinal"])[ok].max() <= tol_t
+        check_flagged_pixels(f"batch {prec} g{group} job {k}", img, tf, ref, ref["records"], cam, ref["start"],
+                             ref["ids"], bg=bg, tol=tol, tol_t=tol_t)
     # the same jobs twice in one launch, in another order
     order = [2, 0, 3, 1, 2]
     outs = [(torch.full_like(jobs[k][3], -1.0), torch.full_like(jobs[k][4], -1.0)) for k in order]
