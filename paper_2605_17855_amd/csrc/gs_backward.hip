@@ -259,12 +259,12 @@ __global__ __launch_bounds__(kBlock) void k_raster_backward_mfma(BackwardJob J, 
       const float4 co = J.conic[g];
       const float4 cl = J.rgb[g];
       const float u = (float)(m.x - ((double)ox + 8.5)), v = (float)(m.y - ((double)oy + 8.5));
-      const float lno = __logf(co.w);
-      mfma::build_row<PREC, S>(&sm.A[t * RS], u, v, co.x, co.y, co.z, lno);
+      const float l2o = mfma::log2_opacity(co.w);
+      mfma::build_row<PREC, S>(&sm.A[t * RS], u, v, co.x, co.y, co.z, l2o);
       sm.p0[t] = make_float4(u, v, co.x, co.y);
       sm.p1[t] = make_float4(co.z, 1.0f / co.w, cl.x, cl.y);
       sm.p2[t] = make_float2(cl.z, __uint_as_float(g));
-      sm.qm[t] = all_rows ? (uint8_t)0xF : (uint8_t)mfma::quad_mask(u, v, co.x, co.y, co.z, lno);
+      sm.qm[t] = all_rows ? (uint8_t)0xF : (uint8_t)mfma::quad_mask(u, v, co.x, co.y, co.z, l2o);
     }
     __syncthreads();
     const int n = mfma::wave_list(sm.qm, cnt, sm.wl[w]);

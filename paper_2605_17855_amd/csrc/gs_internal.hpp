@@ -13,6 +13,7 @@ constexpr int kBlock = 256;          // threads per workgroup for every kernel h
 constexpr float kAlphaMax = 0.99f;   // opacity clamp
 constexpr float kTMin = 1e-4f;       // transmittance stop
 constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
 // log2(1/255): the 1/255 alpha cut taken on log2(alpha)
 constexpr float kCutLog2 = -7.994353436858858f;
 

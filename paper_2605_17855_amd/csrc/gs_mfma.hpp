@@ -59,26 +59,33 @@ struct Narrow<GS_PREC_BF16_MFMA> {
 //   splits 2: [k0..k5, l0, l1 | l2..l5, 0 x 4]
 //   splits 3: the splits-2 row, then [m0..m5, 0, 0 | 0 x 8]
 //
+// log2 of a Gaussian's opacity, the form the row and the quadrant test take it in (one
+// transcendental instruction; opacities are normal numbers in (0, 1]).
+__device__ __forceinline__ float log2_opacity(float o) { return __builtin_amdgcn_logf(o); }
+
 // Contraction is off here: with it, the compiler may fuse the product that forms k[i] with
 // the subtraction that forms the residual (one rounding instead of two), and whether it does
 // depends on the surrounding code, so the same Gaussian's row could differ between the
 // ungrouped, grouped and batched kernels.  Every operation below rounds as written.
+// l2o = log2_opacity(o); the constant slot is log2(o) - (log2 e / 2) q.
 template <int PREC, int S>
-__device__ __forceinline__ void build_row(uint16_t *row, float u, float v, float a, float b, float c, float lno) {
+__device__ __forceinline__ void build_row(uint16_t *row, float u, float v, float a, float b, float c, float l2o) {
 #pragma clang fp contract(off)
   using N = Narrow<PREC>;
   const float p3 = fmaf(a, u, b * v), p4 = fmaf(b, u, c * v);
   const float q = fmaf(u, p3, v * p4);
   float k[6] = {-0.5f * kLog2e * a, -kLog2e * b, -0.5f * kLog2e * c, kLog2e * p3, kLog2e * p4,
-                kLog2e * fmaf(-0.5f, q, lno)};
-  uint16_t hi[6], lo[6], lo2[6];
+                fmaf(-0.5f * kLog2e, q, l2o)};
+  uint16_t hi[6], lo[6], lo2[6] = {};
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     hi[i] = N::enc(k[i]);
     float r = (k[i] - N::dec(hi[i])) * N::kScale;
     lo[i] = N::enc(r);
-    r = (r - N::dec(lo[i])) * N::kScale;
-    lo2[i] = N::enc(r);
+    if constexpr (S == 3) {   // (the encoders' register pin would keep an unused third piece alive)
+      r = (r - N::dec(lo[i])) * N::kScale;
+      lo2[i] = N::enc(r);
+    }
   }
   short8 v0, v1;
 #pragma unroll
@@ -120,9 +127,9 @@ __device__ __forceinline__ void build_row(uint16_t *row, float u, float v, float
 constexpr float kQuadMargin = 1.0f;
 constexpr float kQuadQ0 = 11.0825270f + kQuadMargin;   // 2 ln 255 + margin
 
-__device__ __forceinline__ uint32_t quad_mask(float u, float v, float a, float b, float c, float lno) {
+__device__ __forceinline__ uint32_t quad_mask(float u, float v, float a, float b, float c, float l2o) {
 #pragma clang fp contract(off)
-  const float Q = fmaf(2.0f, lno, kQuadQ0);
+  const float Q = fmaf(2.0f * kLn2, l2o, kQuadQ0);   // 2 ln(o) + 2 ln 255 + margin
   if (!(Q > 0.0f)) return 0u;               // o < 1/255 e^{-margin/2}: never reaches the cut
   const float det = (float)((double)a * c - (double)b * b);
   if (!(a > 0.0f && c > 0.0f && det > 0.0f)) return 0xFu;

@@ -226,8 +226,8 @@ __device__ __forceinline__ void raster_bin_mfma_group(const RasterJob &J, const 
       const float4 cl = J.rgb[g];
       mk = (uint32_t) static_cast<const uint16_t *>(J.masks)[e];
       const float u = (float)(m.x - fx0), v = (float)(m.y - fy0);
-      const float lno = __logf(co.w);
-      build_row<PREC, S>(&sm.A[t * RS], u, v, co.x, co.y, co.z, lno);
+      const float l2o = log2_opacity(co.w);
+      build_row<PREC, S>(&sm.A[t * RS], u, v, co.x, co.y, co.z, l2o);
       sm.col[0][t] = cl.x;
       sm.col[1][t] = cl.y;
       sm.col[2][t] = cl.z;
@@ -238,7 +238,7 @@ __device__ __forceinline__ void raster_bin_mfma_group(const RasterJob &J, const 
         if ((mk >> k) & 1u) {
           // the quadrant test in member tile k's own frame
           const float ut = u + (float)(8 * G - 8 - (k % G) * kTile), vt = v + (float)(8 * G - 8 - (k / G) * kTile);
-          q |= (P.all_rows ? 0xFu : quad_mask(ut, vt, co.x, co.y, co.z, lno)) << (4 * j);
+          q |= (P.all_rows ? 0xFu : quad_mask(ut, vt, co.x, co.y, co.z, l2o)) << (4 * j);
         }
       }
       sm.qm[t] = (uint16_t)q;
@@ -368,12 +368,12 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
         const float4 co = J.conic[g];
         const float4 cl = J.rgb[g];
         const float u = (float)(m.x - ((double)ox + 8.5)), v = (float)(m.y - ((double)oy + 8.5));
-        const float lno = __logf(co.w);
-        build_row<PREC, S>(&sm.A[buf][t * RS], u, v, co.x, co.y, co.z, lno);
+        const float l2o = log2_opacity(co.w);
+        build_row<PREC, S>(&sm.A[buf][t * RS], u, v, co.x, co.y, co.z, l2o);
         sm.col[buf][0][t] = cl.x;
         sm.col[buf][1][t] = cl.y;
         sm.col[buf][2][t] = cl.z;
-        sm.qm[buf][t] = P.all_rows ? (uint8_t)0xF : (uint8_t)quad_mask(u, v, co.x, co.y, co.z, lno);
+        sm.qm[buf][t] = P.all_rows ? (uint8_t)0xF : (uint8_t)quad_mask(u, v, co.x, co.y, co.z, l2o);
       }
       __syncthreads();
       const int nw = wave_list(sm.qm[buf], cnt, sm.wl[w]);
@@ -395,7 +395,7 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
         mk = G == 8 ? (TileMask) static_cast<const uint64_t *>(J.masks)[e]
                     : (TileMask) static_cast<const uint16_t *>(J.masks)[e];
         sm.r0[t] = m;
-        sm.r1[t] = make_float4(co.x, co.y, co.z, __logf(co.w));
+        sm.r1[t] = make_float4(co.x, co.y, co.z, log2_opacity(co.w));
         sm.r2[t] = cl;
       }
 #pragma unroll kTileUnroll
