@@ -154,10 +154,16 @@ Workspace carve(void *ws, int64_t n, uint64_t capacity) {
 
 // Workgroups per bin.  With 4x4 and 8x8 groups each workgroup takes one row of the group's
 // member tiles: a 1080p frame has 510 (4x4) or 135 (8x8) groups, too few to fill 256 CUs
-// with one workgroup per group walking 16 or 64 tiles.  Every tile still sees its rows in
-// the same order with the same arithmetic, so the image does not depend on the split.
+// with one workgroup per group walking 16 or 64 tiles.  2x2 groups with rows built in the
+// group frame take one row of two member tiles per workgroup as well: ~2,000 workgroups each
+// walking four tiles left most CUs idle while the last, densest groups finished.  Every tile
+// still sees its rows in the same order with the same arithmetic, so the image does not
+// depend on the split.
 int raster_parts(const gs_options &o) {
-  return (o.precision != GS_PREC_FP32 && o.group >= 4) ? o.group : 1;
+  if (o.precision == GS_PREC_FP32) return 1;
+  if (o.group >= 4) return o.group;
+  if (o.group == 2 && !(o.flags & GS_OPT_TILE_ROWS)) return 2;
+  return 1;
 }
 
 gsi::RasterJob make_job(const gs_projected &p, const gs_bins &b, const gsi::Grid &g, float *image, float *aux,

@@ -166,7 +166,7 @@ struct GroupFrame {
 template <int S>
 struct MfmaGroupShared {
   static constexpr int RS = (S == 3) ? 32 : 16;
-  static constexpr int NTP = 4;    // member tiles per workgroup: a 2x2 group
+  static constexpr int NTP = 2;    // member tiles per workgroup: one row of a 2x2 group
   __align__(16) uint16_t A[kBlock * RS];
   float col[3][kBlock];
   uint16_t qm[kBlock];             // bit 4 j + q: quadrant q of the workgroup's member tile j
@@ -180,10 +180,15 @@ struct MfmaGroupShared {
 template <int G, int PREC, int S, bool AUX>
 __device__ __forceinline__ void raster_bin_mfma_group(const RasterJob &J, const RasterParams &P, int item,
                                                       MfmaGroupShared<S> &sm) {
+  // two workgroups per 2x2 group (J.parts == 2), each taking one row of member tiles: twice the
+  // workgroups of one per group, each half as long, which the CUs balance far better (a 1080p
+  // frame has ~2,000 groups for 256 CUs); both stage the group's chunk, each builds only the
+  // rows of entries that reach one of its own tiles
   constexpr int NTP = MfmaGroupShared<S>::NTP;
+  static_assert(NTP == 2, "the tile step below selects between two member tiles");
   constexpr int RS = MfmaGroupShared<S>::RS;
-  const int bin = G >= 4 ? item / J.parts : item;
-  const int k0 = G >= 4 ? (item % J.parts) * (G * G / J.parts) : 0;   // first member tile of the workgroup
+  const int bin = item / 2;
+  const int k0 = (item % 2) * NTP;   // first member tile of the workgroup
   const int gx = bin % J.GX, gy = bin / J.GX;
   const int ox = gx * G * kTile, oy = gy * G * kTile;
   const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
@@ -192,7 +197,9 @@ __device__ __forceinline__ void raster_bin_mfma_group(const RasterJob &J, const 
   const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
   const double fx0 = (double)ox + 8.0 * G + 0.5, fy0 = (double)oy + 8.0 * G + 0.5;   // group frame origin
 
-  TileState st[NTP];
+  // the two member tiles' blending state, kept in registers (named, not an array: a copy
+  // indexed by the tile loop's counter would place it in private memory)
+  TileState st0, st1;
   uint32_t rows_done[NTP];
   uint32_t alive_w = 0;            // uniform per wave: member tiles where this wave's pixels still blend
 #pragma unroll
@@ -200,9 +207,10 @@ __device__ __forceinline__ void raster_bin_mfma_group(const RasterJob &J, const 
     const int k = k0 + j;
     const int tx0 = ox + (k % G) * kTile, ty0 = oy + (k / G) * kTile;
     const bool inside = (tx0 + px < J.W) && (ty0 + py < J.H);
-    st[j].T = 1.0f; st[j].C0 = st[j].C1 = st[j].C2 = 0.0f; st[j].W = 0.0f;
-    st[j].cut = inside ? kCutLog2 : INFINITY;
-    st[j].nstop = 0; st[j].nblend = 0; st[j].last = 0;
+    TileState &sj = j == 0 ? st0 : st1;   // (j is a constant in the unrolled loop)
+    sj.T = 1.0f; sj.C0 = sj.C1 = sj.C2 = 0.0f; sj.W = 0.0f;
+    sj.cut = inside ? kCutLog2 : INFINITY;
+    sj.nstop = 0; sj.nblend = 0; sj.last = 0;
     rows_done[j] = 0;
     if (__ballot(inside) != 0) alive_w |= 1u << j;
   }
@@ -218,13 +226,14 @@ __device__ __forceinline__ void raster_bin_mfma_group(const RasterJob &J, const 
       if (!any) break;
     }
     uint32_t mk = 0;
-    if (t < cnt) {
+    if (t < cnt) mk = (uint32_t) static_cast<const uint16_t *>(J.masks)[cs + t];
+    if (t < cnt && ((mk >> k0) & ((1u << NTP) - 1u)) == 0u) sm.qm[t] = 0;   // no tile of this workgroup
+    else if (t < cnt) {
       const uint32_t e = cs + t;
       const uint32_t g = J.vals[e];
       const double2 m = J.xy[g];
       const float4 co = J.conic[g];
       const float4 cl = J.rgb[g];
-      mk = (uint32_t) static_cast<const uint16_t *>(J.masks)[e];
       const float u = (float)(m.x - fx0), v = (float)(m.y - fy0);
       const float l2o = log2_opacity(co.w);
       build_row<PREC, S>(&sm.A[t * RS], u, v, co.x, co.y, co.z, l2o);
@@ -271,10 +280,12 @@ __device__ __forceinline__ void raster_bin_mfma_group(const RasterJob &J, const 
       short8 B0, B1, B20, B21;
       make_pixel_operand<PREC>(B0, B1, B20, B21, (k % G) * kTile - 8 * G + 8, (k / G) * kTile - 8 * G + 8);
       const int nw = wave_list_bit(sm.qm, cnt, 4 * j + w, sm.wl[w]);
-      TileState cur = st[j];
-      process_rows<PREC, S, AUX>(sm.A, &sm.col[0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, cur, rows_done[j],
+      TileState cur;
+      if (j == 0) cur = st0; else cur = st1;
+      process_rows<PREC, S, AUX>(sm.A, &sm.col[0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, cur,
+                                 j == 0 ? rows_done[0] : rows_done[1],
                                  AUX ? sm.tpos[j] : nullptr);
-      st[j] = cur;
+      if (j == 0) st0 = cur; else st1 = cur;
       if (__ballot(cur.cut != INFINITY) == 0) alive_w &= ~(1u << j);
     }
     if (AUX) {
@@ -293,19 +304,20 @@ __device__ __forceinline__ void raster_bin_mfma_group(const RasterJob &J, const 
     const int xx = ox + (k % G) * kTile + px, yy = oy + (k / G) * kTile + py;
     if (xx >= J.W || yy >= J.H) continue;
     const int64_t pix = (int64_t)yy * J.W + xx;
-    J.image[pix] = st[j].C0 + st[j].T * P.bg[0];
-    J.image[HW + pix] = st[j].C1 + st[j].T * P.bg[1];
-    J.image[2 * HW + pix] = st[j].C2 + st[j].T * P.bg[2];
+    const TileState &sj = j == 0 ? st0 : st1;
+    J.image[pix] = sj.C0 + sj.T * P.bg[0];
+    J.image[HW + pix] = sj.C1 + sj.T * P.bg[1];
+    J.image[2 * HW + pix] = sj.C2 + sj.T * P.bg[2];
     if (AUX) {
       int plane = 0;
-      if (P.aux_flags & GS_AUX_TFINAL) J.aux[(plane++) * HW + pix] = st[j].T;
-      if (P.aux_flags & GS_AUX_WSUM) J.aux[(plane++) * HW + pix] = st[j].W;
+      if (P.aux_flags & GS_AUX_TFINAL) J.aux[(plane++) * HW + pix] = sj.T;
+      if (P.aux_flags & GS_AUX_WSUM) J.aux[(plane++) * HW + pix] = sj.W;
       if (P.aux_flags & GS_AUX_NEVAL) {
-        const bool stopped = st[j].cut == INFINITY;
-        J.aux[(plane++) * HW + pix] = (float)(stopped ? st[j].nstop : rows_done[j]);
+        const bool stopped = sj.cut == INFINITY;
+        J.aux[(plane++) * HW + pix] = (float)(stopped ? sj.nstop : rows_done[j]);
       }
-      if (P.aux_flags & GS_AUX_NBLEND) J.aux[(plane++) * HW + pix] = (float)st[j].nblend;
-      if (P.aux_flags & GS_AUX_LAST) J.aux[(plane++) * HW + pix] = (float)st[j].last;
+      if (P.aux_flags & GS_AUX_NBLEND) J.aux[(plane++) * HW + pix] = (float)sj.nblend;
+      if (P.aux_flags & GS_AUX_LAST) J.aux[(plane++) * HW + pix] = (float)sj.last;
     }
   }
 }
