@@ -213,11 +213,14 @@ typedef struct {
 } gs_job;
 
 /* Rasterizes n_jobs images (at most gs_max_batch()) in one persistent launch: workgroups take
- * (job, bin) items from `work_counter` (device, one uint32, zeroed by the call) until every
- * bin of every job is done.  Each image is bit-identical to gs_rasterize of the same job alone
+ * (job, bin) items from the work counters in `work_counter` (device memory of
+ * GS_BATCH_COUNTER_BYTES bytes, cleared by the call; eight counters 64 bytes apart, each
+ * serving an interleaved eighth of the items, so that claims do not all queue on one address)
+ * until every bin of every job is done.  Each image is bit-identical to gs_rasterize of the same job alone
  * (the per-bin work does not depend on the launch).  All jobs share opt (group, precision,
  * splits, background, aux).  The job descriptions are copied into the launch, so `jobs` may be
  * reused when the call returns.  Serving: batches the ready requests of a request loop. */
+#define GS_BATCH_COUNTER_BYTES 512
 int32_t gs_max_batch(void);
 gs_status gs_rasterize_batch(const gs_job *jobs, int32_t n_jobs, const gs_options *opt, uint32_t *work_counter,
                              void *stream);
@@ -232,8 +235,9 @@ gs_status gs_rasterize_batch(const gs_job *jobs, int32_t n_jobs, const gs_option
  * The counter is cleared by a kernel on `stream` before each launch (no memset).  Every call on
  * one GPU shares that GPU's array, so calls whose launches overlap on one GPU (different streams,
  * or threads) race on the counter and must be serialized by the caller.  n_jobs above
- * gs_max_batch() returns GS_ERR_UNSUPPORTED; the launch itself needs 4 of the scratch bytes. */
-#define GS_NOALLOC_SCRATCH_BYTES 256
+ * gs_max_batch() returns GS_ERR_UNSUPPORTED; the launch's work counters take
+ * GS_BATCH_COUNTER_BYTES of the scratch bytes. */
+#define GS_NOALLOC_SCRATCH_BYTES 512
 gs_status gs_rasterize_batch_noalloc(const gs_job *jobs, int32_t n_jobs, const gs_options *opt, void *stream);
 
 const char *gs_status_string(gs_status s);

@@ -302,8 +302,9 @@ gs_status batch_table(const gs_job *jobs, int32_t n_jobs, const gs_options *opt,
   return GS_OK;
 }
 
-// One persistent launch over the table; `counter` (one uint32 of device memory) is cleared by a
-// fill kernel on the stream first (no memset node, so the launch can be captured in a graph).
+// One persistent launch over the table; `counter` (GS_BATCH_COUNTER_BYTES of device memory) is
+// cleared by a fill kernel on the stream first (no memset node, so the launch can be captured in
+// a graph).
 gs_status batch_launch(const gsi::BatchTable &table, const gs_options &opt, uint32_t *counter, hipStream_t st) {
   int dev = 0, cus = 0;
   GS_HIP(hipGetDevice(&dev));
@@ -312,7 +313,7 @@ gs_status batch_launch(const gsi::BatchTable &table, const gs_options &opt, uint
   // persistent grid: enough workgroups to fill every CU several times, never more than items
   int64_t grid = (int64_t)cus * 8;
   if (grid > table.total) grid = table.total;
-  GS_HIP(gsi::launch_fill_u32(counter, 1, 0u, st));
+  GS_HIP(gsi::launch_fill_u32(counter, GS_BATCH_COUNTER_BYTES / 4, 0u, st));
   if (opt.precision == GS_PREC_FP32)
     GS_HIP(gsi::launch_raster_fp32_batch(table, (int)grid, p, counter, st));
   else
@@ -549,8 +550,8 @@ gs_status gs_rasterize_batch_noalloc(const gs_job *jobs, int32_t n_jobs, const g
   gsi::BatchTable table{};
   gs_status s = batch_table(jobs, n_jobs, opt, &table);
   if (s || n_jobs == 0) return s;
-  // the launch needs one work counter; the scratch array holds kScratchBytes
-  static_assert(sizeof(uint32_t) <= kScratchBytes, "scratch too small for the work counter");
+  // the launch's work counters; the scratch array holds kScratchBytes
+  static_assert(GS_BATCH_COUNTER_BYTES <= kScratchBytes, "scratch too small for the work counters");
   uint32_t *counter = nullptr;
   if ((s = scratch_on_current_device(&counter))) return s;
   return batch_launch(table, *opt, counter, static_cast<hipStream_t>(stream));

@@ -331,8 +331,55 @@ struct BatchTable {
   int n_jobs, total;
   RasterJob jobs[kMaxBatch];   // jobs[j].bin0: first (job, bin) item of job j, ascending
 };
-// Persistent batched launches: `grid` workgroups take items [0, table.total) from *counter
-// (zeroed before).
+// Persistent batched launches: `grid` workgroups take items [0, table.total) from the counters
+// (zeroed before).  The items form kBatchSeqs interleaved sequences of kBatchRun-item runs
+// (sequence c: runs c, c + 8, c + 16, ...), each drained one item per claim by the workgroups b
+// with b % kBatchSeqs == c through its own counter, kBatchCounterStride words from the next.
+// With one counter for every workgroup the claims queued on one address: 140 µs for the 8,160
+// bins of a 1080p frame against 78 µs for the single-image launch (100 µs now).  As workgroup b
+// runs on XCD b mod 8, a sequence's runs of neighbouring bins (a job's bins are row-major) also
+// read their shared Gaussians through one L2.  (Claims of four items were slower, 179 µs: the
+// workgroups that start last then hold four items each.)  Every sequence with items has
+// workgroups (grid >= 8, or grid = total < 8 with every item in run 0), so every item is taken
+// exactly once.
+constexpr int kBatchSeqs = 8;
+constexpr int kBatchRun = 16;
+constexpr int kBatchCounterStride = GS_BATCH_COUNTER_BYTES / 4 / kBatchSeqs;
+static_assert(kBatchCounterStride >= 16, "counters of the batched launch share a 64-byte line");
+
+// Item of claim k of sequence c (increasing in k).
+__device__ __forceinline__ int64_t batch_item(uint32_t k, int c) {
+  return ((int64_t)(k / kBatchRun) * kBatchSeqs + c) * kBatchRun + (int64_t)(k % kBatchRun);
+}
+
+// The work loop of a persistent batched rasterizer: item(i) renders work item i.  The next claim
+// is issued before the current item is rendered, so its round trip overlaps it; the barriers
+// around each hand-over also keep an item's staging out of LDS still read for the one before.
+template <typename F>
+__device__ __forceinline__ void batch_items(uint32_t *counters, int total, int *s_item, F &&item) {
+  const int seq = (int)(blockIdx.x % kBatchSeqs);
+  uint32_t *ctr = counters + seq * kBatchCounterStride;
+  if (threadIdx.x == 0) {
+    const int64_t i = batch_item(atomicAdd(ctr, 1u), seq);
+    *s_item = i < total ? (int)i : total;
+  }
+  __syncthreads();
+  int it = *s_item;
+  __syncthreads();
+  while (it < total) {
+    uint32_t nxt = 0;
+    if (threadIdx.x == 0) nxt = atomicAdd(ctr, 1u);
+    item(it);
+    if (threadIdx.x == 0) {
+      const int64_t i = batch_item(nxt, seq);
+      *s_item = i < total ? (int)i : total;
+    }
+    __syncthreads();
+    it = *s_item;
+    __syncthreads();
+  }
+}
+
 hipError_t launch_raster_fp32_batch(const BatchTable &table, int grid, const RasterParams &p, uint32_t *counter,
                                     hipStream_t st);
 hipError_t launch_raster_mfma_batch(const BatchTable &table, int grid, const RasterParams &p, uint32_t *counter,

@@ -142,15 +142,9 @@ __global__ __launch_bounds__(kBlock) void k_raster_fp32(RasterJob J, RasterParam
 template <int G, bool AUX>
 __global__ __launch_bounds__(kBlock) void k_raster_fp32_batch(const BatchTable tb,
                                                               RasterParams P, uint32_t *counter) {
-  const int total = tb.total;
   __shared__ Fp32Shared sm;
   __shared__ int s_item;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
-    __syncthreads();
-    const int item = s_item;
-    __syncthreads();
-    if (item >= total) break;
+  batch_items(counter, tb.total, &s_item, [&](int item) {
     int lo = 0, hi = tb.n_jobs;   // last job with bin0 <= item
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
@@ -158,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_fp32_batch(const BatchTable t
     }
     const RasterJob J = tb.jobs[lo];
     raster_bin_fp32<G, AUX>(J, P, item - J.bin0, sm);
-  }
+  });
 }
 
 struct BatchArgs {

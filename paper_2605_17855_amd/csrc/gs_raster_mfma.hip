@@ -525,22 +525,17 @@ __global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParam
   raster_item<G, PREC, S, AUX, GF>(J, P, item, sm, B0, B1, B20, B21);
 }
 
-// Persistent batched rasterizer: workgroups take (job, item) work items from *counter until
-// all `total` are done; job j owns items [jobs[j].bin0, jobs[j].bin0 + jobs[j].items).
+// Persistent batched rasterizer: workgroups take (job, item) work items from the counters
+// (batch_items) until all `total` are done; job j owns items [jobs[j].bin0, jobs[j].bin0 +
+// jobs[j].items).
 template <int G, int PREC, int S, bool AUX, bool GF>
 __global__ __launch_bounds__(kBlock) void k_raster_mfma_batch(const BatchTable tb,
                                                               RasterParams P, uint32_t *counter) {
-  const int total = tb.total;
   __shared__ typename SharedFor<G, PREC, S, GF>::type sm;
   __shared__ int s_item;
   short8 B0, B1, B20, B21;
   make_pixel_operand<PREC>(B0, B1, B20, B21);
-  for (;;) {
-    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
-    __syncthreads();
-    const int item = s_item;
-    __syncthreads();
-    if (item >= total) break;
+  batch_items(counter, tb.total, &s_item, [&](int item) {
     int lo = 0, hi = tb.n_jobs;   // last job with bin0 <= item
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
@@ -548,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_mfma_batch(const BatchTable t
     }
     const RasterJob J = tb.jobs[lo];
     raster_item<G, PREC, S, AUX, GF>(J, P, item - J.bin0, sm, B0, B1, B20, B21);
-  }
+  });
 }
 
 struct BatchArgs {

@@ -22,6 +22,8 @@ GS_AUX_TFINAL, GS_AUX_WSUM, GS_AUX_NEVAL, GS_AUX_NBLEND, GS_AUX_LAST = 1, 2, 4, 
 GS_OPT_TIGHT = 1
 GS_OPT_ALL_ROWS = 2
 GS_OPT_TILE_ROWS = 4
+GS_BATCH_COUNTER_BYTES = 512          # work counters of one batched launch (include/gs.h)
+BATCH_COUNTER_WORDS = GS_BATCH_COUNTER_BYTES // 4
 PRECISIONS = {"fp32": GS_PREC_FP32, "fp16": GS_PREC_FP16_MFMA, "bf16": GS_PREC_BF16_MFMA}
 TILE = 16
 
@@ -328,7 +330,8 @@ def gs_radix_sort_u64(keys, vals, lo_bit: int, hi_bit: int, ws=None, stream=None
 
 
 def gs_rasterize_batch(items, opt: gs_options, counter, stream=None):
-    """items: list of (Projected, Bins, camera, image, aux-or-None).  One persistent launch."""
+    """items: list of (Projected, Bins, camera, image, aux-or-None).  One persistent launch.
+    counter: device memory of GS_BATCH_COUNTER_BYTES (e.g. BATCH_COUNTER_WORDS int32)."""
     n = len(items)
     arr = (gs_job * max(n, 1))()
     for i, (proj, bins, cam, image, aux) in enumerate(items):

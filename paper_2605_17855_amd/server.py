@@ -422,7 +422,8 @@ class GpuBackend:
         self.raster_stream = torch.cuda.Stream()
         self.raster_h = self.raster_stream.cuda_stream
         self.max_inflight = max_inflight_batches
-        self.counters = torch.zeros(2 * max_inflight_batches, dtype=torch.int32, device="cuda")
+        self.counters = torch.zeros(2 * max_inflight_batches * gs.BATCH_COUNTER_WORDS, dtype=torch.int32,
+                                    device="cuda")
         self.counter_i = 0
         self.raster_events = [self.hip.event() for _ in range(2 * max_inflight_batches)]
         self.pool = cf.ThreadPoolExecutor(max_workers=slots)
@@ -569,8 +570,8 @@ class GpuBackend:
             arr[i].aux = None
         k = self.counter_i % len(self.raster_events)
         self.counter_i += 1
-        rc = self.L.gs_rasterize_batch(arr, len(jobs), C.byref(self.opt), self.counters[k:].data_ptr(),
-                                       self.raster_h)
+        rc = self.L.gs_rasterize_batch(arr, len(jobs), C.byref(self.opt),
+                                       self.counters[k * gs.BATCH_COUNTER_WORDS:].data_ptr(), self.raster_h)
         if rc != gs.GS_OK:
             raise gs.GsError(rc, self.L.gs_last_error().decode())
         if self.keep_results:

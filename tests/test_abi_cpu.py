@@ -242,3 +242,13 @@ def test_backward_rejects_invalid_calls():
     c = _cam()
     c.width = 0
     assert call(C.byref(p), C.byref(b), C.byref(c), C.byref(gs.options()), d, C.byref(g), None) == gs.GS_ERR_INVALID_ARG
+
+
+def test_python_constants_match_header():
+    """The binding's copies of the header's sizes and flags."""
+    import re
+    hdr = open(os.path.join(ROOT, "include", "gs.h")).read()
+    defs = dict(re.findall(r"#define (GS_[A-Z_]+) (\d+)", hdr))
+    assert int(defs["GS_BATCH_COUNTER_BYTES"]) == gs.GS_BATCH_COUNTER_BYTES
+    assert gs.BATCH_COUNTER_WORDS * 4 == gs.GS_BATCH_COUNTER_BYTES
+    assert int(defs["GS_NOALLOC_SCRATCH_BYTES"]) >= gs.GS_BATCH_COUNTER_BYTES

@@ -333,7 +333,7 @@ def test_batch_matches_single_renders(prec, group):
         img = torch.full_like(r.image, -1.0)
         ax = torch.full_like(r.aux, -1.0)
         jobs.append((r.proj, r.bins, cam, img, ax, r, ds))
-    counter = torch.zeros(1, dtype=torch.int32, device="cuda")
+    counter = torch.zeros(gs.BATCH_COUNTER_WORDS, dtype=torch.int32, device="cuda")
     note(f"batch launch {prec} g{group}")
     gs.gs_rasterize_batch([(j[0], j[1], j[2], j[3], j[4]) for j in jobs], opt, counter)
     torch.cuda.synchronize()

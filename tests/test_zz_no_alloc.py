@@ -39,7 +39,7 @@ def _launch(jobs, opt, noalloc):
     if noalloc:
         gs.gs_rasterize_batch_noalloc(items, opt)
     else:
-        counter = torch.zeros(1, dtype=torch.int32, device="cuda")
+        counter = torch.zeros(gs.BATCH_COUNTER_WORDS, dtype=torch.int32, device="cuda")
         gs.gs_rasterize_batch(items, opt, counter)
     torch.cuda.synchronize()
     return [(i.cpu().numpy(), a.cpu().numpy()) for i, a in outs]
