@@ -330,13 +330,15 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
                                                 MfmaShared<G, S> &sm, short8 B0, short8 B1, short8 B20,
                                                 short8 B21) {
   constexpr int NT = G * G;
+  // member tiles per workgroup: all of them for G <= 2 (one workgroup per bin, the tile loops
+  // below fully unrolled), one row of G for G >= 4 (J.parts == G workgroups per group)
+  constexpr int NTW = G >= 4 ? G : NT;
   constexpr int RS = (S == 3) ? 32 : 16;
   constexpr int kTileUnroll = G >= 4 ? 1 : NT;
   using TileMask = typename std::conditional<(NT > 32), uint64_t, uint32_t>::type;
-  // G <= 2: one workgroup per bin (the tile loops below stay fully unrolled)
   const int bin = G >= 4 ? item / J.parts : item;
-  const int k0 = G >= 4 ? (item % J.parts) * (NT / J.parts) : 0;
-  const int k1 = G >= 4 ? k0 + NT / J.parts : NT;
+  const int k0 = G >= 4 ? (item % J.parts) * NTW : 0;
+  const int k1 = k0 + NTW;
   const int gx = bin % J.GX, gy = bin / J.GX;
   const int ox = gx * G * kTile, oy = gy * G * kTile;
   const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
@@ -344,18 +346,20 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
   const int qx0 = (w & 1) * 8, qy0 = (w >> 1) * 8;
   const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
 
-  TileState st[NT];
-  TileMask alive_mask = 0;       // uniform: member tiles with pixels still blending
-  uint32_t rows_done[NT];        // uniform: entries of each tile consumed so far
+  // the workgroup's member tiles k0 + i (G >= 4: private memory, one register copy per step)
+  TileState st[NTW];
+  TileMask alive_mask = 0;       // uniform: member tiles with pixels still blending (bit k)
+  uint32_t rows_done[NTW];       // uniform: entries of each tile consumed so far
 #pragma unroll kTileUnroll
-  for (int k = 0; k < NT; ++k) {
+  for (int i = 0; i < NTW; ++i) {
+    const int k = k0 + i;
     const int tx0 = ox + (k % G) * kTile, ty0 = oy + (k / G) * kTile;
     const bool inside = (tx0 + px < J.W) && (ty0 + py < J.H);
-    st[k].T = 1.0f; st[k].C0 = st[k].C1 = st[k].C2 = 0.0f; st[k].W = 0.0f;
-    st[k].cut = inside ? kCutLog2 : INFINITY;
-    st[k].nstop = 0; st[k].nblend = 0; st[k].last = 0;
-    rows_done[k] = 0;
-    if (k >= k0 && k < k1 && tx0 < J.W && ty0 < J.H) alive_mask |= (TileMask)1 << k;
+    st[i].T = 1.0f; st[i].C0 = st[i].C1 = st[i].C2 = 0.0f; st[i].W = 0.0f;
+    st[i].cut = inside ? kCutLog2 : INFINITY;
+    st[i].nstop = 0; st[i].nblend = 0; st[i].last = 0;
+    rows_done[i] = 0;
+    if (tx0 < J.W && ty0 < J.H) alive_mask |= (TileMask)1 << k;
   }
 
   int it = 0;          // processing steps so far (LDS double-buffer parity)
@@ -453,12 +457,12 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
                                sm.alive[(it - 1) & 1][3];
           if (!any) alive_mask &= ~((TileMask)1 << last_k);
         }
-        TileState cur = st[k];
+        TileState cur = st[k - k0];
         const int nw = wave_list(sm.qm[buf], (int)nk, sm.wl[w]);
         process_rows<PREC, S, AUX>(sm.A[buf], &sm.col[buf][0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, cur,
-                                   rows_done[k]);
-        st[k] = cur;
-        rows_done[k] += nk;
+                                   rows_done[k - k0]);
+        st[k - k0] = cur;
+        rows_done[k - k0] += nk;
         const uint64_t ab = __ballot(cur.cut != INFINITY);
         if (lane == 0) sm.alive[it & 1][w] = ab != 0;
         last_k = k;
@@ -474,28 +478,29 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
     const int xx = ox + (k % G) * kTile + px, yy = oy + (k / G) * kTile + py;
     if (xx >= J.W || yy >= J.H) continue;
     const int64_t pix = (int64_t)yy * J.W + xx;
-    J.image[pix] = st[k].C0 + st[k].T * P.bg[0];
-    J.image[HW + pix] = st[k].C1 + st[k].T * P.bg[1];
-    J.image[2 * HW + pix] = st[k].C2 + st[k].T * P.bg[2];
+    const TileState &sk = st[k - k0];
+    J.image[pix] = sk.C0 + sk.T * P.bg[0];
+    J.image[HW + pix] = sk.C1 + sk.T * P.bg[1];
+    J.image[2 * HW + pix] = sk.C2 + sk.T * P.bg[2];
     if (AUX) {
       int plane = 0;
-      if (P.aux_flags & GS_AUX_TFINAL) J.aux[(plane++) * HW + pix] = st[k].T;
-      if (P.aux_flags & GS_AUX_WSUM) J.aux[(plane++) * HW + pix] = st[k].W;
+      if (P.aux_flags & GS_AUX_TFINAL) J.aux[(plane++) * HW + pix] = sk.T;
+      if (P.aux_flags & GS_AUX_WSUM) J.aux[(plane++) * HW + pix] = sk.W;
       if (P.aux_flags & GS_AUX_NEVAL) {
-        const bool stopped = st[k].cut == INFINITY;
-        J.aux[(plane++) * HW + pix] = (float)(stopped ? st[k].nstop : rows_done[k]);
+        const bool stopped = sk.cut == INFINITY;
+        J.aux[(plane++) * HW + pix] = (float)(stopped ? sk.nstop : rows_done[k - k0]);
       }
-      if (P.aux_flags & GS_AUX_NBLEND) J.aux[(plane++) * HW + pix] = (float)st[k].nblend;
-      if (P.aux_flags & GS_AUX_LAST) J.aux[(plane++) * HW + pix] = (float)st[k].last;
+      if (P.aux_flags & GS_AUX_NBLEND) J.aux[(plane++) * HW + pix] = (float)sk.nblend;
+      if (P.aux_flags & GS_AUX_LAST) J.aux[(plane++) * HW + pix] = (float)sk.last;
     }
   }
 }
 
-// Work item = workgroup id.  Workgroups go round-robin to the 8 XCDs, so neighbouring tiles
-// run on different XCDs and the dense middle of a frame is shared by all of them; giving each
-// XCD a contiguous band of tiles (for L2 reuse of shared records) left the XCDs holding the
-// dense bands running last and was slower (105 vs 87 us at 1080p / 1M Gaussians).  (Forcing
-// 64 VGPRs for 8 waves per SIMD spilled to scratch and was slower than the 72 VGPRs here.)
+// Work item = workgroup id, mapped to bins in the XCD-aware order (4x4 blocks of neighbouring
+// bins per XCD in turn, xcd_raster_bin) for one workgroup per bin; giving each XCD one
+// contiguous band of tiles instead left the XCDs holding the dense bands running last (105 vs
+// 87 us at 1080p / 1M Gaussians).  (Forcing 64 VGPRs for 8 waves per SIMD spilled to scratch and
+// was slower than the 72 VGPRs here.)
 // The LDS layout and the renderer of one work item: rows in the group frame where its pixel
 // operand is exact, per-tile rows otherwise.
 // GF: the group-frame path (only where GroupFrame holds; GS_OPT_TILE_ROWS selects the per-tile
