@@ -327,18 +327,9 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, co
 // firsts (or a wave-wide search) give the first, the workgroup stages their offsets in LDS,
 // and each entry finds its Gaussian by binary search there.
 
-// Last Gaussian (local index) of the staged offsets s_pos[0..span] whose first entry is <= e.
-__device__ __forceinline__ uint32_t local_gaussian(const uint64_t *s_pos, uint32_t span, uint64_t e) {
-  uint32_t lo = 0, hi = span;   // invariant s_pos[lo] <= e < s_pos[hi]
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (s_pos[mid] <= e) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
-// The same with a fixed number of steps (span <= ITEMS, s_pos[0] <= e < s_pos[span]): no
-// data-dependent loop, so the searches of a thread's several entries interleave.
+// Last Gaussian (local index) of the staged offsets s_pos[0..span] whose first entry is <= e
+// (span <= ITEMS, s_pos[0] <= e < s_pos[span]), in a fixed number of steps: no data-dependent
+// loop, so the searches of a thread's several entries interleave.
 template <int ITEMS>
 __device__ __forceinline__ uint32_t local_gaussian_fixed(const uint64_t *s_pos, uint32_t span, uint64_t e) {
   uint32_t lo = 0;
@@ -469,6 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order,
                                                           uint32_t *bin_keys, uint32_t *vals, uint32_t *ranges,
                                                           uint64_t nranges, FirstCounts fc) {
   __shared__ uint64_t s_pos[ITEMS + 1];
+  __shared__ uint32_t s_g[ITEMS];
   __shared__ uint32_t s_first;
   __shared__ uint32_t h[kDigits];
   const uint32_t tile = xcd_sort_tile(blockIdx.x, (K + ITEMS - 1) / ITEMS);
@@ -478,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order,
   if (tile == ~0u) return;
   h[threadIdx.x] = 0;
   uint32_t first, span;
-  stage_block_gaussians<ITEMS>(dpos, block_first, nvis, e0, s_pos, &s_first, &first, &span);
+  stage_block_gaussians<ITEMS>(dpos, block_first, nvis, e0, s_pos, &s_first, &first, &span, order, s_g);
   const uint32_t dmask = (1u << fc.nbits0) - 1u;
 #pragma unroll
   for (int it = 0; it < ITEMS / kBlock; ++it) {
@@ -487,9 +479,9 @@ __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order,
     if (__ballot(valid) == 0) continue;
     uint32_t rank = 0, g = 0, left = 0;
     if (valid) {
-      const uint32_t l = local_gaussian(s_pos, span, e);
+      const uint32_t l = local_gaussian_fixed<ITEMS>(s_pos, span, e);
       rank = first + l;
-      g = order[rank];
+      g = s_g[l];
       left = (uint32_t)(e - s_pos[l]);
     }
     uint32_t bin = 0;   // (the walks always end early for counts from the preprocess)
