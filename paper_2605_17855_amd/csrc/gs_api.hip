@@ -107,13 +107,13 @@ gs_status check_bins(const gs_bins *b, int group, bool need_keys) {
 }
 
 struct Workspace {
-  void *scan;            // scan partials (count scan, then the depth-order offset scan)
-  void *sort;            // radix sort scratch (per-tile digit counts and totals)
+  void *scan;            // scan partials of the count scan
+  void *sort;            // radix sort scratch (per-tile digit counts and totals; depth, then bin sort)
   uint32_t *dkey;        // depth keys of the visible Gaussians (n)
   uint32_t *dkey_alt;    // depth sort double buffer (n)
-  uint32_t *dval_alt;    // (n)
+  uint32_t *dval_alt;    // depth sort value buffers (n each)
+  uint32_t *dval_b;
   uint64_t *dpos;        // first entry of each visible Gaussian in depth order (n + 1)
-  uint32_t *csort;       // entry count of each visible Gaussian in depth order (n)
   uint32_t *bkey;        // bin key of each entry (capacity)
   uint32_t *bval;        // depth rank of each entry's Gaussian (capacity)
   uint32_t *bkey_alt;    // bin sort double buffer (capacity)
@@ -135,12 +135,14 @@ Workspace carve(void *ws, int64_t n, uint64_t capacity) {
   };
   const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
   w.scan = take(gsi::scan_tmp_bytes(n));
-  w.sort = take(gsi::radix_tmp_bytes(nn > capacity ? nn : capacity));
+  const size_t sort_bytes = gsi::radix_tmp_bytes(nn > capacity ? nn : capacity);
+  const size_t depth_bytes = gsi::depth_sort_tmp_bytes(nn);
+  w.sort = take(sort_bytes > depth_bytes ? sort_bytes : depth_bytes);
   w.dkey = reinterpret_cast<uint32_t *>(take(nn * 4));
   w.dkey_alt = reinterpret_cast<uint32_t *>(take(nn * 4));
   w.dval_alt = reinterpret_cast<uint32_t *>(take(nn * 4));
+  w.dval_b = reinterpret_cast<uint32_t *>(take(nn * 4));
   w.dpos = reinterpret_cast<uint64_t *>(take((nn + 1) * 8));
-  w.csort = reinterpret_cast<uint32_t *>(take(nn * 4));
   w.bkey = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
   w.bval = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
   w.bkey_alt = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
@@ -218,25 +220,22 @@ gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
   const gsi::Grid g = gsi::make_grid(cam->width, cam->height, opt->group);
   const Workspace w = carve(ws, n, bins->capacity);
   // The one host wait reads the entry count K and the visible count V, which k_depth_keys writes
-  // to the caller's pinned host memory (and to the workspace).  The depth sort and depth-order
-  // offset scan (which read V on the device) are enqueued before the host polls for them, so
-  // the GPU keeps working while the host waits.
+  // to the caller's pinned host memory (and to the workspace).  The depth sort (which reads V on
+  // the device and also places each Gaussian's first entry) is enqueued before the host polls
+  // for them, so the GPU keeps working while the host waits.
   volatile uint64_t *hkv = proj->host_counts;
   if (hkv) hkv[0] = hkv[1] = ~0ull;   // overwritten by the kernel
   const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
   GS_HIP(gsi::launch_depth_keys(proj->order, reinterpret_cast<const float4 *>(proj->rgb), proj->n_visible, nn, w.dkey,
                                 proj->offset + n, w.counts, proj->host_counts, w.sort, st));
   // from here on the kernel may be writing the counts: every exit waits for the stream first
-  bool in_alt = false;
-  hipError_t e = gsi::sort_depth(proj->order, proj->n_visible, nn, w.dkey, w.dkey_alt, w.dval_alt, w.sort, st, &in_alt,
-                      proj->count, w.csort);
-  const uint32_t *dkeys = in_alt ? w.dkey_alt : w.dkey;   // depth bits in depth order
-  if (e == hipSuccess && in_alt) e = hipMemcpyAsync(proj->order, w.dval_alt, nn * 4, hipMemcpyDeviceToDevice, st);
-  // first entry of each Gaussian in depth order (the sort placed the counts in that order when
-  // it ran; a single Gaussian needs no sort)
-  if (e == hipSuccess)
-    e = nn > 1 ? gsi::launch_scan_dev(w.csort, w.dpos, (int64_t)nn, proj->n_visible, w.scan, st, w.bfirst, w.nbfirst)
-               : gsi::launch_scan_gather(proj->count, proj->order, w.dpos, (int64_t)nn, proj->n_visible, w.scan, st);
+  // depth bits in depth order, and the first entry of each Gaussian in that order (a single
+  // Gaussian needs no sort: a gathered scan of its count)
+  const uint32_t *dkeys = w.dkey;
+  hipError_t e = nn > 1 ? gsi::sort_depth(proj->order, proj->n_visible, nn, w.dkey, w.dkey_alt, w.dval_alt, w.dval_b,
+                                          w.sort, st, proj->count, w.dpos, w.bfirst, w.nbfirst)
+                        : gsi::launch_scan_gather(proj->count, proj->order, w.dpos, (int64_t)nn, proj->n_visible,
+                                                  w.scan, st);
   if (e != hipSuccess) {
     (void)hipStreamSynchronize(st);
     return hip_fail(e, "depth sort");

@@ -215,16 +215,14 @@ hipError_t launch_scan_compact(const uint32_t *in, uint64_t *out, int64_t n, uin
 // out[0..m] = exclusive prefix sum of in[idx[i]] for i < m = *n_dev (m <= n_max)
 hipError_t launch_scan_gather(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n_max,
                               const uint32_t *n_dev, void *tmp, hipStream_t st);
-// out[0..m] = exclusive prefix sum of in[i] for i < m = *n_dev (m <= n_max); with block_first,
-// also block_first[b] = the i whose run [out[i], out[i] + in[i]) holds entry b * kFirstsBlock,
-// for b < n_blocks (the binning's first Gaussian of each block of entries)
+// entries per block of the binning's block firsts (the first Gaussian of each block of entries)
 constexpr uint64_t kFirstsBlock = 1024;
-hipError_t launch_scan_dev(const uint32_t *in, uint64_t *out, int64_t n_max, const uint32_t *n_dev, void *tmp,
-                           hipStream_t st, uint32_t *block_first = nullptr, uint64_t n_blocks = 0);
 
 // ---- binning, sort, ranges -------------------------------------------------
 // scratch of a radix sort over at most n keys (per-tile digit counts and digit totals)
 size_t radix_tmp_bytes(uint64_t n);
+// scratch of the depth sort of n_max keys (sort_depth; counts, totals and the last pass's weights)
+size_t depth_sort_tmp_bytes(uint64_t n_max);
 // Stable sort of (keys, vals) on key bits [lo, hi); ping-pongs with (keys_alt, vals_alt) and
 // reports in *in_alt whether the result ended in the alternate buffers.
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
@@ -235,20 +233,23 @@ hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32
 hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max,
                              uint32_t *keys, const uint64_t *K, uint64_t *counts, uint64_t *host_counts, void *tmp,
                              hipStream_t st);
-// Sorts the visible list order[0..*nvis) by the depth keys (4 passes, stable), using keys_alt/
-// vals_alt (n_max each) as scratch, and writes count_sorted[i] = count[order[i]] for the
-// sorted list (n_max > 1).  Reads the visible count on the device, so it can be enqueued
-// before the host knows it.
+// Sorts the visible list order[0..*nvis) stably by the depth keys in keys (four passes over
+// bits [0, 31): depths are positive), using keys_alt, vals_alt and vals_b (n_max each) as
+// scratch; the sorted depth keys end in keys.  The last pass also writes dpos[i] = the
+// entries of the Gaussians before the i-th in depth order (the exclusive scan of count[order[i]],
+// dpos[*nvis] = all entries) and first[b] = the i whose entries hold entry b * kFirstsBlock, for
+// b < nfirst.  n_max > 1 (otherwise nothing is done).  Reads the visible count on the device,
+// so it can be enqueued before the host knows it.
 hipError_t sort_depth(uint32_t *order, const uint32_t *nvis, uint64_t n_max, uint32_t *keys, uint32_t *keys_alt,
-                      uint32_t *vals_alt, void *tmp, hipStream_t st, bool *in_alt, const uint32_t *count,
-                      uint32_t *count_sorted);
+                      uint32_t *vals_alt, uint32_t *vals_b, void *tmp, hipStream_t st, const uint32_t *count,
+                      uint64_t *dpos, uint32_t *first, uint64_t nfirst);
 // Entries of the V depth-ordered visible Gaussians (the i-th one's first entry at dpos[i];
 // dkeys[i] its depth bits) as (bin key, rank in depth order) pairs in (bkey, bval), a stable
 // sort on the bin bits ping-ponging with (bkey_alt, bval_alt) whose last pass writes the final
 // Gaussian indices to vals and the 64-bit keys to keys, then the bin ranges (cleared first) and,
 // for group > 1, the membership masks.  With tight (opacity-aware culling) entries follow the
 // culled spans of tight_row_span.  vals and keys must not alias the four work arrays.
-// block_first (or nullptr): the first Gaussian of every 1,024-entry block (launch_scan_dev).
+// block_first (or nullptr): the first Gaussian of every 1,024-entry block (sort_depth).
 hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint64_t *dpos, const uint32_t *block_first,
                         uint32_t V, uint64_t K,
                         const uint16_t *rect, const double *xy, const float *conic, bool tight, const Grid &g,

@@ -333,19 +333,11 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(uint64_t *bsum, uint32_t *b
 // PREFIXED: bsum/bvis already hold each tile's exclusive offset (k_scan_top ran); otherwise
 // they hold sums of `spt` consecutive groups per tile (spt = 1: the reduce pass's tile sums;
 // more: the preprocess's 256-value sums)
-// With bf.first, the scan of per-Gaussian entry counts also records, for every block of
-// kFirstsBlock entries that starts inside a Gaussian's run [out[i], out[i] + in[i]), that
-// Gaussian's index i: the binning then needs no search for its block's first Gaussian.
-struct BlockFirsts {
-  uint32_t *first;
-  uint64_t n;         // blocks recorded (those of a capacity-sized entry array)
-};
-
 template <bool GATHER, bool COMPACT, int kScanItems, bool PREFIXED>
 __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, const uint32_t *idx, int64_t n_host,
                                                       const uint32_t *n_dev, const uint64_t *bsum,
                                                       const uint32_t *bvis, uint64_t *out, uint32_t *order,
-                                                      uint32_t *nvis, int spt, BlockFirsts bf) {
+                                                      uint32_t *nvis, int spt) {
   constexpr int64_t kScanTile = scan_tile<kScanItems>();
   __shared__ uint64_t sh[4];
   __shared__ uint32_t shv[4];
@@ -396,10 +388,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, const 
     if (base + i < n) {
       out[base + i] = run;
       if (COMPACT && v[i] > 0) order[runv++] = (uint32_t)(base + i);
-      if (bf.first && v[i] > 0) {
-        for (uint64_t b = (run + kFirstsBlock - 1) / kFirstsBlock; b * kFirstsBlock < run + v[i] && b < bf.n; ++b)
-          bf.first[b] = (uint32_t)(base + i);
-      }
     }
     run += v[i];
   }
@@ -407,8 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t *in, const 
 
 template <bool GATHER, bool COMPACT, int ITEMS>
 hipError_t scan_impl_t(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n, const uint32_t *n_dev,
-                       uint32_t *order, uint32_t *nvis, void *tmp, bool presummed, hipStream_t st,
-                       BlockFirsts bf = BlockFirsts{nullptr, 0}) {
+                       uint32_t *order, uint32_t *nvis, void *tmp, bool presummed, hipStream_t st) {
   const int64_t nb = (n + scan_tile<ITEMS>() - 1) / scan_tile<ITEMS>();
   uint64_t *bsum = static_cast<uint64_t *>(tmp);
   if (presummed) {
@@ -416,7 +403,7 @@ hipError_t scan_impl_t(const uint32_t *in, const uint32_t *idx, uint64_t *out, i
     const int64_t n256 = (n + kBlock - 1) / kBlock;
     uint32_t *bv = reinterpret_cast<uint32_t *>(bsum + (n256 > 0 ? n256 : 1));
     hipLaunchKernelGGL((k_scan_down<GATHER, COMPACT, ITEMS, false>), dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kBlock),
-                       0, st, in, idx, n, n_dev, bsum, bv, out, order, nvis, (int)(scan_tile<ITEMS>() / kBlock), bf);
+                       0, st, in, idx, n, n_dev, bsum, bv, out, order, nvis, (int)(scan_tile<ITEMS>() / kBlock));
     return hipGetLastError();
   }
   uint32_t *bvis = reinterpret_cast<uint32_t *>(bsum + (nb > 0 ? nb : 1));
@@ -426,21 +413,20 @@ hipError_t scan_impl_t(const uint32_t *in, const uint32_t *idx, uint64_t *out, i
   if (nb > kDirectTiles) {
     hipLaunchKernelGGL((k_scan_top<COMPACT>), dim3(1), dim3(kBlock), 0, st, bsum, bvis, nb);
     hipLaunchKernelGGL((k_scan_down<GATHER, COMPACT, ITEMS, true>), dim3((unsigned)nb), dim3(kBlock), 0, st, in, idx,
-                       n, n_dev, bsum, bvis, out, order, nvis, 1, bf);
+                       n, n_dev, bsum, bvis, out, order, nvis, 1);
   } else {
     hipLaunchKernelGGL((k_scan_down<GATHER, COMPACT, ITEMS, false>), dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kBlock),
-                       0, st, in, idx, n, n_dev, bsum, bvis, out, order, nvis, 1, bf);
+                       0, st, in, idx, n, n_dev, bsum, bvis, out, order, nvis, 1);
   }
   return hipGetLastError();
 }
 
 template <bool GATHER, bool COMPACT>
 hipError_t scan_impl(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n, const uint32_t *n_dev,
-                     uint32_t *order, uint32_t *nvis, void *tmp, hipStream_t st, bool presummed = false,
-                     BlockFirsts bf = BlockFirsts{nullptr, 0}) {
+                     uint32_t *order, uint32_t *nvis, void *tmp, hipStream_t st, bool presummed = false) {
   if (n <= kSmallScan)
-    return scan_impl_t<GATHER, COMPACT, 4>(in, idx, out, n, n_dev, order, nvis, tmp, presummed, st, bf);
-  return scan_impl_t<GATHER, COMPACT, 16>(in, idx, out, n, n_dev, order, nvis, tmp, presummed, st, bf);
+    return scan_impl_t<GATHER, COMPACT, 4>(in, idx, out, n, n_dev, order, nvis, tmp, presummed, st);
+  return scan_impl_t<GATHER, COMPACT, 16>(in, idx, out, n, n_dev, order, nvis, tmp, presummed, st);
 }
 
 }  // namespace
@@ -507,12 +493,6 @@ size_t scan_tmp_bytes(int64_t n) {
 hipError_t launch_scan_compact(const uint32_t *in, uint64_t *out, int64_t n, uint32_t *order, uint32_t *nvis,
                                void *tmp, bool presummed, hipStream_t st) {
   return scan_impl<false, true>(in, nullptr, out, n, nullptr, order, nvis, tmp, st, presummed && scan_presummed(n));
-}
-
-hipError_t launch_scan_dev(const uint32_t *in, uint64_t *out, int64_t n_max, const uint32_t *n_dev, void *tmp,
-                           hipStream_t st, uint32_t *block_first, uint64_t n_blocks) {
-  return scan_impl<false, false>(in, nullptr, out, n_max, n_dev, nullptr, nullptr, tmp, st, false,
-                                 BlockFirsts{block_first, n_blocks});
 }
 
 hipError_t launch_scan_gather(const uint32_t *in, const uint32_t *idx, uint64_t *out, int64_t n_max,

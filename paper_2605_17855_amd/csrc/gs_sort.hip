@@ -17,7 +17,12 @@
 // Each pass is three kernels without inter-workgroup waits: per-tile digit counts, one
 // workgroup per digit scanning its row of tile counts (and writing the row total), and a
 // stable scatter that derives the digit bases from the row totals and writes each digit's
-// run through LDS so that lanes store consecutive addresses.
+// run through LDS so that lanes store consecutive addresses.  The depth sort takes the 31
+// bits of a positive depth in four passes (8, 8, 8 and 7 bits); its last pass also counts,
+// per tile and digit, the entries of the keys' Gaussians, so that its scatter writes each
+// Gaussian's first entry in depth order (the offset scan the binning needs) next to the
+// sorted keys.  (Three passes of up to 11 bits were measured slower: a 2,048-digit pass
+// costs nearly two 256-digit ones.)
 #include "gs_internal.hpp"
 
 namespace gsi {
@@ -36,7 +41,8 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint64_t n, ui
 // (1,024-key tiles: the ~200K visible Gaussians of a 1M scene still give ~200 workgroups, and
 // the per-pass digit scans stay short; 512-key tiles were 1.3 % slower end to end), larger
 // ones R = 8 (2,048 keys).
-constexpr int kDigits = 256;
+constexpr int kDigits = 256;                   // digits of at most 8 bits
+constexpr int kDepthBits = 31;                 // a positive float's sign bit is zero
 constexpr int kSmallR = 4;                      // sorts up to kSmallSort keys: 1,024-key tiles
 constexpr int kLargeR = 8;                      // larger sorts: 2,048-key tiles
 constexpr uint64_t kSmallSort = 1ull << 20;
@@ -60,26 +66,30 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nbit
 
 // Exclusive scan of v over the 256 threads of the workgroup (wave shuffles, one LDS
 // exchange of the four wave totals); *total = the sum.  sh4 holds 4 values.
-__device__ __forceinline__ uint32_t block_exclusive_scan_u32(uint32_t v, uint32_t *sh4, uint32_t *total) {
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan_t(T v, T *sh4, T *total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  uint32_t incl = v;
+  T incl = v;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t u = __shfl_up(incl, off, 64);
+    const T u = __shfl_up(incl, off, 64);
     if (lane >= off) incl += u;
   }
   if (lane == 63) sh4[w] = incl;
   __syncthreads();
-  uint32_t before = 0, all = 0;
+  T before = 0, all = 0;
 #pragma unroll
   for (int k = 0; k < kBlock / 64; ++k) {
-    const uint32_t x = sh4[k];
-    before += k < w ? x : 0u;
+    const T x = sh4[k];
+    before += k < w ? x : (T)0;
     all += x;
   }
   __syncthreads();
   *total = all;
   return before + incl - v;
+}
+__device__ __forceinline__ uint32_t block_exclusive_scan_u32(uint32_t v, uint32_t *sh4, uint32_t *total) {
+  return block_exclusive_scan_t<uint32_t>(v, sh4, total);
 }
 
 // Per-tile digit counts: counts[d * tiles + tile].  Keys are loaded up front (8 in flight
@@ -90,41 +100,73 @@ __device__ __forceinline__ uint64_t count_of(uint64_t n_host, const uint32_t *n_
   return n_dev ? (uint64_t)*n_dev : n_host;
 }
 
-template <typename KT, int R>
+// Weights of the depth sort's last pass: the entry count of each key's Gaussian
+// (count[vals[i]]), summed per tile and digit into wcounts[d * tiles + tile] by the count
+// kernel, scanned over the tiles of each digit into wprefix (64-bit) with the digit totals in
+// wtotals.
+struct DigitWeights {
+  const uint32_t *vals;
+  const uint32_t *count;
+  uint32_t *wcounts;
+  uint64_t *wprefix;
+  uint64_t *wtotals;
+};
+
+template <typename KT, int R, int DIG, bool WEIGHTED>
 __global__ __launch_bounds__(kBlock) void k_radix_count(const KT *keys, uint64_t n_host, const uint32_t *n_dev,
-                                                        int shift, int nbits, uint32_t tiles_max, uint32_t *counts) {
+                                                        int shift, int nbits, uint32_t tiles_max, uint32_t *counts,
+                                                        DigitWeights wt) {
   constexpr int kRounds = SortTile<R>::kRounds, kWaveTile = SortTile<R>::kWaveTile, kSortTile = SortTile<R>::kTile;
-  __shared__ uint32_t h[kDigits];
+  __shared__ uint32_t h[DIG];
+  __shared__ uint32_t hw[WEIGHTED ? DIG : 1];
   const uint64_t n = count_of(n_host, n_dev);
   const uint32_t tile = xcd_sort_tile(blockIdx.x, (n + kSortTile - 1) / kSortTile);
   if (tile == ~0u) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  h[t] = 0;
+  const int ndig = 1 << nbits;
+  for (int d = t; d < ndig; d += kBlock) {
+    h[d] = 0;
+    if (WEIGHTED) hw[d] = 0;
+  }
   const uint32_t dmask = (1u << nbits) - 1u;
   const uint64_t base = (uint64_t)tile * kSortTile + (uint64_t)w * kWaveTile;
   KT key[kRounds];
+  uint32_t c[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint64_t i = base + (uint64_t)r * 64 + lane;
     key[r] = i < n ? keys[i] : (KT)0;
+    c[r] = WEIGHTED && i < n ? wt.vals[i] : 0u;
+  }
+  if (WEIGHTED) {
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) c[r] = base + (uint64_t)r * 64 + lane < n ? wt.count[c[r]] : 0u;
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const bool valid = base + (uint64_t)r * 64 + lane < n;
     const uint32_t d = (uint32_t)(key[r] >> shift) & dmask;
-    if (valid) atomicAdd(&h[d], 1u);   // (cheaper than grouping equal digits per wave first)
+    if (valid) {
+      atomicAdd(&h[d], 1u);   // (cheaper than grouping equal digits per wave first)
+      if (WEIGHTED) atomicAdd(&hw[d], c[r]);
+    }
   }
   __syncthreads();
-  counts[(uint64_t)t * tiles_max + tile] = h[t];
+  for (int d = t; d < ndig; d += kBlock) {
+    counts[(uint64_t)d * tiles_max + tile] = h[d];
+    if (WEIGHTED) wt.wcounts[(uint64_t)d * tiles_max + tile] = hw[d];
+  }
 }
 
 // One workgroup per digit d: counts[d][*] becomes the exclusive prefix over tiles (within the
 // digit) and totals[d] the digit's total.
+// With weights (wt.wcounts), the digit's row of weights likewise into wt.wprefix and wt.wtotals.
 __global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t *counts, uint32_t tiles_max,
                                                              uint32_t *totals, uint64_t n_host, const uint32_t *n_dev,
-                                                             uint32_t tile_size) {
+                                                             uint32_t tile_size, DigitWeights wt) {
   __shared__ uint32_t sh[4];
+  __shared__ uint64_t sh8[4];
   const int d = blockIdx.x, t = threadIdx.x;
   uint32_t *row = counts + (uint64_t)d * tiles_max;
   // tiles holding keys (the count kernel wrote no counts for the others)
@@ -144,6 +186,21 @@ __global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t *counts, u
       row[b0 + i] = run;
       run += c;
     }
+  if (wt.wcounts) {
+    const uint32_t *wrow = wt.wcounts + (uint64_t)d * tiles_max;
+    uint64_t *prow = wt.wprefix + (uint64_t)d * tiles_max;
+    uint64_t ws = 0;
+    for (uint32_t i = 0; i < per; ++i)
+      if (b0 + i < tiles) ws += wrow[b0 + i];
+    uint64_t wtot;
+    uint64_t wrun = block_exclusive_scan_t<uint64_t>(ws, sh8, &wtot);
+    if (t == 0) wt.wtotals[d] = wtot;
+    for (uint32_t i = 0; i < per; ++i)
+      if (b0 + i < tiles) {
+        prow[b0 + i] = wrun;
+        wrun += wrow[b0 + i];
+      }
+  }
 }
 
 // Stable scatter of one tile: ranks from per-wave digit counters; the tile's start for digit
@@ -160,39 +217,76 @@ struct FinalOut {
   uint64_t *keys;          // 64-bit key of each sorted entry
 };
 
-template <typename KT, int R>
+// First entries of the depth sort's last pass (WEIGHTED): dpos[p] = the entries of the
+// Gaussians before the p-th in depth order, i.e. the exclusive scan of their entry counts
+// (dpos[n] = all entries), and first[b] = p for every block b of kFirstsBlock entries whose
+// first entry is one of the p-th Gaussian's (b < nfirst).  The key's place among the entries
+// is the digit's weight base (the weights of smaller digits, then of this digit in earlier
+// tiles) plus the weights of the keys before it in its tile's run of the digit.
+struct FirstEntries {
+  uint64_t *dpos;
+  uint32_t *first;
+  uint64_t nfirst;
+};
+
+template <typename KT, int R, int DIG, bool WEIGHTED>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const uint32_t *vin, KT *kout, uint32_t *vout,
                                                           uint64_t n_host, const uint32_t *n_dev, int shift, int nbits,
                                                           uint32_t tiles_max, const uint32_t *offsets,
-                                                          const uint32_t *totals, const uint32_t *aux_in,
-                                                          uint32_t *aux_out, FinalOut fin) {
+                                                          const uint32_t *totals, FinalOut fin, DigitWeights wt,
+                                                          FirstEntries fe) {
   constexpr int kRounds = SortTile<R>::kRounds, kWaveTile = SortTile<R>::kWaveTile, kSortTile = SortTile<R>::kTile;
-  __shared__ uint32_t wcnt[4][kDigits];
-  __shared__ uint32_t bstart[kDigits];
-  __shared__ uint32_t gbase[kDigits];
+  constexpr int M = DIG / kBlock;   // digits per thread in the digit-level scans
+  static_assert(DIG % kBlock == 0, "digits in whole multiples of the workgroup");
+  __shared__ uint32_t wcnt[4][DIG];
+  __shared__ uint32_t bstart[DIG];
+  __shared__ uint32_t gbase[DIG];
   __shared__ uint32_t sh4[4];
+  __shared__ uint64_t sh8[4];
   __shared__ KT s_key[kSortTile];
   __shared__ uint32_t s_val[kSortTile];
+  __shared__ uint64_t gw[WEIGHTED ? DIG : 1];          // weight base of each digit in this tile
+  __shared__ uint32_t s_w[WEIGHTED ? kSortTile : 1];   // key weights in tile-local sorted order
+  __shared__ uint32_t s_wx[WEIGHTED ? kSortTile : 1];  // their exclusive scan
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint64_t n = count_of(n_host, n_dev);
+  if (WEIGHTED && n == 0 && blockIdx.x == 0 && t == 0) fe.dpos[0] = 0;   // no keys: no entries
   const uint32_t tile = xcd_sort_tile(blockIdx.x, (n + kSortTile - 1) / kSortTile);
   if (tile == ~0u) return;
   const uint64_t tile0 = (uint64_t)tile * kSortTile;
+  const int ndig = 1 << nbits;
   const uint32_t dmask = (1u << nbits) - 1u;
   const uint64_t lt = (1ull << lane) - 1ull;
   const uint64_t base = tile0 + (uint64_t)w * kWaveTile;
   KT key[kRounds];
-  uint32_t val[kRounds], pos[kRounds], dig[kRounds];
+  uint32_t val[kRounds], pos[kRounds], dig[kRounds], kw[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint64_t i = base + (uint64_t)r * 64 + lane;
     key[r] = i < n ? kin[i] : (KT)0;
     val[r] = i < n ? vin[i] : 0u;
   }
+  if (WEIGHTED) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
-  const uint32_t tot_d = t < (1 << nbits) ? totals[t] : 0u;   // the digit scan covers 2^nbits digits
-  const uint32_t off_d = offsets[(uint64_t)t * tiles_max + tile];
+    for (int r = 0; r < kRounds; ++r) kw[r] = base + (uint64_t)r * 64 + lane < n ? wt.count[val[r]] : 0u;
+  }
+  // this thread's digits t*M .. t*M + M - 1: their totals, this tile's offsets within them and,
+  // weighted, the same two of the weights
+  uint32_t tot_d[M], off_d[M];
+  uint64_t wtot_d[WEIGHTED ? M : 1], woff_d[WEIGHTED ? M : 1];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const int d = t * M + j;
+    tot_d[j] = d < ndig ? totals[d] : 0u;
+    off_d[j] = d < ndig ? offsets[(uint64_t)d * tiles_max + tile] : 0u;
+    if (WEIGHTED) {
+      wtot_d[j] = d < ndig ? wt.wtotals[d] : 0ull;
+      woff_d[j] = d < ndig ? wt.wprefix[(uint64_t)d * tiles_max + tile] : 0ull;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    for (int d = t; d < ndig; d += kBlock) wcnt[k][d] = 0;
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
@@ -216,19 +310,41 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   __syncthreads();
-  // thread t = digit: tile-local start (scan over digits of the tile's counts) and global
-  // start (scan over digits of the totals, plus this tile's offset within the digit)
-  const uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
-  const uint32_t tot = c0 + c1 + c2 + c3;
+  // per digit: tile-local start (scan over digits of the tile's counts) and global start
+  // (scan over digits of the totals, plus this tile's offset within the digit)
+  uint32_t c[M][4], loc = 0, gsum = 0;
+  uint64_t wsum = 0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const int d = t * M + j;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[j][k] = d < ndig ? wcnt[k][d] : 0u;
+    loc += c[j][0] + c[j][1] + c[j][2] + c[j][3];
+    gsum += tot_d[j];
+    if (WEIGHTED) wsum += wtot_d[j];
+  }
   uint32_t all;
-  const uint32_t bs = block_exclusive_scan_u32(tot, sh4, &all);
-  const uint32_t gb = block_exclusive_scan_u32(tot_d, sh4, &all) + off_d;
-  bstart[t] = bs;
-  gbase[t] = gb;
-  wcnt[0][t] = bs;
-  wcnt[1][t] = bs + c0;
-  wcnt[2][t] = bs + c0 + c1;
-  wcnt[3][t] = bs + c0 + c1 + c2;
+  uint32_t bs = block_exclusive_scan_u32(loc, sh4, &all);
+  uint32_t gb = block_exclusive_scan_u32(gsum, sh4, &all);
+  uint64_t wall = 0, wb = 0;
+  if (WEIGHTED) wb = block_exclusive_scan_t<uint64_t>(wsum, sh8, &wall);
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const int d = t * M + j;
+    if (d < ndig) {
+      bstart[d] = bs;
+      gbase[d] = gb + off_d[j];
+      wcnt[0][d] = bs;
+      wcnt[1][d] = bs + c[j][0];
+      wcnt[2][d] = bs + c[j][0] + c[j][1];
+      wcnt[3][d] = bs + c[j][0] + c[j][1] + c[j][2];
+      if (WEIGHTED) gw[d] = wb + woff_d[j];
+    }
+    bs += c[j][0] + c[j][1] + c[j][2] + c[j][3];
+    gb += tot_d[j];
+    if (WEIGHTED) wb += wtot_d[j];
+  }
+  if (WEIGHTED && tile == 0 && t == 0) fe.dpos[n] = wall;
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
@@ -237,10 +353,43 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
       const uint32_t lp = wcnt[w][dig[r]] + pos[r];
       s_key[lp] = key[r];
       s_val[lp] = val[r];
+      if (WEIGHTED) s_w[lp] = kw[r];
     }
   }
   __syncthreads();
   const uint32_t nvalid = (uint32_t)((n - tile0) < (uint64_t)kSortTile ? (n - tile0) : (uint64_t)kSortTile);
+  if (WEIGHTED) {
+    // exclusive scan of the weights in tile-local sorted order (R consecutive keys per thread;
+    // 32 bits hold a tile's sum unless the frame has 2^32 entries, which the caller rejects)
+    uint32_t x[kRounds], ssum = 0;
+#pragma unroll
+    for (int q = 0; q < kRounds; ++q) {
+      const uint32_t i = (uint32_t)t * kRounds + q;
+      x[q] = i < nvalid ? s_w[i] : 0u;
+      ssum += x[q];
+    }
+    uint32_t tall;
+    uint32_t ex = block_exclusive_scan_u32(ssum, sh4, &tall);
+#pragma unroll
+    for (int q = 0; q < kRounds; ++q) {
+      s_wx[t * kRounds + q] = ex;
+      ex += x[q];
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < nvalid; i += kBlock) {
+      const KT k = s_key[i];
+      const uint32_t d = (uint32_t)(k >> shift) & dmask;
+      const uint32_t p = gbase[d] + (i - bstart[d]);
+      kout[p] = k;
+      vout[p] = s_val[i];
+      const uint64_t o = gw[d] + (s_wx[i] - s_wx[bstart[d]]);
+      fe.dpos[p] = o;
+      const uint64_t end = o + s_w[i];
+      for (uint64_t bk = (o + kFirstsBlock - 1) / kFirstsBlock; bk * kFirstsBlock < end && bk < fe.nfirst; ++bk)
+        fe.first[bk] = p;
+    }
+    return;
+  }
   if (fin.vals) {
     // all gathers of the thread first, then the stores (several round trips in flight)
     uint32_t gi[kRounds], dk[kRounds];
@@ -267,16 +416,14 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
   for (uint32_t i = t; i < nvalid; i += kBlock) {
     const KT k = s_key[i];
     const uint32_t d = (uint32_t)(k >> shift) & dmask;
-    const uint32_t v = s_val[i];
     kout[gbase[d] + (i - bstart[d])] = k;
-    vout[gbase[d] + (i - bstart[d])] = v;
-    if (aux_out) aux_out[gbase[d] + (i - bstart[d])] = aux_in[v];   // a payload gathered through the value
+    vout[gbase[d] + (i - bstart[d])] = s_val[i];
   }
 }
 
 // Depth keys of the visible Gaussians (key[i] = bits(depth of order[i]), i < *nvis), the entry
 // and visible counts, and the first depth pass's per-tile digit counts (one workgroup per sort
-// tile of R x 256 keys; counts[d * gridDim.x + tile] for the digit bits [0, nbits0)).
+// tile of R x 256 keys; counts[d * tiles + tile] for the digit bits [0, nbits0)).
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis,
                                                        uint32_t *keys, const uint64_t *K, uint64_t *counts,
@@ -298,7 +445,8 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, co
   const uint32_t tile = xcd_sort_tile(blockIdx.x, ((uint64_t)V + kSortTile - 1) / kSortTile);
   if (tile == ~0u) return;
   const uint64_t tile0 = (uint64_t)tile * kSortTile;
-  h[threadIdx.x] = 0;
+  const int ndig = 1 << nbits0;
+  for (int d = threadIdx.x; d < ndig; d += kBlock) h[d] = 0;
   __syncthreads();
   const uint32_t dmask = (1u << nbits0) - 1u;
   uint32_t g[R];
@@ -317,7 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, co
     }
   }
   __syncthreads();
-  dcounts[(uint64_t)threadIdx.x * tiles + tile] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < ndig; d += kBlock) dcounts[(uint64_t)d * tiles + tile] = h[d];
 }
 
 // ---- binning: one thread per entry -------------------------------------------
@@ -700,17 +848,10 @@ inline uint64_t sort_tiles(uint64_t n) {
                          : (n + SortTile<kLargeR>::kTile - 1) / SortTile<kLargeR>::kTile;
 }
 
-size_t radix_tmp_bytes(uint64_t n) {
-  uint64_t tiles = sort_tiles(n < kSmallSort ? n : kSmallSort);
-  if (sort_tiles(n) > tiles) tiles = sort_tiles(n);
-  return ((size_t)kDigits * (tiles ? tiles : 1) + kDigits) * sizeof(uint32_t);
-}
-
 // Digit width of the passes over key bits [lo, hi): passes of (nearly) equal width, at most
-// 8 bits each (13 bits -> 7 + 6, 32 -> 4 x 8).
-inline int pass_width(int lo, int hi) {
-  const int passes = (hi - lo + 7) / 8;
-  return (hi - lo + passes - 1) / passes;
+// maxw bits each (13 bits -> 7 + 6 and 32 -> 4 x 8 with 8; 31 -> 11 + 11 + 9 with 11).
+constexpr int pass_width(int lo, int hi, int maxw = 8) {
+  return (hi - lo + (hi - lo + maxw - 1) / maxw - 1) / ((hi - lo + maxw - 1) / maxw);
 }
 
 // first_counted: the per-tile digit counts of the first pass are already in tmp (written where
@@ -718,7 +859,7 @@ inline int pass_width(int lo, int hi) {
 template <typename KT, int R>
 hipError_t radix_passes_r(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n,
                           const uint32_t *n_dev, int lo, int hi, void *tmp, hipStream_t st, bool *in_alt,
-                          const uint32_t *aux_in, uint32_t *aux_out, const FinalOut *fin, bool first_counted) {
+                          const FinalOut *fin, bool first_counted) {
   const uint32_t tiles = (uint32_t)((n + SortTile<R>::kTile - 1) / SortTile<R>::kTile);
   uint32_t *counts = static_cast<uint32_t *>(tmp);
   uint32_t *totals = counts + (uint64_t)kDigits * tiles;
@@ -726,18 +867,19 @@ hipError_t radix_passes_r(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals
   uint32_t *vin = vals, *vout = vals_alt;
   const int width = pass_width(lo, hi);
   const FinalOut none{nullptr, nullptr, nullptr, nullptr};
+  const DigitWeights now{nullptr, nullptr, nullptr, nullptr, nullptr};
+  const FirstEntries nofe{nullptr, nullptr, 0};
   for (int shift = lo; shift < hi; shift += width) {
     const int bits = (hi - shift) < width ? (hi - shift) : width;
     const bool last = shift + width >= hi;
     if (!(first_counted && shift == lo))
-      hipLaunchKernelGGL((k_radix_count<KT, R>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, kin, n, n_dev, shift,
-                         bits, tiles, counts);
+      hipLaunchKernelGGL((k_radix_count<KT, R, kDigits, false>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, kin,
+                         n, n_dev, shift, bits, tiles, counts, now);
     hipLaunchKernelGGL(k_radix_digit_scan, dim3(1u << bits), dim3(kBlock), 0, st, counts, tiles, totals, n, n_dev,
-                       (uint32_t)SortTile<R>::kTile);
-    hipLaunchKernelGGL((k_radix_scatter<KT, R>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, kin, vin, kout, vout,
-                       n, n_dev,
-                       shift, bits, tiles, counts, totals, aux_in, last ? aux_out : nullptr,
-                       (last && fin) ? *fin : none);
+                       (uint32_t)SortTile<R>::kTile, now);
+    hipLaunchKernelGGL((k_radix_scatter<KT, R, kDigits, false>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, kin,
+                       vin, kout, vout, n, n_dev, shift, bits, tiles, counts, totals, (last && fin) ? *fin : none,
+                       now, nofe);
     std::swap(kin, kout);
     std::swap(vin, vout);
     *in_alt = !*in_alt;
@@ -745,20 +887,18 @@ hipError_t radix_passes_r(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals
   return hipGetLastError();
 }
 
-// n: the number of keys, or (with n_dev) an upper bound of *n_dev.  With aux_out, the last
-// pass also writes aux_out[i] = aux_in[value of the i-th sorted key].
+// n: the number of keys, or (with n_dev) an upper bound of *n_dev.
 template <typename KT>
 hipError_t radix_passes_t(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n,
                           const uint32_t *n_dev, int lo, int hi, void *tmp, hipStream_t st, bool *in_alt,
-                          const uint32_t *aux_in = nullptr, uint32_t *aux_out = nullptr,
                           const FinalOut *fin = nullptr, bool first_counted = false) {
   *in_alt = false;
   if (hi <= lo || n <= 1) return hipSuccess;
   if (n <= kSmallSort)
-    return radix_passes_r<KT, kSmallR>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt, aux_in,
-                                       aux_out, fin, first_counted);
-  return radix_passes_r<KT, kLargeR>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt, aux_in,
-                                     aux_out, fin, first_counted);
+    return radix_passes_r<KT, kSmallR>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt, fin,
+                                       first_counted);
+  return radix_passes_r<KT, kLargeR>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt, fin,
+                                     first_counted);
 }
 
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
@@ -766,28 +906,121 @@ hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32
   return radix_passes_t<uint64_t>(keys, vals, keys_alt, vals_alt, n, nullptr, lo, hi, tmp, st, in_alt);
 }
 
+// ---- depth sort -----------------------------------------------------------------------
+// Four passes over the 31 bits of a positive depth (8, 8, 8 and 7 bits), the last one weighted.
+constexpr int kDepthWidth = pass_width(0, kDepthBits);
+constexpr int kDepthPasses = (kDepthBits + kDepthWidth - 1) / kDepthWidth;
+constexpr int kDepthLastBits = kDepthBits - (kDepthPasses - 1) * kDepthWidth;
+constexpr int kDepthLastDigits = 1 << kDepthLastBits;
+static_assert(kDepthWidth == 8 && kDepthPasses == 4 && kDepthLastBits == 7, "depth passes of 8, 8, 8 and 7 bits");
+
+// Scratch of the depth sort over tiles sort tiles (the same for every pass): per-tile digit
+// counts and digit totals, and the last pass's weights per tile and digit with their 64-bit
+// scans and totals.
+struct DepthTmp {
+  uint64_t *wprefix;
+  uint64_t *wtotals;
+  uint32_t *counts;
+  uint32_t *totals;
+  uint32_t *wcounts;
+  size_t bytes;
+};
+inline DepthTmp depth_tmp(void *tmp, uint64_t tiles) {
+  DepthTmp d;
+  char *p = static_cast<char *>(tmp);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char * {
+    char *q = p ? p + off : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return q;
+  };
+  const uint64_t t = tiles ? tiles : 1;
+  d.wprefix = reinterpret_cast<uint64_t *>(take(kDepthLastDigits * t * 8));
+  d.wtotals = reinterpret_cast<uint64_t *>(take(kDepthLastDigits * 8));
+  d.counts = reinterpret_cast<uint32_t *>(take(kDigits * t * 4));
+  d.totals = reinterpret_cast<uint32_t *>(take(kDigits * 4));
+  d.wcounts = reinterpret_cast<uint32_t *>(take(kDepthLastDigits * t * 4));
+  d.bytes = off;
+  return d;
+}
+
+// Keys ping-pong between keys and keys_alt; values run order -> vals_alt -> vals_b ->
+// vals_alt -> order, so that the sorted list ends where it started.
+template <int R>
+hipError_t depth_passes(uint32_t *order, const uint32_t *nvis, uint64_t n_max, uint32_t *keys, uint32_t *keys_alt,
+                        uint32_t *vals_alt, uint32_t *vals_b, void *tmp, hipStream_t st, const uint32_t *count,
+                        uint64_t *dpos, uint32_t *first, uint64_t nfirst) {
+  const uint32_t tiles = (uint32_t)sort_tiles(n_max);
+  const DepthTmp d = depth_tmp(tmp, tiles);
+  const unsigned grid = xcd_sort_grid(tiles);
+  const uint32_t tile_keys = (uint32_t)SortTile<R>::kTile;
+  const FinalOut none{nullptr, nullptr, nullptr, nullptr};
+  const DigitWeights now{nullptr, nullptr, nullptr, nullptr, nullptr};
+  const FirstEntries nofe{nullptr, nullptr, 0};
+  uint32_t *kbuf[2] = {keys, keys_alt};
+  uint32_t *vbuf[kDepthPasses + 1];
+  vbuf[0] = vbuf[kDepthPasses] = order;
+  for (int p = 1; p < kDepthPasses; ++p) vbuf[p] = (p & 1) ? vals_alt : vals_b;
+  for (int p = 0; p < kDepthPasses; ++p) {
+    const int shift = p * kDepthWidth;
+    uint32_t *kin = kbuf[p & 1], *kout = kbuf[(p + 1) & 1];
+    if (p + 1 < kDepthPasses) {
+      if (p > 0)   // the first pass was counted by k_depth_keys
+        hipLaunchKernelGGL((k_radix_count<uint32_t, R, kDigits, false>), dim3(grid), dim3(kBlock), 0, st, kin, n_max,
+                           nvis, shift, kDepthWidth, tiles, d.counts, now);
+      hipLaunchKernelGGL(k_radix_digit_scan, dim3(1u << kDepthWidth), dim3(kBlock), 0, st, d.counts, tiles, d.totals,
+                         n_max, nvis, tile_keys, now);
+      hipLaunchKernelGGL((k_radix_scatter<uint32_t, R, kDigits, false>), dim3(grid), dim3(kBlock), 0, st, kin,
+                         vbuf[p], kout, vbuf[p + 1], n_max, nvis, shift, kDepthWidth, tiles, d.counts, d.totals, none,
+                         now, nofe);
+    } else {
+      // weighted by the Gaussians' entry counts, with the first entries and block firsts
+      const DigitWeights wt{vbuf[p], count, d.wcounts, d.wprefix, d.wtotals};
+      hipLaunchKernelGGL((k_radix_count<uint32_t, R, kDigits, true>), dim3(grid), dim3(kBlock), 0, st, kin, n_max,
+                         nvis, shift, kDepthLastBits, tiles, d.counts, wt);
+      hipLaunchKernelGGL(k_radix_digit_scan, dim3(1u << kDepthLastBits), dim3(kBlock), 0, st, d.counts, tiles,
+                         d.totals, n_max, nvis, tile_keys, wt);
+      hipLaunchKernelGGL((k_radix_scatter<uint32_t, R, kDigits, true>), dim3(grid), dim3(kBlock), 0, st, kin, vbuf[p],
+                         kout, vbuf[p + 1], n_max, nvis, shift, kDepthLastBits, tiles, d.counts, d.totals, none, wt,
+                         FirstEntries{dpos, first, nfirst});
+    }
+  }
+  return hipGetLastError();
+}
+
+size_t radix_tmp_bytes(uint64_t n) {
+  uint64_t tiles = sort_tiles(n < kSmallSort ? n : kSmallSort);
+  if (sort_tiles(n) > tiles) tiles = sort_tiles(n);
+  return ((size_t)kDigits * (tiles ? tiles : 1) + kDigits) * sizeof(uint32_t);
+}
+
+size_t depth_sort_tmp_bytes(uint64_t n) { return depth_tmp(nullptr, sort_tiles(n ? n : 1)).bytes; }
+
 hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max,
                              uint32_t *keys, const uint64_t *K, uint64_t *counts, uint64_t *host_counts, void *tmp,
                              hipStream_t st) {
   // one workgroup per tile of the depth sort that follows (sort_depth, same n_max): its first
   // pass's digit counts are taken here
-  const int nbits0 = pass_width(0, 32);
-  uint32_t *dcounts = static_cast<uint32_t *>(tmp);
   const uint32_t tiles = (uint32_t)sort_tiles(n_max ? n_max : 1);
+  uint32_t *dcounts = depth_tmp(tmp, tiles).counts;
   if (n_max <= kSmallSort)
     hipLaunchKernelGGL((k_depth_keys<kSmallR>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, order, rgb, nvis, keys,
-                       K, counts, host_counts, nbits0, dcounts, tiles);
+                       K, counts, host_counts, kDepthWidth, dcounts, tiles);
   else
     hipLaunchKernelGGL((k_depth_keys<kLargeR>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, order, rgb, nvis, keys,
-                       K, counts, host_counts, nbits0, dcounts, tiles);
+                       K, counts, host_counts, kDepthWidth, dcounts, tiles);
   return hipGetLastError();
 }
 
 hipError_t sort_depth(uint32_t *order, const uint32_t *nvis, uint64_t n_max, uint32_t *keys, uint32_t *keys_alt,
-                      uint32_t *vals_alt, void *tmp, hipStream_t st, bool *in_alt, const uint32_t *count,
-                      uint32_t *count_sorted) {
-  return radix_passes_t<uint32_t>(keys, order, keys_alt, vals_alt, n_max, nvis, 0, 32, tmp, st, in_alt, count,
-                                  count_sorted, nullptr, true);
+                      uint32_t *vals_alt, uint32_t *vals_b, void *tmp, hipStream_t st, const uint32_t *count,
+                      uint64_t *dpos, uint32_t *first, uint64_t nfirst) {
+  if (n_max <= 1) return hipSuccess;
+  if (n_max <= kSmallSort)
+    return depth_passes<kSmallR>(order, nvis, n_max, keys, keys_alt, vals_alt, vals_b, tmp, st, count, dpos, first,
+                                 nfirst);
+  return depth_passes<kLargeR>(order, nvis, n_max, keys, keys_alt, vals_alt, vals_b, tmp, st, count, dpos, first,
+                               nfirst);
 }
 
 hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint64_t *dpos, const uint32_t *block_first,
@@ -831,8 +1064,8 @@ hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint
   const FinalOut fin{order, dkeys, vals, keys};
   // the bin passes ping-pong between (bkey, bval) and (bkey_alt, bval_alt); the last one writes
   // the final indices and 64-bit keys, and its sorted bin keys land in kf
-  hipError_t e = radix_passes_t<uint32_t>(bkey, bval, bkey_alt, bval_alt, K, nullptr, 0, hi, tmp, st, &in_alt, nullptr,
-                                          nullptr, &fin, true);
+  hipError_t e = radix_passes_t<uint32_t>(bkey, bval, bkey_alt, bval_alt, K, nullptr, 0, hi, tmp, st, &in_alt, &fin,
+                                          true);
   if (e != hipSuccess) return e;
   const uint32_t *kf = in_alt ? bkey_alt : bkey;
   hipLaunchKernelGGL(k_ranges_final, dim3(grid_for(K, (uint64_t)kBlock * kRangeItems)), dim3(kBlock), 0, st, kf, K,

@@ -29,9 +29,11 @@ import numpy as np
 # rank and the sort's two double buffers (4 + 4 + 4 + 4) and its per-tile digit counts (1 B per
 # key: 256 four-byte counts per tile of at least 1,024 keys), rounded up
 BYTES_PER_ENTRY = 32
-# per-Gaussian workspace bytes: scan partials, depth keys and their double buffers, each
-# visible Gaussian's entry count and first-entry offset in depth order
-BYTES_PER_GAUSSIAN = 28
+# per-Gaussian workspace bytes: scan partials, depth keys and their double buffers, the depth
+# sort's two value buffers, each visible Gaussian's first-entry offset in depth order, and the
+# depth sort's per-tile tables (2.5 B per key: 256 digit counts and 128 weights with their
+# 64-bit scans per tile of 1,024 keys), rounded up
+BYTES_PER_GAUSSIAN = 32
 
 
 @dataclasses.dataclass
