@@ -180,14 +180,15 @@ __device__ __forceinline__ int wave_list(const uint8_t *qm, int nrows, uint8_t *
 // Compacts, in order, the rows [0, nrows) whose 16-bit mask has bit `bit` into the wave's own
 // list; returns its length (uniform).  (The grouped rasterizer keeps one quadrant bit per
 // member tile and wave in each row's mask.)
-__device__ __forceinline__ int wave_list_bit(const uint16_t *qm, int nrows, int bit, uint8_t *wl) {
+template <typename IDX>
+__device__ __forceinline__ int wave_list_bit(const uint16_t *qm, int nrows, int bit, IDX *wl) {
   const int lane = threadIdx.x & 63;
   int n = 0;
   for (int r0 = 0; r0 < nrows; r0 += 64) {
     const int r = r0 + lane;
     const bool in = r < nrows && ((qm[r] >> bit) & 1u);
     const uint64_t b = __ballot(in);
-    if (in) wl[n + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u))] = (uint8_t)r;
+    if (in) wl[n + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u))] = (IDX)r;
     n += __popcll(b);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -203,7 +204,7 @@ __device__ __forceinline__ int wave_list_bit(const uint16_t *qm, int nrows, int 
 template <int PREC>
 __device__ __forceinline__ void make_pixel_operand(short8 &B0, short8 &B1, short8 &B20, short8 &B21, int xo = 0,
                                                    int yo = 0) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = (threadIdx.x >> 6) & 3;   // the wave's quadrant
   const int qx0 = (w & 1) * 8, qy0 = (w >> 1) * 8;
   {
     using N = Narrow<PREC>;

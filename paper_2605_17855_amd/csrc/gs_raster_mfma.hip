@@ -51,10 +51,11 @@ struct TileState {
 // copied to the wave's own buffer wc, so the blend reads them at fixed offsets.
 // tpos (auxiliary outputs of the grouped kernel only): position of each staged row in the
 // member tile's own list, within the chunk; without it the row index is that position.
-template <int PREC, int S, bool AUX>
-__device__ __forceinline__ void process_rows(const uint16_t *sA, const float *scol, const uint8_t *wl, int n,
+// CH: rows per staged chunk (the stride of the colour planes); IDX: the row index type.
+template <int PREC, int S, bool AUX, int CH = kBlock, typename IDX = uint8_t>
+__device__ __forceinline__ void process_rows(const uint16_t *sA, const float *scol, const IDX *wl, int n,
                                              float4 *wc, short8 B0, short8 B1, short8 B20, short8 B21,
-                                             TileState &st, uint32_t row_base, const uint8_t *tpos = nullptr) {
+                                             TileState &st, uint32_t row_base, const IDX *tpos = nullptr) {
   using N = Narrow<PREC>;
   constexpr int RS = (S == 3) ? 32 : 16;
   const int lane = threadIdx.x & 63;
@@ -70,7 +71,7 @@ __device__ __forceinline__ void process_rows(const uint16_t *sA, const float *sc
     const uint16_t *rp = sA + (size_t)ri * RS + 8 * (lane >> 5);
     const short8 a = real ? *reinterpret_cast<const short8 *>(rp) : pad;
     const int rpos = (AUX && tpos) ? (int)tpos[ri] : ri;
-    const float4 gc = make_float4(scol[ri], scol[kBlock + ri], scol[2 * kBlock + ri], __int_as_float(rpos));
+    const float4 gc = make_float4(scol[ri], scol[CH + ri], scol[2 * CH + ri], __int_as_float(rpos));
     float16v z = {};
     float16v d0 = N::mma(a, B0, z);
     float16v d1 = N::mma(a, B1, z);
@@ -163,29 +164,37 @@ struct GroupFrame {
   static constexpr bool value = G == 2;
 };
 
+constexpr int kGroupFrameThreads = 512;   // eight waves: one per (member tile, quadrant)
+
 template <int S>
 struct MfmaGroupShared {
   static constexpr int RS = (S == 3) ? 32 : 16;
-  static constexpr int NTP = 2;    // member tiles per workgroup: one row of a 2x2 group
-  __align__(16) uint16_t A[kBlock * RS];
-  float col[3][kBlock];
-  uint16_t qm[kBlock];             // bit 4 j + q: quadrant q of the workgroup's member tile j
-  uint8_t tpos[NTP][kBlock];       // auxiliary outputs: row position in member tile j's list
-  uint32_t wcnt[NTP][4];
-  uint32_t alive[2][4];
-  uint8_t wl[4][kBlock];
-  float4 wc[4][32];
+  static constexpr int NTP = 2;        // member tiles per workgroup: one row of a 2x2 group
+  static constexpr int NW = 4 * NTP;   // waves: one per (member tile, quadrant)
+  // entries per chunk: one per thread, or (three pieces per row) half as many, which keeps
+  // four waves per SIMD within the LDS
+  static constexpr int CH = S == 3 ? kGroupFrameThreads / 2 : kGroupFrameThreads;
+  __align__(16) uint16_t A[CH * RS];
+  float col[3][CH];
+  uint16_t qm[CH];                 // bit 4 j + q: quadrant q of the workgroup's member tile j
+  uint16_t tpos[NTP][CH];          // auxiliary outputs: row position in member tile j's list
+  uint32_t wcnt[NTP][NW];
+  uint32_t alive[2][NW];
+  uint16_t wl[NW][CH];
+  float4 wc[NW][32];
 };
+static_assert(MfmaGroupShared<2>::NW * 64 == kGroupFrameThreads, "one wave per (member tile, quadrant)");
 
 template <int G, int PREC, int S, bool AUX>
 __device__ __forceinline__ void raster_bin_mfma_group(const RasterJob &J, const RasterParams &P, int item,
                                                       MfmaGroupShared<S> &sm) {
-  // two workgroups per 2x2 group (J.parts == 2), each taking one row of member tiles: twice the
-  // workgroups of one per group, each half as long, which the CUs balance far better (a 1080p
-  // frame has ~2,000 groups for 256 CUs); both stage the group's chunk, each builds only the
-  // rows of entries that reach one of its own tiles
-  constexpr int NTP = MfmaGroupShared<S>::NTP;
-  static_assert(NTP == 2, "the tile step below selects between two member tiles");
+  // two workgroups per 2x2 group (J.parts == 2), each taking one row of member tiles with eight
+  // waves, wave w blending quadrant w & 3 of member tile w >> 2: the two tiles run side by side
+  // (walking them one after the other in four waves left the CUs short of waves: 96 VGPRs for
+  // both tiles' state, twice the time per workgroup); both workgroups stage the group's chunk,
+  // each builds only the rows of entries that reach one of its own tiles
+  constexpr int NTP = MfmaGroupShared<S>::NTP, NW = MfmaGroupShared<S>::NW, CH = MfmaGroupShared<S>::CH;
+  static_assert(NTP == 2, "two member tiles per workgroup");
   constexpr int RS = MfmaGroupShared<S>::RS;
   const int bin = item / 2;
   const int k0 = (item % 2) * NTP;   // first member tile of the workgroup
@@ -193,36 +202,32 @@ __device__ __forceinline__ void raster_bin_mfma_group(const RasterJob &J, const 
   const int ox = gx * G * kTile, oy = gy * G * kTile;
   const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int qx0 = (w & 1) * 8, qy0 = (w >> 1) * 8;
-  const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
+  const int j = w >> 2, q = w & 3;   // this wave's member tile (of the workgroup) and quadrant
+  const int k = k0 + j;
+  const int px = (q & 1) * 8 + (lane & 7), py = (q >> 1) * 8 + (lane >> 3);
   const double fx0 = (double)ox + 8.0 * G + 0.5, fy0 = (double)oy + 8.0 * G + 0.5;   // group frame origin
+  const int tx0 = ox + (k % G) * kTile, ty0 = oy + (k / G) * kTile;
 
-  // the two member tiles' blending state, kept in registers (named, not an array: a copy
-  // indexed by the tile loop's counter would place it in private memory)
-  TileState st0, st1;
-  uint32_t rows_done[NTP];
-  uint32_t alive_w = 0;            // uniform per wave: member tiles where this wave's pixels still blend
-#pragma unroll
-  for (int j = 0; j < NTP; ++j) {
-    const int k = k0 + j;
-    const int tx0 = ox + (k % G) * kTile, ty0 = oy + (k / G) * kTile;
-    const bool inside = (tx0 + px < J.W) && (ty0 + py < J.H);
-    TileState &sj = j == 0 ? st0 : st1;   // (j is a constant in the unrolled loop)
-    sj.T = 1.0f; sj.C0 = sj.C1 = sj.C2 = 0.0f; sj.W = 0.0f;
-    sj.cut = inside ? kCutLog2 : INFINITY;
-    sj.nstop = 0; sj.nblend = 0; sj.last = 0;
-    rows_done[j] = 0;
-    if (__ballot(inside) != 0) alive_w |= 1u << j;
-  }
+  TileState st;
+  const bool inside = (tx0 + px < J.W) && (ty0 + py < J.H);
+  st.T = 1.0f; st.C0 = st.C1 = st.C2 = 0.0f; st.W = 0.0f;
+  st.cut = inside ? kCutLog2 : INFINITY;
+  st.nstop = 0; st.nblend = 0; st.last = 0;
+  uint32_t rows_done = 0;
+  bool alive = __ballot(inside) != 0;   // uniform per wave: its pixels still blend
+  // pixel-side operand of this wave's quadrant of tile k in the group frame
+  short8 B0, B1, B20, B21;
+  make_pixel_operand<PREC>(B0, B1, B20, B21, (k % G) * kTile - 8 * G + 8, (k / G) * kTile - 8 * G + 8);
 
   int it = 0;
-  for (uint32_t cs = start; cs < end; cs += kBlock) {
-    const int cnt = (int)min((uint32_t)kBlock, end - cs);
+  for (uint32_t cs = start; cs < end; cs += CH) {
+    const int cnt = (int)min((uint32_t)CH, end - cs);
     if (it > 0) {
       // every wave is done with the previous chunk and has posted whether it still blends
       __syncthreads();
-      const uint32_t any = sm.alive[(it - 1) & 1][0] | sm.alive[(it - 1) & 1][1] | sm.alive[(it - 1) & 1][2] |
-                           sm.alive[(it - 1) & 1][3];
+      uint32_t any = 0;
+#pragma unroll
+      for (int v = 0; v < NW; ++v) any |= sm.alive[(it - 1) & 1][v];
       if (!any) break;
     }
     uint32_t mk = 0;
@@ -240,85 +245,70 @@ __device__ __forceinline__ void raster_bin_mfma_group(const RasterJob &J, const 
       sm.col[0][t] = cl.x;
       sm.col[1][t] = cl.y;
       sm.col[2][t] = cl.z;
-      uint32_t q = 0;
+      uint32_t qmask = 0;
 #pragma unroll
-      for (int j = 0; j < NTP; ++j) {
-        const int k = k0 + j;
-        if ((mk >> k) & 1u) {
-          // the quadrant test in member tile k's own frame
-          const float ut = u + (float)(8 * G - 8 - (k % G) * kTile), vt = v + (float)(8 * G - 8 - (k / G) * kTile);
-          q |= (P.all_rows ? 0xFu : quad_mask(ut, vt, co.x, co.y, co.z, l2o)) << (4 * j);
+      for (int jj = 0; jj < NTP; ++jj) {
+        const int kk = k0 + jj;
+        if ((mk >> kk) & 1u) {
+          // the quadrant test in member tile kk's own frame
+          const float ut = u + (float)(8 * G - 8 - (kk % G) * kTile), vt = v + (float)(8 * G - 8 - (kk / G) * kTile);
+          qmask |= (P.all_rows ? 0xFu : quad_mask(ut, vt, co.x, co.y, co.z, l2o)) << (4 * jj);
         }
       }
-      sm.qm[t] = (uint16_t)q;
+      sm.qm[t] = (uint16_t)qmask;
     }
-    if (AUX) {
+    if (AUX) {   // each wave counts each member tile's entries among its 64
 #pragma unroll
-      for (int j = 0; j < NTP; ++j) {
-        const uint64_t bk = __ballot((mk >> (k0 + j)) & 1u);
-        if (lane == 0) sm.wcnt[j][w] = (uint32_t)__popcll(bk);
+      for (int jj = 0; jj < NTP; ++jj) {
+        const uint64_t bk = __ballot((mk >> (k0 + jj)) & 1u);
+        if (lane == 0) sm.wcnt[jj][w] = (uint32_t)__popcll(bk);
       }
     }
     __syncthreads();
     if (AUX) {
       // each row's position in every member tile's list (entries of the chunk with its bit)
 #pragma unroll
-      for (int j = 0; j < NTP; ++j) {
-        const uint64_t bk = __ballot((mk >> (k0 + j)) & 1u);
-        const uint32_t woff = (w > 0 ? sm.wcnt[j][0] : 0u) + (w > 1 ? sm.wcnt[j][1] : 0u) +
-                              (w > 2 ? sm.wcnt[j][2] : 0u);
-        sm.tpos[j][t] = (uint8_t)(woff + __builtin_amdgcn_mbcnt_hi((uint32_t)(bk >> 32),
-                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)bk, 0u)));
+      for (int jj = 0; jj < NTP; ++jj) {
+        const uint64_t bk = __ballot((mk >> (k0 + jj)) & 1u);
+        uint32_t woff = 0;
+        for (int v = 0; v < w; ++v) woff += sm.wcnt[jj][v];
+        if (t < CH)
+          sm.tpos[jj][t] = (uint16_t)(woff + __builtin_amdgcn_mbcnt_hi((uint32_t)(bk >> 32),
+                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)bk, 0u)));
       }
       __syncthreads();
     }
-    // one copy of the tile step: the member tile's state is moved into registers for it
-#pragma unroll 1
-    for (int j = 0; j < NTP; ++j) {
-      if (!((alive_w >> j) & 1u)) continue;
-      const int k = k0 + j;
-      short8 B0, B1, B20, B21;
-      make_pixel_operand<PREC>(B0, B1, B20, B21, (k % G) * kTile - 8 * G + 8, (k / G) * kTile - 8 * G + 8);
-      const int nw = wave_list_bit(sm.qm, cnt, 4 * j + w, sm.wl[w]);
-      TileState cur;
-      if (j == 0) cur = st0; else cur = st1;
-      process_rows<PREC, S, AUX>(sm.A, &sm.col[0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, cur,
-                                 j == 0 ? rows_done[0] : rows_done[1],
-                                 AUX ? sm.tpos[j] : nullptr);
-      if (j == 0) st0 = cur; else st1 = cur;
-      if (__ballot(cur.cut != INFINITY) == 0) alive_w &= ~(1u << j);
+    if (alive) {
+      const int nw = wave_list_bit(sm.qm, cnt, 4 * j + q, sm.wl[w]);
+      process_rows<PREC, S, AUX, CH, uint16_t>(sm.A, &sm.col[0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, st,
+                                               rows_done, AUX ? sm.tpos[j] : nullptr);
+      alive = __ballot(st.cut != INFINITY) != 0;
     }
     if (AUX) {
 #pragma unroll
-      for (int j = 0; j < NTP; ++j)
-        rows_done[j] += sm.wcnt[j][0] + sm.wcnt[j][1] + sm.wcnt[j][2] + sm.wcnt[j][3];
+      for (int v = 0; v < NW; ++v) rows_done += sm.wcnt[j][v];
     }
-    if (lane == 0) sm.alive[it & 1][w] = alive_w != 0;
+    if (lane == 0) sm.alive[it & 1][w] = alive;
     ++it;
   }
 
+  const int xx = tx0 + px, yy = ty0 + py;
+  if (xx >= J.W || yy >= J.H) return;
   const int64_t HW = (int64_t)J.W * J.H;
-#pragma unroll
-  for (int j = 0; j < NTP; ++j) {
-    const int k = k0 + j;
-    const int xx = ox + (k % G) * kTile + px, yy = oy + (k / G) * kTile + py;
-    if (xx >= J.W || yy >= J.H) continue;
-    const int64_t pix = (int64_t)yy * J.W + xx;
-    const TileState &sj = j == 0 ? st0 : st1;
-    J.image[pix] = sj.C0 + sj.T * P.bg[0];
-    J.image[HW + pix] = sj.C1 + sj.T * P.bg[1];
-    J.image[2 * HW + pix] = sj.C2 + sj.T * P.bg[2];
-    if (AUX) {
-      int plane = 0;
-      if (P.aux_flags & GS_AUX_TFINAL) J.aux[(plane++) * HW + pix] = sj.T;
-      if (P.aux_flags & GS_AUX_WSUM) J.aux[(plane++) * HW + pix] = sj.W;
-      if (P.aux_flags & GS_AUX_NEVAL) {
-        const bool stopped = sj.cut == INFINITY;
-        J.aux[(plane++) * HW + pix] = (float)(stopped ? sj.nstop : rows_done[j]);
-      }
-      if (P.aux_flags & GS_AUX_NBLEND) J.aux[(plane++) * HW + pix] = (float)sj.nblend;
-      if (P.aux_flags & GS_AUX_LAST) J.aux[(plane++) * HW + pix] = (float)sj.last;
+  const int64_t pix = (int64_t)yy * J.W + xx;
+  J.image[pix] = st.C0 + st.T * P.bg[0];
+  J.image[HW + pix] = st.C1 + st.T * P.bg[1];
+  J.image[2 * HW + pix] = st.C2 + st.T * P.bg[2];
+  if (AUX) {
+    int plane = 0;
+    if (P.aux_flags & GS_AUX_TFINAL) J.aux[(plane++) * HW + pix] = st.T;
+    if (P.aux_flags & GS_AUX_WSUM) J.aux[(plane++) * HW + pix] = st.W;
+    if (P.aux_flags & GS_AUX_NEVAL) {
+      const bool stopped = st.cut == INFINITY;
+      J.aux[(plane++) * HW + pix] = (float)(stopped ? st.nstop : rows_done);
     }
+    if (P.aux_flags & GS_AUX_NBLEND) J.aux[(plane++) * HW + pix] = (float)st.nblend;
+    if (P.aux_flags & GS_AUX_LAST) J.aux[(plane++) * HW + pix] = (float)st.last;
   }
 }
 
@@ -519,8 +509,14 @@ __device__ __forceinline__ void raster_item(const RasterJob &J, const RasterPara
     raster_bin_mfma<G, PREC, S, AUX>(J, P, item, sm, B0, B1, B20, B21);
 }
 
+// threads per workgroup: eight waves for the group-frame path, four otherwise
+template <bool GF>
+struct RasterThreads {
+  static constexpr int value = GF ? kGroupFrameThreads : kBlock;
+};
+
 template <int G, int PREC, int S, bool AUX, bool GF>
-__global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParams P) {
+__global__ __launch_bounds__(RasterThreads<GF>::value) void k_raster_mfma(RasterJob J, RasterParams P) {
   __shared__ typename SharedFor<G, PREC, S, GF>::type sm;
   short8 B0, B1, B20, B21;
   make_pixel_operand<PREC>(B0, B1, B20, B21);
@@ -534,7 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_raster_mfma(RasterJob J, RasterParam
 // (batch_items) until all `total` are done; job j owns items [jobs[j].bin0, jobs[j].bin0 +
 // jobs[j].items).
 template <int G, int PREC, int S, bool AUX, bool GF>
-__global__ __launch_bounds__(kBlock) void k_raster_mfma_batch(const BatchTable tb,
+__global__ __launch_bounds__(RasterThreads<GF>::value) void k_raster_mfma_batch(const BatchTable tb,
                                                               RasterParams P, uint32_t *counter) {
   __shared__ typename SharedFor<G, PREC, S, GF>::type sm;
   __shared__ int s_item;
@@ -559,12 +555,13 @@ struct BatchArgs {
 
 template <int G, int PREC, int S, bool AUX, bool GF>
 hipError_t launch_gf(const RasterJob &j, const RasterParams &p, const BatchArgs *b, hipStream_t st) {
+  constexpr int threads = RasterThreads<GF>::value;
   if (b) {
-    hipLaunchKernelGGL((k_raster_mfma_batch<G, PREC, S, AUX, GF>), dim3((unsigned)b->grid), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL((k_raster_mfma_batch<G, PREC, S, AUX, GF>), dim3((unsigned)b->grid), dim3(threads), 0, st,
                        *b->table, p, b->counter);
   } else {
     const unsigned grid = j.parts == 1 ? xcd_raster_grid(j.GX, j.GY) : (unsigned)j.items;
-    hipLaunchKernelGGL((k_raster_mfma<G, PREC, S, AUX, GF>), dim3(grid), dim3(kBlock), 0, st, j, p);
+    hipLaunchKernelGGL((k_raster_mfma<G, PREC, S, AUX, GF>), dim3(grid), dim3(threads), 0, st, j, p);
   }
   return hipGetLastError();
 }
