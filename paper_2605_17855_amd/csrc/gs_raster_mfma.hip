@@ -164,16 +164,16 @@ struct GroupFrame {
   static constexpr bool value = G == 2;
 };
 
-constexpr int kGroupFrameThreads = 512;   // eight waves: one per (member tile, quadrant)
-
 template <int S>
 struct MfmaGroupShared {
   static constexpr int RS = (S == 3) ? 32 : 16;
   static constexpr int NTP = 2;        // member tiles per workgroup: one row of a 2x2 group
-  static constexpr int NW = 4 * NTP;   // waves: one per (member tile, quadrant)
-  // entries per chunk: one per thread, or (three pieces per row) half as many, which keeps
-  // four waves per SIMD within the LDS
-  static constexpr int CH = S == 3 ? kGroupFrameThreads / 2 : kGroupFrameThreads;
+  // member tiles blended side by side: both (eight waves, one per tile and quadrant) when a row
+  // is one or two pieces; with three pieces, the registers of eight waves would leave two
+  // workgroups per CU, so four waves walk the two tiles one after the other
+  static constexpr int PAR = S == 3 ? 1 : 2;
+  static constexpr int NW = 4 * PAR;   // waves
+  static constexpr int CH = 64 * NW;   // entries per staged chunk, one per thread
   __align__(16) uint16_t A[CH * RS];
   float col[3][CH];
   uint16_t qm[CH];                 // bit 4 j + q: quadrant q of the workgroup's member tile j
@@ -183,41 +183,54 @@ struct MfmaGroupShared {
   uint16_t wl[NW][CH];
   float4 wc[NW][32];
 };
-static_assert(MfmaGroupShared<2>::NW * 64 == kGroupFrameThreads, "one wave per (member tile, quadrant)");
 
 template <int G, int PREC, int S, bool AUX>
 __device__ __forceinline__ void raster_bin_mfma_group(const RasterJob &J, const RasterParams &P, int item,
                                                       MfmaGroupShared<S> &sm) {
-  // two workgroups per 2x2 group (J.parts == 2), each taking one row of member tiles with eight
-  // waves, wave w blending quadrant w & 3 of member tile w >> 2: the two tiles run side by side
-  // (walking them one after the other in four waves left the CUs short of waves: 96 VGPRs for
-  // both tiles' state, twice the time per workgroup); both workgroups stage the group's chunk,
-  // each builds only the rows of entries that reach one of its own tiles
-  constexpr int NTP = MfmaGroupShared<S>::NTP, NW = MfmaGroupShared<S>::NW, CH = MfmaGroupShared<S>::CH;
-  static_assert(NTP == 2, "two member tiles per workgroup");
-  constexpr int RS = MfmaGroupShared<S>::RS;
+  // two workgroups per 2x2 group (J.parts == 2), each taking one row of member tiles (twice the
+  // workgroups of one per group: the CUs balance them far better); wave w blends quadrant
+  // w & 3 of member tile w >> 2 (eight waves), or of both member tiles in turn (four waves).
+  // Both workgroups stage the group's chunk; each builds only the rows of entries that reach
+  // one of its own tiles
+  using SH = MfmaGroupShared<S>;
+  constexpr int NTP = SH::NTP, NW = SH::NW, CH = SH::CH, PAR = SH::PAR, RS = SH::RS;
+  constexpr int TPW = NTP / PAR;   // member tiles per wave
+  static_assert(NTP == 2 && (PAR == 1 || PAR == 2), "two member tiles per workgroup");
   const int bin = item / 2;
   const int k0 = (item % 2) * NTP;   // first member tile of the workgroup
   const int gx = bin % J.GX, gy = bin / J.GX;
   const int ox = gx * G * kTile, oy = gy * G * kTile;
   const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int j = w >> 2, q = w & 3;   // this wave's member tile (of the workgroup) and quadrant
-  const int k = k0 + j;
+  const int q = w & 3;                          // this wave's quadrant
+  const int j0 = PAR == 2 ? (w >> 2) : 0;       // its first member tile (of the workgroup)
   const int px = (q & 1) * 8 + (lane & 7), py = (q >> 1) * 8 + (lane >> 3);
   const double fx0 = (double)ox + 8.0 * G + 0.5, fy0 = (double)oy + 8.0 * G + 0.5;   // group frame origin
-  const int tx0 = ox + (k % G) * kTile, ty0 = oy + (k / G) * kTile;
 
-  TileState st;
-  const bool inside = (tx0 + px < J.W) && (ty0 + py < J.H);
-  st.T = 1.0f; st.C0 = st.C1 = st.C2 = 0.0f; st.W = 0.0f;
-  st.cut = inside ? kCutLog2 : INFINITY;
-  st.nstop = 0; st.nblend = 0; st.last = 0;
-  uint32_t rows_done = 0;
-  bool alive = __ballot(inside) != 0;   // uniform per wave: its pixels still blend
-  // pixel-side operand of this wave's quadrant of tile k in the group frame
+  // the wave's member tiles' blending state, in registers (named, not an array: a copy indexed
+  // by the tile loop's counter would place it in private memory)
+  TileState st0, st1;
+  uint32_t rows_done[TPW];
+  uint32_t alive_w = 0;            // uniform per wave: its tiles whose pixels still blend (bit i)
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int k = k0 + j0 + i;
+    const int tx0 = ox + (k % G) * kTile, ty0 = oy + (k / G) * kTile;
+    const bool inside = (tx0 + px < J.W) && (ty0 + py < J.H);
+    TileState &si = i == 0 ? st0 : st1;   // (i is a constant in the unrolled loop)
+    si.T = 1.0f; si.C0 = si.C1 = si.C2 = 0.0f; si.W = 0.0f;
+    si.cut = inside ? kCutLog2 : INFINITY;
+    si.nstop = 0; si.nblend = 0; si.last = 0;
+    rows_done[i] = 0;
+    if (__ballot(inside) != 0) alive_w |= 1u << i;
+  }
+  // pixel-side operand of the wave's quadrant in the group frame: fixed for a wave with one
+  // member tile, made per tile step otherwise
   short8 B0, B1, B20, B21;
-  make_pixel_operand<PREC>(B0, B1, B20, B21, (k % G) * kTile - 8 * G + 8, (k / G) * kTile - 8 * G + 8);
+  if (TPW == 1) {
+    const int k = k0 + j0;
+    make_pixel_operand<PREC>(B0, B1, B20, B21, (k % G) * kTile - 8 * G + 8, (k / G) * kTile - 8 * G + 8);
+  }
 
   int it = 0;
   for (uint32_t cs = start; cs < end; cs += CH) {
@@ -272,43 +285,59 @@ __device__ __forceinline__ void raster_bin_mfma_group(const RasterJob &J, const 
         const uint64_t bk = __ballot((mk >> (k0 + jj)) & 1u);
         uint32_t woff = 0;
         for (int v = 0; v < w; ++v) woff += sm.wcnt[jj][v];
-        if (t < CH)
-          sm.tpos[jj][t] = (uint16_t)(woff + __builtin_amdgcn_mbcnt_hi((uint32_t)(bk >> 32),
-                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)bk, 0u)));
+        sm.tpos[jj][t] = (uint16_t)(woff + __builtin_amdgcn_mbcnt_hi((uint32_t)(bk >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bk, 0u)));
       }
       __syncthreads();
     }
-    if (alive) {
+    // one copy of the tile step: the member tile's state is moved into registers for it
+#pragma unroll 1
+    for (int i = 0; i < TPW; ++i) {
+      if (!((alive_w >> i) & 1u)) continue;
+      const int j = j0 + i, k = k0 + j;
+      if (TPW > 1)
+        make_pixel_operand<PREC>(B0, B1, B20, B21, (k % G) * kTile - 8 * G + 8, (k / G) * kTile - 8 * G + 8);
       const int nw = wave_list_bit(sm.qm, cnt, 4 * j + q, sm.wl[w]);
-      process_rows<PREC, S, AUX, CH, uint16_t>(sm.A, &sm.col[0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, st,
-                                               rows_done, AUX ? sm.tpos[j] : nullptr);
-      alive = __ballot(st.cut != INFINITY) != 0;
+      TileState cur;
+      if (i == 0) cur = st0; else cur = st1;
+      process_rows<PREC, S, AUX, CH, uint16_t>(sm.A, &sm.col[0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, cur,
+                                               i == 0 ? rows_done[0] : rows_done[TPW - 1],
+                                               AUX ? sm.tpos[j] : nullptr);
+      if (i == 0) st0 = cur; else st1 = cur;
+      if (__ballot(cur.cut != INFINITY) == 0) alive_w &= ~(1u << i);
     }
     if (AUX) {
 #pragma unroll
-      for (int v = 0; v < NW; ++v) rows_done += sm.wcnt[j][v];
+      for (int i = 0; i < TPW; ++i)
+#pragma unroll
+        for (int v = 0; v < NW; ++v) rows_done[i] += sm.wcnt[j0 + i][v];
     }
-    if (lane == 0) sm.alive[it & 1][w] = alive;
+    if (lane == 0) sm.alive[it & 1][w] = alive_w != 0;
     ++it;
   }
 
-  const int xx = tx0 + px, yy = ty0 + py;
-  if (xx >= J.W || yy >= J.H) return;
   const int64_t HW = (int64_t)J.W * J.H;
-  const int64_t pix = (int64_t)yy * J.W + xx;
-  J.image[pix] = st.C0 + st.T * P.bg[0];
-  J.image[HW + pix] = st.C1 + st.T * P.bg[1];
-  J.image[2 * HW + pix] = st.C2 + st.T * P.bg[2];
-  if (AUX) {
-    int plane = 0;
-    if (P.aux_flags & GS_AUX_TFINAL) J.aux[(plane++) * HW + pix] = st.T;
-    if (P.aux_flags & GS_AUX_WSUM) J.aux[(plane++) * HW + pix] = st.W;
-    if (P.aux_flags & GS_AUX_NEVAL) {
-      const bool stopped = st.cut == INFINITY;
-      J.aux[(plane++) * HW + pix] = (float)(stopped ? st.nstop : rows_done);
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int k = k0 + j0 + i;
+    const int xx = ox + (k % G) * kTile + px, yy = oy + (k / G) * kTile + py;
+    if (xx >= J.W || yy >= J.H) continue;
+    const int64_t pix = (int64_t)yy * J.W + xx;
+    const TileState &si = i == 0 ? st0 : st1;
+    J.image[pix] = si.C0 + si.T * P.bg[0];
+    J.image[HW + pix] = si.C1 + si.T * P.bg[1];
+    J.image[2 * HW + pix] = si.C2 + si.T * P.bg[2];
+    if (AUX) {
+      int plane = 0;
+      if (P.aux_flags & GS_AUX_TFINAL) J.aux[(plane++) * HW + pix] = si.T;
+      if (P.aux_flags & GS_AUX_WSUM) J.aux[(plane++) * HW + pix] = si.W;
+      if (P.aux_flags & GS_AUX_NEVAL) {
+        const bool stopped = si.cut == INFINITY;
+        J.aux[(plane++) * HW + pix] = (float)(stopped ? si.nstop : rows_done[i]);
+      }
+      if (P.aux_flags & GS_AUX_NBLEND) J.aux[(plane++) * HW + pix] = (float)si.nblend;
+      if (P.aux_flags & GS_AUX_LAST) J.aux[(plane++) * HW + pix] = (float)si.last;
     }
-    if (P.aux_flags & GS_AUX_NBLEND) J.aux[(plane++) * HW + pix] = (float)st.nblend;
-    if (P.aux_flags & GS_AUX_LAST) J.aux[(plane++) * HW + pix] = (float)st.last;
   }
 }
 
@@ -509,14 +538,14 @@ __device__ __forceinline__ void raster_item(const RasterJob &J, const RasterPara
     raster_bin_mfma<G, PREC, S, AUX>(J, P, item, sm, B0, B1, B20, B21);
 }
 
-// threads per workgroup: eight waves for the group-frame path, four otherwise
-template <bool GF>
+// threads per workgroup: those of the group-frame path's layout, else four waves
+template <bool GF, int S>
 struct RasterThreads {
-  static constexpr int value = GF ? kGroupFrameThreads : kBlock;
+  static constexpr int value = GF ? 64 * MfmaGroupShared<S>::NW : kBlock;
 };
 
 template <int G, int PREC, int S, bool AUX, bool GF>
-__global__ __launch_bounds__(RasterThreads<GF>::value) void k_raster_mfma(RasterJob J, RasterParams P) {
+__global__ __launch_bounds__((RasterThreads<GF, S>::value)) void k_raster_mfma(RasterJob J, RasterParams P) {
   __shared__ typename SharedFor<G, PREC, S, GF>::type sm;
   short8 B0, B1, B20, B21;
   make_pixel_operand<PREC>(B0, B1, B20, B21);
@@ -530,7 +559,7 @@ __global__ __launch_bounds__(RasterThreads<GF>::value) void k_raster_mfma(Raster
 // (batch_items) until all `total` are done; job j owns items [jobs[j].bin0, jobs[j].bin0 +
 // jobs[j].items).
 template <int G, int PREC, int S, bool AUX, bool GF>
-__global__ __launch_bounds__(RasterThreads<GF>::value) void k_raster_mfma_batch(const BatchTable tb,
+__global__ __launch_bounds__((RasterThreads<GF, S>::value)) void k_raster_mfma_batch(const BatchTable tb,
                                                               RasterParams P, uint32_t *counter) {
   __shared__ typename SharedFor<G, PREC, S, GF>::type sm;
   __shared__ int s_item;
@@ -555,7 +584,7 @@ struct BatchArgs {
 
 template <int G, int PREC, int S, bool AUX, bool GF>
 hipError_t launch_gf(const RasterJob &j, const RasterParams &p, const BatchArgs *b, hipStream_t st) {
-  constexpr int threads = RasterThreads<GF>::value;
+  constexpr int threads = RasterThreads<GF, S>::value;
   if (b) {
     hipLaunchKernelGGL((k_raster_mfma_batch<G, PREC, S, AUX, GF>), dim3((unsigned)b->grid), dim3(threads), 0, st,
                        *b->table, p, b->counter);
