@@ -308,7 +308,7 @@ def _batch_oracle(k, sc, cam, bg):
     return _BATCH_REFS[k]
 
 
-@pytest.mark.parametrize("prec,group", [("fp16", 1), ("fp32", 1), ("bf16", 2), ("fp16", 8)])
+@pytest.mark.parametrize("prec,group", [("fp16", 1), ("fp32", 1), ("bf16", 2), ("fp16", 2), ("fp16", 8)])
 def test_batch_matches_single_renders(prec, group):
     """Persistent batched rasterization: every image equals rendering its job alone (bit-identical),
     and every batched image and its T_final plane meet the oracle's bars (flagged pixels: one of
