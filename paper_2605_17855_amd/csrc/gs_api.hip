@@ -163,7 +163,7 @@ Workspace carve(void *ws, int64_t n, uint64_t capacity) {
 // depend on the split.
 int raster_parts(const gs_options &o) {
   if (o.precision == GS_PREC_FP32) return 1;
-  if (o.group >= 4) return o.group;
+  if (o.group >= 4) return o.group * o.group / gsi::group_item_tiles(o.group);
   if (o.group == 2 && !(o.flags & GS_OPT_TILE_ROWS)) return 2;
   return 1;
 }

@@ -130,9 +130,10 @@ template <int G, int S>
 struct MfmaShared {
   static constexpr int NT = G * G;
   static constexpr int RS = (S == 3) ? 32 : 16;
-  // G = 1 stages one chunk at a time (a tile's list rarely exceeds one chunk); grouped tiles
-  // double-buffer, so one member tile's rows are built while another's are still read
-  static constexpr int NBUF = G == 1 ? 1 : 2;
+  // one buffer where a workgroup has one tile (G = 1, and 4x4 and 8x8 groups split to one member
+  // tile per workgroup: the chunk barrier orders each build after the last read); several
+  // member tiles double-buffer, so one member tile's rows are built while another's are read
+  static constexpr int NBUF = (G == 1 || (G >= 4 && group_item_tiles(G) == 1)) ? 1 : 2;
   __align__(16) uint16_t A[NBUF][kBlock * RS];
   float col[NBUF][3][kBlock];       // colour planes r, g, b of the staged rows
   double2 r0[G > 1 ? kBlock : 1];  // FP64 centre; every tile rounds its own offset
@@ -350,8 +351,8 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
                                                 short8 B21) {
   constexpr int NT = G * G;
   // member tiles per workgroup: all of them for G <= 2 (one workgroup per bin, the tile loops
-  // below fully unrolled), one row of G for G >= 4 (J.parts == G workgroups per group)
-  constexpr int NTW = G >= 4 ? G : NT;
+  // below fully unrolled), group_item_tiles(G) for G >= 4 (J.parts workgroups per group)
+  constexpr int NTW = G >= 4 ? group_item_tiles(G) : NT;
   constexpr int RS = (S == 3) ? 32 : 16;
   constexpr int kTileUnroll = G >= 4 ? 1 : NT;
   using TileMask = typename std::conditional<(NT > 32), uint64_t, uint32_t>::type;
@@ -423,15 +424,20 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
       TileMask mk = 0;
       if (t < cnt) {
         const uint32_t e = cs + t;
-        const uint32_t g = J.vals[e];
-        const double2 m = J.xy[g];
-        const float4 co = J.conic[g];
-        const float4 cl = J.rgb[g];
         mk = G == 8 ? (TileMask) static_cast<const uint64_t *>(J.masks)[e]
                     : (TileMask) static_cast<const uint16_t *>(J.masks)[e];
-        sm.r0[t] = m;
-        sm.r1[t] = make_float4(co.x, co.y, co.z, log2_opacity(co.w));
-        sm.r2[t] = cl;
+        // the records of entries that reach one of this workgroup's member tiles (the others'
+        // rows are never built here)
+        const TileMask mine = NTW == NT ? ~(TileMask)0 : (TileMask)(((TileMask)1 << NTW) - 1u) << k0;
+        if (mk & mine) {
+          const uint32_t g = J.vals[e];
+          const double2 m = J.xy[g];
+          const float4 co = J.conic[g];
+          const float4 cl = J.rgb[g];
+          sm.r0[t] = m;
+          sm.r1[t] = make_float4(co.x, co.y, co.z, log2_opacity(co.w));
+          sm.r2[t] = cl;
+        }
       }
 #pragma unroll kTileUnroll
       for (int k = k0; k < k1; ++k) {
@@ -445,14 +451,14 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
         if (!any) alive_mask &= ~((TileMask)1 << last_k);
         last_k = -1;
       }
-      // G = 2: fully unrolled, all state in registers.  G = 4 and 8: one copy of the step; the
-      // member tiles' state lives in private memory and the step works on a register copy
+      // G = 2: fully unrolled, all state in registers.  G = 4 and 8: one copy of the step for the
+      // workgroup's member tiles (one tile: its state stays in registers)
 #pragma unroll kTileUnroll
       for (int k = k0; k < k1; ++k) {
         const uint4 ck = *reinterpret_cast<const uint4 *>(sm.wcnt[cp][k]);
         const uint32_t nk = ck.x + ck.y + ck.z + ck.w;
         if (!((alive_mask >> k) & 1u) || nk == 0) continue;
-        const int buf = it & 1;
+        const int buf = MfmaShared<G, S>::NBUF == 1 ? 0 : (it & 1);
         // tile-frame origin in absolute pixels, exactly as the G = 1 path forms it
         const double fx0 = (double)(ox + (k % G) * kTile) + 8.5, fy0 = (double)(oy + (k / G) * kTile) + 8.5;
         const uint64_t bk = __ballot((mk >> k) & 1u);
