@@ -163,9 +163,8 @@ Workspace carve(void *ws, int64_t n, uint64_t capacity) {
 // depend on the split.
 int raster_parts(const gs_options &o) {
   if (o.precision == GS_PREC_FP32) return 1;
-  if (o.group >= 4) return o.group * o.group / gsi::group_item_tiles(o.group);
-  if (o.group == 2 && !(o.flags & GS_OPT_TILE_ROWS)) return 2;
-  return 1;
+  if (o.group == 2 && !(o.flags & GS_OPT_TILE_ROWS)) return 2;   // the group-frame rows
+  return o.group * o.group / gsi::group_item_tiles(o.group);
 }
 
 gsi::RasterJob make_job(const gs_projected &p, const gs_bins &b, const gsi::Grid &g, float *image, float *aux,

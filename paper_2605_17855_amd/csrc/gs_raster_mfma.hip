@@ -133,7 +133,7 @@ struct MfmaShared {
   // one buffer where a workgroup has one tile (G = 1, and 4x4 and 8x8 groups split to one member
   // tile per workgroup: the chunk barrier orders each build after the last read); several
   // member tiles double-buffer, so one member tile's rows are built while another's are read
-  static constexpr int NBUF = (G == 1 || (G >= 4 && group_item_tiles(G) == 1)) ? 1 : 2;
+  static constexpr int NBUF = group_item_tiles(G) == 1 ? 1 : 2;
   __align__(16) uint16_t A[NBUF][kBlock * RS];
   float col[NBUF][3][kBlock];       // colour planes r, g, b of the staged rows
   double2 r0[G > 1 ? kBlock : 1];  // FP64 centre; every tile rounds its own offset
@@ -352,12 +352,13 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
   constexpr int NT = G * G;
   // member tiles per workgroup: all of them for G <= 2 (one workgroup per bin, the tile loops
   // below fully unrolled), group_item_tiles(G) for G >= 4 (J.parts workgroups per group)
-  constexpr int NTW = G >= 4 ? group_item_tiles(G) : NT;
+  constexpr int NTW = group_item_tiles(G);
+  constexpr bool SPLIT = NTW < NT;   // the group's member tiles over J.parts workgroups
   constexpr int RS = (S == 3) ? 32 : 16;
-  constexpr int kTileUnroll = G >= 4 ? 1 : NT;
+  constexpr int kTileUnroll = SPLIT ? 1 : NT;
   using TileMask = typename std::conditional<(NT > 32), uint64_t, uint32_t>::type;
-  const int bin = G >= 4 ? item / J.parts : item;
-  const int k0 = G >= 4 ? (item % J.parts) * NTW : 0;
+  const int bin = SPLIT ? item / J.parts : item;
+  const int k0 = SPLIT ? (item % J.parts) * NTW : 0;
   const int k1 = k0 + NTW;
   const int gx = bin % J.GX, gy = bin / J.GX;
   const int ox = gx * G * kTile, oy = gy * G * kTile;
