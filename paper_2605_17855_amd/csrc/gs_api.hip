@@ -154,13 +154,14 @@ Workspace carve(void *ws, int64_t n, uint64_t capacity) {
   return w;
 }
 
-// Workgroups per bin.  With 4x4 and 8x8 groups each workgroup takes one row of the group's
-// member tiles: a 1080p frame has 510 (4x4) or 135 (8x8) groups, too few to fill 256 CUs
-// with one workgroup per group walking 16 or 64 tiles.  2x2 groups with rows built in the
-// group frame take one row of two member tiles per workgroup as well: ~2,000 workgroups each
-// walking four tiles left most CUs idle while the last, densest groups finished.  Every tile
-// still sees its rows in the same order with the same arithmetic, so the image does not
-// depend on the split.
+// Workgroups per bin.  Groups whose rows are built per member tile take one workgroup per
+// member tile (group_item_tiles): a 1080p frame has only 510 (4x4) or 135 (8x8) groups, and a
+// workgroup walking a row of member tiles kept their states in private memory.  2x2 groups
+// with rows built in the group frame take one row of two member tiles per workgroup, blended
+// side by side by eight waves (or in turn by four, with three pieces per row): one workgroup
+// per group left most CUs idle while the last, densest groups finished.  Every tile still
+// sees its rows in the same order with the same arithmetic, so the image does not depend on
+// the split.
 int raster_parts(const gs_options &o) {
   if (o.precision == GS_PREC_FP32) return 1;
   if (o.group == 2 && !(o.flags & GS_OPT_TILE_ROWS)) return 2;   // the group-frame rows
