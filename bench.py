@@ -117,6 +117,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-backward", action="store_true", help="skip the backward-pass timing")
     ap.add_argument("--no-pipelined", action="store_true", help="skip the two-frames-in-flight rate")
+    ap.add_argument("--no-device-counts", action="store_true",
+                    help="skip the frames without the host wait (eager and graph-replayed)")
     ap.add_argument("--no-all-rows", action="store_true",
                     help="skip the MFMA run without quadrant culling (its launches share the kernel's name)")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving workload")
@@ -223,6 +225,53 @@ def pipelined_frames(gs, torch, ds, cams, n, opt, steps, warmup, inflight=2):
         frame(i)
     torch.cuda.synchronize()
     return steps / (time.perf_counter() - t0)
+
+
+def device_count_frames(gs, torch, ds, cams, n, capacity, opt_kwargs, steps, warmup, ref_image):
+    """Frames/s of the frame without the host wait (GS_OPT_DEVICE_COUNTS: the bin sort reads its
+    counts on the device, grids sized for `capacity`), run eagerly and replayed from captured
+    HIP graphs: one graph per pose (the camera is a kernel argument), all over the same buffers.
+    `capacity` holds every pose's entries; the replay of pose 0 is compared with `ref_image`, the
+    frame that waits for its counts."""
+    opt = gs.options(device_counts=True, **opt_kwargs)
+    rend = gs.Renderer(n, 1920, 1080, group=opt.group, capacity=capacity)
+
+    def frame(cam):
+        gs.gs_preprocess(ds, cam, opt, rend.proj, rend.ws)
+        gs.gs_bin_sort(rend.proj, cam, opt, rend.bins, rend.ws)
+        gs.gs_rasterize(rend.proj, rend.bins, cam, opt, rend.image)
+
+    for i in range(warmup):
+        frame(cams[i % len(cams)])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        frame(cams[i % len(cams)])
+    torch.cuda.synchronize()
+    eager = steps / (time.perf_counter() - t0)
+    poses = min(steps, len(cams))
+    graphs = []
+    for i in range(poses):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            frame(cams[i])
+        graphs.append(g)
+    torch.cuda.synchronize()
+    graphs[0].replay()
+    torch.cuda.synchronize()
+    same = bool(ref_image is not None and np.array_equal(rend.image.double().cpu().numpy(), ref_image))
+    fits = gs.entry_count(rend.proj) <= capacity
+    for i in range(warmup):
+        graphs[i % poses].replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        graphs[i % poses].replay()
+    torch.cuda.synchronize()
+    replay = steps / (time.perf_counter() - t0)
+    return {"option": "GS_OPT_DEVICE_COUNTS", "capacity": capacity, "eager_frames_per_s": eager,
+            "graph_frames_per_s": replay, "graphs": poses, "pose0_image_equals_host_count_frame": same,
+            "last_frame_fits_capacity": bool(fits)}
 
 
 def work_units(gs, torch, ds, cams, rend, opt_kwargs, steps):
@@ -610,6 +659,12 @@ def main():
         pipelined = {"frames_in_flight": 2, "frames_per_s": pipelined_frames(gs, torch, ds, cams, sc.n, opt,
                                                                               args.steps, args.warmup)}
 
+    device_counts = None
+    if not args.no_device_counts:
+        log("timing the frame without the host wait, eager and replayed from captured graphs")
+        device_counts = device_count_frames(gs, torch, ds, cams, sc.n, rend.bins.capacity, okw, args.steps,
+                                            args.warmup, first_img)
+
     all_rows = None
     if args.precision != "fp32" and not args.no_all_rows:
         # the same frames with quadrant culling off (every row in every quadrant, as the FP32
@@ -699,6 +754,7 @@ def main():
         "raster_speedup_vs_fp32": (compare["raster_avg_ms"] / float(np.mean(raster_ms))) if compare else None,
         "mfma_all_rows": all_rows,
         "pipelined": pipelined,
+        "device_counts": device_counts,
         "raster_speedup_vs_fp32_all_rows": (compare["raster_avg_ms"] / all_rows["raster_avg_ms"])
         if (compare and all_rows) else None,
         "roofline": roofline,

@@ -25,7 +25,8 @@
  *   - All device work is enqueued on `stream` (a hipStream_t passed as void*,
  *     NULL = the null stream).  gs_bin_sort and gs_render wait once on the host for
  *     the entry and visible counts (a bounded poll of gs_projected.host_counts, which
- *     the device writes, or a stream synchronization).  Every other call is asynchronous.
+ *     the device writes, or a stream synchronization), unless GS_OPT_DEVICE_COUNTS is set.
+ *     Every other call is asynchronous.
  *     An error return of gs_bin_sort or gs_render after work was enqueued first waits
  *     for that work, so the caller may reuse every buffer at once.
  *   - Errors are return codes.  Arguments are validated on the host before any
@@ -97,7 +98,17 @@ enum {
    * always use per-tile rows).  The image equals the 1x1 one in exact arithmetic
    * and to the split operands' rounding in FP16/BF16.  This flag makes every member tile build its
    * rows in its own frame instead, which gives images bit-identical to group 1. */
-  GS_OPT_TILE_ROWS = 4u
+  GS_OPT_TILE_ROWS = 4u,
+  /* gs_bin_sort and gs_render without the host wait: the kernels that follow the count scan read
+   * the entry and visible counts from device memory, and their grids are sized for
+   * bins->capacity entries (those past the count return at once), so the call only enqueues work
+   * and can be captured into a HIP graph (every launch is a kernel; no copy, memset or wait).
+   * *n_keys is not written (n_keys may be NULL).  The entry count K stays on the device, in
+   * proj->offset[n].  If K exceeds bins->capacity (a capacity overflow) no entry is binned: every
+   * range is (0, 0) and the image is the background; the caller checks proj->offset[n] <=
+   * capacity once the stream has run and renders again with larger buffers.  Images and bins
+   * equal those of the call with the host wait.  bins->capacity must be below 2^32. */
+  GS_OPT_DEVICE_COUNTS = 8u
 };
 
 typedef struct {
@@ -180,7 +191,9 @@ gs_status gs_preprocess(const gs_scene *scene, const gs_camera *cam, const gs_op
  * Also sorts proj->order[0 .. visible count) by depth (ties by Gaussian index).
  * *n_keys (host) receives the entry count; the call waits once on the host, for that count.
  * If it exceeds bins->capacity nothing is written to *bins and GS_ERR_CAPACITY is returned
- * (proj->order may already be in depth order): grow the buffers and call again. */
+ * (proj->order may already be in depth order): grow the buffers and call again.
+ * With GS_OPT_DEVICE_COUNTS the call does not wait and the overflow is found on the device
+ * (see the flag). */
 gs_status gs_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam, const gs_options *opt,
                       const gs_bins *bins, uint64_t *n_keys, void *ws, size_t ws_bytes, void *stream);
 

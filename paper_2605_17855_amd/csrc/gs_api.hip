@@ -70,7 +70,7 @@ gs_status check_options(const gs_options *o) {
   }
   if (o->aux_flags & ~(uint32_t)(GS_AUX_TFINAL | GS_AUX_WSUM | GS_AUX_NEVAL | GS_AUX_NBLEND | GS_AUX_LAST))
     return fail(GS_ERR_INVALID_ARG, "aux_flags 0x%x", o->aux_flags);
-  if (o->flags & ~(uint32_t)(GS_OPT_TIGHT | GS_OPT_ALL_ROWS | GS_OPT_TILE_ROWS))
+  if (o->flags & ~(uint32_t)(GS_OPT_TIGHT | GS_OPT_ALL_ROWS | GS_OPT_TILE_ROWS | GS_OPT_DEVICE_COUNTS))
     return fail(GS_ERR_INVALID_ARG, "flags 0x%x", o->flags);
   for (int i = 0; i < 3; ++i)
     if (!std::isfinite(o->bg[i])) return fail(GS_ERR_INVALID_ARG, "background non-finite");
@@ -106,6 +106,17 @@ gs_status check_bins(const gs_bins *b, int group, bool need_keys) {
   return GS_OK;
 }
 
+// n_keys is required unless the counts stay on the device, whose 32-bit entry count needs a
+// capacity below 2^32.
+gs_status check_device_counts(const gs_options *o, const gs_bins *b, const uint64_t *n_keys) {
+  if (!(o->flags & GS_OPT_DEVICE_COUNTS)) {
+    if (!n_keys) return fail(GS_ERR_INVALID_ARG, "n_keys is NULL");
+  } else if (b->capacity >= (1ull << 32)) {
+    return fail(GS_ERR_UNSUPPORTED, "capacity %llu >= 2^32 with device counts", (unsigned long long)b->capacity);
+  }
+  return GS_OK;
+}
+
 struct Workspace {
   void *scan;            // scan partials of the count scan
   void *sort;            // radix sort scratch (per-tile digit counts and totals; depth, then bin sort)
@@ -120,7 +131,8 @@ struct Workspace {
   uint32_t *bval_alt;    // (capacity)
   uint32_t *bfirst;      // first Gaussian (depth rank) of each 1,024-entry block (capacity / 1,024 + 1)
   uint64_t nbfirst;
-  uint64_t *counts;      // {K, V}: packed for the one device-to-host copy
+  uint64_t *counts;      // {K, V}: packed for the one device-to-host copy; then the entry count of
+                         // the device-count bin sort (low 32 bits of counts[2])
   size_t total;
 };
 
@@ -149,7 +161,7 @@ Workspace carve(void *ws, int64_t n, uint64_t capacity) {
   w.bval_alt = reinterpret_cast<uint32_t *>(take((size_t)capacity * 4));
   w.nbfirst = capacity / gsi::kFirstsBlock + 1;
   w.bfirst = reinterpret_cast<uint32_t *>(take(w.nbfirst * 4));
-  w.counts = reinterpret_cast<uint64_t *>(take(2 * sizeof(uint64_t)));
+  w.counts = reinterpret_cast<uint64_t *>(take(3 * sizeof(uint64_t)));
   w.total = off;
   return w;
 }
@@ -223,11 +235,15 @@ gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
   // to the caller's pinned host memory (and to the workspace).  The depth sort (which reads V on
   // the device and also places each Gaussian's first entry) is enqueued before the host polls
   // for them, so the GPU keeps working while the host waits.
-  volatile uint64_t *hkv = proj->host_counts;
+  // With the counts read on the device (GS_OPT_DEVICE_COUNTS) there is no host wait: the bin
+  // sort's grids are sized for the capacity and its kernels take K (0 on overflow) and V from
+  // the workspace.
+  const bool dev_counts = (opt->flags & GS_OPT_DEVICE_COUNTS) != 0;
+  volatile uint64_t *hkv = dev_counts ? nullptr : proj->host_counts;
   if (hkv) hkv[0] = hkv[1] = ~0ull;   // overwritten by the kernel
   const uint64_t nn = (uint64_t)(n > 0 ? n : 1);
   GS_HIP(gsi::launch_depth_keys(proj->order, reinterpret_cast<const float4 *>(proj->rgb), proj->n_visible, nn, w.dkey,
-                                proj->offset + n, w.counts, proj->host_counts, w.sort, st));
+                                proj->offset + n, w.counts, const_cast<uint64_t *>(hkv), bins->capacity, w.sort, st));
   // from here on the kernel may be writing the counts: every exit waits for the stream first
   // depth bits in depth order, and the first entry of each Gaussian in that order (a single
   // Gaussian needs no sort: a gathered scan of its count)
@@ -239,6 +255,15 @@ gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
   if (e != hipSuccess) {
     (void)hipStreamSynchronize(st);
     return hip_fail(e, "depth sort");
+  }
+  if (dev_counts) {
+    const uint32_t *kdev = reinterpret_cast<const uint32_t *>(w.counts + 2);
+    GS_HIP(gsi::bin_and_sort(proj->order, dkeys, w.dpos, nn > 1 ? w.bfirst : nullptr, (uint32_t)nn, bins->capacity,
+                             proj->n_visible, kdev, proj->rect, proj->xy, proj->conic,
+                             (opt->flags & GS_OPT_TIGHT) != 0, g, w.bkey, w.bval, w.bkey_alt, w.bval_alt,
+                             bins->ranges, opt->group > 1 ? bins->masks : nullptr, bins->vals, bins->keys, w.sort,
+                             st));
+    return GS_OK;
   }
   uint64_t kv[2] = {0, 0};
   if (!hkv || !poll_counts(hkv, kv)) {
@@ -267,7 +292,8 @@ gs_status do_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
   }
   // one thread per entry (also clears the bin ranges), the bin passes (the last one places the
   // Gaussian indices and 64-bit keys), the ranges and masks
-  GS_HIP(gsi::bin_and_sort(proj->order, dkeys, w.dpos, nn > 1 ? w.bfirst : nullptr, V, K, proj->rect, proj->xy, proj->conic,
+  GS_HIP(gsi::bin_and_sort(proj->order, dkeys, w.dpos, nn > 1 ? w.bfirst : nullptr, V, K, nullptr, nullptr, proj->rect,
+                           proj->xy, proj->conic,
                            (opt->flags & GS_OPT_TIGHT) != 0, g, w.bkey, w.bval, w.bkey_alt, w.bval_alt, bins->ranges,
                            opt->group > 1 ? bins->masks : nullptr, bins->vals, bins->keys, w.sort, st));
   return GS_OK;
@@ -431,7 +457,7 @@ gs_status gs_bin_sort(const gs_projected *proj, int64_t n, const gs_camera *cam,
   if ((s = check_camera(cam)) || (s = check_options(opt)) || (s = check_projected(proj, n, true)) ||
       (s = check_bins(bins, opt->group, true)))
     return s;
-  if (!n_keys) return fail(GS_ERR_INVALID_ARG, "n_keys is NULL");
+  if ((s = check_device_counts(opt, bins, n_keys))) return s;
   const size_t need = carve(nullptr, n, bins->capacity).total;
   if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID_ARG, "workspace %zu bytes, need %zu", ws_bytes, need);
   return do_bin_sort(proj, n, cam, opt, bins, n_keys, ws, static_cast<hipStream_t>(stream));
@@ -490,7 +516,7 @@ gs_status gs_render(const gs_scene *scene, const gs_camera *cam, const gs_option
     return s;
   if (!image) return fail(GS_ERR_INVALID_ARG, "image is NULL");
   if (opt->aux_flags && !aux) return fail(GS_ERR_INVALID_ARG, "aux is NULL with aux_flags set");
-  if (!n_keys) return fail(GS_ERR_INVALID_ARG, "n_keys is NULL");
+  if ((s = check_device_counts(opt, bins, n_keys))) return s;
   const size_t need = carve(nullptr, scene->n, bins->capacity).total;
   if (!ws || ws_bytes < need) return fail(GS_ERR_INVALID_ARG, "workspace %zu bytes, need %zu", ws_bytes, need);
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -234,11 +234,13 @@ size_t depth_sort_tmp_bytes(uint64_t n_max);
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
                       int hi, void *tmp, hipStream_t st, bool *in_alt);
 // keys[i] = depth bits of order[i] for i < *nvis (n_max >= *nvis), counts = {*K, *nvis} (the
-// entry and visible counts side by side, for one copy to the host), and in tmp the first depth
-// pass's per-tile digit counts for the sort_depth call that follows (same n_max and tmp).
+// entry and visible counts side by side, for one copy to the host), the low 32 bits of counts[2]
+// = *K if *K <= capacity else 0 (the entry count the device-count bin sort takes), and in tmp
+// the first depth pass's per-tile digit counts for the sort_depth call that follows (same n_max
+// and tmp).
 hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max,
-                             uint32_t *keys, const uint64_t *K, uint64_t *counts, uint64_t *host_counts, void *tmp,
-                             hipStream_t st);
+                             uint32_t *keys, const uint64_t *K, uint64_t *counts, uint64_t *host_counts,
+                             uint64_t capacity, void *tmp, hipStream_t st);
 // Sorts the visible list order[0..*nvis) stably by the depth keys in keys (four passes over
 // bits [0, 31): depths are positive), using keys_alt, vals_alt and vals_b (n_max each) as
 // scratch; the sorted depth keys end in keys.  The last pass also writes dpos[i] = the
@@ -256,8 +258,10 @@ hipError_t sort_depth(uint32_t *order, const uint32_t *nvis, uint64_t n_max, uin
 // for group > 1, the membership masks.  With tight (opacity-aware culling) entries follow the
 // culled spans of tight_row_span.  vals and keys must not alias the four work arrays.
 // block_first (or nullptr): the first Gaussian of every 1,024-entry block (sort_depth).
+// V_dev and K_dev (both or neither): the visible and entry counts read on the device, V and K
+// then upper bounds of them (grids sized for K; the surplus workgroups return at once).
 hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint64_t *dpos, const uint32_t *block_first,
-                        uint32_t V, uint64_t K,
+                        uint32_t V, uint64_t K, const uint32_t *V_dev, const uint32_t *K_dev,
                         const uint16_t *rect, const double *xy, const float *conic, bool tight, const Grid &g,
                         uint32_t *bkey, uint32_t *bval, uint32_t *bkey_alt, uint32_t *bval_alt, uint32_t *ranges,
                         void *masks, uint32_t *vals, uint64_t *keys, void *tmp, hipStream_t st);

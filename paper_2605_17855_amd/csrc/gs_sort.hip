@@ -427,8 +427,8 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis,
                                                        uint32_t *keys, const uint64_t *K, uint64_t *counts,
-                                                       uint64_t *host_counts, int nbits0, uint32_t *dcounts,
-                                                       uint32_t tiles) {
+                                                       uint64_t *host_counts, uint64_t capacity, int nbits0,
+                                                       uint32_t *dcounts, uint32_t tiles) {
   constexpr int kSortTile = SortTile<R>::kTile;
   __shared__ uint32_t h[kDigits];
   const uint32_t V = *nvis;
@@ -436,6 +436,8 @@ __global__ __launch_bounds__(kBlock) void k_depth_keys(const uint32_t *order, co
     const uint64_t k = *K;
     counts[0] = k;
     counts[1] = V;
+    // the entry count of a bin sort that reads it on the device: 0 (nothing binned) on overflow
+    reinterpret_cast<uint32_t *>(counts + 2)[0] = k <= capacity ? (uint32_t)k : 0u;
     if (host_counts) {     // the caller's pinned host memory, polled by the host
       host_counts[0] = k;
       host_counts[1] = V;
@@ -549,8 +551,9 @@ struct FirstCounts {
 // entry.
 template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const uint64_t *dpos,
-                                                    const uint32_t *block_first, uint32_t nvis,
-                                                    uint64_t K, const ushort4 *rect, int G, int GX,
+                                                    const uint32_t *block_first, uint32_t nvis_host,
+                                                    uint64_t K_host, const uint32_t *nvis_dev, const uint32_t *K_dev,
+                                                    const ushort4 *rect, int G, int GX,
                                                     uint32_t *bin_keys, uint32_t *vals, uint32_t *ranges,
                                                     uint64_t nranges, FirstCounts fc) {
   constexpr int NI = ITEMS / kBlock;
@@ -558,6 +561,8 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
   __shared__ uint32_t s_g[ITEMS];
   __shared__ uint32_t s_first;
   __shared__ uint32_t h[kDigits];
+  const uint32_t nvis = (uint32_t)count_of(nvis_host, nvis_dev);
+  const uint64_t K = count_of(K_host, K_dev);
   const uint32_t tile = xcd_sort_tile(blockIdx.x, (K + ITEMS - 1) / ITEMS);
   const uint64_t e0 = (uint64_t)tile * ITEMS;
   clear_ranges(ranges, nranges);
@@ -602,15 +607,18 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
 // dependent loads and prefix pass are not.)
 template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order, const uint64_t *dpos,
-                                                          const uint32_t *block_first, uint32_t nvis,
-                                                          uint64_t K, const ushort4 *rect, const double2 *xy,
-                                                          const float4 *conic, int TX, int G, int GX,
-                                                          uint32_t *bin_keys, uint32_t *vals, uint32_t *ranges,
-                                                          uint64_t nranges, FirstCounts fc) {
+                                                          const uint32_t *block_first, uint32_t nvis_host,
+                                                          uint64_t K_host, const uint32_t *nvis_dev,
+                                                          const uint32_t *K_dev, const ushort4 *rect,
+                                                          const double2 *xy, const float4 *conic, int TX, int G,
+                                                          int GX, uint32_t *bin_keys, uint32_t *vals,
+                                                          uint32_t *ranges, uint64_t nranges, FirstCounts fc) {
   __shared__ uint64_t s_pos[ITEMS + 1];
   __shared__ uint32_t s_g[ITEMS];
   __shared__ uint32_t s_first;
   __shared__ uint32_t h[kDigits];
+  const uint32_t nvis = (uint32_t)count_of(nvis_host, nvis_dev);
+  const uint64_t K = count_of(K_host, K_dev);
   const uint32_t tile = xcd_sort_tile(blockIdx.x, (K + ITEMS - 1) / ITEMS);
   const uint64_t e0 = (uint64_t)tile * ITEMS;
   const int lane = threadIdx.x & 63;
@@ -729,10 +737,12 @@ __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order,
 // gathers, so several round trips are in flight at once.
 constexpr int kRangeItems = 4;
 
-__global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n,
-                                                   const uint32_t *order, const uint32_t *dkeys, const ushort4 *rect,
-                                                   const double2 *xy, const float4 *conic, int tight, int G, int GX,
-                                                   uint32_t *vals, uint32_t *ranges, void *masks, uint64_t *keys) {
+__global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n_host,
+                                                   const uint32_t *n_dev, const uint32_t *order, const uint32_t *dkeys,
+                                                   const ushort4 *rect, const double2 *xy, const float4 *conic,
+                                                   int tight, int G, int GX, uint32_t *vals, uint32_t *ranges,
+                                                   void *masks, uint64_t *keys) {
+  const uint64_t n = count_of(n_host, n_dev);
   const uint64_t base = (uint64_t)blockIdx.x * kBlock * kRangeItems + threadIdx.x;
   uint32_t bin[kRangeItems], prev[kRangeItems], next[kRangeItems], r[kRangeItems];
 #pragma unroll
@@ -785,9 +795,11 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, con
 
 // Bin ranges and (group > 1) membership masks once the last bin pass has placed the final
 // Gaussian indices and 64-bit keys: only the sorted bin keys are read for the ranges.
-__global__ __launch_bounds__(kBlock) void k_ranges_final(const uint32_t *bin_keys, uint64_t n, const uint32_t *vals,
+__global__ __launch_bounds__(kBlock) void k_ranges_final(const uint32_t *bin_keys, uint64_t n_host,
+                                                         const uint32_t *n_dev, const uint32_t *vals,
                                                          const ushort4 *rect, const double2 *xy, const float4 *conic,
                                                          int tight, int G, int GX, uint32_t *ranges, void *masks) {
+  const uint64_t n = count_of(n_host, n_dev);
   const uint64_t base = (uint64_t)blockIdx.x * kBlock * kRangeItems + threadIdx.x;
   uint32_t bin[kRangeItems], prev[kRangeItems], next[kRangeItems];
 #pragma unroll
@@ -997,18 +1009,18 @@ size_t radix_tmp_bytes(uint64_t n) {
 size_t depth_sort_tmp_bytes(uint64_t n) { return depth_tmp(nullptr, sort_tiles(n ? n : 1)).bytes; }
 
 hipError_t launch_depth_keys(const uint32_t *order, const float4 *rgb, const uint32_t *nvis, uint64_t n_max,
-                             uint32_t *keys, const uint64_t *K, uint64_t *counts, uint64_t *host_counts, void *tmp,
-                             hipStream_t st) {
+                             uint32_t *keys, const uint64_t *K, uint64_t *counts, uint64_t *host_counts,
+                             uint64_t capacity, void *tmp, hipStream_t st) {
   // one workgroup per tile of the depth sort that follows (sort_depth, same n_max): its first
   // pass's digit counts are taken here
   const uint32_t tiles = (uint32_t)sort_tiles(n_max ? n_max : 1);
   uint32_t *dcounts = depth_tmp(tmp, tiles).counts;
   if (n_max <= kSmallSort)
     hipLaunchKernelGGL((k_depth_keys<kSmallR>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, order, rgb, nvis, keys,
-                       K, counts, host_counts, kDepthWidth, dcounts, tiles);
+                       K, counts, host_counts, capacity, kDepthWidth, dcounts, tiles);
   else
     hipLaunchKernelGGL((k_depth_keys<kLargeR>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, order, rgb, nvis, keys,
-                       K, counts, host_counts, kDepthWidth, dcounts, tiles);
+                       K, counts, host_counts, capacity, kDepthWidth, dcounts, tiles);
   return hipGetLastError();
 }
 
@@ -1024,7 +1036,7 @@ hipError_t sort_depth(uint32_t *order, const uint32_t *nvis, uint64_t n_max, uin
 }
 
 hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint64_t *dpos, const uint32_t *block_first,
-                        uint32_t V, uint64_t K,
+                        uint32_t V, uint64_t K, const uint32_t *V_dev, const uint32_t *K_dev,
                         const uint16_t *rect, const double *xy, const float *conic, bool tight, const Grid &g,
                         uint32_t *bkey, uint32_t *bval, uint32_t *bkey_alt, uint32_t *bval_alt, uint32_t *ranges,
                         void *masks, uint32_t *vals, uint64_t *keys, void *tmp, hipStream_t st) {
@@ -1034,7 +1046,9 @@ hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint
   const double2 *m2 = reinterpret_cast<const double2 *>(xy);
   const float4 *c4 = reinterpret_cast<const float4 *>(conic);
   const int hi = bits_for((uint64_t)g.nbins);
-  // with a sort to follow (K > 1), the binning takes its first pass's digit counts
+  // with a sort to follow (K > 1), the binning takes its first pass's digit counts; with the
+  // counts on the device, K is the bound that sizes the grids and picks the tile size, as the
+  // sort's own passes do
   const bool large = K > kSmallSort;
   const unsigned tiles = grid_for(K, large ? SortTile<kLargeR>::kTile : SortTile<kSmallR>::kTile);
   const FirstCounts fc{K > 1 ? static_cast<uint32_t *>(tmp) : nullptr, pass_width(0, hi), tiles};
@@ -1042,21 +1056,21 @@ hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint
   if (tight) {
     if (large)
       hipLaunchKernelGGL((k_binning_tight<SortTile<kLargeR>::kTile>), dim3(grid), dim3(kBlock), 0, st, order, dpos,
-                         block_first, V, K, r4, m2, c4, g.TX, g.G, g.GX, bkey, bval, ranges, nranges, fc);
+                         block_first, V, K, V_dev, K_dev, r4, m2, c4, g.TX, g.G, g.GX, bkey, bval, ranges, nranges, fc);
     else
       hipLaunchKernelGGL((k_binning_tight<SortTile<kSmallR>::kTile>), dim3(grid), dim3(kBlock), 0, st, order, dpos,
-                         block_first, V, K, r4, m2, c4, g.TX, g.G, g.GX, bkey, bval, ranges, nranges, fc);
+                         block_first, V, K, V_dev, K_dev, r4, m2, c4, g.TX, g.G, g.GX, bkey, bval, ranges, nranges, fc);
   } else {
     if (large)
       hipLaunchKernelGGL((k_binning<SortTile<kLargeR>::kTile>), dim3(grid), dim3(kBlock), 0, st, order, dpos,
-                         block_first, V, K, r4, g.G, g.GX, bkey, bval, ranges, nranges, fc);
+                         block_first, V, K, V_dev, K_dev, r4, g.G, g.GX, bkey, bval, ranges, nranges, fc);
     else
       hipLaunchKernelGGL((k_binning<SortTile<kSmallR>::kTile>), dim3(grid), dim3(kBlock), 0, st, order, dpos,
-                         block_first, V, K, r4, g.G, g.GX, bkey, bval, ranges, nranges, fc);
+                         block_first, V, K, V_dev, K_dev, r4, g.G, g.GX, bkey, bval, ranges, nranges, fc);
   }
   if (K <= 1) {
     // nothing to sort: the single entry's index, key and range directly
-    hipLaunchKernelGGL(k_ranges, dim3(1), dim3(kBlock), 0, st, bkey, bval, K, order, dkeys, r4, m2, c4,
+    hipLaunchKernelGGL(k_ranges, dim3(1), dim3(kBlock), 0, st, bkey, bval, K, K_dev, order, dkeys, r4, m2, c4,
                        tight ? 1 : 0, g.G, g.GX, vals, ranges, masks, keys);
     return hipGetLastError();
   }
@@ -1064,12 +1078,12 @@ hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint
   const FinalOut fin{order, dkeys, vals, keys};
   // the bin passes ping-pong between (bkey, bval) and (bkey_alt, bval_alt); the last one writes
   // the final indices and 64-bit keys, and its sorted bin keys land in kf
-  hipError_t e = radix_passes_t<uint32_t>(bkey, bval, bkey_alt, bval_alt, K, nullptr, 0, hi, tmp, st, &in_alt, &fin,
+  hipError_t e = radix_passes_t<uint32_t>(bkey, bval, bkey_alt, bval_alt, K, K_dev, 0, hi, tmp, st, &in_alt, &fin,
                                           true);
   if (e != hipSuccess) return e;
   const uint32_t *kf = in_alt ? bkey_alt : bkey;
   hipLaunchKernelGGL(k_ranges_final, dim3(grid_for(K, (uint64_t)kBlock * kRangeItems)), dim3(kBlock), 0, st, kf, K,
-                     vals, r4, m2, c4, tight ? 1 : 0, g.G, g.GX, ranges, masks);
+                     K_dev, vals, r4, m2, c4, tight ? 1 : 0, g.G, g.GX, ranges, masks);
   return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ GS_AUX_TFINAL, GS_AUX_WSUM, GS_AUX_NEVAL, GS_AUX_NBLEND, GS_AUX_LAST = 1, 2, 4, 
 GS_OPT_TIGHT = 1
 GS_OPT_ALL_ROWS = 2
 GS_OPT_TILE_ROWS = 4
+GS_OPT_DEVICE_COUNTS = 8
 GS_BATCH_COUNTER_BYTES = 512          # work counters of one batched launch (include/gs.h)
 BATCH_COUNTER_WORDS = GS_BATCH_COUNTER_BYTES // 4
 PRECISIONS = {"fp32": GS_PREC_FP32, "fp16": GS_PREC_FP16_MFMA, "bf16": GS_PREC_BF16_MFMA}
@@ -131,7 +132,8 @@ def _check(status: int):
 
 
 def options(group: int = 1, precision="fp32", splits: int = 2, bg=(0.0, 0.0, 0.0), aux_flags: int = 0,
-            tight: bool = False, all_rows: bool = False, tile_rows: bool = False) -> gs_options:
+            tight: bool = False, all_rows: bool = False, tile_rows: bool = False,
+            device_counts: bool = False) -> gs_options:
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     o = gs_options()
@@ -139,7 +141,7 @@ def options(group: int = 1, precision="fp32", splits: int = 2, bg=(0.0, 0.0, 0.0
     o.bg = (C.c_float * 3)(*bg)
     o.aux_flags = aux_flags
     o.flags = (GS_OPT_TIGHT if tight else 0) | (GS_OPT_ALL_ROWS if all_rows else 0) | \
-        (GS_OPT_TILE_ROWS if tile_rows else 0)
+        (GS_OPT_TILE_ROWS if tile_rows else 0) | (GS_OPT_DEVICE_COUNTS if device_counts else 0)
     return o
 
 
@@ -252,8 +254,9 @@ def gs_preprocess(scene: DeviceScene, cam, opt: gs_options, proj: Projected, ws,
                                _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
 
 
-def gs_bin_sort(proj: Projected, cam, opt: gs_options, bins: Bins, ws, stream=None) -> int:
-    """Returns the entry count; raises GsError (status GS_ERR_CAPACITY with .n_keys) when bins is too small."""
+def gs_bin_sort(proj: Projected, cam, opt: gs_options, bins: Bins, ws, stream=None):
+    """Returns the entry count; raises GsError (status GS_ERR_CAPACITY with .n_keys) when bins is too small.
+    With GS_OPT_DEVICE_COUNTS returns None: the count stays on the device (entry_count)."""
     n_keys = C.c_uint64(0)
     st = lib().gs_bin_sort(C.byref(proj.struct), proj.n, C.byref(camera(cam)), C.byref(opt), C.byref(bins.struct),
                            C.byref(n_keys), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream))
@@ -261,7 +264,13 @@ def gs_bin_sort(proj: Projected, cam, opt: gs_options, bins: Bins, ws, stream=No
         err = GsError(st, lib().gs_last_error().decode())
         err.n_keys = int(n_keys.value)
         raise err
-    return int(n_keys.value)
+    return None if opt.flags & GS_OPT_DEVICE_COUNTS else int(n_keys.value)
+
+
+def entry_count(proj: Projected) -> int:
+    """The entry count that the last gs_preprocess/gs_render left on the device (offset[n]);
+    reads device memory, so it waits for the work before it on the current stream."""
+    return int(proj.offset[proj.n].item())
 
 
 def gs_rasterize(proj: Projected, bins: Bins, cam, opt: gs_options, image, aux=None, stream=None):
@@ -306,8 +315,10 @@ def gs_rasterize_backward_mfma(proj: Projected, bins: Bins, cam, opt: gs_options
 
 
 def gs_render(scene: DeviceScene, cam, opt: gs_options, proj: Projected, bins: Bins, image, aux, ws,
-              stream=None) -> int:
-    """Returns the entry count; raises GsError (status GS_ERR_CAPACITY with .n_keys) when bins is too small."""
+              stream=None):
+    """Returns the entry count; raises GsError (status GS_ERR_CAPACITY with .n_keys) when bins is too small.
+    With GS_OPT_DEVICE_COUNTS returns None without waiting: the count stays on the device (entry_count),
+    and a count above bins.capacity leaves the background image."""
     n_keys = C.c_uint64(0)
     st = lib().gs_render(C.byref(scene.struct), C.byref(camera(cam)), C.byref(opt), C.byref(proj.struct),
                          C.byref(bins.struct), _ptr(image), _ptr(aux), C.byref(n_keys), _ptr(ws),
@@ -316,7 +327,7 @@ def gs_render(scene: DeviceScene, cam, opt: gs_options, proj: Projected, bins: B
         err = GsError(st, lib().gs_last_error().decode())
         err.n_keys = int(n_keys.value)
         raise err
-    return int(n_keys.value)
+    return None if opt.flags & GS_OPT_DEVICE_COUNTS else int(n_keys.value)
 
 
 def gs_radix_sort_u64(keys, vals, lo_bit: int, hi_bit: int, ws=None, stream=None):
@@ -396,6 +407,10 @@ class Renderer:
         npl = aux_planes(opt.aux_flags)
         if npl and (self.aux is None or self.aux.shape[0] != npl):
             self.aux = torch.empty((npl, self.height, self.width), dtype=torch.float32, device=self.device)
+        if opt.flags & GS_OPT_DEVICE_COUNTS:
+            # no host wait and so no retry: the caller checks entry_count(self.proj) <= capacity
+            return gs_render(scene, cam, opt, self.proj, self.bins, self.image, self.aux if npl else None,
+                             self.ws, stream)
         for _ in range(2):
             try:
                 return gs_render(scene, cam, opt, self.proj, self.bins, self.image,

@@ -55,7 +55,7 @@ def test_num_bins():
     ("splits", 0, gs.GS_ERR_INVALID_ARG),
     ("aux_flags", 32, gs.GS_ERR_INVALID_ARG),
     ("aux_flags", 64, gs.GS_ERR_INVALID_ARG),
-    ("flags", 8, gs.GS_ERR_INVALID_ARG),
+    ("flags", 16, gs.GS_ERR_INVALID_ARG),
     ("flags", 0x80000000, gs.GS_ERR_INVALID_ARG),
 ])
 def test_rasterize_rejects_bad_options(field, value, status):
@@ -252,3 +252,37 @@ def test_python_constants_match_header():
     assert int(defs["GS_BATCH_COUNTER_BYTES"]) == gs.GS_BATCH_COUNTER_BYTES
     assert gs.BATCH_COUNTER_WORDS * 4 == gs.GS_BATCH_COUNTER_BYTES
     assert int(defs["GS_NOALLOC_SCRATCH_BYTES"]) >= gs.GS_BATCH_COUNTER_BYTES
+    # the option flags
+    enum = dict(re.findall(r"\b(GS_OPT_[A-Z_]+) = (\d+)u", hdr))
+    assert {k: int(v) for k, v in enum.items()} == {k: getattr(gs, k) for k in enum}
+    assert set(enum) == {"GS_OPT_TIGHT", "GS_OPT_ALL_ROWS", "GS_OPT_TILE_ROWS", "GS_OPT_DEVICE_COUNTS"}
+
+
+def test_device_counts_argument_checks():
+    """With GS_OPT_DEVICE_COUNTS n_keys may be NULL (the count stays on the device) and the
+    capacity must fit the device's 32-bit entry count; without it n_keys is required.  All of it
+    is decided on the host, before any HIP call (a tiny workspace is the first check after)."""
+    L = gs.lib()
+    c = _cam()
+    p = gs.gs_projected(1, 1, 1, 1, 1, 1, 1, 1)
+    s = gs.gs_scene(10, 0, 0, 1, 1, 1, 1, 16)
+    ws = C.c_void_p(1)
+    dev = gs.options(device_counts=True)
+    assert dev.flags == gs.GS_OPT_DEVICE_COUNTS
+    b = gs.gs_bins(1, 1, 1, 1 << 20, 1)
+    nk = C.c_uint64(0)
+    for opt, n_keys, status, msg in ((gs.options(), None, gs.GS_ERR_INVALID_ARG, b"n_keys"),
+                                     (dev, None, gs.GS_ERR_INVALID_ARG, b"workspace"),
+                                     (dev, C.byref(nk), gs.GS_ERR_INVALID_ARG, b"workspace")):
+        assert L.gs_bin_sort(C.byref(p), 10, C.byref(c), C.byref(opt), C.byref(b), n_keys, ws, 8,
+                             None) == status
+        assert msg in L.gs_last_error()
+        assert L.gs_render(C.byref(s), C.byref(c), C.byref(opt), C.byref(p), C.byref(b), C.c_void_p(1), None, n_keys,
+                           ws, 8, None) == status
+        assert msg in L.gs_last_error()
+    big = gs.gs_bins(1, 1, 1, 1 << 32, 1)
+    assert L.gs_bin_sort(C.byref(p), 10, C.byref(c), C.byref(dev), C.byref(big), None, ws, 8,
+                         None) == gs.GS_ERR_UNSUPPORTED
+    assert b"2^32" in L.gs_last_error()
+    assert L.gs_render(C.byref(s), C.byref(c), C.byref(dev), C.byref(p), C.byref(big), C.c_void_p(1), None, None, ws,
+                       8, None) == gs.GS_ERR_UNSUPPORTED
