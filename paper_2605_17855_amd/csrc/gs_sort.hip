@@ -215,6 +215,7 @@ struct FinalOut {
   const uint32_t *dkeys;   // their depth bits
   uint32_t *vals;          // Gaussian index of each sorted entry
   uint64_t *keys;          // 64-bit key of each sorted entry
+  uint32_t bin_mask;       // the bin bits of a sort key (above them: the member-tile rectangle)
 };
 
 // First entries of the depth sort's last pass (WEIGHTED): dpos[p] = the entries of the
@@ -409,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const KT *kin, const u
       const uint32_t p = gbase[d] + (i - bstart[d]);
       kout[p] = k;
       fin.vals[p] = gi[r];
-      fin.keys[p] = ((uint64_t)(uint32_t)k << 32) | dk[r];
+      fin.keys[p] = ((uint64_t)((uint32_t)k & fin.bin_mask) << 32) | dk[r];
     }
     return;
   }
@@ -499,6 +500,25 @@ __device__ __forceinline__ void clear_ranges(uint32_t *ranges, uint64_t nranges)
     ranges[i] = 0u;
 }
 
+// Member tiles of a group entry without culling: the rectangle of the footprint's tiles inside
+// group (gx, gy), [x0, x1) x [y0, y1) in member-tile units.  The binning packs it (x0, x1 - 1,
+// y0, y1 - 1 at 3 bits each) above the bin bits of the entry's sort key, which the bin passes
+// carry along without sorting on them, so the ranges kernel expands it into the mask without
+// gathering the Gaussian's rect again.
+constexpr int kRectDescBits = 12;
+__device__ __forceinline__ uint32_t rect_desc(ushort4 rc, int G, int gx, int gy) {
+  const int x0 = max((int)rc.x - gx * G, 0), x1 = min((int)rc.z - gx * G, G);
+  const int y0 = max((int)rc.y - gy * G, 0), y1 = min((int)rc.w - gy * G, G);
+  return (uint32_t)x0 | (uint32_t)(x1 - 1) << 3 | (uint32_t)y0 << 6 | (uint32_t)(y1 - 1) << 9;
+}
+__device__ __forceinline__ uint64_t rect_desc_mask(uint32_t desc, int G) {
+  const int x0 = desc & 7, x1 = (int)((desc >> 3) & 7) + 1, y0 = (desc >> 6) & 7, y1 = (int)((desc >> 9) & 7) + 1;
+  const uint64_t row = ((1ull << (x1 - x0)) - 1ull) << x0;   // x1 - x0 <= G <= 8
+  uint64_t m = 0;
+  for (int ly = y0; ly < y1; ++ly) m |= row << (ly * G);
+  return m;
+}
+
 // Stages the first-entry offsets of the Gaussians that own entries [e0, e0 + ITEMS) into
 // s_pos[0..span] (s_pos[l] = dpos[first + l]) and, with s_g, their indices s_g[l] = order[first + l].
 template <int ITEMS>
@@ -553,7 +573,7 @@ template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const uint64_t *dpos,
                                                     const uint32_t *block_first, uint32_t nvis_host,
                                                     uint64_t K_host, const uint32_t *nvis_dev, const uint32_t *K_dev,
-                                                    const ushort4 *rect, int G, int GX,
+                                                    const ushort4 *rect, int G, int GX, int desc_shift,
                                                     uint32_t *bin_keys, uint32_t *vals, uint32_t *ranges,
                                                     uint64_t nranges, FirstCounts fc) {
   constexpr int NI = ITEMS / kBlock;
@@ -589,7 +609,8 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
       const int wdt = gx1 - gx0 + 1;
       const int gy = gy0 + (int)(j / (uint32_t)wdt), gx = gx0 + (int)(j % (uint32_t)wdt);
       const uint32_t bin = (uint32_t)(gy * GX + gx);
-      bin_keys[e] = bin;
+      // (desc_shift > 0: group bins without culling, the member-tile rectangle above the bin bits)
+      bin_keys[e] = desc_shift ? bin | rect_desc(r[it], G, gx, gy) << desc_shift : bin;
       vals[e] = first + l[it];   // the Gaussian's rank in depth order; the last sort pass turns it into its index
       if (fc.counts) atomicAdd(&h[bin & dmask], 1u);
     }
@@ -740,9 +761,10 @@ constexpr int kRangeItems = 4;
 __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, const uint32_t *ranks, uint64_t n_host,
                                                    const uint32_t *n_dev, const uint32_t *order, const uint32_t *dkeys,
                                                    const ushort4 *rect, const double2 *xy, const float4 *conic,
-                                                   int tight, int G, int GX, uint32_t *vals, uint32_t *ranges,
-                                                   void *masks, uint64_t *keys) {
+                                                   int tight, int G, int GX, int desc_shift, uint32_t *vals,
+                                                   uint32_t *ranges, void *masks, uint64_t *keys) {
   const uint64_t n = count_of(n_host, n_dev);
+  const uint32_t bmask = desc_shift ? (1u << desc_shift) - 1u : ~0u;
   const uint64_t base = (uint64_t)blockIdx.x * kBlock * kRangeItems + threadIdx.x;
   uint32_t bin[kRangeItems], prev[kRangeItems], next[kRangeItems], r[kRangeItems];
 #pragma unroll
@@ -750,8 +772,8 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, con
     const uint64_t i = base + (uint64_t)j * kBlock;
     const bool in = i < n;
     bin[j] = in ? bin_keys[i] : 0u;
-    prev[j] = (in && i > 0) ? bin_keys[i - 1] : 0xFFFFFFFFu;
-    next[j] = (in && i + 1 < n) ? bin_keys[i + 1] : 0xFFFFFFFFu;
+    prev[j] = (in && i > 0) ? bin_keys[i - 1] & bmask : 0xFFFFFFFFu;
+    next[j] = (in && i + 1 < n) ? bin_keys[i + 1] & bmask : 0xFFFFFFFFu;
     r[j] = in ? ranks[i] : 0u;
   }
   uint32_t g[kRangeItems], d[kRangeItems];
@@ -765,7 +787,7 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, con
   for (int j = 0; j < kRangeItems; ++j) {
     const uint64_t i = base + (uint64_t)j * kBlock;
     if (i >= n) break;
-    const uint32_t b = bin[j];
+    const uint32_t b = bin[j] & bmask;
     if (prev[j] != b) ranges[2 * (uint64_t)b] = (uint32_t)i;
     if (next[j] != b) ranges[2 * (uint64_t)b + 1] = (uint32_t)(i + 1);
     keys[i] = ((uint64_t)b << 32) | d[j];
@@ -774,7 +796,9 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, con
       const ushort4 rc = rect[g[j]];
       const int gx = (int)(b % (uint32_t)GX), gy = (int)(b / (uint32_t)GX);
       uint64_t m = 0;
-      if (tight) {
+      if (desc_shift) {
+        m = rect_desc_mask(bin[j] >> desc_shift, G);
+      } else if (tight) {
         // member tiles the alpha-cut ellipse meets
         const double2 mu = xy[g[j]];
         const float4 co = conic[g[j]];
@@ -798,8 +822,10 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, con
 __global__ __launch_bounds__(kBlock) void k_ranges_final(const uint32_t *bin_keys, uint64_t n_host,
                                                          const uint32_t *n_dev, const uint32_t *vals,
                                                          const ushort4 *rect, const double2 *xy, const float4 *conic,
-                                                         int tight, int G, int GX, uint32_t *ranges, void *masks) {
+                                                         int tight, int G, int GX, int desc_shift, uint32_t *ranges,
+                                                         void *masks) {
   const uint64_t n = count_of(n_host, n_dev);
+  const uint32_t bmask = desc_shift ? (1u << desc_shift) - 1u : ~0u;
   const uint64_t base = (uint64_t)blockIdx.x * kBlock * kRangeItems + threadIdx.x;
   uint32_t bin[kRangeItems], prev[kRangeItems], next[kRangeItems];
 #pragma unroll
@@ -807,17 +833,21 @@ __global__ __launch_bounds__(kBlock) void k_ranges_final(const uint32_t *bin_key
     const uint64_t i = base + (uint64_t)j * kBlock;
     const bool in = i < n;
     bin[j] = in ? bin_keys[i] : 0u;
-    prev[j] = (in && i > 0) ? bin_keys[i - 1] : 0xFFFFFFFFu;
-    next[j] = (in && i + 1 < n) ? bin_keys[i + 1] : 0xFFFFFFFFu;
+    prev[j] = (in && i > 0) ? bin_keys[i - 1] & bmask : 0xFFFFFFFFu;
+    next[j] = (in && i + 1 < n) ? bin_keys[i + 1] & bmask : 0xFFFFFFFFu;
   }
 #pragma unroll
   for (int j = 0; j < kRangeItems; ++j) {
     const uint64_t i = base + (uint64_t)j * kBlock;
     if (i >= n) break;
-    const uint32_t b = bin[j];
+    const uint32_t b = bin[j] & bmask;
     if (prev[j] != b) ranges[2 * (uint64_t)b] = (uint32_t)i;
     if (next[j] != b) ranges[2 * (uint64_t)b + 1] = (uint32_t)(i + 1);
-    if (G > 1 && masks) {
+    if (G > 1 && masks && desc_shift) {
+      const uint64_t m = rect_desc_mask(bin[j] >> desc_shift, G);
+      if (G == 8) static_cast<uint64_t *>(masks)[i] = m;
+      else static_cast<uint16_t *>(masks)[i] = (uint16_t)m;
+    } else if (G > 1 && masks) {
       const uint32_t g = vals[i];
       const ushort4 rc = rect[g];
       const int gx = (int)(b % (uint32_t)GX), gy = (int)(b / (uint32_t)GX);
@@ -1046,6 +1076,9 @@ hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint
   const double2 *m2 = reinterpret_cast<const double2 *>(xy);
   const float4 *c4 = reinterpret_cast<const float4 *>(conic);
   const int hi = bits_for((uint64_t)g.nbins);
+  // group bins without culling carry their member-tile rectangle above the bin bits (they fit:
+  // at most 2^18 groups); culled groups' masks are computed from the Gaussians' records again
+  const int desc_shift = (g.G > 1 && !tight && masks && hi + kRectDescBits <= 32) ? hi : 0;
   // with a sort to follow (K > 1), the binning takes its first pass's digit counts; with the
   // counts on the device, K is the bound that sizes the grids and picks the tile size, as the
   // sort's own passes do
@@ -1063,19 +1096,21 @@ hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint
   } else {
     if (large)
       hipLaunchKernelGGL((k_binning<SortTile<kLargeR>::kTile>), dim3(grid), dim3(kBlock), 0, st, order, dpos,
-                         block_first, V, K, V_dev, K_dev, r4, g.G, g.GX, bkey, bval, ranges, nranges, fc);
+                         block_first, V, K, V_dev, K_dev, r4, g.G, g.GX, desc_shift, bkey, bval, ranges, nranges,
+                         fc);
     else
       hipLaunchKernelGGL((k_binning<SortTile<kSmallR>::kTile>), dim3(grid), dim3(kBlock), 0, st, order, dpos,
-                         block_first, V, K, V_dev, K_dev, r4, g.G, g.GX, bkey, bval, ranges, nranges, fc);
+                         block_first, V, K, V_dev, K_dev, r4, g.G, g.GX, desc_shift, bkey, bval, ranges, nranges,
+                         fc);
   }
   if (K <= 1) {
     // nothing to sort: the single entry's index, key and range directly
     hipLaunchKernelGGL(k_ranges, dim3(1), dim3(kBlock), 0, st, bkey, bval, K, K_dev, order, dkeys, r4, m2, c4,
-                       tight ? 1 : 0, g.G, g.GX, vals, ranges, masks, keys);
+                       tight ? 1 : 0, g.G, g.GX, desc_shift, vals, ranges, masks, keys);
     return hipGetLastError();
   }
   bool in_alt = false;
-  const FinalOut fin{order, dkeys, vals, keys};
+  const FinalOut fin{order, dkeys, vals, keys, desc_shift ? (1u << desc_shift) - 1u : ~0u};
   // the bin passes ping-pong between (bkey, bval) and (bkey_alt, bval_alt); the last one writes
   // the final indices and 64-bit keys, and its sorted bin keys land in kf
   hipError_t e = radix_passes_t<uint32_t>(bkey, bval, bkey_alt, bval_alt, K, K_dev, 0, hi, tmp, st, &in_alt, &fin,
@@ -1083,7 +1118,7 @@ hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint
   if (e != hipSuccess) return e;
   const uint32_t *kf = in_alt ? bkey_alt : bkey;
   hipLaunchKernelGGL(k_ranges_final, dim3(grid_for(K, (uint64_t)kBlock * kRangeItems)), dim3(kBlock), 0, st, kf, K,
-                     K_dev, vals, r4, m2, c4, tight ? 1 : 0, g.G, g.GX, ranges, masks);
+                     K_dev, vals, r4, m2, c4, tight ? 1 : 0, g.G, g.GX, desc_shift, ranges, masks);
   return hipGetLastError();
 }
 
