@@ -167,8 +167,9 @@ Workspace carve(void *ws, int64_t n, uint64_t capacity) {
 }
 
 // Workgroups per bin.  Groups whose rows are built per member tile take one workgroup per
-// member tile (group_item_tiles): a 1080p frame has only 510 (4x4) or 135 (8x8) groups, and a
-// workgroup walking a row of member tiles kept their states in private memory.  2x2 groups
+// member tile: a 1080p frame has only 510 (4x4) or 135 (8x8) groups, and a workgroup walking
+// a row of member tiles kept their states in private memory (1M Gaussians at 1080p, FP16:
+// raster 4x4 284 -> 142 us, 8x8 883 -> 250 us with one tile per workgroup).  2x2 groups
 // with rows built in the group frame take one row of two member tiles per workgroup, blended
 // side by side by eight waves (or in turn by four, with three pieces per row): one workgroup
 // per group left most CUs idle while the last, densest groups finished.  Every tile still
@@ -177,7 +178,7 @@ Workspace carve(void *ws, int64_t n, uint64_t capacity) {
 int raster_parts(const gs_options &o) {
   if (o.precision == GS_PREC_FP32) return 1;
   if (o.group == 2 && !(o.flags & GS_OPT_TILE_ROWS)) return 2;   // the group-frame rows
-  return o.group * o.group / gsi::group_item_tiles(o.group);
+  return o.group * o.group;
 }
 
 gsi::RasterJob make_job(const gs_projected &p, const gs_bins &b, const gsi::Grid &g, float *image, float *aux,

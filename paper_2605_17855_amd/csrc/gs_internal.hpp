@@ -9,12 +9,6 @@
 namespace gsi {
 
 constexpr int kTile = 16;            // tile side in pixels (Background: 16x16 tiles)
-// Member tiles per MFMA rasterizer work item of a group with rows built per member tile: the
-// group's G x G tiles are split over G * G / this many workgroups.  One: each workgroup scans
-// the group's list for the entries of its own tile, whose state then stays in registers (1M
-// Gaussians at 1080p, FP16: raster 4x4 284 -> 182 us and 8x8 883 -> 517 us with two tiles, from
-// one row of G tiles per workgroup, whose states lived in private memory).
-constexpr int group_item_tiles(int /*G*/) { return 1; }
 constexpr int kBlock = 256;          // threads per workgroup for every kernel here
 constexpr float kAlphaMax = 0.99f;   // opacity clamp
 constexpr float kTMin = 1e-4f;       // transmittance stop

@@ -159,15 +159,16 @@ __device__ __forceinline__ uint32_t quad_mask(float u, float v, float a, float b
 }
 
 // Compacts, in order, the rows [0, nrows) whose quadrant mask holds this wave's bit into the
-// wave's own list; returns its length (uniform).
-__device__ __forceinline__ int wave_list(const uint8_t *qm, int nrows, uint8_t *wl) {
+// wave's own list; returns its length (uniform).  IDX holds a row index (uint8_t up to 256 rows).
+template <typename IDX>
+__device__ __forceinline__ int wave_list(const uint8_t *qm, int nrows, IDX *wl) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int n = 0;
   for (int r0 = 0; r0 < nrows; r0 += 64) {
     const int r = r0 + lane;
     const bool in = r < nrows && ((qm[r] >> w) & 1u);
     const uint64_t b = __ballot(in);
-    if (in) wl[n + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u))] = (uint8_t)r;
+    if (in) wl[n + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u))] = (IDX)r;
     n += __popcll(b);
   }
   // the list is written and read by lanes of this wave only

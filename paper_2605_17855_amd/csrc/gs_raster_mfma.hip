@@ -27,11 +27,12 @@
 // Rows are staged for the whole tile; each wave then runs only the rows whose alpha can reach
 // the cut somewhere in its quadrant (quadrant culling, below), gathered from LDS by index.
 //
-// Grouping.  For G > 1 a chunk of the group's list is staged in LDS once; for every member
-// tile the entries whose mask bit is set are compacted in order (ballot + mbcnt) and their
-// A rows are built in that tile's frame.  Per-tile blending state lives in registers.  Each
-// tile sees the same Gaussians in the same order with the same arithmetic as with G = 1, so
-// grouped and ungrouped images are bit-identical.
+// Grouping.  2x2 groups build each entry's row once, in the frame of the group, for all
+// their member tiles (below).  Larger groups (and 2x2 with per-tile rows) give each member
+// tile a workgroup that walks the group's list: the entries whose mask bit is set are
+// compacted in order (ballot + mbcnt) and their A rows built in that tile's frame, so each
+// tile sees the same Gaussians in the same order with the same arithmetic as with G = 1 and
+// those images are bit-identical to ungrouped ones.
 #include <type_traits>
 
 #include "gs_mfma.hpp"
@@ -126,25 +127,33 @@ __device__ __forceinline__ void process_rows(const uint16_t *sA, const float *sc
   }
 }
 
-template <int G, int S>
+// LDS of the 1x1-tile rasterizer: one chunk of kBlock rows (the chunk barrier orders each
+// build after the last read).
+template <int S>
 struct MfmaShared {
-  static constexpr int NT = G * G;
   static constexpr int RS = (S == 3) ? 32 : 16;
-  // one buffer where a workgroup has one tile (G = 1, and 4x4 and 8x8 groups split to one member
-  // tile per workgroup: the chunk barrier orders each build after the last read); several
-  // member tiles double-buffer, so one member tile's rows are built while another's are read
-  static constexpr int NBUF = group_item_tiles(G) == 1 ? 1 : 2;
-  __align__(16) uint16_t A[NBUF][kBlock * RS];
-  float col[NBUF][3][kBlock];       // colour planes r, g, b of the staged rows
-  double2 r0[G > 1 ? kBlock : 1];  // FP64 centre; every tile rounds its own offset
-  float4 r1[G > 1 ? kBlock : 1];   // (a, b, c, ln o)
-  float4 r2[G > 1 ? kBlock : 1];   // (r, g, b, -)
-  __align__(16) uint32_t wcnt[2][NT][4];   // by chunk parity: a wave may stage chunk c+1 while
-                                   // another still reads chunk c's counts
+  __align__(16) uint16_t A[kBlock * RS];
+  float col[3][kBlock];            // colour planes r, g, b of the staged rows
   uint32_t alive[2][4];
-  uint8_t qm[NBUF][kBlock];        // quadrant masks of the staged rows
+  uint8_t qm[kBlock];              // quadrant masks of the staged rows
   uint8_t wl[4][kBlock];           // each wave's row list (wave-private)
   float4 wc[4][32];                // each wave's colours of its current block (wave-private)
+};
+
+// LDS of one member tile of a group with per-tile rows: a buffer of CAP rows that fills over
+// several steps through the group's list before it is blended (448 rows keep the layout under
+// 26 KB: six workgroups per CU).
+template <int S>
+struct MfmaTileShared {
+  static constexpr int RS = (S == 3) ? 32 : 16;
+  static constexpr int CAP = (S == 3) ? kBlock : 448;
+  __align__(16) uint16_t A[CAP * RS];
+  float col[3][CAP];
+  __align__(16) uint32_t wcnt[2][4];   // this tile's entries per wave in a step, by step parity
+  uint32_t alive[4];
+  uint8_t qm[CAP];
+  uint16_t wl[4][CAP];
+  float4 wc[4][32];
 };
 
 // ---- grouped tiles with the Gaussian-side rows built once per group -----------------------
@@ -342,184 +351,170 @@ __device__ __forceinline__ void raster_bin_mfma_group(const RasterJob &J, const 
   }
 }
 
-// Renders work item `item` of job J (one workgroup): member tiles
-// [part * G^2 / parts, (part + 1) * G^2 / parts) (row-major) of bin item / parts, part =
-// item % parts.  Shared by the single-image and batched kernels.
-template <int G, int PREC, int S, bool AUX>
-__device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const RasterParams &P, int item,
-                                                MfmaShared<G, S> &sm, short8 B0, short8 B1, short8 B20,
-                                                short8 B21) {
-  constexpr int NT = G * G;
-  // member tiles per workgroup: all of them for G <= 2 (one workgroup per bin, the tile loops
-  // below fully unrolled), group_item_tiles(G) for G >= 4 (J.parts workgroups per group)
-  constexpr int NTW = group_item_tiles(G);
-  constexpr bool SPLIT = NTW < NT;   // the group's member tiles over J.parts workgroups
-  constexpr int RS = (S == 3) ? 32 : 16;
-  constexpr int kTileUnroll = SPLIT ? 1 : NT;
-  using TileMask = typename std::conditional<(NT > 32), uint64_t, uint32_t>::type;
-  const int bin = SPLIT ? item / J.parts : item;
-  const int k0 = SPLIT ? (item % J.parts) * NTW : 0;
-  const int k1 = k0 + NTW;
-  const int gx = bin % J.GX, gy = bin / J.GX;
-  const int ox = gx * G * kTile, oy = gy * G * kTile;
+// Writes pixel (xx, yy) (nothing past the image): colour over the background by the final
+// transmittance and the auxiliary planes.  rows_done: the entries of the tile's list consumed.
+template <bool AUX>
+__device__ __forceinline__ void write_tile(const RasterJob &J, const RasterParams &P, int xx, int yy,
+                                           const TileState &sk, uint32_t rows_done) {
+  if (xx >= J.W || yy >= J.H) return;
+  const int64_t HW = (int64_t)J.W * J.H;
+  const int64_t pix = (int64_t)yy * J.W + xx;
+  J.image[pix] = sk.C0 + sk.T * P.bg[0];
+  J.image[HW + pix] = sk.C1 + sk.T * P.bg[1];
+  J.image[2 * HW + pix] = sk.C2 + sk.T * P.bg[2];
+  if (AUX) {
+    int plane = 0;
+    if (P.aux_flags & GS_AUX_TFINAL) J.aux[(plane++) * HW + pix] = sk.T;
+    if (P.aux_flags & GS_AUX_WSUM) J.aux[(plane++) * HW + pix] = sk.W;
+    if (P.aux_flags & GS_AUX_NEVAL) {
+      const bool stopped = sk.cut == INFINITY;
+      J.aux[(plane++) * HW + pix] = (float)(stopped ? sk.nstop : rows_done);
+    }
+    if (P.aux_flags & GS_AUX_NBLEND) J.aux[(plane++) * HW + pix] = (float)sk.nblend;
+    if (P.aux_flags & GS_AUX_LAST) J.aux[(plane++) * HW + pix] = (float)sk.last;
+  }
+}
+
+// Renders bin `bin` of job J (one workgroup, 1x1 tiles): the tile's list chunk by chunk.
+template <int PREC, int S, bool AUX>
+__device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const RasterParams &P, int bin, MfmaShared<S> &sm,
+                                                short8 B0, short8 B1, short8 B20, short8 B21) {
+  constexpr int RS = MfmaShared<S>::RS;
+  const int ox = (bin % J.GX) * kTile, oy = (bin / J.GX) * kTile;
   const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int qx0 = (w & 1) * 8, qy0 = (w >> 1) * 8;
-  const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
-
-  // the workgroup's member tiles k0 + i (G >= 4: private memory, one register copy per step)
-  TileState st[NTW];
-  TileMask alive_mask = 0;       // uniform: member tiles with pixels still blending (bit k)
-  uint32_t rows_done[NTW];       // uniform: entries of each tile consumed so far
-#pragma unroll kTileUnroll
-  for (int i = 0; i < NTW; ++i) {
-    const int k = k0 + i;
-    const int tx0 = ox + (k % G) * kTile, ty0 = oy + (k / G) * kTile;
-    const bool inside = (tx0 + px < J.W) && (ty0 + py < J.H);
-    st[i].T = 1.0f; st[i].C0 = st[i].C1 = st[i].C2 = 0.0f; st[i].W = 0.0f;
-    st[i].cut = inside ? kCutLog2 : INFINITY;
-    st[i].nstop = 0; st[i].nblend = 0; st[i].last = 0;
-    rows_done[i] = 0;
-    if (tx0 < J.W && ty0 < J.H) alive_mask |= (TileMask)1 << k;
-  }
-
-  int it = 0;          // processing steps so far (LDS double-buffer parity)
-  int cp = 0;          // chunk parity
-  int last_k = -1;     // tile processed in the previous step, if its alive bits are pending
-  for (uint32_t cs = start; cs < end && alive_mask; cs += kBlock) {
+  const int px = (w & 1) * 8 + (lane & 7), py = (w >> 1) * 8 + (lane >> 3);
+  TileState st;
+  st.T = 1.0f; st.C0 = st.C1 = st.C2 = 0.0f; st.W = 0.0f;
+  st.cut = (ox + px < J.W) && (oy + py < J.H) ? kCutLog2 : INFINITY;
+  st.nstop = 0; st.nblend = 0; st.last = 0;
+  uint32_t rows_done = 0;   // uniform: entries consumed so far
+  int it = 0;
+  for (uint32_t cs = start; cs < end; cs += kBlock) {
     const int cnt = (int)min((uint32_t)kBlock, end - cs);
-    if (G == 1) {
-      constexpr int buf = 0;
-      if (it > 0) {
-        // every wave is done with the previous chunk (single buffer) and has posted whether
-        // its pixels are still blending
-        __syncthreads();
-        const uint32_t any = sm.alive[(it - 1) & 1][0] | sm.alive[(it - 1) & 1][1] | sm.alive[(it - 1) & 1][2] |
-                             sm.alive[(it - 1) & 1][3];
-        if (!any) break;
-      }
-      if (t < cnt) {
-        const uint32_t e = cs + t;
-        const uint32_t g = J.vals[e];
-        const double2 m = J.xy[g];
-        const float4 co = J.conic[g];
-        const float4 cl = J.rgb[g];
-        const float u = (float)(m.x - ((double)ox + 8.5)), v = (float)(m.y - ((double)oy + 8.5));
-        const float l2o = log2_opacity(co.w);
-        build_row<PREC, S>(&sm.A[buf][t * RS], u, v, co.x, co.y, co.z, l2o);
-        sm.col[buf][0][t] = cl.x;
-        sm.col[buf][1][t] = cl.y;
-        sm.col[buf][2][t] = cl.z;
-        sm.qm[buf][t] = P.all_rows ? (uint8_t)0xF : (uint8_t)quad_mask(u, v, co.x, co.y, co.z, l2o);
-      }
+    if (it > 0) {
+      // every wave is done with the previous chunk (single buffer) and has posted whether its
+      // pixels are still blending
       __syncthreads();
-      const int nw = wave_list(sm.qm[buf], cnt, sm.wl[w]);
-      process_rows<PREC, S, AUX>(sm.A[buf], &sm.col[buf][0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, st[0],
-                                 rows_done[0]);
-      rows_done[0] += cnt;
-      const uint64_t bal = __ballot(st[0].cut != INFINITY);
-      if (lane == 0) sm.alive[it & 1][w] = bal != 0;
-      ++it;
-    } else {
-      // stage the chunk once for every member tile (Algorithm 1: load the chunk into shared memory)
-      TileMask mk = 0;
-      if (t < cnt) {
-        const uint32_t e = cs + t;
-        mk = G == 8 ? (TileMask) static_cast<const uint64_t *>(J.masks)[e]
-                    : (TileMask) static_cast<const uint16_t *>(J.masks)[e];
-        // the records of entries that reach one of this workgroup's member tiles (the others'
-        // rows are never built here)
-        const TileMask mine = NTW == NT ? ~(TileMask)0 : (TileMask)(((TileMask)1 << NTW) - 1u) << k0;
-        if (mk & mine) {
-          const uint32_t g = J.vals[e];
-          const double2 m = J.xy[g];
-          const float4 co = J.conic[g];
-          const float4 cl = J.rgb[g];
-          sm.r0[t] = m;
-          sm.r1[t] = make_float4(co.x, co.y, co.z, log2_opacity(co.w));
-          sm.r2[t] = cl;
-        }
-      }
-#pragma unroll kTileUnroll
-      for (int k = k0; k < k1; ++k) {
-        const uint64_t bk = __ballot((mk >> k) & 1u);
-        if (lane == 0) sm.wcnt[cp][k][w] = (uint32_t)__popcll(bk);
-      }
-      __syncthreads();
-      if (last_k >= 0) {
-        const uint32_t any = sm.alive[(it - 1) & 1][0] | sm.alive[(it - 1) & 1][1] | sm.alive[(it - 1) & 1][2] |
-                             sm.alive[(it - 1) & 1][3];
-        if (!any) alive_mask &= ~((TileMask)1 << last_k);
-        last_k = -1;
-      }
-      // G = 2: fully unrolled, all state in registers.  G = 4 and 8: one copy of the step for the
-      // workgroup's member tiles (one tile: its state stays in registers)
-#pragma unroll kTileUnroll
-      for (int k = k0; k < k1; ++k) {
-        const uint4 ck = *reinterpret_cast<const uint4 *>(sm.wcnt[cp][k]);
-        const uint32_t nk = ck.x + ck.y + ck.z + ck.w;
-        if (!((alive_mask >> k) & 1u) || nk == 0) continue;
-        const int buf = MfmaShared<G, S>::NBUF == 1 ? 0 : (it & 1);
-        // tile-frame origin in absolute pixels, exactly as the G = 1 path forms it
-        const double fx0 = (double)(ox + (k % G) * kTile) + 8.5, fy0 = (double)(oy + (k / G) * kTile) + 8.5;
-        const uint64_t bk = __ballot((mk >> k) & 1u);
-        if ((mk >> k) & 1u) {
-          const uint32_t woff = (w > 0 ? ck.x : 0u) + (w > 1 ? ck.y : 0u) + (w > 2 ? ck.z : 0u);
-          const uint32_t pos =
-              woff + __builtin_amdgcn_mbcnt_hi((uint32_t)(bk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bk, 0u));
-          const double2 r0 = sm.r0[t];
-          const float4 r1 = sm.r1[t];
-          const float u = (float)(r0.x - fx0), v = (float)(r0.y - fy0);
-          build_row<PREC, S>(&sm.A[buf][pos * RS], u, v, r1.x, r1.y, r1.z, r1.w);
-          const float4 r2 = sm.r2[t];
-          sm.col[buf][0][pos] = r2.x;
-          sm.col[buf][1][pos] = r2.y;
-          sm.col[buf][2][pos] = r2.z;
-          sm.qm[buf][pos] = P.all_rows ? (uint8_t)0xF : (uint8_t)quad_mask(u, v, r1.x, r1.y, r1.z, r1.w);
-        }
-        __syncthreads();
-        if (last_k >= 0) {
-          const uint32_t any = sm.alive[(it - 1) & 1][0] | sm.alive[(it - 1) & 1][1] | sm.alive[(it - 1) & 1][2] |
-                               sm.alive[(it - 1) & 1][3];
-          if (!any) alive_mask &= ~((TileMask)1 << last_k);
-        }
-        TileState cur = st[k - k0];
-        const int nw = wave_list(sm.qm[buf], (int)nk, sm.wl[w]);
-        process_rows<PREC, S, AUX>(sm.A[buf], &sm.col[buf][0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, cur,
-                                   rows_done[k - k0]);
-        st[k - k0] = cur;
-        rows_done[k - k0] += nk;
-        const uint64_t ab = __ballot(cur.cut != INFINITY);
-        if (lane == 0) sm.alive[it & 1][w] = ab != 0;
-        last_k = k;
-        ++it;
-      }
-      cp ^= 1;
+      const uint32_t any = sm.alive[(it - 1) & 1][0] | sm.alive[(it - 1) & 1][1] | sm.alive[(it - 1) & 1][2] |
+                           sm.alive[(it - 1) & 1][3];
+      if (!any) break;
     }
+    if (t < cnt) {
+      const uint32_t e = cs + t;
+      const uint32_t g = J.vals[e];
+      const double2 m = J.xy[g];
+      const float4 co = J.conic[g];
+      const float4 cl = J.rgb[g];
+      const float u = (float)(m.x - ((double)ox + 8.5)), v = (float)(m.y - ((double)oy + 8.5));
+      const float l2o = log2_opacity(co.w);
+      build_row<PREC, S>(&sm.A[t * RS], u, v, co.x, co.y, co.z, l2o);
+      sm.col[0][t] = cl.x;
+      sm.col[1][t] = cl.y;
+      sm.col[2][t] = cl.z;
+      sm.qm[t] = P.all_rows ? (uint8_t)0xF : (uint8_t)quad_mask(u, v, co.x, co.y, co.z, l2o);
+    }
+    __syncthreads();
+    const int nw = wave_list(sm.qm, cnt, sm.wl[w]);
+    process_rows<PREC, S, AUX>(sm.A, &sm.col[0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, st, rows_done);
+    rows_done += cnt;
+    const uint64_t bal = __ballot(st.cut != INFINITY);
+    if (lane == 0) sm.alive[it & 1][w] = bal != 0;
+    ++it;
   }
+  write_tile<AUX>(J, P, ox + px, oy + py, st, rows_done);
+}
 
-  const int64_t HW = (int64_t)J.W * J.H;
-#pragma unroll kTileUnroll
-  for (int k = k0; k < k1; ++k) {
-    const int xx = ox + (k % G) * kTile + px, yy = oy + (k / G) * kTile + py;
-    if (xx >= J.W || yy >= J.H) continue;
-    const int64_t pix = (int64_t)yy * J.W + xx;
-    const TileState &sk = st[k - k0];
-    J.image[pix] = sk.C0 + sk.T * P.bg[0];
-    J.image[HW + pix] = sk.C1 + sk.T * P.bg[1];
-    J.image[2 * HW + pix] = sk.C2 + sk.T * P.bg[2];
-    if (AUX) {
-      int plane = 0;
-      if (P.aux_flags & GS_AUX_TFINAL) J.aux[(plane++) * HW + pix] = sk.T;
-      if (P.aux_flags & GS_AUX_WSUM) J.aux[(plane++) * HW + pix] = sk.W;
-      if (P.aux_flags & GS_AUX_NEVAL) {
-        const bool stopped = sk.cut == INFINITY;
-        J.aux[(plane++) * HW + pix] = (float)(stopped ? sk.nstop : rows_done[k - k0]);
+// Renders member tile item % parts (row-major in the group) of group item / parts, for groups
+// whose rows are built per member tile (one workgroup per member tile).  The workgroup walks
+// the group's list in steps of kBlock entries; in each step the entries whose mask holds its
+// tile (compacted in list order by ballot) have their rows built in the tile's own frame and
+// appended to the row buffer.  The buffer is blended once it could not take another step, and
+// at the end, so MFMA blocks fill up across steps (a 4x4 or 8x8 tile takes only a share of its
+// group's entries) and a step costs one barrier.  The tile sees the rows of its 1x1 list in
+// the same order with the same arithmetic, so the image is bit-identical to 1x1 tiles.
+template <int G, int PREC, int S, bool AUX>
+__device__ __forceinline__ void raster_member_tile(const RasterJob &J, const RasterParams &P, int item,
+                                                   MfmaTileShared<S> &sm, short8 B0, short8 B1, short8 B20,
+                                                   short8 B21) {
+  constexpr int RS = MfmaTileShared<S>::RS, CAP = MfmaTileShared<S>::CAP;
+  const int bin = item / J.parts, k = item % J.parts;
+  const int tx0 = ((bin % J.GX) * G + k % G) * kTile, ty0 = ((bin / J.GX) * G + k / G) * kTile;
+  if (tx0 >= J.W || ty0 >= J.H) return;   // a member tile past the image (uniform)
+  const uint32_t start = J.ranges[2 * bin], end = J.ranges[2 * bin + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int px = (w & 1) * 8 + (lane & 7), py = (w >> 1) * 8 + (lane >> 3);
+  // tile-frame origin in absolute pixels, exactly as the 1x1 path forms it
+  const double fx0 = (double)tx0 + 8.5, fy0 = (double)ty0 + 8.5;
+  TileState st;
+  st.T = 1.0f; st.C0 = st.C1 = st.C2 = 0.0f; st.W = 0.0f;
+  st.cut = (tx0 + px < J.W) && (ty0 + py < J.H) ? kCutLog2 : INFINITY;
+  st.nstop = 0; st.nblend = 0; st.last = 0;
+  uint32_t rows_done = 0;   // uniform: rows of this tile blended so far (list position of buffer row 0)
+  int filled = 0;           // uniform: rows in the buffer
+  int cp = 0;
+  bool live = true;
+  auto blend = [&]() {
+    const int nw = wave_list(sm.qm, filled, sm.wl[w]);
+    process_rows<PREC, S, AUX, CAP, uint16_t>(sm.A, &sm.col[0][0], sm.wl[w], nw, sm.wc[w], B0, B1, B20, B21, st,
+                                              rows_done);
+    rows_done += (uint32_t)filled;
+    filled = 0;
+  };
+  for (uint32_t cs = start; cs < end; cs += kBlock) {
+    if (filled > CAP - kBlock) {
+      // the rows of the earlier steps are in place; then every wave is done reading them and
+      // has posted whether its pixels are still blending
+      __syncthreads();
+      blend();
+      const uint64_t ab = __ballot(st.cut != INFINITY);
+      if (lane == 0) sm.alive[w] = ab != 0;
+      __syncthreads();
+      if (!(sm.alive[0] | sm.alive[1] | sm.alive[2] | sm.alive[3])) {
+        live = false;
+        break;
       }
-      if (P.aux_flags & GS_AUX_NBLEND) J.aux[(plane++) * HW + pix] = (float)sk.nblend;
-      if (P.aux_flags & GS_AUX_LAST) J.aux[(plane++) * HW + pix] = (float)sk.last;
     }
+    const int cnt = (int)min((uint32_t)kBlock, end - cs);
+    bool mine = false;
+    double2 m = make_double2(0.0, 0.0);
+    float4 co = make_float4(0.0f, 0.0f, 0.0f, 0.0f), cl = co;
+    if (t < cnt) {
+      const uint32_t e = cs + t;
+      const uint64_t mk = G == 8 ? static_cast<const uint64_t *>(J.masks)[e]
+                                 : (uint64_t) static_cast<const uint16_t *>(J.masks)[e];
+      mine = (mk >> k) & 1u;
+      if (mine) {
+        const uint32_t g = J.vals[e];
+        m = J.xy[g];
+        co = J.conic[g];
+        cl = J.rgb[g];
+      }
+    }
+    const uint64_t bk = __ballot(mine);
+    if (lane == 0) sm.wcnt[cp][w] = (uint32_t)__popcll(bk);
+    __syncthreads();
+    const uint4 ck = *reinterpret_cast<const uint4 *>(sm.wcnt[cp]);
+    if (mine) {
+      const uint32_t woff = (w > 0 ? ck.x : 0u) + (w > 1 ? ck.y : 0u) + (w > 2 ? ck.z : 0u);
+      const int pos = filled + (int)(woff + __builtin_amdgcn_mbcnt_hi((uint32_t)(bk >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bk, 0u)));
+      const float u = (float)(m.x - fx0), v = (float)(m.y - fy0);
+      const float l2o = log2_opacity(co.w);
+      build_row<PREC, S>(&sm.A[pos * RS], u, v, co.x, co.y, co.z, l2o);
+      sm.col[0][pos] = cl.x;
+      sm.col[1][pos] = cl.y;
+      sm.col[2][pos] = cl.z;
+      sm.qm[pos] = P.all_rows ? (uint8_t)0xF : (uint8_t)quad_mask(u, v, co.x, co.y, co.z, l2o);
+    }
+    filled += (int)(ck.x + ck.y + ck.z + ck.w);
+    cp ^= 1;
   }
+  if (live && filled > 0) {
+    __syncthreads();
+    blend();
+  }
+  write_tile<AUX>(J, P, tx0 + px, ty0 + py, st, rows_done);
 }
 
 // Work item = workgroup id, mapped to bins in the XCD-aware order (4x4 blocks of neighbouring
@@ -533,7 +528,8 @@ __device__ __forceinline__ void raster_bin_mfma(const RasterJob &J, const Raster
 // rows there as well, bit-identical to 1x1 tiles).
 template <int G, int PREC, int S, bool GF>
 struct SharedFor {
-  using type = typename std::conditional<GF, MfmaGroupShared<S>, MfmaShared<G, S>>::type;
+  using type = typename std::conditional<GF, MfmaGroupShared<S>,
+                                         typename std::conditional<G == 1, MfmaShared<S>, MfmaTileShared<S>>::type>::type;
 };
 
 template <int G, int PREC, int S, bool AUX, bool GF, typename SM>
@@ -541,8 +537,10 @@ __device__ __forceinline__ void raster_item(const RasterJob &J, const RasterPara
                                             short8 B1, short8 B20, short8 B21) {
   if constexpr (GF)
     raster_bin_mfma_group<G, PREC, S, AUX>(J, P, item, sm);
+  else if constexpr (G == 1)
+    raster_bin_mfma<PREC, S, AUX>(J, P, item, sm, B0, B1, B20, B21);
   else
-    raster_bin_mfma<G, PREC, S, AUX>(J, P, item, sm, B0, B1, B20, B21);
+    raster_member_tile<G, PREC, S, AUX>(J, P, item, sm, B0, B1, B20, B21);
 }
 
 // threads per workgroup: those of the group-frame path's layout, else four waves
