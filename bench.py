@@ -12,7 +12,11 @@ chosen form against the FP64 oracle on sampled tiles, the oracle's own rate on
 the host cores, and a serving run (8 resident scenes, mixed resolutions, continuous
 batching; p50/p99 latency of an open-loop Poisson stream) under "serving".
 
+With --scene dense6m the same legs run on the dense stress scene (6M Gaussians, log-scale
+N(ln 0.05, 0.5), opacity sigmoid(N(-1, 1))) along its own 200-pose orbit, e.g. with --group 4.
+
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-serve]
+       python bench.py --scene dense6m --group 4 [...]
        python bench.py --serve-only [--serve-requests R] [--serve-load F]
        python bench.py --sweep [--sweep-steps K]
 """
@@ -48,7 +52,7 @@ POWER_FLOPS = 12                    # the power's 6 multiply-adds, moved onto th
 RASTER_COUNTERS = dict(sha256="e4dc199ddf76b0e36a222695491b43cb6650e290d0e2802b9707e7b82a1902b8",
                        fetch_kib=65235, write_kib=25069, fetch_scale=2.0, write_scale=1.0,
                        insts_valu=34.80e6, active_valu_quads=38.49e6,
-                       precision="fp16", splits=2, group=1)
+                       precision="fp16", splits=2, group=1, scene="clustered1m")
 SIMDS = 1024                # 256 CUs x 4 SIMDs
 CLOCK_HZ = 2.4e9
 VALU_CYCLES = 4             # a wave64 VALU instruction on a 16-lane SIMD
@@ -69,7 +73,7 @@ def raster_source_hash():
 def raster_counters(args):
     """The stored counters when they describe this kernel and workload, else None."""
     c = RASTER_COUNTERS
-    if (args.precision, args.splits, args.group) != (c["precision"], c["splits"], c["group"]):
+    if (args.precision, args.splits, args.group, args.scene) != (c["precision"], c["splits"], c["group"], c["scene"]):
         return None
     try:
         if raster_source_hash() != c["sha256"]:
@@ -110,6 +114,8 @@ def parse():
     ap.add_argument("--precision", default="fp16", choices=["fp16", "bf16", "fp32"])
     ap.add_argument("--splits", type=int, default=2)
     ap.add_argument("--group", type=int, default=1)
+    ap.add_argument("--scene", default="clustered1m", choices=["clustered1m", "dense6m"],
+                    help="the 1M-Gaussian scene, or the dense 6M-Gaussian stress scene")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tight", action="store_true", help="skip the opacity-aware tile culling variant")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 plain comparison run")
@@ -613,9 +619,16 @@ def main():
         print(json.dumps({"sweep": sweep(gs, torch, args)}), flush=True)
         return
 
-    log("generating the 1M-Gaussian scene")
-    sc, _ = scenes.clustered_1m()
-    cams = scenes.orbit(200, 1920, 1080, seed=2)
+    if args.scene == "dense6m":
+        log("generating the dense 6M-Gaussian scene")
+        sc, _ = scenes.dense_6m()
+        cams = scenes.orbit(200, 1920, 1080, seed=5)
+        scene_text = "6M Gaussians, dense 64-cluster mixture (log-scale N(ln 0.05, 0.5), opacity sigmoid(N(-1, 1)))"
+    else:
+        log("generating the 1M-Gaussian scene")
+        sc, _ = scenes.clustered_1m()
+        cams = scenes.orbit(200, 1920, 1080, seed=2)
+        scene_text = "1M Gaussians, 64-cluster mixture"
     ds = gs.DeviceScene(sc)
     okw = dict(group=args.group, precision=args.precision, splits=args.splits)
     rend = gs.Renderer(sc.n, 1920, 1080, group=args.group)
@@ -736,7 +749,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.precision if args.precision != "fp32" else "fp32",
         "data": "synthetic",
-        "config": {"workload": f"1M Gaussians, 64-cluster mixture, SH degree 3, 1920x1080, {min(args.steps, len(cams))} "
+        "config": {"workload": f"{scene_text}, SH degree 3, 1920x1080, {min(args.steps, len(cams))} "
                                f"poses of a {len(cams)}-pose orbit (one frame per pose), "
                                f"{args.group}x{args.group} tile groups, {args.precision} splits {args.splits}",
                    "gaussians": sc.n, "width": 1920, "height": 1080, "group": args.group,

@@ -27,7 +27,7 @@ def test_traffic_only_for_the_profiled_kernel():
     b = _bench()
 
     class A:
-        precision, splits, group = "fp16", 2, 1
+        precision, splits, group, scene = "fp16", 2, 1, "clustered1m"
     t = b.raster_traffic(A)
     c = b.RASTER_COUNTERS
     if b.raster_source_hash() == c["sha256"]:
@@ -35,4 +35,6 @@ def test_traffic_only_for_the_profiled_kernel():
     else:
         assert t is None
     A.group = 4
+    assert b.raster_traffic(A) is None
+    A.group, A.scene = 1, "dense6m"
     assert b.raster_traffic(A) is None
