@@ -817,8 +817,9 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t *bin_keys, con
   }
 }
 
-// Bin ranges and (group > 1) membership masks once the last bin pass has placed the final
-// Gaussian indices and 64-bit keys: only the sorted bin keys are read for the ranges.
+// Bin ranges and (MASKS: group > 1) membership masks once the last bin pass has placed the
+// final Gaussian indices and 64-bit keys: only the sorted bin keys are read for the ranges.
+template <bool MASKS>
 __global__ __launch_bounds__(kBlock) void k_ranges_final(const uint32_t *bin_keys, uint64_t n_host,
                                                          const uint32_t *n_dev, const uint32_t *vals,
                                                          const ushort4 *rect, const double2 *xy, const float4 *conic,
@@ -843,11 +844,11 @@ __global__ __launch_bounds__(kBlock) void k_ranges_final(const uint32_t *bin_key
     const uint32_t b = bin[j] & bmask;
     if (prev[j] != b) ranges[2 * (uint64_t)b] = (uint32_t)i;
     if (next[j] != b) ranges[2 * (uint64_t)b + 1] = (uint32_t)(i + 1);
-    if (G > 1 && masks && desc_shift) {
+    if (MASKS && desc_shift) {
       const uint64_t m = rect_desc_mask(bin[j] >> desc_shift, G);
       if (G == 8) static_cast<uint64_t *>(masks)[i] = m;
       else static_cast<uint16_t *>(masks)[i] = (uint16_t)m;
-    } else if (G > 1 && masks) {
+    } else if (MASKS) {
       const uint32_t g = vals[i];
       const ushort4 rc = rect[g];
       const int gx = (int)(b % (uint32_t)GX), gy = (int)(b / (uint32_t)GX);
@@ -1117,8 +1118,13 @@ hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint
                                           true);
   if (e != hipSuccess) return e;
   const uint32_t *kf = in_alt ? bkey_alt : bkey;
-  hipLaunchKernelGGL(k_ranges_final, dim3(grid_for(K, (uint64_t)kBlock * kRangeItems)), dim3(kBlock), 0, st, kf, K,
-                     K_dev, vals, r4, m2, c4, tight ? 1 : 0, g.G, g.GX, desc_shift, ranges, masks);
+  const dim3 rgrid(grid_for(K, (uint64_t)kBlock * kRangeItems));
+  if (g.G > 1 && masks)
+    hipLaunchKernelGGL(k_ranges_final<true>, rgrid, dim3(kBlock), 0, st, kf, K, K_dev, vals, r4, m2, c4, tight ? 1 : 0,
+                       g.G, g.GX, desc_shift, ranges, masks);
+  else
+    hipLaunchKernelGGL(k_ranges_final<false>, rgrid, dim3(kBlock), 0, st, kf, K, K_dev, vals, r4, m2, c4,
+                       tight ? 1 : 0, g.G, g.GX, desc_shift, ranges, masks);
   return hipGetLastError();
 }
 
