@@ -3,13 +3,14 @@ analysis, made a run-time decision).
 
 Which group side renders a scene fastest depends on the scene and the resolution: grouping
 shrinks the sort by the load reduction but adds staging work per member tile, and where the
-balance falls differs from the paper's hardware (on the sensitivity workloads here 1x1 tiles
-with opacity-aware culling win at 3M Gaussians, 8x8 groups in the dense 6M scene).  With the
-MFMA precisions every group side, with or without opacity-aware culling, gives bit-identical
-images, so the choice changes only the speed: `AdaptiveRenderer` renders the first frames of
-a scene once with each candidate (group side, culling) variant, timed on the stream with HIP
-events, and then keeps the fastest (re-probing after `reprobe_every` frames, or after
-`chooser.reset()`).
+balance falls differs from the paper's hardware (on the sensitivity workloads here 4x4 groups
+win at 3M Gaussians, 8x8 groups in the dense 6M scene).  With the MFMA precisions every group
+side, with or without opacity-aware culling, gives the same image (bit-identical with per-tile
+rows), so the choice changes only the speed: `AdaptiveRenderer` renders the first frames of a
+scene with each candidate (group side, culling) variant, timed on the stream with HIP events,
+and then keeps the fastest (re-probing after `reprobe_every` frames, or after
+`chooser.reset()`).  By default each probe frame renders its view with every variant, so the
+variants are compared on the same views.
 """
 from __future__ import annotations
 
@@ -67,7 +68,7 @@ class AdaptiveRenderer:
 
     def __init__(self, n: int, width: int, height: int, precision="fp16", splits: int = 2,
                  groups=(1, 2, 4, 8), tight=(False, True), probes: int = 2, reprobe_every: int = 0,
-                 bg=(0.0, 0.0, 0.0), device="cuda", tile_rows: bool = False):
+                 bg=(0.0, 0.0, 0.0), device="cuda", tile_rows: bool = False, paired: bool = True):
         prec = gs.PRECISIONS[precision] if isinstance(precision, str) else precision
         if prec == gs.GS_PREC_FP32:
             groups = [g for g in groups if g != 8]      # the FP32 rasterizer has no 8x8 groups
@@ -81,7 +82,19 @@ class AdaptiveRenderer:
                      for v in self.variants}
         self.renderers = {g: gs.Renderer(n, width, height, group=g, device=device) for g in groups}
         self.chooser = GroupChooser(self.variants, probes, reprobe_every)
+        # paired: a probe frame renders its view with every variant (one probe round), instead of
+        # one variant per frame in turn, whose views differ from variant to variant
+        self.paired = paired
         self.last_variant = None
+
+    def _timed(self, scene, cam, v, st) -> float:
+        import torch
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        self.renderers[v[0]].render(scene, cam, self.opts[v], stream=st)
+        b.record(st)
+        b.synchronize()
+        return a.elapsed_time(b)
 
     def render(self, scene: "gs.DeviceScene", cam, stream=None):
         """Renders one frame; returns (image tensor, (group side, culling) used)."""
@@ -89,15 +102,16 @@ class AdaptiveRenderer:
         if (cam.width, cam.height) != (self.width, self.height):
             raise ValueError("camera size differs from the renderer's")
         v = self.chooser.next()
-        ren = self.renderers[v[0]]
         st = stream if stream is not None else torch.cuda.current_stream()
+        if self.chooser.chosen is None and self.paired:
+            # one probe round on this view; the image returned is the last variant's
+            for v in self.variants:
+                self.chooser.observe(v, self._timed(scene, cam, v, st))
+            self.last_variant = v
+            return self.renderers[v[0]].image, v
+        ren = self.renderers[v[0]]
         if self.chooser.chosen is None:
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(st)
-            ren.render(scene, cam, self.opts[v], stream=st)
-            b.record(st)
-            b.synchronize()
-            self.chooser.observe(v, a.elapsed_time(b))
+            self.chooser.observe(v, self._timed(scene, cam, v, st))
         else:
             ren.render(scene, cam, self.opts[v], stream=st)
             self.chooser.observe(v, 0.0)
