@@ -42,6 +42,11 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint64_t n, ui
 // the per-pass digit scans stay short; 512-key tiles were 1.3 % slower end to end), larger
 // ones R = 8 (2,048 keys).
 constexpr int kDigits = 256;                   // digits of at most 8 bits
+// A sort of more than kSmallSort keys on exactly 9 bits (the bins of 4x4 groups at 1080p, 8x8
+// at 2160p) takes them in one pass of 512 digits: one pass over the entries instead of two
+// (5 + 4 bits), its per-tile counts still 1 byte per key with 2,048-key tiles.
+constexpr int kWideDigits = 512;
+constexpr int kWideBits = 9;
 constexpr int kDepthBits = 31;                 // a positive float's sign bit is zero
 constexpr int kSmallR = 4;                      // sorts up to kSmallSort keys: 1,024-key tiles
 constexpr int kLargeR = 8;                      // larger sorts: 2,048-key tiles
@@ -580,14 +585,14 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
   __shared__ uint64_t s_pos[ITEMS + 1];
   __shared__ uint32_t s_g[ITEMS];
   __shared__ uint32_t s_first;
-  __shared__ uint32_t h[kDigits];
+  __shared__ uint32_t h[kWideDigits];
   const uint32_t nvis = (uint32_t)count_of(nvis_host, nvis_dev);
   const uint64_t K = count_of(K_host, K_dev);
   const uint32_t tile = xcd_sort_tile(blockIdx.x, (K + ITEMS - 1) / ITEMS);
   const uint64_t e0 = (uint64_t)tile * ITEMS;
   clear_ranges(ranges, nranges);
   if (tile == ~0u) return;
-  h[threadIdx.x] = 0;
+  for (int d = threadIdx.x; d < kWideDigits; d += kBlock) h[d] = 0;
   uint32_t first, span;
   stage_block_gaussians<ITEMS>(dpos, block_first, nvis, e0, s_pos, &s_first, &first, &span, order, s_g);
   const uint32_t dmask = (1u << fc.nbits0) - 1u;
@@ -617,7 +622,7 @@ __global__ __launch_bounds__(kBlock) void k_binning(const uint32_t *order, const
   }
   if (fc.counts) {
     __syncthreads();
-    fc.counts[(uint64_t)threadIdx.x * fc.tiles + tile] = h[threadIdx.x];
+    for (int d = threadIdx.x; d < (1 << fc.nbits0); d += kBlock) fc.counts[(uint64_t)d * fc.tiles + tile] = h[d];
   }
 }
 
@@ -637,7 +642,7 @@ __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order,
   __shared__ uint64_t s_pos[ITEMS + 1];
   __shared__ uint32_t s_g[ITEMS];
   __shared__ uint32_t s_first;
-  __shared__ uint32_t h[kDigits];
+  __shared__ uint32_t h[kWideDigits];
   const uint32_t nvis = (uint32_t)count_of(nvis_host, nvis_dev);
   const uint64_t K = count_of(K_host, K_dev);
   const uint32_t tile = xcd_sort_tile(blockIdx.x, (K + ITEMS - 1) / ITEMS);
@@ -645,7 +650,7 @@ __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order,
   const int lane = threadIdx.x & 63;
   clear_ranges(ranges, nranges);
   if (tile == ~0u) return;
-  h[threadIdx.x] = 0;
+  for (int d = threadIdx.x; d < kWideDigits; d += kBlock) h[d] = 0;
   uint32_t first, span;
   stage_block_gaussians<ITEMS>(dpos, block_first, nvis, e0, s_pos, &s_first, &first, &span, order, s_g);
   const uint32_t dmask = (1u << fc.nbits0) - 1u;
@@ -746,7 +751,7 @@ __global__ __launch_bounds__(kBlock) void k_binning_tight(const uint32_t *order,
   }
   if (fc.counts) {
     __syncthreads();
-    fc.counts[(uint64_t)threadIdx.x * fc.tiles + tile] = h[threadIdx.x];
+    for (int d = threadIdx.x; d < (1 << fc.nbits0); d += kBlock) fc.counts[(uint64_t)d * fc.tiles + tile] = h[d];
   }
 }
 
@@ -899,16 +904,16 @@ constexpr int pass_width(int lo, int hi, int maxw = 8) {
 
 // first_counted: the per-tile digit counts of the first pass are already in tmp (written where
 // the keys were produced).  fin: the last pass places final Gaussian indices and 64-bit keys.
-template <typename KT, int R>
+template <typename KT, int R, int DIG>
 hipError_t radix_passes_r(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals_alt, uint64_t n,
                           const uint32_t *n_dev, int lo, int hi, void *tmp, hipStream_t st, bool *in_alt,
                           const FinalOut *fin, bool first_counted) {
   const uint32_t tiles = (uint32_t)((n + SortTile<R>::kTile - 1) / SortTile<R>::kTile);
   uint32_t *counts = static_cast<uint32_t *>(tmp);
-  uint32_t *totals = counts + (uint64_t)kDigits * tiles;
+  uint32_t *totals = counts + (uint64_t)DIG * tiles;
   KT *kin = keys, *kout = keys_alt;
   uint32_t *vin = vals, *vout = vals_alt;
-  const int width = pass_width(lo, hi);
+  const int width = DIG == kWideDigits ? kWideBits : pass_width(lo, hi);
   const FinalOut none{nullptr, nullptr, nullptr, nullptr};
   const DigitWeights now{nullptr, nullptr, nullptr, nullptr, nullptr};
   const FirstEntries nofe{nullptr, nullptr, 0};
@@ -916,11 +921,11 @@ hipError_t radix_passes_r(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals
     const int bits = (hi - shift) < width ? (hi - shift) : width;
     const bool last = shift + width >= hi;
     if (!(first_counted && shift == lo))
-      hipLaunchKernelGGL((k_radix_count<KT, R, kDigits, false>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, kin,
+      hipLaunchKernelGGL((k_radix_count<KT, R, DIG, false>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, kin,
                          n, n_dev, shift, bits, tiles, counts, now);
     hipLaunchKernelGGL(k_radix_digit_scan, dim3(1u << bits), dim3(kBlock), 0, st, counts, tiles, totals, n, n_dev,
                        (uint32_t)SortTile<R>::kTile, now);
-    hipLaunchKernelGGL((k_radix_scatter<KT, R, kDigits, false>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, kin,
+    hipLaunchKernelGGL((k_radix_scatter<KT, R, DIG, false>), dim3(xcd_sort_grid(tiles)), dim3(kBlock), 0, st, kin,
                        vin, kout, vout, n, n_dev, shift, bits, tiles, counts, totals, (last && fin) ? *fin : none,
                        now, nofe);
     std::swap(kin, kout);
@@ -938,10 +943,13 @@ hipError_t radix_passes_t(KT *keys, uint32_t *vals, KT *keys_alt, uint32_t *vals
   *in_alt = false;
   if (hi <= lo || n <= 1) return hipSuccess;
   if (n <= kSmallSort)
-    return radix_passes_r<KT, kSmallR>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt, fin,
-                                       first_counted);
-  return radix_passes_r<KT, kLargeR>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt, fin,
-                                     first_counted);
+    return radix_passes_r<KT, kSmallR, kDigits>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt,
+                                                fin, first_counted);
+  if (hi - lo == kWideBits)
+    return radix_passes_r<KT, kLargeR, kWideDigits>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st,
+                                                    in_alt, fin, first_counted);
+  return radix_passes_r<KT, kLargeR, kDigits>(keys, vals, keys_alt, vals_alt, n, n_dev, lo, hi, tmp, st, in_alt,
+                                              fin, first_counted);
 }
 
 hipError_t radix_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n, int lo,
@@ -1032,9 +1040,11 @@ hipError_t depth_passes(uint32_t *order, const uint32_t *nvis, uint64_t n_max, u
 }
 
 size_t radix_tmp_bytes(uint64_t n) {
-  uint64_t tiles = sort_tiles(n < kSmallSort ? n : kSmallSort);
-  if (sort_tiles(n) > tiles) tiles = sort_tiles(n);
-  return ((size_t)kDigits * (tiles ? tiles : 1) + kDigits) * sizeof(uint32_t);
+  // the most digit counts of any sort of at most n keys: 256 per 1,024-key tile up to
+  // kSmallSort keys, 512 per 2,048-key tile above (the same 1 count per 4 keys), and the totals
+  uint64_t counts = (uint64_t)kDigits * sort_tiles(n < kSmallSort ? n : kSmallSort);
+  if (n > kSmallSort && (uint64_t)kWideDigits * sort_tiles(n) > counts) counts = (uint64_t)kWideDigits * sort_tiles(n);
+  return ((size_t)(counts ? counts : kDigits) + kWideDigits) * sizeof(uint32_t);
 }
 
 size_t depth_sort_tmp_bytes(uint64_t n) { return depth_tmp(nullptr, sort_tiles(n ? n : 1)).bytes; }
@@ -1085,7 +1095,8 @@ hipError_t bin_and_sort(const uint32_t *order, const uint32_t *dkeys, const uint
   // sort's own passes do
   const bool large = K > kSmallSort;
   const unsigned tiles = grid_for(K, large ? SortTile<kLargeR>::kTile : SortTile<kSmallR>::kTile);
-  const FirstCounts fc{K > 1 ? static_cast<uint32_t *>(tmp) : nullptr, pass_width(0, hi), tiles};
+  const int nbits0 = (large && hi == kWideBits) ? kWideBits : pass_width(0, hi);   // as radix_passes_t splits [0, hi)
+  const FirstCounts fc{K > 1 ? static_cast<uint32_t *>(tmp) : nullptr, nbits0, tiles};
   const unsigned grid = xcd_sort_grid(tiles);   // the sort's tile order (k_radix_scatter)
   if (tight) {
     if (large)

@@ -101,6 +101,26 @@ def test_radix_sort_bit_ranges(lo, hi):
     assert np.array_equal(vd.cpu().numpy().view(np.uint32), vals[order])
 
 
+@pytest.mark.parametrize("lo,hi,n", [(0, 9, 1_500_001), (32, 41, 2_100_000), (3, 12, 1_048_577)])
+def test_radix_sort_nine_bit_single_pass(lo, hi, n):
+    """Above 2^20 keys a 9-bit range is sorted in one pass of 512 digits (the bins of 4x4 groups
+    at 1080p): bit-exact against a stable argsort, duplicates included."""
+    import torch
+    note(f"radix sort {n} keys, bits [{lo},{hi})")
+    rng = np.random.default_rng(lo * 1000 + hi + n)
+    keys = rng.integers(0, 1 << 62, n, dtype=np.uint64)
+    keys[rng.random(n) < 0.3] = np.uint64(12345) << np.uint64(lo)   # a heavy duplicate digit
+    vals = np.arange(n, dtype=np.uint32)
+    kd = torch.from_numpy(keys.view(np.int64).copy()).cuda()
+    vd = torch.from_numpy(vals.view(np.int32).copy()).cuda()
+    gs.gs_radix_sort_u64(kd, vd, lo, hi)
+    torch.cuda.synchronize()
+    field = (keys >> np.uint64(lo)) & np.uint64((1 << (hi - lo)) - 1)
+    order = np.argsort(field, kind="stable")
+    assert np.array_equal(vd.cpu().numpy().view(np.uint32), vals[order])
+    assert np.array_equal(kd.cpu().numpy().view(np.uint64), keys[order])
+
+
 @pytest.mark.parametrize("group", [1, 2, 4, 8])
 def test_bin_sort_small(small, group):
     sc, cam, ref, ds = small
