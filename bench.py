@@ -49,7 +49,7 @@ POWER_FLOPS = 12                    # the power's 6 multiply-adds, moved onto th
 # (SQ_INSTS_VALU) and the SIMD cycles spent on VALU instructions (SQ_ACTIVE_INST_VALU, in units
 # of 4 cycles, summed over the SIMDs).  They describe the kernel built from the source and
 # compiler flags hashed in `sha256`; after any change to either they are reported as null.
-RASTER_COUNTERS = dict(sha256="25bcbb356571ab2baa8d392a7e91f24cb2acac2510a1d03cad66e070b97757bd",
+RASTER_COUNTERS = dict(sha256="97c7411ab9156cc5cc8b8d5597cdbef1983b75d60f013d73bf4da0f983cfc227",
                        fetch_kib=65246, write_kib=25081, fetch_scale=2.0, write_scale=1.0,
                        insts_valu=34.77e6, active_valu_quads=38.46e6,
                        precision="fp16", splits=2, group=1, scene="clustered1m")

@@ -52,7 +52,7 @@ extern "C" {
 typedef enum {
   GS_OK = 0,
   GS_ERR_INVALID_ARG = 1,   /* null pointer, negative size, bad enum value */
-  GS_ERR_UNSUPPORTED = 2,   /* valid but outside the supported range (SH degree > 3, group not 1/2/4, W or H > 16384, n >= 2^31) */
+  GS_ERR_UNSUPPORTED = 2,   /* valid but outside the supported range (SH degree > 3, group not 1/2/4/8, W or H > 16384, n >= 2^31) */
   GS_ERR_CAPACITY = 3,      /* the entry count exceeds gs_bins.capacity; the required count is returned */
   GS_ERR_HIP = 4            /* a HIP runtime call failed; see gs_last_error() */
 } gs_status;
@@ -92,12 +92,12 @@ enum {
    * every aux plane are those of the full rows).  This flag makes every quadrant run every row
    * of its tile, the plain tile loop; it exists to check that equality and changes no result. */
   GS_OPT_ALL_ROWS = 2u,
-  /* Grouped MFMA rasterization (group > 1) stages a chunk of the group's list once and, by default,
-   * also builds each entry's Gaussian-side row once, in the frame of the whole group, for all its
-   * member tiles (the tiles then differ only in the pixel-side operand; 2x2 groups, larger ones
-   * always use per-tile rows).  The image equals the 1x1 one in exact arithmetic
-   * and to the split operands' rounding in FP16/BF16.  This flag makes every member tile build its
-   * rows in its own frame instead, which gives images bit-identical to group 1. */
+  /* Grouped MFMA rasterization (group > 1).  By default 2x2 groups build each entry's
+   * Gaussian-side row once, in the frame of the whole group, for all its member tiles (the tiles
+   * then differ only in the pixel-side operand); the image equals the 1x1 one in exact
+   * arithmetic and to the split operands' rounding in FP16/BF16.  Larger groups build the rows
+   * of each member tile in its own frame (one workgroup per member tile walking the group's
+   * list), which gives images bit-identical to group 1; this flag does the same for 2x2 groups. */
   GS_OPT_TILE_ROWS = 4u,
   /* gs_bin_sort and gs_render without the host wait: the kernels that follow the count scan read
    * the entry and visible counts from device memory, and their grids are sized for
